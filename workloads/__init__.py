@@ -1,0 +1,300 @@
+"""Seeded synthetic inputs for the DEM hot path (both the GPU solver's tests
+and the CPU oracle read these; neither side's arithmetic lives here).
+
+Every generator draws from NumPy's PCG64 with a fixed seed, except sphere
+placement by random sequential addition, which runs in ``pack.c`` with its own
+SplitMix64 stream seeded from the same seed.  A workload is a dict::
+
+    {"name", "params": {rho, E, nu, e_n, mu_s, mu_r, mu_t, eta, g, dt,
+                        mesh_omega, mesh_center},
+     "x", "v", "w" (n,3), "q" (n,4) scalar first, "R" (n,),
+     "tri" (m,3,3), "rmesh" (m,), "steps", "R_max"}
+
+Units are SI.  Parameters not stated by a configuration take Table 2's
+values (E = 1 MPa, nu = 0.3, eta = 0, g = (0,0,-9.81)) and the first
+configuration's contact parameters (e_n = 0.7, mu = 0.5/0.1/0.1).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_PACK_SRC = os.path.join(_HERE, "pack.c")
+_PACK_LIB = os.path.join(_HERE, "libpack.so")
+
+MM = 1e-3
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_PACK_LIB):
+        tmp = _PACK_LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _PACK_SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _PACK_LIB)
+    return _PACK_LIB
+
+
+_pack = None
+
+
+def _packlib():
+    global _pack
+    if _pack is None:
+        if not os.path.exists(_PACK_LIB):
+            build()
+        L = C.CDLL(_PACK_LIB)
+        D = C.POINTER(C.c_double)
+        L.pack_rsa.restype = C.c_int64
+        L.pack_rsa.argtypes = [C.c_int64, D, D, D, C.c_int32, D, C.c_uint64, C.c_int64, D]
+        _pack = L
+    return _pack
+
+
+def rsa_place(R, lo, hi, seed, shape=0, cyl=(0.0, 0.0, 0.0, 0.0), max_attempts=100000):
+    """Random sequential addition of spheres with radii R, largest first (a
+    late large sphere would otherwise find no room); returns centres in the
+    order of R."""
+    R_in = np.asarray(R, dtype=np.float64)
+    order = np.argsort(-R_in, kind="stable")
+    R = np.ascontiguousarray(R_in[order])
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    cyl = np.ascontiguousarray(cyl, dtype=np.float64)
+    x = np.zeros((len(R), 3))
+    D = C.POINTER(C.c_double)
+    got = _packlib().pack_rsa(len(R), R.ctypes.data_as(D), lo.ctypes.data_as(D),
+                              hi.ctypes.data_as(D), int(shape), cyl.ctypes.data_as(D),
+                              C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), int(max_attempts),
+                              x.ctypes.data_as(D))
+    if got != len(R):
+        raise RuntimeError(f"random sequential addition placed {got} of {len(R)} spheres")
+    out = np.empty_like(x)
+    out[order] = x
+    return out
+
+
+# ---------------------------------------------------------------------------
+# parameters
+# ---------------------------------------------------------------------------
+def default_params(**kw) -> dict:
+    p = dict(rho=2500.0, E=1e6, nu=0.3, e_n=0.7, mu_s=0.5, mu_r=0.1, mu_t=0.1, eta=0.0,
+             g=(0.0, 0.0, -9.81), dt=1e-6, mesh_omega=(0.0, 0.0, 0.0),
+             mesh_center=(0.0, 0.0, 0.0))
+    p.update(kw)
+    return p
+
+
+def dt_eq(R_min, rho, E, nu):
+    """Eq. dt time step (needed where a configuration gives no step)."""
+    return R_min * math.sqrt(rho * (1.0 - nu * nu) / E)
+
+
+# ---------------------------------------------------------------------------
+# geometry
+# ---------------------------------------------------------------------------
+def shoemake_quaternions(rng, n):
+    """Uniformly random unit quaternions (Shoemake 1992), scalar first."""
+    u1, u2, u3 = rng.random(n), rng.random(n), rng.random(n)
+    a, b = np.sqrt(1.0 - u1), np.sqrt(u1)
+    q = np.stack([a * np.sin(2 * np.pi * u2), a * np.cos(2 * np.pi * u2),
+                  b * np.sin(2 * np.pi * u3), b * np.cos(2 * np.pi * u3)], axis=1)
+    return np.ascontiguousarray(q)
+
+
+def cube_mesh(lo, hi):
+    """12 triangles: each face of the box split along its min->max diagonal."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    tris = []
+    for ax in range(3):
+        u, v = [a for a in range(3) if a != ax]
+        for side in (lo[ax], hi[ax]):
+            def P(a, b):
+                p = np.zeros(3)
+                p[ax] = side
+                p[u] = a
+                p[v] = b
+                return p
+            p00, p11 = P(lo[u], lo[v]), P(hi[u], hi[v])
+            p10, p01 = P(hi[u], lo[v]), P(lo[u], hi[v])
+            tris.append([p00, p10, p11])
+            tris.append([p00, p11, p01])
+    return np.ascontiguousarray(np.array(tris))
+
+
+def floor_mesh(cx, cy, half, z=0.0):
+    """Square floor at height z from two triangles."""
+    a = np.array([cx - half, cy - half, z])
+    b = np.array([cx + half, cy - half, z])
+    c = np.array([cx + half, cy + half, z])
+    d = np.array([cx - half, cy + half, z])
+    return np.ascontiguousarray(np.array([[a, b, c], [a, c, d]]))
+
+
+def drum_mesh(radius, length, nseg=128, nring=31):
+    """Closed drum around the y axis: nseg x nring x 2 shell triangles plus
+    two end-cap fans of nseg triangles (8,192 for the defaults)."""
+    th = np.linspace(0, 2 * np.pi, nseg + 1)[:-1]
+    ys = np.linspace(-length / 2, length / 2, nring + 1)
+    ring = np.stack([radius * np.cos(th), np.zeros(nseg), radius * np.sin(th)], axis=1)
+    tris = []
+    for r in range(nring):
+        for s in range(nseg):
+            s2 = (s + 1) % nseg
+            p00 = ring[s] + [0, ys[r], 0]
+            p10 = ring[s2] + [0, ys[r], 0]
+            p01 = ring[s] + [0, ys[r + 1], 0]
+            p11 = ring[s2] + [0, ys[r + 1], 0]
+            tris.append([p00, p10, p11])
+            tris.append([p00, p11, p01])
+    for y in (ys[0], ys[-1]):
+        ctr = np.array([0.0, y, 0.0])
+        for s in range(nseg):
+            s2 = (s + 1) % nseg
+            tris.append([ctr, ring[s] + [0, y, 0], ring[s2] + [0, y, 0]])
+    return np.ascontiguousarray(np.array(tris))
+
+
+def _finish(name, params, x, R, rng, tri, steps, v=None, w=None, q=None, R_max=None):
+    n = len(R)
+    if v is None:
+        v = np.zeros((n, 3))
+    if w is None:
+        w = np.zeros((n, 3))
+    if q is None:
+        q = shoemake_quaternions(rng, n)
+    tri = np.zeros((0, 3, 3)) if tri is None else np.ascontiguousarray(tri, dtype=np.float64)
+    return {"name": name, "params": params, "x": np.ascontiguousarray(x, dtype=np.float64),
+            "v": np.ascontiguousarray(v, dtype=np.float64),
+            "w": np.ascontiguousarray(w, dtype=np.float64),
+            "q": np.ascontiguousarray(q, dtype=np.float64),
+            "R": np.ascontiguousarray(R, dtype=np.float64), "tri": tri,
+            "rmesh": np.zeros(len(tri)), "steps": int(steps),
+            "R_max": float(R.max() if R_max is None else R_max)}
+
+
+# ---------------------------------------------------------------------------
+# the five configurations
+# ---------------------------------------------------------------------------
+def cfg1(seed=101, pitch=2.2 * MM):
+    """1,000 spheres, R ~ U[0.8, 1.2] mm, rho 2500, jittered 10^3 lattice
+    (centres 1.1 + k*pitch mm, +-0.05 mm jitter) in the lower corner of a
+    closed 12-triangle cube of side 30 mm; zero velocity, random orientation;
+    mu 0.5/0.1/0.1, e_n 0.7, dt = 1e-6 s, 2,000 steps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n1 = 10
+    R = rng.uniform(0.8 * MM, 1.2 * MM, n1 ** 3)
+    k = np.arange(n1)
+    g = np.stack(np.meshgrid(k, k, k, indexing="ij"), axis=-1).reshape(-1, 3)
+    x = 1.1 * MM + g * pitch + rng.uniform(-0.05 * MM, 0.05 * MM, (n1 ** 3, 3))
+    tri = cube_mesh([0, 0, 0], [30 * MM] * 3)
+    return _finish("cfg1_box_drop_1k", default_params(dt=1e-6), x, R, rng, tri, 2000, R_max=1.2 * MM)
+
+
+def cfg2(seed=202, n=200_000, phi_rsa=0.35, shrink=0.93):
+    """200,000 spheres, R = 1 mm * exp(0.2 Z), granular column on a
+    600 x 600 mm two-triangle floor, full friction, dt = 5e-7 s, 20,000 steps.
+
+    The loose packing: random sequential addition of the spheres at radii
+    shrink*R into a 60 x 60 mm column (packing fraction phi_rsa at the shrunk
+    radii), then the true radii, so neighbours closer than the shrink margin
+    start slightly overlapped (packing fraction phi_rsa/shrink^3 ~ 0.44).  The
+    column height follows from N and the fraction (a 300 mm column cannot
+    hold 200,000 such spheres)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = MM * np.exp(0.2 * rng.standard_normal(n))
+    vol = float(np.sum(4.0 / 3.0 * np.pi * (shrink * R) ** 3))
+    L = 60 * MM
+    H = vol / (phi_rsa * L * L)
+    x = rsa_place(shrink * R, [-L / 2, -L / 2, 0.0], [L / 2, L / 2, H], seed)
+    # lift so that no sphere starts below the floor at its true radius
+    x[:, 2] += (1.0 - shrink) * R.max()
+    tri = floor_mesh(0.0, 0.0, 300 * MM, 0.0)
+    return _finish("cfg2_column_collapse_200k", default_params(dt=5e-7), x, R, rng, tri, 20000)
+
+
+def cfg3(seed=303, n=2_000_000, phi_rsa=0.36, shrink=0.92):
+    """2,000,000 spheres, R ~ U[0.9, 1.1] mm, in a rotating drum (radius
+    0.15 m, axis y, length 0.40 m, 8,192 triangles, 1 rad/s), filled to the
+    level needed by random sequential addition below the axis region;
+    dt from Eq. dt at R_min = 0.9 mm."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = rng.uniform(0.9 * MM, 1.1 * MM, n)
+    Rd, Ld = 0.15, 0.40
+    vol = float(np.sum(4.0 / 3.0 * np.pi * (shrink * R) ** 3))
+    # fill height: the circular segment below z = zf holds vol/phi_rsa
+    target = vol / (phi_rsa * (Ld - 4 * MM))
+    lo_z, hi_z = -Rd, Rd
+    for _ in range(80):
+        zf = 0.5 * (lo_z + hi_z)
+        a = math.acos(max(-1.0, min(1.0, -zf / Rd)))
+        area = Rd * Rd * (a - math.sin(a) * math.cos(a))
+        lo_z, hi_z = (zf, hi_z) if area < target else (lo_z, zf)
+    x = rsa_place(shrink * R, [-Rd, -Ld / 2 + 2 * MM, -Rd], [Rd, Ld / 2 - 2 * MM, zf], seed,
+                  shape=1, cyl=(0.0, 0.0, Rd - 1.5 * MM, zf))
+    tri = drum_mesh(Rd, Ld)
+    p = default_params(dt=dt_eq(0.9 * MM, 2500.0, 1e6, 0.3), mesh_omega=(0.0, 1.0, 0.0))
+    return _finish("cfg3_rotating_drum_2M", p, x, R, rng, tri, 2000, R_max=1.1 * MM)
+
+
+def cfg4_sim(s, n_s, seed=404):
+    """One simulation of the batched sweep: a 'box drop' of n_s spheres,
+    R ~ U[0.8, 1.2] mm, on an n x n lattice of pitch 2.5 mm (n = ceil(n_s^1/3))
+    layered upward from mid-height of a 12-triangle cube of side 5n mm,
+    horizontally centred; mu_s = 0.1 + 0.8 s/255, mu_r = mu_t = 0.1."""
+    rng = np.random.Generator(np.random.PCG64(404_000 + s))
+    nl = int(math.ceil(n_s ** (1.0 / 3.0) - 1e-9))
+    Ls = 5.0 * nl * MM
+    R = rng.uniform(0.8 * MM, 1.2 * MM, n_s)
+    k = np.arange(n_s)
+    ix, iy, iz = k % nl, (k // nl) % nl, k // (nl * nl)
+    off = (Ls - (nl - 1) * 2.5 * MM) / 2.0
+    x = np.stack([off + ix * 2.5 * MM, off + iy * 2.5 * MM, Ls / 2 + iz * 2.5 * MM], axis=1)
+    tri = cube_mesh([0, 0, 0], [Ls] * 3)
+    p = default_params(dt=dt_eq(0.8 * MM, 2500.0, 1e6, 0.3), mu_s=0.1 + 0.8 * s / 255.0)
+    return _finish(f"cfg4_sim{s}", p, x, R, rng, tri, 5000, R_max=1.2 * MM)
+
+
+def cfg4(nsims=256, seed=404, sizes=None):
+    """256 independent box drops of uneven size N_s ~ U{500..20,000}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if sizes is None:
+        sizes = rng.integers(500, 20_000, size=nsims, endpoint=True)
+    return [cfg4_sim(s, int(sizes[s]), seed) for s in range(nsims)]
+
+
+def cfg5(seed=505, n=8_000_000, phi_rsa=0.38, shrink=0.85):
+    """8,000,000 spheres, half R = 1.0 mm and half 1.4 mm (seeded shuffle), a
+    dense packing in a closed 12-triangle cube: random sequential addition at
+    shrunk radii, then the true radii (packing fraction ~0.62); full
+    friction, g on, eta = 0, dt from Eq. dt at 1.0 mm."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = np.where(rng.permutation(n) < n // 2, 1.0 * MM, 1.4 * MM)
+    vol = float(np.sum(4.0 / 3.0 * np.pi * (shrink * R) ** 3))
+    L = (vol / phi_rsa) ** (1.0 / 3.0)
+    x = rsa_place(shrink * R, [0.0, 0.0, 0.0], [L, L, L], seed)
+    tri = cube_mesh([-0.5 * MM] * 3, [L + 0.5 * MM] * 3)
+    p = default_params(dt=dt_eq(1.0 * MM, 2500.0, 1e6, 0.3))
+    return _finish("cfg5_dense_packing_8M", p, x, R, rng, tri, 10000, R_max=1.4 * MM)
+
+
+# ---------------------------------------------------------------------------
+# small cases for tests
+# ---------------------------------------------------------------------------
+def random_cluster(n, seed, box=10 * MM, r_lo=0.8 * MM, r_hi=1.2 * MM, vel=0.05, spin=20.0,
+                   overlap=0.15, params=None, tri=None):
+    """n spheres at random in a cube (packing by random sequential addition at
+    radii (1-overlap)R, so some neighbours start overlapped), with random
+    velocities and spins.  Used for small parity and edge cases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = rng.uniform(r_lo, r_hi, n)
+    x = rsa_place((1.0 - overlap) * R, [0, 0, 0], [box] * 3, seed + 17)
+    v = rng.normal(0.0, vel, (n, 3))
+    w = rng.normal(0.0, spin, (n, 3))
+    p = default_params(dt=2e-6) if params is None else params
+    return _finish(f"cluster{n}_{seed}", p, x, R, rng, tri, 100, v=v, w=w)
