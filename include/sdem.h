@@ -1,0 +1,168 @@
+/*
+ * sdem: the per-timestep hot path of a soft-sphere DEM solver (TinyDEM,
+ * Vetter, arXiv 2507.12610) on AMD MI355X (gfx950), as a C ABI.
+ *
+ * One call of sdem_step advances every simulation of a context by whole time
+ * steps.  A step is, in order (Section 2.3 and Section 3.3 of the paper):
+ *   1. broad phase: bounding box of the particle centres, cubic cells of edge
+ *      cell_factor * 2 R_max, particles sorted by cell;
+ *   2. narrow phase: particle pairs with delta = R_i + R_j - d >= 0 in the
+ *      27-cell neighbourhood, and particle-triangle pairs with
+ *      delta = R_i + R_m - |x_i - closest point| >= 0 (Fig. 4C);
+ *   3. contact forces and torques: Hertz normal force with damping (Eq. fn,
+ *      cn), Mindlin sliding, rolling and twisting springs with Coulomb limits
+ *      (Eq. fs..ft, Coulombs/r/t, um..um_kinetic), torques, and the pairwise
+ *      antisymmetry that updates both bodies from one evaluation (Section 3.2);
+ *      friction springs carried from the previous step by contact key;
+ *   4. semi-implicit Euler for translation (Eq. v, x), SPIRAL for the
+ *      orientation quaternion (Eq. spiral), then Eq. w; Stokes drag
+ *      (Section 2.1).
+ *
+ * Conventions
+ *  - Units are SI.  Vectors are structure-of-arrays: x[0..n) holds the x
+ *    components, x[n..2n) y, x[2n..3n) z.  Quaternions q[4][n], scalar part
+ *    first.  Radii R[n].
+ *  - The persistent id of a particle is its index in the arrays given to
+ *    sdem_init / sdem_init_batch.  Every read returns data ordered by id.
+ *  - Contact keys (Section 3.2): (ki, kj) with ki < kj the two particle ids
+ *    for a particle pair, or kj = -m <= 0 for triangle m of the particle's own
+ *    simulation (m counted from 0 in the order given to sdem_add_mesh).
+ *  - Pointers passed to sdem_init, sdem_read_* may be device or host memory;
+ *    the library copies, it never keeps a caller pointer.  Mesh and history
+ *    arrays are host memory.
+ *  - Device memory: the caller supplies one workspace of
+ *    sdem_workspace_bytes() bytes (any device allocation, 256-byte aligned)
+ *    and a HIP stream; the library allocates no device memory.  All work is
+ *    enqueued on that stream.  A context is not thread-safe.
+ *  - Errors: every call returns an sdem_status; sdem_last_error() gives a
+ *    thread-local message.  No exception crosses the ABI.
+ */
+#ifndef SDEM_H
+#define SDEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdem_ctx sdem_ctx;
+
+typedef enum {
+  SDEM_OK = 0,
+  SDEM_EINVAL = -1,     /* argument outside its documented range            */
+  SDEM_ECAPACITY = -2,  /* contacts, cells or triangles exceed the capacity */
+  SDEM_ENONFINITE = -3, /* a position, velocity or spin became NaN or inf   */
+  SDEM_EHIP = -4,       /* a HIP runtime call failed                        */
+  SDEM_ESTATE = -5      /* call not allowed in the context's current state  */
+} sdem_status;
+
+typedef enum { SDEM_FP64 = 0, SDEM_MIXED = 1 } sdem_precision;
+
+/* Parameters of one simulation: the material block of Table 2, gravity g,
+ * the time step dt (> 0; Eq. dt gives the paper's default), and a rigid
+ * rotation of that simulation's mesh (angular velocity mesh_omega about an
+ * axis through mesh_center; zero for the static meshes of the paper).
+ * Requirements (Table 2): rho > 0, E > 0, -1 < nu <= 0.5, 0 <= e_n <= 1,
+ * mu_s, mu_r, mu_t >= 0, eta >= 0, dt > 0. */
+typedef struct {
+  double rho, E, nu, e_n, mu_s, mu_r, mu_t, eta;
+  double g[3];
+  double dt;
+  double mesh_omega[3];
+  double mesh_center[3];
+} sdem_params;
+
+/* Capacities and launch shape of a context.
+ *  n_max         particles over all simulations
+ *  contacts_max  contacts (particle pairs + particle-triangle) per step
+ *  cells_max     grid cells per step over all simulations (the grid spans
+ *                the bounding box of each simulation's centres)
+ *  tri_max       triangles over all simulations
+ *  nsims_max     simulations
+ *  precision     SDEM_FP64: all arithmetic in double.  SDEM_MIXED: contact
+ *                force and torque arithmetic in float, with double for
+ *                positions, velocities, differences, the contact test,
+ *                springs, force sums and integration
+ *  block         threads per workgroup for particle and contact kernels, a
+ *                multiple of 64 in [64, 1024]; 0 selects 256
+ *  cell_factor   cell edge = cell_factor * 2 * R_max, >= 1; 0 selects 1 */
+typedef struct {
+  int64_t n_max, contacts_max, cells_max, tri_max;
+  int32_t nsims_max, precision, block, reserved;
+  double cell_factor;
+} sdem_config;
+
+/* Bytes of device workspace a context with these capacities needs. */
+size_t sdem_workspace_bytes(const sdem_config* cfg);
+
+/* One simulation of n particles (n may be 0).  x, v, w [3][n], q [4][n],
+ * R [n] (R > 0); v, w may be NULL (zero), q may be NULL (identity).
+ * Returns SDEM_EINVAL on a bad parameter or radius, SDEM_ECAPACITY if n,
+ * the workspace or nsims exceed the capacities. */
+int sdem_init(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params, int64_t n,
+              const double* x, const double* v, const double* w, const double* q,
+              const double* R, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* nsims independent simulations in one context (one launch per phase for
+ * all of them).  Simulation s owns particles [offsets[s], offsets[s+1]) of the
+ * arrays (host array offsets, offsets[0] = 0) and has params[s]. */
+int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg, int32_t nsims,
+                    const sdem_params* params, const int64_t* offsets, const double* x,
+                    const double* v, const double* w, const double* q, const double* R,
+                    void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Sets the triangle mesh of simulation `sim` (replacing any earlier one):
+ * tri [ntri][3][3] vertex coordinates (host), rmesh [ntri] element radii
+ * R_m >= 0 (host, NULL for 0).  Allowed before the first step only. */
+int sdem_add_mesh(sdem_ctx* ctx, int32_t sim, int64_t ntri, const double* tri,
+                  const double* rmesh);
+
+/* Loads friction-spring history (host arrays): nc keys (ki, kj) as in the
+ * conventions above, springs us[nc][3], ur[nc][3], ut[nc] in the orientation
+ * of body ki.  Keys that are not in contact at the next step are dropped. */
+int sdem_set_history(sdem_ctx* ctx, int64_t nc, const int32_t* ki, const int32_t* kj,
+                     const double* us, const double* ur, const double* ut);
+
+/* Advances all simulations by nsteps steps.  Returns SDEM_ECAPACITY or
+ * SDEM_ENONFINITE if a step failed; the steps before it stand, the failed
+ * step is abandoned, the reads return the state and contacts at its start,
+ * and the context accepts no further steps. */
+int sdem_step(sdem_ctx* ctx, int64_t nsteps);
+
+/* Current state by persistent id: x, v, w [3][n], q [4][n], and the net
+ * contact force F and torque T [3][n] of the last step.  Any pointer may be
+ * NULL.  Synchronises the stream. */
+int sdem_read_state(sdem_ctx* ctx, double* x, double* v, double* w, double* q, double* F,
+                    double* T);
+
+/* Contacts of the last step in key order (ki ascending, then kj ascending,
+ * signed) with their springs after that step: us, ur [cap][3], ut [cap].
+ * *n_out receives the number of contacts; at most cap are written.  Any
+ * array may be NULL.  Synchronises the stream. */
+int sdem_read_contacts(sdem_ctx* ctx, int64_t cap, int64_t* n_out, int32_t* ki, int32_t* kj,
+                       double* us, double* ur, double* ut);
+
+/* Steps completed, and the sums over those steps of particle-pair and
+ * particle-triangle contact counts (for contacts/s).  Any pointer may be
+ * NULL.  Synchronises the stream. */
+int sdem_stats(sdem_ctx* ctx, int64_t* steps, int64_t* pp_contacts, int64_t* pw_contacts);
+
+/* Releases the host-side context (the workspace stays the caller's). */
+int sdem_destroy(sdem_ctx* ctx);
+
+/* Thread-local message describing the last failure. */
+const char* sdem_last_error(void);
+
+/* Device self-test of the rounding the contact test relies on: out[k] =
+ * sqrt(in[k]) and out[n+k] = in[k] / in2[k] computed on the GPU (device
+ * arrays in, in2 [n], out [2n]).  Used to check that the device square root
+ * and division are correctly rounded, as the host's are. */
+int sdem_selftest_rounding(int64_t n, const double* in, const double* in2, double* out,
+                           void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

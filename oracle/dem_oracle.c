@@ -341,7 +341,8 @@ struct orc_sim {
   double *F, *T, *Fs, *Ts;
   int64_t ntri;
   double *tri0, *tri, *rmesh;
-  double t;
+  double t, t0;  /* t = t0 + nstep * dt */
+  int64_t nstep;
   int32_t search_mode;
   double cell_factor;
   contact_rec* hist; /* springs of the previous step, key order */
@@ -467,6 +468,8 @@ int orc_set_history(orc_sim* s, int64_t nc, const int32_t* ki, const int32_t* kj
 
 void orc_set_time(orc_sim* s, double t) {
   s->t = t;
+  s->t0 = t;
+  s->nstep = 0;
   update_mesh(s);
 }
 double orc_get_time(const orc_sim* s) { return s->t; }
@@ -534,7 +537,9 @@ static void build_cells(orc_sim* s) {
       if (s->x[3 * i + k] > hi[k]) hi[k] = s->x[3 * i + k];
     }
   }
-  s->h = s->cell_factor * 2.0 * Rmax;
+  /* small margin: rounding of the cell coordinate must not put two touching
+   * spheres two cells apart */
+  s->h = s->cell_factor * 2.0 * Rmax * (1.0 + 1e-9);
   s->ncell = 1;
   for (int k = 0; k < 3; ++k) {
     s->lo[k] = lo[k];
@@ -758,7 +763,8 @@ static int step_once(orc_sim* s) {
   for (int64_t i = 0; i < n; ++i)
     integrate_one(&s->p, s->m[i], s->I[i], s->R[i], s->F + 3 * i, s->T + 3 * i, s->x + 3 * i,
                   s->v + 3 * i, s->w + 3 * i, s->q + 4 * i);
-  s->t = s->t + s->p.dt;
+  s->nstep += 1;
+  s->t = s->t0 + (double)s->nstep * s->p.dt;
   update_mesh(s);
   return 0;
 }

@@ -1,0 +1,7 @@
+"""Soft-sphere DEM hot path (TinyDEM, arXiv 2507.12610) on AMD MI355X.
+
+The product is the C ABI in ``include/sdem.h`` implemented by HIP kernels in
+``csrc/`` (built into ``libsdem.so``); ``sdem`` is its Python binding.
+"""
+from .sdem import (SDEM_FP64, SDEM_MIXED, Config, Params, SdemError, Solver, lib,  # noqa: F401
+                   selftest_rounding)

@@ -1,0 +1,679 @@
+// Host side of the sdem C ABI: argument checks, workspace carving, parameter
+// derivation, step sequencing (HIP graphs of two steps), and reads.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "sdem_internal.h"
+
+using namespace sdem;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(SDEM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                             \
+  } while (0)
+
+constexpr double kPiHost = 3.14159265358979323846;
+constexpr int kMaxSimsHost = 4096;
+
+struct Layout {
+  size_t total = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    total = (total + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + total) : nullptr;
+    total += count * sizeof(T);
+    return p;
+  }
+};
+
+int64_t nchunks_max(const sdem_config& c) {
+  return (c.n_max + kBboxChunk - 1) / kBboxChunk + c.nsims_max;
+}
+
+}  // namespace
+
+struct sdem_ctx {
+  Ctx c{};
+  State st[2]{};
+  Contacts ct[2]{};
+  int cur = 0;  // buffer holding the current state and the last step's contacts
+  hipStream_t stream = nullptr;
+  sdem_config cfg{};
+  int nsims = 0;
+  int64_t n = 0;
+  bool failed = false;
+  bool stepped = false;
+  double* scratch = nullptr;  // [19][n] for reads into host memory
+  std::vector<sdem_params> params;
+  std::vector<int64_t> offsets;
+  std::vector<std::vector<double>> mesh_tri, mesh_r;
+  std::vector<double> rmax;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool graph_failed = false;
+};
+
+static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Contacts ct[2],
+                    double** scratch) {
+  Layout L;
+  L.base = base;
+  const size_t N = (size_t)std::max<int64_t>(cfg.n_max, 1);
+  const size_t Cm = (size_t)std::max<int64_t>(cfg.contacts_max, 1);
+  const size_t Gm = (size_t)std::max<int64_t>(cfg.cells_max, 1);
+  const size_t M = (size_t)std::max<int64_t>(cfg.tri_max, 1);
+  const size_t S = (size_t)std::max<int32_t>(cfg.nsims_max, 1);
+  const size_t NC = (size_t)nchunks_max(cfg);
+  Ctx cc{};
+  cc.ctr = L.take<Counters>(1);
+  cc.sp = L.take<SimParams>(S);
+  cc.sg = L.take<SimGrid>(S);
+  cc.sim_of = L.take<int32_t>(N);
+  cc.chunks = L.take<int32_t>(3 * NC);
+  cc.chunk0 = L.take<int32_t>(S + 1);
+  cc.part = L.take<double>(6 * NC);
+  cc.cell_cnt = L.take<int32_t>(Gm);
+  cc.cell_start = L.take<int32_t>(Gm + 1);
+  cc.key_tmp = L.take<int32_t>(N);
+  cc.rank = L.take<int32_t>(N);
+  cc.perm = L.take<int32_t>(N);
+  cc.scan_tmp = L.take<int32_t>(kScanBlocks + 1);
+  cc.F = L.take<double>(3 * N);
+  cc.T = L.take<double>(3 * N);
+  cc.tri_ref = L.take<double>(9 * M);
+  cc.tri = L.take<double>(9 * M);
+  cc.tri_pl = L.take<double>(4 * M);
+  cc.rmesh = L.take<double>(M);
+  cc.tri_sim = L.take<int32_t>(M);
+  for (int b = 0; b < 2; ++b) {
+    State s{};
+    s.x = L.take<double>(3 * N);
+    s.v = L.take<double>(3 * N);
+    s.w = L.take<double>(3 * N);
+    s.q = L.take<double>(4 * N);
+    s.R = L.take<double>(N);
+    s.pid = L.take<int32_t>(N);
+    s.key = L.take<int32_t>(N);
+    s.src = L.take<int32_t>(N);
+    if (st) st[b] = s;
+  }
+  for (int b = 0; b < 2; ++b) {
+    Contacts k{};
+    k.cnt = L.take<int32_t>(N + 1);
+    k.off = L.take<int32_t>(N + 1);
+    k.a = L.take<int32_t>(Cm);
+    k.b = L.take<int32_t>(Cm);
+    k.ki = L.take<int32_t>(Cm);
+    k.kj = L.take<int32_t>(Cm);
+    k.us = L.take<double>(3 * Cm);
+    k.ur = L.take<double>(3 * Cm);
+    k.ut = L.take<double>(Cm);
+    if (ct) ct[b] = k;
+  }
+  double* scr = L.take<double>(19 * N);
+  if (scratch) *scratch = scr;
+  L.total = (L.total + 255) & ~size_t(255);
+  if (c) *c = cc;
+  return L;
+}
+
+static int check_config(const sdem_config* cfg) {
+  if (!cfg) return fail(SDEM_EINVAL, "config is NULL");
+  if (cfg->n_max < 0 || cfg->n_max > 0x3fffffff) return fail(SDEM_EINVAL, "n_max out of range");
+  if (cfg->contacts_max < 0 || cfg->contacts_max > 0x3fffffff)
+    return fail(SDEM_EINVAL, "contacts_max out of range");
+  if (cfg->cells_max < 1 || cfg->cells_max > 0x3fffffff)
+    return fail(SDEM_EINVAL, "cells_max out of range");
+  if (cfg->tri_max < 0 || cfg->tri_max > 0x3fffffff) return fail(SDEM_EINVAL, "tri_max out of range");
+  if (cfg->nsims_max < 1 || cfg->nsims_max > kMaxSimsHost)
+    return fail(SDEM_EINVAL, "nsims_max must be in [1, %d]", kMaxSimsHost);
+  if (cfg->precision != SDEM_FP64 && cfg->precision != SDEM_MIXED)
+    return fail(SDEM_EINVAL, "unknown precision %d", cfg->precision);
+  if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64))
+    return fail(SDEM_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+  if (!(cfg->cell_factor == 0.0 || cfg->cell_factor >= 1.0) || !isfinite(cfg->cell_factor))
+    return fail(SDEM_EINVAL, "cell_factor must be >= 1");
+  return SDEM_OK;
+}
+
+static int check_params(const sdem_params& p, int s) {
+  // Table 2 "Requirements"
+  if (!(p.rho > 0) || !(p.E > 0) || !isfinite(p.rho) || !isfinite(p.E))
+    return fail(SDEM_EINVAL, "sim %d: rho and E must be > 0", s);
+  if (!(p.nu > -1.0 && p.nu <= 0.5)) return fail(SDEM_EINVAL, "sim %d: nu must be in (-1, 0.5]", s);
+  if (!(p.e_n >= 0.0 && p.e_n <= 1.0)) return fail(SDEM_EINVAL, "sim %d: e_n must be in [0, 1]", s);
+  if (!(p.mu_s >= 0) || !(p.mu_r >= 0) || !(p.mu_t >= 0) || !isfinite(p.mu_s) ||
+      !isfinite(p.mu_r) || !isfinite(p.mu_t))
+    return fail(SDEM_EINVAL, "sim %d: friction coefficients must be >= 0", s);
+  if (!(p.eta >= 0) || !isfinite(p.eta)) return fail(SDEM_EINVAL, "sim %d: eta must be >= 0", s);
+  if (!(p.dt > 0) || !isfinite(p.dt)) return fail(SDEM_EINVAL, "sim %d: dt must be > 0", s);
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(p.g[k]) || !isfinite(p.mesh_omega[k]) || !isfinite(p.mesh_center[k]))
+      return fail(SDEM_EINVAL, "sim %d: g, mesh_omega, mesh_center must be finite", s);
+  return SDEM_OK;
+}
+
+static bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged ||
+         a.type == hipMemoryTypeUnified;
+}
+
+static SimParams derive(const sdem_params& p, double cell_factor, double rmax) {
+  SimParams d{};
+  d.rho = p.rho;
+  d.E = p.E;
+  d.nu = p.nu;
+  d.e_n = p.e_n;
+  d.mu_s = p.mu_s;
+  d.mu_r = p.mu_r;
+  d.mu_t = p.mu_t;
+  d.eta = p.eta;
+  for (int k = 0; k < 3; ++k) {
+    d.g[k] = p.g[k];
+    d.om[k] = p.mesh_omega[k];
+    d.ctr[k] = p.mesh_center[k];
+  }
+  d.dt = p.dt;
+  const double r = kPiHost / log(p.e_n);  // e_n = 1 -> inf -> beta 0; e_n = 0 -> beta 1
+  d.beta = 1.0 / sqrt(1.0 + r * r);
+  const double E = p.E, nu = p.nu;
+  d.Es_pp = E / (2.0 * (1.0 - nu * nu));
+  d.Gs_pp = E / (4.0 * (2.0 - nu) * (1.0 + nu));
+  d.Es_pw = E / (1.0 - nu * nu);
+  d.Gs_pw = E / (2.0 * (1.0 + nu) * (2.0 - nu));
+  // cell edge >= 2 R_max; the small margin keeps neighbours within one cell
+  // index of each other despite rounding of the cell coordinate
+  const double rm = rmax > 0 ? rmax : 1.0;
+  d.h = cell_factor * 2.0 * rm * (1.0 + 1e-9);
+  d.rotating = (p.mesh_omega[0] != 0.0 || p.mesh_omega[1] != 0.0 || p.mesh_omega[2] != 0.0);
+  return d;
+}
+
+static int upload_params(sdem_ctx* x) {
+  std::vector<SimParams> sp(x->nsims);
+  int tri0 = 0;
+  for (int s = 0; s < x->nsims; ++s) {
+    sp[s] = derive(x->params[s], x->cfg.cell_factor, x->rmax[s]);
+    sp[s].p0 = (int32_t)x->offsets[s];
+    sp[s].np = (int32_t)(x->offsets[s + 1] - x->offsets[s]);
+    sp[s].tri0 = tri0;
+    sp[s].ntri = (int32_t)x->mesh_r[s].size();
+    tri0 += sp[s].ntri;
+  }
+  HIP_TRY(hipMemcpyAsync(x->c.sp, sp.data(), sizeof(SimParams) * x->nsims, hipMemcpyHostToDevice,
+                         x->stream));
+  HIP_TRY(hipStreamSynchronize(x->stream));
+  return SDEM_OK;
+}
+
+extern "C" {
+
+size_t sdem_workspace_bytes(const sdem_config* cfg) {
+  if (check_config(cfg) != SDEM_OK) return 0;
+  return carve(*cfg, nullptr, nullptr, nullptr, nullptr, nullptr).total;
+}
+
+int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
+                    const sdem_params* params, const int64_t* offsets, const double* x,
+                    const double* v, const double* w, const double* q, const double* R,
+                    void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out) return fail(SDEM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_config(cfg_in);
+  if (rc) return rc;
+  sdem_config cfg = *cfg_in;
+  if (cfg.cell_factor == 0.0) cfg.cell_factor = 1.0;
+  if (cfg.block == 0) cfg.block = kThreads;
+  if (nsims < 1 || nsims > cfg.nsims_max)
+    return fail(SDEM_ECAPACITY, "nsims %d outside [1, nsims_max=%d]", nsims, cfg.nsims_max);
+  if (!params || !offsets) return fail(SDEM_EINVAL, "params and offsets are required");
+  if (offsets[0] != 0) return fail(SDEM_EINVAL, "offsets[0] must be 0");
+  for (int s = 0; s < nsims; ++s) {
+    if (offsets[s + 1] < offsets[s]) return fail(SDEM_EINVAL, "offsets must be non-decreasing");
+    if ((rc = check_params(params[s], s))) return rc;
+  }
+  const int64_t n = offsets[nsims];
+  if (n > cfg.n_max) return fail(SDEM_ECAPACITY, "n = %lld exceeds n_max = %lld", (long long)n,
+                                 (long long)cfg.n_max);
+  if (n > 0 && (!x || !R)) return fail(SDEM_EINVAL, "x and R are required");
+  const size_t need = sdem_workspace_bytes(&cfg);
+  if (!workspace || ws_bytes < need)
+    return fail(SDEM_ECAPACITY, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail(SDEM_EINVAL, "workspace must be 256-byte aligned");
+
+  // radii: validate and find each simulation's largest (cell edge, Section 3.3)
+  std::vector<double> Rh((size_t)n);
+  if (n) {
+    HIP_TRY(hipMemcpy(Rh.data(), R, sizeof(double) * n, hipMemcpyDefault));
+  }
+  std::vector<double> rmax(nsims, 0.0);
+  for (int s = 0; s < nsims; ++s)
+    for (int64_t i = offsets[s]; i < offsets[s + 1]; ++i) {
+      if (!(Rh[i] > 0) || !isfinite(Rh[i]))
+        return fail(SDEM_EINVAL, "radius %lld is not a positive finite number", (long long)i);
+      rmax[s] = std::max(rmax[s], Rh[i]);
+    }
+
+  sdem_ctx* X = new sdem_ctx();
+  X->cfg = cfg;
+  X->nsims = nsims;
+  X->n = n;
+  X->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  X->params.assign(params, params + nsims);
+  X->offsets.assign(offsets, offsets + nsims + 1);
+  X->mesh_tri.assign(nsims, {});
+  X->mesh_r.assign(nsims, {});
+  X->rmax = rmax;
+  carve(cfg, reinterpret_cast<char*>(workspace), &X->c, X->st, X->ct, &X->scratch);
+  Ctx& c = X->c;
+  c.n = (int32_t)n;
+  c.nsims = nsims;
+  c.ntri = 0;
+  c.cap_contacts = (int32_t)cfg.contacts_max;
+  c.cap_cells = (int32_t)cfg.cells_max;
+
+  auto bail = [&](int code) {
+    delete X;
+    return code;
+  };
+  hipStream_t st = X->stream;
+  // per-slot simulation id and bounding-box chunks
+  std::vector<int32_t> sim_of((size_t)std::max<int64_t>(n, 1)), chunks, chunk0(nsims + 1);
+  for (int s = 0; s < nsims; ++s) {
+    chunk0[s] = (int32_t)(chunks.size() / 3);
+    for (int64_t i = offsets[s]; i < offsets[s + 1]; ++i) sim_of[i] = s;
+    for (int64_t b = offsets[s]; b < offsets[s + 1]; b += kBboxChunk) {
+      chunks.push_back(s);
+      chunks.push_back((int32_t)b);
+      chunks.push_back((int32_t)std::min<int64_t>(offsets[s + 1], b + kBboxChunk));
+    }
+  }
+  chunk0[nsims] = (int32_t)(chunks.size() / 3);
+  c.nchunks = chunk0[nsims];
+  std::vector<int32_t> iota((size_t)std::max<int64_t>(n, 1));
+  for (int64_t i = 0; i < n; ++i) iota[i] = (int32_t)i;
+
+  auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, st) : hipSuccess;
+  };
+  const size_t v3 = sizeof(double) * 3 * n;
+  State& A = X->st[0];
+  hipError_t e = hipSuccess;
+  if (!e) e = hipMemsetAsync(c.ctr, 0, sizeof(Counters), st);
+  if (!e) e = hipMemsetAsync(c.cell_cnt, 0, sizeof(int32_t) * cfg.cells_max, st);
+  for (int b = 0; b < 2 && !e; ++b) {
+    e = hipMemsetAsync(X->ct[b].cnt, 0, sizeof(int32_t) * (n + 1), st);
+    if (!e) e = hipMemsetAsync(X->ct[b].off, 0, sizeof(int32_t) * (n + 1), st);
+  }
+  if (!e) e = hipMemsetAsync(c.F, 0, v3 ? v3 : 8, st);
+  if (!e) e = hipMemsetAsync(c.T, 0, v3 ? v3 : 8, st);
+  if (!e) e = cp(A.x, x, v3);
+  if (!e) e = v ? cp(A.v, v, v3) : hipMemsetAsync(A.v, 0, v3 ? v3 : 8, st);
+  if (!e) e = w ? cp(A.w, w, v3) : hipMemsetAsync(A.w, 0, v3 ? v3 : 8, st);
+  if (!e && q) e = cp(A.q, q, 4 * sizeof(double) * n);
+  if (!e && !q && n) {
+    std::vector<double> qi((size_t)4 * n, 0.0);
+    for (int64_t i = 0; i < n; ++i) qi[i] = 1.0;
+    e = hipMemcpy(A.q, qi.data(), qi.size() * sizeof(double), hipMemcpyHostToDevice);
+  }
+  if (!e) e = cp(A.R, R, sizeof(double) * n);
+  if (!e) e = cp(A.pid, iota.data(), sizeof(int32_t) * n);
+  if (!e) e = cp(A.src, iota.data(), sizeof(int32_t) * n);
+  if (!e) e = cp(c.sim_of, sim_of.data(), sizeof(int32_t) * n);
+  if (!e) e = cp(c.chunks, chunks.data(), sizeof(int32_t) * chunks.size());
+  if (!e) e = cp(c.chunk0, chunk0.data(), sizeof(int32_t) * chunk0.size());
+  if (!e) e = hipStreamSynchronize(st);
+  if (e) {
+    fail(SDEM_EHIP, "init copies failed: %s", hipGetErrorString(e));
+    return bail(SDEM_EHIP);
+  }
+  if ((rc = upload_params(X))) return bail(rc);
+  *out = X;
+  return SDEM_OK;
+}
+
+int sdem_init(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params, int64_t n,
+              const double* x, const double* v, const double* w, const double* q,
+              const double* R, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (n < 0) return fail(SDEM_EINVAL, "n must be >= 0");
+  const int64_t off[2] = {0, n};
+  return sdem_init_batch(out, cfg, 1, params, off, x, v, w, q, R, workspace, ws_bytes,
+                         hip_stream);
+}
+
+int sdem_add_mesh(sdem_ctx* X, int32_t sim, int64_t ntri, const double* tri, const double* rmesh) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (X->stepped) return fail(SDEM_ESTATE, "meshes are fixed once stepping has started");
+  if (sim < 0 || sim >= X->nsims) return fail(SDEM_EINVAL, "sim %d out of range", sim);
+  if (ntri < 0 || (ntri > 0 && !tri)) return fail(SDEM_EINVAL, "bad triangle array");
+  for (int64_t m = 0; m < 9 * ntri; ++m)
+    if (!isfinite(tri[m])) return fail(SDEM_EINVAL, "triangle vertex %lld is not finite", (long long)m);
+  for (int64_t m = 0; rmesh && m < ntri; ++m)
+    if (!(rmesh[m] >= 0) || !isfinite(rmesh[m]))
+      return fail(SDEM_EINVAL, "mesh radius %lld must be >= 0", (long long)m);
+  int64_t total = ntri;
+  for (int s = 0; s < X->nsims; ++s)
+    if (s != sim) total += (int64_t)X->mesh_r[s].size();
+  if (total > X->cfg.tri_max)
+    return fail(SDEM_ECAPACITY, "%lld triangles exceed tri_max = %lld", (long long)total,
+                (long long)X->cfg.tri_max);
+  X->mesh_tri[sim].assign(tri, tri + 9 * ntri);
+  X->mesh_r[sim].assign((size_t)ntri, 0.0);
+  if (rmesh) X->mesh_r[sim].assign(rmesh, rmesh + ntri);
+  // concatenate every simulation's mesh
+  std::vector<double> all, rad;
+  std::vector<int32_t> owner;
+  for (int s = 0; s < X->nsims; ++s) {
+    all.insert(all.end(), X->mesh_tri[s].begin(), X->mesh_tri[s].end());
+    rad.insert(rad.end(), X->mesh_r[s].begin(), X->mesh_r[s].end());
+    owner.insert(owner.end(), X->mesh_r[s].size(), s);
+  }
+  Ctx& c = X->c;
+  c.ntri = (int32_t)rad.size();
+  hipStream_t st = X->stream;
+  if (c.ntri) {
+    HIP_TRY(hipMemcpyAsync(c.tri_ref, all.data(), sizeof(double) * all.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.rmesh, rad.data(), sizeof(double) * rad.size(), hipMemcpyHostToDevice,
+                           st));
+    HIP_TRY(hipMemcpyAsync(c.tri_sim, owner.data(), sizeof(int32_t) * owner.size(),
+                           hipMemcpyHostToDevice, st));
+  }
+  int rc = upload_params(X);
+  if (rc) return rc;
+  HIP_TRY(launch_mesh_planes(c, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SDEM_OK;
+}
+
+int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* kj,
+                     const double* us, const double* ur, const double* ut) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (X->failed) return fail(SDEM_ESTATE, "context failed in an earlier step");
+  if (nc < 0 || (nc > 0 && (!ki || !kj || !us || !ur || !ut)))
+    return fail(SDEM_EINVAL, "bad history arrays");
+  if (nc > X->cfg.contacts_max)
+    return fail(SDEM_ECAPACITY, "%lld history entries exceed contacts_max", (long long)nc);
+  const int64_t n = X->n;
+  hipStream_t st = X->stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<int32_t> pid((size_t)std::max<int64_t>(n, 1)), slot((size_t)std::max<int64_t>(n, 1));
+  if (n) HIP_TRY(hipMemcpy(pid.data(), X->st[X->cur].pid, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  for (int64_t s = 0; s < n; ++s) slot[pid[s]] = (int32_t)s;
+  std::vector<int32_t> owner((size_t)nc);
+  std::vector<int32_t> simof((size_t)std::max<int64_t>(n, 1));
+  for (int s = 0; s < X->nsims; ++s)
+    for (int64_t i = X->offsets[s]; i < X->offsets[s + 1]; ++i) simof[i] = s;
+  for (int64_t e = 0; e < nc; ++e) {
+    if (ki[e] < 0 || ki[e] >= n) return fail(SDEM_EINVAL, "history key %lld: bad ki", (long long)e);
+    if (kj[e] > 0) {
+      if (kj[e] >= n || kj[e] <= ki[e] || simof[kj[e]] != simof[ki[e]])
+        return fail(SDEM_EINVAL, "history key %lld: bad particle pair", (long long)e);
+      owner[e] = std::min(slot[ki[e]], slot[kj[e]]);
+    } else {
+      if (-(int64_t)kj[e] >= (int64_t)X->mesh_r[simof[ki[e]]].size())
+        return fail(SDEM_EINVAL, "history key %lld: no such triangle", (long long)e);
+      owner[e] = slot[ki[e]];
+    }
+  }
+  // group by owner slot (counting sort)
+  std::vector<int32_t> cnt((size_t)n + 1, 0), off((size_t)n + 1, 0);
+  for (int64_t e = 0; e < nc; ++e) ++cnt[owner[e]];
+  for (int64_t s = 0; s < n; ++s) off[s + 1] = off[s] + cnt[s];
+  std::vector<int32_t> pos(off.begin(), off.end());
+  const size_t cap = (size_t)X->cfg.contacts_max;
+  std::vector<int32_t> K1((size_t)nc), K2((size_t)nc);
+  std::vector<double> U((size_t)3 * nc), V((size_t)3 * nc), Wt((size_t)nc);
+  for (int64_t e = 0; e < nc; ++e) {
+    const int32_t d = pos[owner[e]]++;
+    K1[d] = ki[e];
+    K2[d] = kj[e];
+    for (int k = 0; k < 3; ++k) {
+      U[(size_t)k * nc + d] = us[3 * e + k];
+      V[(size_t)k * nc + d] = ur[3 * e + k];
+    }
+    Wt[d] = ut[e];
+  }
+  Contacts& C = X->ct[X->cur];
+  HIP_TRY(hipMemcpy(C.cnt, cnt.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(C.off, off.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+  if (nc) {
+    HIP_TRY(hipMemcpy(C.ki, K1.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(C.kj, K2.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice));
+    for (int k = 0; k < 3; ++k) {
+      HIP_TRY(hipMemcpy(C.us + k * cap, U.data() + (size_t)k * nc, sizeof(double) * nc,
+                        hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(C.ur + k * cap, V.data() + (size_t)k * nc, sizeof(double) * nc,
+                        hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(C.ut, Wt.data(), sizeof(double) * nc, hipMemcpyHostToDevice));
+  }
+  return SDEM_OK;
+}
+
+static hipError_t enqueue_steps(sdem_ctx* X, int k) {
+  for (int i = 0; i < k; ++i) {
+    const int a = (X->cur + i) & 1;
+    hipError_t e = launch_step(X->c, X->st[a], X->st[a ^ 1], X->ct[a], X->ct[a ^ 1],
+                               X->cfg.precision, X->stream);
+    if (e) return e;
+  }
+  return hipSuccess;
+}
+
+// A graph of two steps starting from buffer parity p (the pointers of both
+// buffers are baked in; after two steps the parity is p again).
+static hipGraphExec_t pair_graph(sdem_ctx* X) {
+  const int p = X->cur;
+  if (X->graph[p] || X->graph_failed || !X->stream) return X->graph[p];
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(X->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    X->graph_failed = true;
+    return nullptr;
+  }
+  hipError_t e = enqueue_steps(X, 2);
+  hipError_t e2 = hipStreamEndCapture(X->stream, &g);
+  hipGraphExec_t ex = nullptr;
+  if (e || e2 || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    X->graph_failed = true;
+    ex = nullptr;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  X->graph[p] = ex;
+  return ex;
+}
+
+int sdem_step(sdem_ctx* X, int64_t nsteps) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (X->failed) return fail(SDEM_ESTATE, "context failed in an earlier step; read it and re-init");
+  if (nsteps < 0) return fail(SDEM_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return SDEM_OK;
+  X->stepped = true;
+  Counters before;
+  HIP_TRY(hipMemcpyAsync(&before, X->c.ctr, sizeof before, hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  const int start = X->cur;
+  int64_t left = nsteps;
+  while (left >= 2) {
+    hipGraphExec_t g = pair_graph(X);
+    if (g) {
+      HIP_TRY(hipGraphLaunch(g, X->stream));
+    } else {
+      HIP_TRY(enqueue_steps(X, 2));
+    }
+    left -= 2;
+  }
+  if (left) {
+    HIP_TRY(enqueue_steps(X, 1));
+    X->cur ^= 1;
+  }
+  Counters after;
+  HIP_TRY(hipMemcpyAsync(&after, X->c.ctr, sizeof after, hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  if (after.flags) {
+    const int64_t done = (int64_t)(after.steps - before.steps) - 1;  // the failed one counted
+    X->cur = (int)((start + done) & 1);
+    X->failed = true;
+    if (after.flags & kFlagCapCells)
+      return fail(SDEM_ECAPACITY,
+                  "step %lld: the grid needs %d cells, cells_max is %lld (particles spread too "
+                  "far; confine them with a mesh or raise cells_max)",
+                  (long long)(before.steps + done), after.need_cells,
+                  (long long)X->cfg.cells_max);
+    if (after.flags & kFlagCapContacts)
+      return fail(SDEM_ECAPACITY, "step %lld: %d contacts exceed contacts_max = %lld",
+                  (long long)(before.steps + done), after.need_contacts,
+                  (long long)X->cfg.contacts_max);
+    return fail(SDEM_ENONFINITE, "step %lld: non-finite position, velocity or spin",
+                (long long)(before.steps + done));
+  }
+  return SDEM_OK;
+}
+
+int sdem_read_state(sdem_ctx* X, double* x, double* v, double* w, double* q, double* F,
+                    double* T) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  const int64_t n = X->n;
+  if (n == 0) return SDEM_OK;
+  double* dst[6] = {x, v, w, q, F, T};
+  double* dev[6];
+  const size_t words[6] = {3, 3, 3, 4, 3, 3};
+  size_t at = 0;
+  for (int k = 0; k < 6; ++k) {
+    if (!dst[k]) {
+      dev[k] = nullptr;
+    } else if (is_device_ptr(dst[k])) {
+      dev[k] = dst[k];
+    } else {
+      dev[k] = X->scratch + at * n;
+    }
+    at += words[k];
+  }
+  HIP_TRY(launch_scatter_state(X->c, X->st[X->cur], dev[0], dev[1], dev[2], dev[3], dev[4], dev[5],
+                               X->stream));
+  for (int k = 0; k < 6; ++k)
+    if (dst[k] && dev[k] != dst[k])
+      HIP_TRY(hipMemcpyAsync(dst[k], dev[k], sizeof(double) * words[k] * n, hipMemcpyDeviceToHost,
+                             X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  return SDEM_OK;
+}
+
+int sdem_read_contacts(sdem_ctx* X, int64_t cap, int64_t* n_out, int32_t* ki, int32_t* kj,
+                       double* us, double* ur, double* ut) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (cap < 0) return fail(SDEM_EINVAL, "cap must be >= 0");
+  const int64_t n = X->n;
+  const Contacts& C = X->ct[X->cur];
+  hipStream_t st = X->stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  int32_t total = 0;
+  if (n) HIP_TRY(hipMemcpy(&total, C.off + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (n_out) *n_out = total;
+  if (!total) return SDEM_OK;
+  const size_t ccap = (size_t)X->cfg.contacts_max;
+  std::vector<int32_t> K1(total), K2(total);
+  std::vector<double> S((size_t)7 * total);
+  HIP_TRY(hipMemcpy(K1.data(), C.ki, sizeof(int32_t) * total, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(K2.data(), C.kj, sizeof(int32_t) * total, hipMemcpyDeviceToHost));
+  for (int k = 0; k < 3; ++k) {
+    HIP_TRY(hipMemcpy(S.data() + (size_t)k * total, C.us + k * ccap, sizeof(double) * total,
+                      hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(S.data() + (size_t)(3 + k) * total, C.ur + k * ccap,
+                      sizeof(double) * total, hipMemcpyDeviceToHost));
+  }
+  HIP_TRY(hipMemcpy(S.data() + (size_t)6 * total, C.ut, sizeof(double) * total,
+                    hipMemcpyDeviceToHost));
+  std::vector<int32_t> order(total);
+  for (int32_t e = 0; e < total; ++e) order[e] = e;
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return K1[a] < K1[b] || (K1[a] == K1[b] && K2[a] < K2[b]);
+  });
+  const int64_t m = std::min<int64_t>(cap, total);
+  std::vector<int32_t> o1(m), o2(m);
+  std::vector<double> ous((size_t)3 * m), our((size_t)3 * m), out((size_t)m);
+  for (int64_t r = 0; r < m; ++r) {
+    const int32_t e = order[r];
+    o1[r] = K1[e];
+    o2[r] = K2[e];
+    for (int k = 0; k < 3; ++k) {
+      ous[3 * r + k] = S[(size_t)k * total + e];
+      our[3 * r + k] = S[(size_t)(3 + k) * total + e];
+    }
+    out[r] = S[(size_t)6 * total + e];
+  }
+  if (m) {
+    if (ki) HIP_TRY(hipMemcpy(ki, o1.data(), sizeof(int32_t) * m, hipMemcpyDefault));
+    if (kj) HIP_TRY(hipMemcpy(kj, o2.data(), sizeof(int32_t) * m, hipMemcpyDefault));
+    if (us) HIP_TRY(hipMemcpy(us, ous.data(), sizeof(double) * 3 * m, hipMemcpyDefault));
+    if (ur) HIP_TRY(hipMemcpy(ur, our.data(), sizeof(double) * 3 * m, hipMemcpyDefault));
+    if (ut) HIP_TRY(hipMemcpy(ut, out.data(), sizeof(double) * m, hipMemcpyDefault));
+  }
+  return SDEM_OK;
+}
+
+int sdem_stats(sdem_ctx* X, int64_t* steps, int64_t* pp, int64_t* pw) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  Counters h;
+  HIP_TRY(hipMemcpyAsync(&h, X->c.ctr, sizeof h, hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  const int64_t done = (int64_t)h.steps - (h.flags ? 1 : 0);
+  if (steps) *steps = done;
+  if (pp) *pp = (int64_t)h.pp_sum;
+  if (pw) *pw = (int64_t)h.pw_sum;
+  return SDEM_OK;
+}
+
+int sdem_destroy(sdem_ctx* X) {
+  if (!X) return SDEM_OK;
+  if (X->stream) (void)hipStreamSynchronize(X->stream);
+  for (int p = 0; p < 2; ++p)
+    if (X->graph[p]) (void)hipGraphExecDestroy(X->graph[p]);
+  delete X;
+  return SDEM_OK;
+}
+
+const char* sdem_last_error(void) { return g_err.c_str(); }
+
+int sdem_selftest_rounding(int64_t n, const double* in, const double* in2, double* out,
+                           void* hip_stream) {
+  if (n < 0 || (n > 0 && (!in || !in2 || !out))) return fail(SDEM_EINVAL, "bad arguments");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  HIP_TRY(launch_selftest(n, in, in2, out, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SDEM_OK;
+}
+
+}  // extern "C"

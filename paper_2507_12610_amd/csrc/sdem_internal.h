@@ -1,0 +1,202 @@
+// Internal definitions of the sdem HIP library (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sdem.h"
+
+namespace sdem {
+
+constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scans
+constexpr int kScanThreads = 256;
+constexpr int kBboxChunk = 4096;    // particles per bounding-box partial
+constexpr int kThreads = 256;       // threads per workgroup of the particle kernels
+constexpr int kForceBlocks = 4096;  // fixed grid of the contact kernel (grid stride)
+
+enum : int {
+  kFlagCapContacts = 1,
+  kFlagCapCells = 2,
+  kFlagNonFinite = 4,
+};
+
+// Per-simulation constants, derived on the host at init.
+struct SimParams {
+  double rho, E, nu, e_n, mu_s, mu_r, mu_t, eta;
+  double g[3];
+  double dt;
+  double om[3], ctr[3];
+  double beta;                 // 1/sqrt(1 + (pi/ln e_n)^2)
+  double Es_pp, Gs_pp;         // uniform material, two spheres
+  double Es_pw, Gs_pw;         // sphere against a rigid wall
+  double h;                    // cell edge
+  int32_t rotating;            // mesh rotates (|om| > 0)
+  int32_t tri0, ntri;          // global triangle range
+  int32_t p0, np;              // particle range (fixed positions in sorted order)
+  int32_t pad;
+};
+
+// Per-simulation grid of the current step (computed on the device).
+struct SimGrid {
+  double lo[3];
+  double inv_h;
+  int32_t dim[3];
+  int32_t cell_off;
+};
+
+// Device-side counters and flags of a context.
+struct Counters {
+  int32_t flags;
+  int32_t ncontacts;     // contacts of the step in progress
+  int32_t ncells;        // cells of the step in progress (all sims)
+  int32_t need_contacts; // last required contact capacity (diagnostic)
+  int32_t need_cells;
+  int32_t pad;
+  unsigned long long steps;
+  unsigned long long pp_sum, pw_sum;
+};
+
+// One buffer of per-particle state, in cell-sorted order; vectors are SoA
+// with stride n.
+struct State {
+  double* x;     // [3][n]
+  double* v;     // [3][n]
+  double* w;     // [3][n]
+  double* q;     // [4][n]
+  double* R;     // [n]
+  int32_t* pid;  // persistent id
+  int32_t* key;  // cell key of this slot (written by the reorder)
+  int32_t* src;  // slot of the same particle in the previous step's order
+};
+
+// One buffer of contacts, grouped by owner slot (owner = lower slot).
+struct Contacts {
+  int32_t* cnt;  // [n+1] contacts per owner slot
+  int32_t* off;  // [n+1] exclusive prefix of cnt
+  int32_t* a;    // owner slot
+  int32_t* b;    // partner slot (>= 0) or -1 - global triangle index
+  int32_t* ki;   // key: lower persistent id (particle pairs) or the particle's id
+  int32_t* kj;   // key: higher persistent id, or -(local triangle index)
+  double* us;    // [3][cap] sliding spring, orientation of body ki
+  double* ur;    // [3][cap] rolling spring
+  double* ut;    // [cap] twisting spring
+};
+
+// Everything a step's kernels read or write.
+struct Ctx {
+  int32_t n, nsims, ntri, cap_contacts, cap_cells, nchunks;
+  SimParams* sp;      // [nsims]
+  SimGrid* sg;        // [nsims]
+  int32_t* sim_of;    // [n] simulation of each slot (fixed)
+  int32_t* chunks;    // [nchunks][3] (sim, begin, end) for the bounding box
+  int32_t* chunk0;    // [nsims+1] first chunk of each simulation
+  double* part;       // [nchunks][6] bounding-box partials
+  int32_t* cell_cnt;  // [cap_cells] zero between steps
+  int32_t* cell_start;// [cap_cells+1]
+  int32_t* key_tmp;   // [n] cell key by previous slot
+  int32_t* rank;      // [n] arrival rank in the cell
+  int32_t* perm;      // [n] new slot -> previous slot (unstable within a cell)
+  int32_t* scan_tmp;  // [kScanBlocks+1]
+  double* F;          // [3][n] contact force of the last step
+  double* T;          // [3][n] contact torque of the last step
+  double* tri_ref;    // [ntri][9] vertices at t = 0
+  double* tri;        // [ntri][9] vertices at the current step
+  double* tri_pl;     // [ntri][4] unit normal and offset of the plane
+  double* rmesh;      // [ntri]
+  int32_t* tri_sim;   // [ntri]
+  Counters* ctr;
+};
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // The dispatcher hands workgroup b to XCD b % 8; give each XCD one
+  // contiguous range of logical blocks so that neighbouring slots share an L2.
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+// ---------------------------------------------------------------------------
+// Exact-rounding geometry shared by the contact search and the force kernel:
+// every operation rounded on its own (no contraction), square root and
+// division correctly rounded, so the contact decision is reproducible.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double pair_gap(double xi, double yi, double zi, double Ri, double xj,
+                                           double yj, double zj, double Rj, double* dx, double* dy,
+                                           double* dz, double* d) {
+#pragma clang fp contract(off)
+  const double ex = xi - xj, ey = yi - yj, ez = zi - zj;
+  const double dd = sqrt((ex * ex + ey * ey) + ez * ez);
+  *dx = ex;
+  *dy = ey;
+  *dz = ez;
+  *d = dd;
+  return (Ri + Rj) - dd;  // delta; contact iff >= 0
+}
+
+// Closest point of triangle (a, b, c) to p by Voronoi regions (vertex, edge,
+// face), after Ericson, Real-Time Collision Detection (2005), Sec. 5.1.5.
+__device__ __forceinline__ void closest_on_triangle(const double p[3], const double* t,
+                                                    double out[3]) {
+#pragma clang fp contract(off)
+  const double a0 = t[0], a1 = t[1], a2 = t[2];
+  const double ab0 = t[3] - a0, ab1 = t[4] - a1, ab2 = t[5] - a2;
+  const double ac0 = t[6] - a0, ac1 = t[7] - a1, ac2 = t[8] - a2;
+  const double ap0 = p[0] - a0, ap1 = p[1] - a1, ap2 = p[2] - a2;
+  const double d1 = (ab0 * ap0 + ab1 * ap1) + ab2 * ap2;
+  const double d2 = (ac0 * ap0 + ac1 * ap1) + ac2 * ap2;
+  if (d1 <= 0.0 && d2 <= 0.0) {
+    out[0] = a0; out[1] = a1; out[2] = a2;
+    return;
+  }
+  const double bp0 = p[0] - t[3], bp1 = p[1] - t[4], bp2 = p[2] - t[5];
+  const double d3 = (ab0 * bp0 + ab1 * bp1) + ab2 * bp2;
+  const double d4 = (ac0 * bp0 + ac1 * bp1) + ac2 * bp2;
+  if (d3 >= 0.0 && d4 <= d3) {
+    out[0] = t[3]; out[1] = t[4]; out[2] = t[5];
+    return;
+  }
+  const double vc = d1 * d4 - d3 * d2;
+  if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+    const double s = d1 / (d1 - d3);
+    out[0] = a0 + s * ab0; out[1] = a1 + s * ab1; out[2] = a2 + s * ab2;
+    return;
+  }
+  const double cp0 = p[0] - t[6], cp1 = p[1] - t[7], cp2 = p[2] - t[8];
+  const double d5 = (ab0 * cp0 + ab1 * cp1) + ab2 * cp2;
+  const double d6 = (ac0 * cp0 + ac1 * cp1) + ac2 * cp2;
+  if (d6 >= 0.0 && d5 <= d6) {
+    out[0] = t[6]; out[1] = t[7]; out[2] = t[8];
+    return;
+  }
+  const double vb = d5 * d2 - d1 * d6;
+  if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+    const double s = d2 / (d2 - d6);
+    out[0] = a0 + s * ac0; out[1] = a1 + s * ac1; out[2] = a2 + s * ac2;
+    return;
+  }
+  const double va = d3 * d6 - d5 * d4;
+  const double e43 = d4 - d3, e56 = d5 - d6;
+  if (va <= 0.0 && e43 >= 0.0 && e56 >= 0.0) {
+    const double s = e43 / (e43 + e56);
+    out[0] = t[3] + s * (t[6] - t[3]);
+    out[1] = t[4] + s * (t[7] - t[4]);
+    out[2] = t[5] + s * (t[8] - t[5]);
+    return;
+  }
+  const double inv = 1.0 / ((va + vb) + vc);
+  const double bv = vb * inv, bw = vc * inv;
+  out[0] = (a0 + ab0 * bv) + ac0 * bw;
+  out[1] = (a1 + ab1 * bv) + ac1 * bw;
+  out[2] = (a2 + ab2 * bv) + ac2 * bw;
+}
+
+// Host launchers (kernels live in the .hip files).
+hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
+                       const Contacts& cnew, int precision, hipStream_t s);
+hipError_t launch_scatter_state(const Ctx& c, const State& S, double* x, double* v, double* w,
+                                double* q, double* F, double* T, hipStream_t s);
+hipError_t launch_mesh_planes(const Ctx& c, hipStream_t s);
+hipError_t launch_selftest(int64_t n, const double* in, const double* in2, double* out,
+                           hipStream_t s);
+
+}  // namespace sdem

@@ -1,0 +1,235 @@
+"""Thin Python binding of the sdem C ABI (``include/sdem.h``).
+
+Argument marshalling only: every step of the DEM hot path runs in the HIP
+kernels of ``libsdem.so``.  PyTorch provides device memory (state upload and
+the workspace) and the HIP stream.  There is no CPU fallback: if the library
+is missing or no GPU is present the constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdem.so")
+
+SDEM_OK, SDEM_EINVAL, SDEM_ECAPACITY, SDEM_ENONFINITE, SDEM_EHIP, SDEM_ESTATE = 0, -1, -2, -3, -4, -5
+SDEM_FP64, SDEM_MIXED = 0, 1
+_NAMES = {SDEM_EINVAL: "EINVAL", SDEM_ECAPACITY: "ECAPACITY", SDEM_ENONFINITE: "ENONFINITE",
+          SDEM_EHIP: "EHIP", SDEM_ESTATE: "ESTATE"}
+
+EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_batch", "sdem_add_mesh",
+           "sdem_set_history", "sdem_step", "sdem_read_state", "sdem_read_contacts", "sdem_stats",
+           "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding")
+
+
+class SdemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sdem {_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("rho", C.c_double), ("E", C.c_double), ("nu", C.c_double),
+                ("e_n", C.c_double), ("mu_s", C.c_double), ("mu_r", C.c_double),
+                ("mu_t", C.c_double), ("eta", C.c_double), ("g", C.c_double * 3),
+                ("dt", C.c_double), ("mesh_omega", C.c_double * 3),
+                ("mesh_center", C.c_double * 3)]
+
+
+class Config(C.Structure):
+    _fields_ = [("n_max", C.c_int64), ("contacts_max", C.c_int64), ("cells_max", C.c_int64),
+                ("tri_max", C.c_int64), ("nsims_max", C.c_int32), ("precision", C.c_int32),
+                ("block", C.c_int32), ("reserved", C.c_int32), ("cell_factor", C.c_double)]
+
+
+_lib = None
+_D = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+_I64 = C.POINTER(C.c_int64)
+_VP = C.c_void_p
+
+
+def lib():
+    """Loads libsdem.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.sdem_workspace_bytes.restype = C.c_size_t
+        L.sdem_workspace_bytes.argtypes = [C.POINTER(Config)]
+        L.sdem_init.argtypes = [C.POINTER(_VP), C.POINTER(Config), C.POINTER(Params), C.c_int64,
+                                _VP, _VP, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
+        L.sdem_init_batch.argtypes = [C.POINTER(_VP), C.POINTER(Config), C.c_int32,
+                                      C.POINTER(Params), _I64, _VP, _VP, _VP, _VP, _VP, _VP,
+                                      C.c_size_t, _VP]
+        L.sdem_add_mesh.argtypes = [_VP, C.c_int32, C.c_int64, _D, _D]
+        L.sdem_set_history.argtypes = [_VP, C.c_int64, _I32, _I32, _D, _D, _D]
+        L.sdem_step.argtypes = [_VP, C.c_int64]
+        L.sdem_read_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP]
+        L.sdem_read_contacts.argtypes = [_VP, C.c_int64, _I64, _VP, _VP, _VP, _VP, _VP]
+        L.sdem_stats.argtypes = [_VP, _I64, _I64, _I64]
+        L.sdem_destroy.argtypes = [_VP]
+        L.sdem_last_error.restype = C.c_char_p
+        L.sdem_last_error.argtypes = []
+        L.sdem_selftest_rounding.argtypes = [C.c_int64, _VP, _VP, _VP, _VP]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != SDEM_OK:
+        raise SdemError(rc, lib().sdem_last_error().decode())
+
+
+def make_params(d: dict) -> Params:
+    g = d.get("g", (0.0, 0.0, -9.81))
+    om = d.get("mesh_omega", (0.0, 0.0, 0.0))
+    ce = d.get("mesh_center", (0.0, 0.0, 0.0))
+    mu_s = d.get("mu_s", 0.3)
+    return Params(d.get("rho", 1e3), d.get("E", 1e6), d.get("nu", 0.3), d.get("e_n", 0.5), mu_s,
+                  d.get("mu_r", 0.3), d.get("mu_t", 2.0 * mu_s / 3.0), d.get("eta", 0.0),
+                  (C.c_double * 3)(*g), d["dt"], (C.c_double * 3)(*om), (C.c_double * 3)(*ce))
+
+
+def selftest_rounding(a, b, device="cuda:0"):
+    """Device sqrt(a) and a/b (float64 arrays) through the C ABI."""
+    import torch
+    ta = torch.as_tensor(np.ascontiguousarray(a, np.float64), device=device)
+    tb = torch.as_tensor(np.ascontiguousarray(b, np.float64), device=device)
+    out = torch.empty(2 * len(a), dtype=torch.float64, device=device)
+    stream = torch.cuda.current_stream(device)
+    _check(lib().sdem_selftest_rounding(len(a), ta.data_ptr(), tb.data_ptr(), out.data_ptr(),
+                                        stream.cuda_stream))
+    o = out.cpu().numpy()
+    return o[: len(a)], o[len(a):]
+
+
+def _grid_cells(x, h):
+    if len(x) == 0 or not np.all(np.isfinite(x)):
+        return max(1, len(x))
+    ext = x.max(0) - x.min(0)
+    return int(np.prod(np.floor(ext / h) + 1))
+
+
+class Solver:
+    """One context of the HIP solver holding one or several simulations.
+
+    ``sims`` is one workload dict or a list of them (see ``workloads``).  The
+    state lives on ``device`` for the lifetime of the object.
+    """
+
+    def __init__(self, sims, precision="fp64", device="cuda:0", contacts_max=None,
+                 cells_max=None, cell_factor=1.0, block=0, cell_slack=8.0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("sdem needs a GPU: torch.cuda.is_available() is False")
+        L = lib()
+        if isinstance(sims, dict):
+            sims = [sims]
+        self.sims = sims
+        self.device = torch.device(device)
+        self.nsims = len(sims)
+        counts = [len(s["R"]) for s in sims]
+        self.offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        n = int(self.offsets[-1])
+        self.n = n
+        ntri = sum(len(s["tri"]) for s in sims)
+        x = np.concatenate([s["x"] for s in sims]) if n else np.zeros((0, 3))
+        if cells_max is None:
+            est = 0
+            for s in sims:
+                h = cell_factor * 2.0 * float(np.max(s["R"])) if len(s["R"]) else 1.0
+                est += _grid_cells(s["x"], h)
+            cells_max = int(max(1024, cell_slack * est, 2 * n))
+        if contacts_max is None:
+            contacts_max = int(max(4096, 8 * n))
+        self.cfg = Config(max(n, 1), contacts_max, cells_max, max(ntri, 1), self.nsims,
+                          SDEM_MIXED if precision == "mixed" else SDEM_FP64, block, 0,
+                          float(cell_factor))
+        nbytes = L.sdem_workspace_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            _check(SDEM_EINVAL)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+
+        def soa(key, k):
+            a = np.concatenate([s[key] for s in sims]) if n else np.zeros((0, k))
+            return torch.as_tensor(np.ascontiguousarray(a.T), device=self.device)
+
+        tx, tv, tw, tq = soa("x", 3), soa("v", 3), soa("w", 3), soa("q", 4)
+        tR = torch.as_tensor(np.concatenate([s["R"] for s in sims]) if n else np.zeros(0),
+                             device=self.device)
+        params = (Params * self.nsims)(*[make_params(s["params"]) for s in sims])
+        torch.cuda.synchronize(self.device)
+        h = _VP()
+        _check(L.sdem_init_batch(C.byref(h), C.byref(self.cfg), self.nsims, params,
+                                 self.offsets.ctypes.data_as(_I64), tx.data_ptr(), tv.data_ptr(),
+                                 tw.data_ptr(), tq.data_ptr(), tR.data_ptr(),
+                                 self.workspace.data_ptr(), nbytes, self.stream.cuda_stream))
+        self._h = h
+        for k, s in enumerate(sims):
+            if len(s["tri"]):
+                tri = np.ascontiguousarray(s["tri"], np.float64).reshape(-1, 9)
+                rm = np.ascontiguousarray(s.get("rmesh", np.zeros(len(tri))), np.float64)
+                _check(L.sdem_add_mesh(h, k, len(tri), tri.ctypes.data_as(_D),
+                                       rm.ctypes.data_as(_D)))
+
+    # ---------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sdem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps=1):
+        _check(lib().sdem_step(self._h, int(nsteps)))
+
+    def set_history(self, ki, kj, us, ur, ut):
+        ki = np.ascontiguousarray(ki, np.int32)
+        kj = np.ascontiguousarray(kj, np.int32)
+        us = np.ascontiguousarray(us, np.float64).reshape(-1, 3)
+        ur = np.ascontiguousarray(ur, np.float64).reshape(-1, 3)
+        ut = np.ascontiguousarray(ut, np.float64)
+        _check(lib().sdem_set_history(self._h, len(ki), ki.ctypes.data_as(_I32),
+                                      kj.ctypes.data_as(_I32), us.ctypes.data_as(_D),
+                                      ur.ctypes.data_as(_D), ut.ctypes.data_as(_D)))
+
+    def state(self, forces=True):
+        """State by persistent id as numpy: x, v, w (n,3), q (n,4), F, T."""
+        n = self.n
+        out = {k: np.empty((3, n)) for k in ("x", "v", "w", "F", "T")}
+        out["q"] = np.empty((4, n))
+        ptr = lambda k: out[k].ctypes.data if n else None
+        _check(lib().sdem_read_state(self._h, ptr("x"), ptr("v"), ptr("w"), ptr("q"),
+                                     ptr("F") if forces else None, ptr("T") if forces else None))
+        return {k: np.ascontiguousarray(a.T) for k, a in out.items()}
+
+    def contacts(self):
+        """Contacts of the last step in key order, with their springs."""
+        nout = C.c_int64(0)
+        lib().sdem_read_contacts(self._h, 0, C.byref(nout), None, None, None, None, None)
+        m = nout.value
+        ki = np.zeros(max(m, 1), np.int32)
+        kj = np.zeros(max(m, 1), np.int32)
+        us = np.zeros((max(m, 1), 3))
+        ur = np.zeros((max(m, 1), 3))
+        ut = np.zeros(max(m, 1))
+        _check(lib().sdem_read_contacts(self._h, m, C.byref(nout), ki.ctypes.data,
+                                        kj.ctypes.data, us.ctypes.data, ur.ctypes.data,
+                                        ut.ctypes.data))
+        return {"ki": ki[:m], "kj": kj[:m], "us": us[:m], "ur": ur[:m], "ut": ut[:m]}
+
+    def stats(self):
+        s, pp, pw = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().sdem_stats(self._h, C.byref(s), C.byref(pp), C.byref(pw)))
+        return {"steps": s.value, "pp": pp.value, "pw": pw.value}

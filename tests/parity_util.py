@@ -1,0 +1,51 @@
+"""Shared comparison helpers for the GPU parity tests (not collected)."""
+import numpy as np
+
+import oracle
+
+
+def rel(a, b):
+    """Normwise-max relative difference max|a-b| / max|b|."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = np.abs(b).max() if b.size else 0.0
+    if den == 0.0:
+        return float(np.abs(a).max()) if a.size else 0.0
+    return float(np.abs(a - b).max() / den)
+
+
+def force_err(Fg, Fo, scale):
+    """Per-particle force error scaled by sum_c |contribution| + m|g|."""
+    d = np.linalg.norm(np.asarray(Fg) - np.asarray(Fo), axis=1)
+    s = np.maximum(np.asarray(scale), 1e-300)
+    return float((d / s).max()) if len(d) else 0.0
+
+
+def keys(c):
+    return np.stack([c["ki"], c["kj"]], 1) if len(c["ki"]) else np.zeros((0, 2), np.int32)
+
+
+def oracle_from(w):
+    return oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"],
+                      tri=w["tri"] if len(w["tri"]) else None,
+                      rmesh=w["rmesh"] if len(w["tri"]) else None)
+
+
+def oracle_resync(w, st, c, t):
+    """Oracle started from a GPU state and GPU springs at time t."""
+    o = oracle.Sim(w["params"], st["x"], v=st["v"], w=st["w"], q=st["q"], R=w["R"],
+                   tri=w["tri"] if len(w["tri"]) else None,
+                   rmesh=w["rmesh"] if len(w["tri"]) else None)
+    o.set_time(t)
+    if len(c["ki"]):
+        o.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])
+    return o
+
+
+def spring_err(cg, co):
+    """Springs matched by key (keys must already be equal)."""
+    out = {}
+    for k in ("us", "ur"):
+        out[k] = rel(cg[k], co[k])
+    out["ut"] = rel(cg["ut"], co["ut"])
+    return out

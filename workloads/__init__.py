@@ -175,7 +175,7 @@ def _finish(name, params, x, R, rng, tri, steps, v=None, w=None, q=None, R_max=N
             "q": np.ascontiguousarray(q, dtype=np.float64),
             "R": np.ascontiguousarray(R, dtype=np.float64), "tri": tri,
             "rmesh": np.zeros(len(tri)), "steps": int(steps),
-            "R_max": float(R.max() if R_max is None else R_max)}
+            "R_max": float((R.max() if len(R) else 0.0) if R_max is None else R_max)}
 
 
 # ---------------------------------------------------------------------------
