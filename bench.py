@@ -1,0 +1,131 @@
+#!/usr/bin/env python3
+"""Throughput of the DEM hot path on one MI355X.
+
+Workload (default): 200,000 polydisperse spheres (R = 1 mm exp(0.2 Z)),
+granular column on a 600 x 600 mm two-triangle floor, full friction,
+dt = 5e-7 s, plain FP64 (the configuration the headline metric is quoted on).
+A step is one full time step of the hot path: bounding box and grid, cell
+sort and state reorder, narrow phase, contact forces with spring carry-over,
+integration.  The state is resident in HBM before timing starts.
+
+Prints one JSON line: particle-steps/s (value) and contacts/s, the roofline
+of the contact-force kernel (algorithmic bytes 128 N + 120 C per launch over
+its mean duration, timed with HIP events on the solver's stream), and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s & contacts/s: FP32/batched vs plain FP64 at stated tolerance"
+HBM_PEAK_GBS = 8000.0
+
+
+def force_bytes(n, c):
+    """Algorithmic HBM bytes of one contact-force launch: per particle x, v, w,
+    R read (80 B) and F, T written (48 B); per contact the pair (8 B) and the
+    seven spring doubles read and written (112 B)."""
+    return 128.0 * n + 120.0 * c
+
+
+def cpu_baseline(w, budget_s=12.0, max_steps=40):
+    import oracle
+    o = oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"],
+                   tri=w["tri"], rmesh=w["rmesh"])
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    k = int(max(1, min(max_steps - 1, budget_s / max(one, 1e-9) - 1)))
+    t1 = time.perf_counter()
+    o.step(k)
+    dt = time.perf_counter() - t1
+    steps = k + 1
+    total = one + dt
+    n = len(w["R"])
+    return {"value": n * steps / total, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} steps of the same workload (N={n}), serial FP64 oracle, "
+                      f"{total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2507_12610_amd import Solver
+
+    w = W.cfg2()
+    n = len(w["R"])
+    print(f"[bench] workload {w['name']}: N={n}, {len(w['tri'])} triangles", file=sys.stderr,
+          flush=True)
+    s = Solver(w, precision=args.precision, device="cuda:0")
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    st0 = s.stats()
+    t0 = time.perf_counter()
+    s.step(args.steps)  # returns after the stream has drained
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.stats()
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    contacts = (st1["pp"] - st0["pp"]) + (st1["pw"] - st0["pw"])
+    value = n * args.steps / wall
+    print(f"[bench] {args.steps} steps in {wall:.3f} s, {contacts / args.steps:.0f} contacts/step",
+          file=sys.stderr, flush=True)
+
+    # per-phase times with HIP events (no graph) on the solver's stream
+    st2 = s.stats()
+    phases = s.step_profiled(args.profile_steps)
+    st3 = s.stats()
+    c_prof = ((st3["pp"] - st2["pp"]) + (st3["pw"] - st2["pw"])) / args.profile_steps
+    fms = phases["force"]
+    achieved = force_bytes(n, c_prof) / (fms * 1e-3) / 1e9
+    dominant = max(phases, key=phases.get)
+    roofline = {"kernel": "k_force (contact forces, torques, spring carry-over)", "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "mean_ms": round(fms, 5), "algorithmic_bytes": force_bytes(n, c_prof),
+                "contacts_per_launch": round(c_prof, 1),
+                "phase_ms": {k: round(v, 5) for k, v in phases.items()},
+                "dominant_phase": dominant}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": w["name"], "particles": n, "triangles": len(w["tri"]),
+                      "dt": w["params"]["dt"], "precision": args.precision,
+                      "radii": "lognormal, median 1 mm, sigma 0.2",
+                      "friction": [w["params"]["mu_s"], w["params"]["mu_r"], w["params"]["mu_t"]]},
+           "contacts_per_s": round(contacts / wall, 1),
+           "contacts_per_step": round(contacts / args.steps, 1),
+           "roofline": roofline}
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

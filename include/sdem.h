@@ -131,6 +131,15 @@ int sdem_set_history(sdem_ctx* ctx, int64_t nc, const int32_t* ki, const int32_t
  * and the context accepts no further steps. */
 int sdem_step(sdem_ctx* ctx, int64_t nsteps);
 
+/* Measurement aid: like sdem_step, but launches each step's kernels directly
+ * (no graph) with HIP events between its phases on the context's stream,
+ * and returns the mean time per step of each phase in phase_ms[5]:
+ *   0 bounding box and grid, 1 cell sort and state reorder (and mesh
+ *   motion), 2 narrow phase (contact counts, scan, records), 3 contact forces
+ *   and torques with the spring carry-over, 4 integration.
+ * Results are identical to sdem_step's. */
+int sdem_step_profiled(sdem_ctx* ctx, int64_t nsteps, double* phase_ms);
+
 /* Current state by persistent id: x, v, w [3][n], q [4][n], and the net
  * contact force F and torque T [3][n] of the last step.  Any pointer may be
  * NULL.  Synchronises the stream. */

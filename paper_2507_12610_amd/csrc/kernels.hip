@@ -880,11 +880,14 @@ static hipError_t scan(int* in, int* out, const int* len_dev, int len_host, int*
 }
 
 hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
-                       const Contacts& cnew, int precision, hipStream_t s) {
+                       const Contacts& cnew, int precision, hipStream_t s, hipEvent_t* ev) {
+  // ev (optional): kPhases + 1 events recorded at the phase boundaries
   const int n = c.n;
   const int nbp = blocks_for(n, kThreads);
+  if (ev) (void)hipEventRecord(ev[0], s);
   if (c.nchunks > 0) k_bbox_part<<<c.nchunks, kThreads, 0, s>>>(c, A);
   k_grid<<<1, kGridThreads, 0, s>>>(c);
+  if (ev) (void)hipEventRecord(ev[1], s);
   k_keys<<<nbp, kThreads, 0, s>>>(c, A);
   // cell starts; clears the counts for the next step; total = n
   hipError_t e = scan(c.cell_cnt, c.cell_start, &c.ctr->ncells, 0, c.scan_tmp + kScanBlocks, 1,
@@ -893,16 +896,20 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
   k_scatter<<<nbp, kThreads, 0, s>>>(c);
   k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B);
   if (c.ntri > 0) k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
+  if (ev) (void)hipEventRecord(ev[2], s);
   k_detect<false><<<nbp, kThreads, 0, s>>>(c, B, cnew);
   e = scan(cnew.cnt, cnew.off, nullptr, n, &c.ctr->ncontacts, 0, c.ctr, c.cap_contacts,
            c.scan_tmp, s);
   if (e) return e;
   k_detect<true><<<nbp, kThreads, 0, s>>>(c, B, cnew);
+  if (ev) (void)hipEventRecord(ev[3], s);
   if (precision == SDEM_MIXED)
     k_force<float><<<kForceBlocks, kThreads, 0, s>>>(c, B, cnew, cold);
   else
     k_force<double><<<kForceBlocks, kThreads, 0, s>>>(c, B, cnew, cold);
+  if (ev) (void)hipEventRecord(ev[4], s);
   k_integrate<<<nbp, kThreads, 0, s>>>(c, B);
+  if (ev) (void)hipEventRecord(ev[5], s);
   return hipGetLastError();
 }
 

@@ -562,6 +562,49 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
   return SDEM_OK;
 }
 
+int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (X->failed) return fail(SDEM_ESTATE, "context failed in an earlier step; read it and re-init");
+  if (nsteps < 0 || !phase_ms) return fail(SDEM_EINVAL, "bad arguments");
+  for (int k = 0; k < kPhases; ++k) phase_ms[k] = 0.0;
+  if (nsteps == 0) return SDEM_OK;
+  X->stepped = true;
+  hipEvent_t ev[kPhases + 1];
+  for (int k = 0; k <= kPhases; ++k) HIP_TRY(hipEventCreate(&ev[k]));
+  Counters before;
+  HIP_TRY(hipMemcpyAsync(&before, X->c.ctr, sizeof before, hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  const int start = X->cur;
+  hipError_t err = hipSuccess;
+  for (int64_t i = 0; i < nsteps && !err; ++i) {
+    const int a = X->cur;
+    err = launch_step(X->c, X->st[a], X->st[a ^ 1], X->ct[a], X->ct[a ^ 1], X->cfg.precision,
+                      X->stream, ev);
+    X->cur ^= 1;
+    if (!err) err = hipEventSynchronize(ev[kPhases]);
+    for (int k = 0; k < kPhases && !err; ++k) {
+      float ms = 0.f;
+      err = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      phase_ms[k] += ms;
+    }
+  }
+  for (int k = 0; k <= kPhases; ++k) (void)hipEventDestroy(ev[k]);
+  if (err) return fail(SDEM_EHIP, "profiled step failed: %s", hipGetErrorString(err));
+  for (int k = 0; k < kPhases; ++k) phase_ms[k] /= (double)nsteps;
+  Counters after;
+  HIP_TRY(hipMemcpyAsync(&after, X->c.ctr, sizeof after, hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  if (after.flags) {
+    const int64_t done = (int64_t)(after.steps - before.steps) - 1;
+    X->cur = (int)((start + done) & 1);
+    X->failed = true;
+    return fail(after.flags & kFlagNonFinite ? SDEM_ENONFINITE : SDEM_ECAPACITY,
+                "profiled step %lld failed (flags %d)", (long long)(before.steps + done),
+                after.flags);
+  }
+  return SDEM_OK;
+}
+
 int sdem_read_state(sdem_ctx* X, double* x, double* v, double* w, double* q, double* F,
                     double* T) {
   if (!X) return fail(SDEM_EINVAL, "ctx is NULL");

@@ -191,8 +191,12 @@ __device__ __forceinline__ void closest_on_triangle(const double p[3], const dou
 }
 
 // Host launchers (kernels live in the .hip files).
+// Phases of a step as timed by sdem_step_profiled: grid, sort+reorder (+mesh),
+// narrow phase, contact forces, integration.
+constexpr int kPhases = 5;
 hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
-                       const Contacts& cnew, int precision, hipStream_t s);
+                       const Contacts& cnew, int precision, hipStream_t s,
+                       hipEvent_t* ev = nullptr);
 hipError_t launch_scatter_state(const Ctx& c, const State& S, double* x, double* v, double* w,
                                 double* q, double* F, double* T, hipStream_t s);
 hipError_t launch_mesh_planes(const Ctx& c, hipStream_t s);

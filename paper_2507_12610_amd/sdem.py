@@ -23,7 +23,8 @@ _NAMES = {SDEM_EINVAL: "EINVAL", SDEM_ECAPACITY: "ECAPACITY", SDEM_ENONFINITE: "
 
 EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_batch", "sdem_add_mesh",
            "sdem_set_history", "sdem_step", "sdem_read_state", "sdem_read_contacts", "sdem_stats",
-           "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding")
+           "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding", "sdem_step_profiled")
+PHASES = ("grid", "sort", "detect", "force", "integrate")
 
 
 class SdemError(RuntimeError):
@@ -70,6 +71,7 @@ def lib():
         L.sdem_add_mesh.argtypes = [_VP, C.c_int32, C.c_int64, _D, _D]
         L.sdem_set_history.argtypes = [_VP, C.c_int64, _I32, _I32, _D, _D, _D]
         L.sdem_step.argtypes = [_VP, C.c_int64]
+        L.sdem_step_profiled.argtypes = [_VP, C.c_int64, _D]
         L.sdem_read_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP]
         L.sdem_read_contacts.argtypes = [_VP, C.c_int64, _I64, _VP, _VP, _VP, _VP, _VP]
         L.sdem_stats.argtypes = [_VP, _I64, _I64, _I64]
@@ -193,6 +195,13 @@ class Solver:
 
     def step(self, nsteps=1):
         _check(lib().sdem_step(self._h, int(nsteps)))
+
+    def step_profiled(self, nsteps=1):
+        """Steps without a graph, timing each phase with HIP events; returns
+        the mean milliseconds per step of each phase."""
+        ms = (C.c_double * len(PHASES))()
+        _check(lib().sdem_step_profiled(self._h, int(nsteps), ms))
+        return dict(zip(PHASES, list(ms)))
 
     def set_history(self, ki, kj, us, ur, ut):
         ki = np.ascontiguousarray(ki, np.int32)

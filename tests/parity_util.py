@@ -14,6 +14,18 @@ def rel(a, b):
     return float(np.abs(a - b).max() / den)
 
 
+def rel_w(wg, wo, R, vo):
+    """Angular velocity error as a surface speed: max|dw| R_max over
+    max(max|v|, max|w| R_max), so rounding-level spins of particles that
+    should not rotate are not compared against themselves."""
+    rmax = float(np.max(R)) if len(R) else 1.0
+    den = max(float(np.abs(vo).max()) if np.size(vo) else 0.0,
+              float(np.abs(wo).max()) * rmax if np.size(wo) else 0.0)
+    if den == 0.0:
+        return float(np.abs(wg).max()) * rmax if np.size(wg) else 0.0
+    return float(np.abs(np.asarray(wg) - np.asarray(wo)).max() * rmax / den)
+
+
 def force_err(Fg, Fo, scale):
     """Per-particle force error scaled by sum_c |contribution| + m|g|."""
     d = np.linalg.norm(np.asarray(Fg) - np.asarray(Fo), axis=1)

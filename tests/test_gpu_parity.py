@@ -7,7 +7,8 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity_util import force_err, keys, oracle_from, oracle_resync, rel, spring_err
+from tests.parity_util import (force_err, keys, oracle_from, oracle_resync, rel, rel_w,
+                               spring_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +30,10 @@ def test_device_sqrt_and_division_correctly_rounded():
                         np.exp(rng.uniform(-700, 700, n // 2))])
     b = np.concatenate([rng.uniform(1e-6, 1e-2, n // 2), np.exp(rng.uniform(-300, 300, n // 2))])
     s, q = selftest_rounding(a, b)
+    with np.errstate(over="ignore", under="ignore"):
+        ref_q = a / b
     assert np.array_equal(s.view(np.int64), np.sqrt(a).view(np.int64))
-    assert np.array_equal(q.view(np.int64), (a / b).view(np.int64))
+    assert np.array_equal(q.view(np.int64), ref_q.view(np.int64))
 
 
 def cluster_case(n=400, seed=1, mesh=True, **pk):
@@ -160,8 +163,9 @@ def test_batch_of_uneven_simulations():
         o.step(5)
         so = o.state()
         sl = slice(off[k], off[k + 1])
-        for key in ("v", "w", "q"):
+        for key in ("v", "q"):
             assert rel(st[key][sl], so[key]) < TOL64, (k, key)
+        assert rel_w(st["w"][sl], so["w"], w["R"], so["v"]) < TOL64, k
         m = (c["ki"] >= off[k]) & (c["ki"] < off[k + 1])
         kg = np.stack([c["ki"][m] - off[k], np.where(c["kj"][m] > 0, c["kj"][m] - off[k],
                                                        c["kj"][m])], 1)
