@@ -1,11 +1,15 @@
 // HIP kernels of one DEM time step on gfx950 (MI355X).
 //
-// Step = bbox -> grid -> cell keys + arrival ranks -> scan of cell counts ->
-// scatter -> stable reorder of the state into cell order -> contact counts ->
-// scan -> contact records -> contact forces (+ spring carry-over) ->
-// integration.  All kernels read the context's flag word first and do
-// nothing once a capacity or finiteness error has been raised, so a failed
-// step leaves the previous step's buffers untouched.
+// Step = bounding box -> grid -> cell keys + arrival ranks -> scan of the cell
+// counts -> scatter -> stable reorder of the state into cell order -> narrow
+// phase (one pass, wave-compacted contact records, partner lists) -> contact
+// forces with spring carry-over (one lane per contact, no atomics) ->
+// integration, which first gathers each particle's contact sums in a fixed
+// order (so results do not depend on scheduling).
+//
+// Every kernel reads the context's flag word first and does nothing once a
+// capacity or finiteness error has been raised, so a failed step leaves the
+// previous step's buffers untouched.
 #include <math.h>
 
 #include "sdem_internal.h"
@@ -22,7 +26,15 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
   return v;
 }
 
-__device__ __forceinline__ void fatomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void raise_flag(Counters* ctr, int f) { atomicOr(&ctr->flags, f); }
 
 // ---------------------------------------------------------------------------
 // 1. bounding box of the centres, per simulation (Section 3.3)
@@ -31,16 +43,16 @@ __global__ __launch_bounds__(kThreads) void k_bbox_part(Ctx c, State A) {
   if (c.ctr->flags) return;
   const int ch = blockIdx.x;
   const int b0 = c.chunks[3 * ch + 1], b1 = c.chunks[3 * ch + 2];
-  const int n = c.n;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
   for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    const double4 p = A.xr[i];
+    const double xv[3] = {p.x, p.y, p.z};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double xv = A.x[k * n + i];
-      lo[k] = fmin(lo[k], xv);
-      hi[k] = fmax(hi[k], xv);
-      bad = bad || !isfinite(xv);
+      lo[k] = fmin(lo[k], xv[k]);
+      hi[k] = fmax(hi[k], xv[k]);
+      bad = bad || !isfinite(xv[k]);
     }
   }
   __shared__ double red[6][kThreads / 64];
@@ -80,12 +92,12 @@ __global__ __launch_bounds__(kThreads) void k_bbox_part(Ctx c, State A) {
 // One workgroup of kGridThreads: one wave per simulation reduces that
 // simulation's partials and lays out its grid (cells of edge h over the
 // bounding box); then the grids are placed one after the other in the global
-// cell table (exclusive scan of the cell counts over simulations).
+// cell table (exclusive scan of the cell counts over simulations).  Also
+// opens the step: counts it and clears the contact allocation counter.
 constexpr int kGridThreads = 1024;
 constexpr int kMaxSims = 4096;
 
-__device__ __forceinline__ int block_exclusive_scan_ll(long long* buf, int len, long long* total) {
-  // buf in LDS; kGridThreads threads; each thread scans a contiguous run
+__device__ __forceinline__ void block_exclusive_scan_ll(long long* buf, int len, long long* total) {
   __shared__ long long tsum[kGridThreads];
   const int per = (len + kGridThreads - 1) / kGridThreads;
   const int b0 = threadIdx.x * per, b1 = min(len, b0 + per);
@@ -107,7 +119,6 @@ __device__ __forceinline__ int block_exclusive_scan_ll(long long* buf, int len, 
   }
   if (threadIdx.x == kGridThreads - 1) *total = tsum[kGridThreads - 1];
   __syncthreads();
-  return 0;
 }
 
 __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
@@ -117,8 +128,8 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
   __shared__ int bad_total;
   if (threadIdx.x == 0) {
     bad_total = 0;
-    // steps started so far (a failed step is counted; the host subtracts it)
-    atomicAdd(&c.ctr->steps, 1ull);
+    atomicAdd(&c.ctr->steps, 1ull);  // steps started (the host discounts a failed one)
+    c.ctr->ncontacts = 0;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kGridThreads / 64;
@@ -179,10 +190,10 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
   if (threadIdx.x == 0) {
     const long long tot = total;
     c.ctr->ncells = (int)(tot < (long long)c.cap_cells ? tot : (long long)c.cap_cells);
-    if (bad_total) atomicOr(&c.ctr->flags, kFlagNonFinite);
+    if (bad_total) raise_flag(c.ctr, kFlagNonFinite);
     if (tot > (long long)c.cap_cells) {
       c.ctr->need_cells = (int)(tot < 0x7fffffffLL ? tot : 0x7fffffffLL);
-      atomicOr(&c.ctr->flags, kFlagCapCells);
+      raise_flag(c.ctr, kFlagCapCells);
     }
   }
 }
@@ -192,42 +203,77 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int cell_coord(double x, double lo, double inv_h, int dim) {
   const double f = floor((x - lo) * inv_h);
-  int ci = f < 0.0 ? 0 : (f >= (double)dim ? dim - 1 : (int)f);
-  return ci;
+  return f < 0.0 ? 0 : (f >= (double)dim ? dim - 1 : (int)f);
 }
 
 __global__ __launch_bounds__(kThreads) void k_keys(Ctx c, State A) {
   if (c.ctr->flags) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = c.n;
-  if (i >= n) return;
+  if (i >= c.n) return;
   const SimGrid g = c.sg[c.sim_of[i]];
-  const int cx = cell_coord(A.x[i], g.lo[0], g.inv_h, g.dim[0]);
-  const int cy = cell_coord(A.x[n + i], g.lo[1], g.inv_h, g.dim[1]);
-  const int cz = cell_coord(A.x[2 * n + i], g.lo[2], g.inv_h, g.dim[2]);
+  const double4 p = A.xr[i];
+  const int cx = cell_coord(p.x, g.lo[0], g.inv_h, g.dim[0]);
+  const int cy = cell_coord(p.y, g.lo[1], g.inv_h, g.dim[1]);
+  const int cz = cell_coord(p.z, g.lo[2], g.inv_h, g.dim[2]);
   const int key = g.cell_off + (cz * g.dim[1] + cy) * g.dim[0] + cx;
   c.key_tmp[i] = key;
   c.rank[i] = atomicAdd(&c.cell_cnt[key], 1);
 }
 
 // ---------------------------------------------------------------------------
-// device-wide exclusive scan of int32 (reduce / scan block sums / downsweep),
-// length read from the device; optionally clears the input.
+// exclusive scan of the cell counts into cell starts, clearing the counts for
+// the next step and writing the end entry.  Tables of up to kScanSmall cells:
+// one workgroup; larger: block sums, a one-workgroup scan of them, downsweep.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int scan_len(const int* len_dev, int len_host) {
-  return len_dev ? *len_dev : len_host;
+constexpr int kScanSmall = 1 << 18;
+constexpr int kScanOne = 1024;  // threads of the one-workgroup scan
+
+__global__ __launch_bounds__(kScanOne) void k_scan_small(Ctx c) {
+  if (c.ctr->flags) return;
+  constexpr int kPer = 8;  // consecutive cells per thread and tile
+  const int len = c.ctr->ncells;
+  __shared__ int ws[kScanOne / 64];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int base = 0; base < len; base += kScanOne * kPer) {
+    const int i0 = base + threadIdx.x * kPer;
+    int v[kPer];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      v[k] = i0 + k < len ? c.cell_cnt[i0 + k] : 0;
+      sum += v[k];
+    }
+    const int x = wave_incl_scan(sum, lane);
+    if (lane == 63) ws[wv] = x;
+    __syncthreads();
+    int run = carry + x - sum;
+    for (int w = 0; w < wv; ++w) run += ws[w];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (i0 + k < len) {
+        c.cell_start[i0 + k] = run;
+        c.cell_cnt[i0 + k] = 0;
+      }
+      run += v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == kScanOne - 1) carry = run;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c.cell_start[len] = carry;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* in, const int* len_dev,
-                                                              int len_host, int* bsum,
-                                                              const Counters* ctr) {
-  if (ctr->flags) return;
-  const int len = scan_len(len_dev, len_host);
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Ctx c) {
+  if (c.ctr->flags) return;
+  const int len = c.ctr->ncells;
   const int chunk = (len + kScanBlocks - 1) / kScanBlocks;
   const int b0 = blockIdx.x * chunk;
   const int b1 = min(len, b0 + chunk);
   int s = 0;
-  for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) s += in[i];
+  for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) s += c.cell_cnt[i];
   s = wave_sum_i32(s);
   __shared__ int ws[kScanThreads / 64];
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
@@ -235,79 +281,57 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* in, con
   if (threadIdx.x == 0) {
     int t = 0;
     for (int w = 0; w < kScanThreads / 64; ++w) t += ws[w];
-    bsum[blockIdx.x] = t;
+    c.scan_tmp[blockIdx.x] = t;
   }
 }
 
-// Single workgroup: exclusive scan of the block sums; writes the grand total
-// to *total and checks it against cap (contact capacity) if cap >= 0.
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(int* bsum, int* total, Counters* ctr,
-                                                           int cap) {
-  if (ctr->flags) return;
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(Ctx c) {
+  if (c.ctr->flags) return;
   constexpr int per = kScanBlocks / kScanThreads;
-  __shared__ long long ws[kScanThreads / 64];
-  long long v[per];
-  long long s = 0;
+  __shared__ int ws[kScanThreads / 64];
+  int v[per];
+  int sum = 0;
 #pragma unroll
   for (int k = 0; k < per; ++k) {
-    v[k] = bsum[threadIdx.x * per + k];
-    s += v[k];
+    v[k] = c.scan_tmp[threadIdx.x * per + k];
+    sum += v[k];
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  long long x = s;
-  for (int o = 1; o < 64; o <<= 1) {
-    const long long y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) ws[wv] = x;
+  const int incl = wave_incl_scan(sum, lane);
+  if (lane == 63) ws[wv] = incl;
   __syncthreads();
-  long long pre = 0;
-  for (int w = 0; w < wv; ++w) pre += ws[w];
-  long long run = pre + x - s;
+  int run = incl - sum;
+  for (int w = 0; w < wv; ++w) run += ws[w];
 #pragma unroll
   for (int k = 0; k < per; ++k) {
-    bsum[threadIdx.x * per + k] = (int)run;
+    c.scan_tmp[threadIdx.x * per + k] = run;
     run += v[k];
   }
-  if (threadIdx.x == kScanThreads - 1) {
-    const long long all = run;
-    const int tot = (int)(all < 0x7fffffffLL ? all : 0x7fffffffLL);
-    if (total) *total = tot;
-    if (cap >= 0 && all > (long long)cap) {
-      ctr->need_contacts = tot;
-      atomicOr(&ctr->flags, kFlagCapContacts);
-    }
-  }
+  if (threadIdx.x == kScanThreads - 1) c.scan_tmp[kScanBlocks] = run;  // grand total
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(int* in, int* out, const int* len_dev,
-                                                            int len_host, const int* bsum,
-                                                            int clear_input, const Counters* ctr) {
-  if (ctr->flags) return;
-  const int len = scan_len(len_dev, len_host);
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(Ctx c) {
+  if (c.ctr->flags) return;
+  const int len = c.ctr->ncells;
   const int chunk = (len + kScanBlocks - 1) / kScanBlocks;
   const int b0 = blockIdx.x * chunk;
   const int b1 = min(len, b0 + chunk);
   __shared__ int ws[kScanThreads / 64];
   __shared__ int carry;
-  if (threadIdx.x == 0) carry = bsum[blockIdx.x];
+  if (threadIdx.x == 0) carry = c.scan_tmp[blockIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int base = b0; base < b1; base += blockDim.x) {
     const int i = base + threadIdx.x;
-    const int v = i < b1 ? in[i] : 0;
-    int x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
+    const int v = i < b1 ? c.cell_cnt[i] : 0;
+    const int x = wave_incl_scan(v, lane);
     if (lane == 63) ws[wv] = x;
     __syncthreads();
     int pre = carry;
     for (int w = 0; w < wv; ++w) pre += ws[w];
     if (i < b1) {
-      out[i] = pre + x - v;
-      if (clear_input) in[i] = 0;
+      c.cell_start[i] = pre + x - v;
+      c.cell_cnt[i] = 0;
     }
     __syncthreads();
     if (threadIdx.x == blockDim.x - 1) {
@@ -317,13 +341,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(int* in, int* out, c
     }
     __syncthreads();
   }
-}
-
-// out[len] = in-sum: separate tiny kernel so that the scan stays simple.
-__global__ void k_scan_end(const int* len_dev, int len_host, int* out, const int* total,
-                           const Counters* ctr) {
-  if (ctr->flags) return;
-  if (threadIdx.x == 0 && blockIdx.x == 0) out[scan_len(len_dev, len_host)] = *total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c.cell_start[len] = c.scan_tmp[kScanBlocks];
 }
 
 // ---------------------------------------------------------------------------
@@ -343,26 +361,24 @@ __global__ __launch_bounds__(kThreads) void k_scatter(Ctx c) {
 __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B) {
   if (c.ctr->flags) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = c.n;
-  if (p >= n) return;
+  if (p >= c.n) return;
   const int so = c.perm[p];
   const int k = c.key_tmp[so];
   const int cs = c.cell_start[k], ce = c.cell_start[k + 1];
   int r = 0;
   for (int t = cs; t < ce; ++t) r += (c.perm[t] < so) ? 1 : 0;
   const int d = cs + r;
-#pragma unroll
-  for (int k3 = 0; k3 < 3; ++k3) {
-    B.x[k3 * n + d] = A.x[k3 * n + so];
-    B.v[k3 * n + d] = A.v[k3 * n + so];
-    B.w[k3 * n + d] = A.w[k3 * n + so];
-  }
-#pragma unroll
-  for (int k4 = 0; k4 < 4; ++k4) B.q[k4 * n + d] = A.q[k4 * n + so];
-  B.R[d] = A.R[so];
+  B.xr[d] = A.xr[so];
+  const double2* vin = reinterpret_cast<const double2*>(A.vw + 6 * (size_t)so);
+  double2* vout = reinterpret_cast<double2*>(B.vw + 6 * (size_t)d);
+  vout[0] = vin[0];
+  vout[1] = vin[1];
+  vout[2] = vin[2];
+  B.q[d] = A.q[so];
   B.pid[d] = A.pid[so];
   B.key[d] = k;
   B.src[d] = so;
+  c.pcnt[d] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +396,7 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all) {
     for (int k = 0; k < 9; ++k) t[k] = t0[k];
   } else if (P.rotating) {
     // rigid rotation by |om| t about the axis om/|om| through ctr, with t the
-    // time at the start of this step (steps already counted the current one)
+    // time at the start of this step (steps already counts the current one)
     const double wl = sqrt((P.om[0] * P.om[0] + P.om[1] * P.om[1]) + P.om[2] * P.om[2]);
     const double kx = P.om[0] / wl, ky = P.om[1] / wl, kz = P.om[2] / wl;
     const double ang = wl * ((double)(c.ctr->steps - 1ull) * P.dt);
@@ -418,26 +434,30 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all) {
 }
 
 // ---------------------------------------------------------------------------
-// 5. narrow phase (Section 3.3): triangles of the particle's simulation, then
-//    particle pairs in the upper half of the 27-cell neighbourhood.  With
-//    cells in (z, y, x) row order the three cells cx-1..cx+1 of a row are one
-//    contiguous slot range, so the half shell is five ranges: the rest of the
-//    own row (slots after this one), the row at (y+1, z), and the three rows
-//    at z+1.  Each pair is found once, by its lower slot (the owner).
+// 5. narrow phase (Section 3.3), one pass.  Each lane (one particle slot)
+//    tests the triangles of its simulation, then the particles in the upper
+//    half of its 27-cell neighbourhood.  With cells in (z, y, x) row order
+//    the three cells cx-1..cx+1 of a row are one contiguous slot range, so the
+//    half shell is five ranges: the rest of the own row (slots after this
+//    one), the row at (y+1, z) and the three rows at z+1.  Each pair is found
+//    once, by its lower slot (the owner).  Hits go to a per-lane list in LDS;
+//    a wave prefix scan gives every lane its place and one atomic per wave
+//    reserves the wave's records.  Pair records are also entered in the
+//    partner's list (one integer atomic per pair).
 // ---------------------------------------------------------------------------
-template <bool WRITE>
 __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn) {
   if (c.ctr->flags) return;
+  __shared__ int hits[kThreads / 64][kMaxOwn][64];
   const int n = c.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int npp = 0, npw = 0;
   if (s < n) {
     const int sim = c.sim_of[s];
     const SimGrid g = c.sg[sim];
     const int tri0 = c.sp[sim].tri0, ntri = c.sp[sim].ntri;
-    const double xs = S.x[s], ys = S.x[n + s], zs = S.x[2 * n + s], Rs = S.R[s];
-    const int my = S.pid[s];
-    int w = WRITE ? cn.off[s] : 0;
+    const double4 ps = S.xr[s];
+    const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
     // ---- triangles
     for (int m = tri0; m < tri0 + ntri; ++m) {
       const double* pl = c.tri_pl + 4 * m;
@@ -450,13 +470,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
       double dx, dy, dz, d;
       const double delta = pair_gap(xs, ys, zs, Rs, cp[0], cp[1], cp[2], c.rmesh[m], &dx, &dy, &dz, &d);
       if (delta >= 0.0) {
-        if (WRITE) {
-          cn.a[w] = s;
-          cn.b[w] = -1 - m;
-          cn.ki[w] = my;
-          cn.kj[w] = -(m - tri0);
-          ++w;
-        }
+        if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = -1 - m;
         ++npw;
       }
     }
@@ -466,63 +480,74 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
     const int cx = loc % nx, cyz = loc / nx, cy = cyz % ny, cz = cyz / ny;
     const int xlo = cx > 0 ? cx - 1 : 0, xhi = cx + 1 < nx ? cx + 1 : nx - 1;
     for (int r = 0; r < 5; ++r) {
-      int yy, zz;
-      if (r == 0) {
-        yy = cy;
-        zz = cz;
-      } else if (r == 1) {
-        yy = cy + 1;
-        zz = cz;
-      } else {
-        yy = cy + (r - 3);
-        zz = cz + 1;
-      }
+      const int yy = r == 0 ? cy : (r == 1 ? cy + 1 : cy + (r - 3));
+      const int zz = r <= 1 ? cz : cz + 1;
       if (yy < 0 || yy >= ny || zz >= nz) continue;
       const int row = g.cell_off + (zz * ny + yy) * nx;
       const int t0 = (r == 0) ? s + 1 : c.cell_start[row + xlo];
       const int t1 = c.cell_start[row + xhi + 1];
-      for (int t = t0; t < t1; ++t) {
-        const double xt = S.x[t], yt = S.x[n + t], zt = S.x[2 * n + t], Rt = S.R[t];
-        const double ex = xs - xt, ey = ys - yt, ez = zs - zt;
-        const double sr = Rs + Rt;
-        // cheap conservative reject before the exactly rounded test
-        if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) continue;
-        double dx, dy, dz, d;
-        const double delta = pair_gap(xs, ys, zs, Rs, xt, yt, zt, Rt, &dx, &dy, &dz, &d);
-        if (delta >= 0.0) {
-          if (WRITE) {
-            const int ot = S.pid[t];
-            cn.a[w] = s;
-            cn.b[w] = t;
-            cn.ki[w] = my < ot ? my : ot;
-            cn.kj[w] = my < ot ? ot : my;
-            ++w;
+      // four candidates per iteration so that four loads are in flight
+      for (int t = t0; t < t1; t += 4) {
+        double4 pt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u < t1 ? t + u : t];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (t + u >= t1) break;
+          const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
+          const double sr = Rs + pt[u].w;
+          // cheap conservative reject before the exactly rounded test
+          if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) continue;
+          double dx, dy, dz, d;
+          const double delta =
+              pair_gap(xs, ys, zs, Rs, pt[u].x, pt[u].y, pt[u].z, pt[u].w, &dx, &dy, &dz, &d);
+          if (delta >= 0.0) {
+            if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = t + u;
+            ++npp;
           }
-          ++npp;
         }
       }
     }
-    if (!WRITE) {
-      cn.cnt[s] = npp + npw;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        c.F[k * n + s] = 0.0;
-        c.T[k * n + s] = 0.0;
+  }
+  // wave compaction: prefix scan of the per-lane counts, one atomic per wave
+  const int total_hits = npw + npp;
+  const int mine = total_hits < kMaxOwn ? total_hits : kMaxOwn;
+  const int incl = wave_incl_scan(mine, lane);
+  const int wtot = __shfl(incl, 63, 64);
+  int base = 0;
+  if (lane == 63 && wtot > 0) base = atomicAdd(&c.ctr->ncontacts, wtot);
+  base = __shfl(base, 63, 64);
+  const int first = base + incl - mine;
+  if (total_hits > kMaxOwn) raise_flag(c.ctr, kFlagCapPerParticle);
+  const bool fits = (long long)base + wtot <= (long long)c.cap_contacts;
+  if (!fits && lane == 63) raise_flag(c.ctr, kFlagCapContacts);
+  if (s < n && fits) {
+    cn.off[s] = first;
+    cn.cnt[s] = mine;
+    for (int k = 0; k < mine; ++k) {
+      const int e = first + k;
+      const int t = hits[wv][k][lane];
+      cn.a[e] = s;
+      cn.b[e] = t;
+      if (t >= 0) {
+        const int r = atomicAdd(&c.pcnt[t], 1);
+        if (r < kMaxRev)
+          c.plist[(size_t)t * kMaxRev + r] = e;
+        else
+          raise_flag(c.ctr, kFlagCapPerParticle);
       }
     }
   }
-  if (!WRITE) {
-    // contact counts for the statistics: one 64-bit atomic per wave
-    const int a = wave_sum_i32(npp), b = wave_sum_i32(npw);
-    if ((threadIdx.x & 63) == 0 && (a | b)) {
-      atomicAdd(&c.ctr->pp_sum, (unsigned long long)a);
-      atomicAdd(&c.ctr->pw_sum, (unsigned long long)b);
-    }
+  // contact counts for the statistics: one 64-bit atomic per wave
+  const int a = wave_sum_i32(npp), b = wave_sum_i32(npw);
+  if (lane == 0 && (a | b)) {
+    atomicAdd(&c.ctr->pp_sum, (unsigned long long)a);
+    atomicAdd(&c.ctr->pw_sum, (unsigned long long)b);
   }
 }
 
 // ---------------------------------------------------------------------------
-// 6. contact forces and torques (Section 2.2, 2.3, 3.2)
+// 6. contact forces and torques (Section 2.2, 2.3, 3.2), one lane per contact
 // ---------------------------------------------------------------------------
 // Static/kinetic update of a vector friction mode m in {s, r}: rotate the old
 // spring into the tangent plane keeping its length, f = -k u - c v, then keep
@@ -577,84 +602,84 @@ __device__ __forceinline__ double sphere_mass(double rho, double R) {
   return (4.0 / 3.0) * kPi * rho * (R * R * R);
 }
 
-// Finds the springs of key (ki, kj) among the previous step's contacts of the
-// previous owner slot po; returns true and the springs if present.
-__device__ __forceinline__ bool find_old(const Contacts& co, int po, int ki, int kj, double us[3],
+// Springs of key (ki, kj) among the previous step's contacts of the previous
+// owner slot po; zero if the pair was not in contact.
+__device__ __forceinline__ void find_old(const Contacts& co, int po, int2 key, double us[3],
                                          double ur[3], double* ut, int cap) {
   const int b0 = co.off[po], b1 = b0 + co.cnt[po];
   for (int e = b0; e < b1; ++e) {
-    if (co.ki[e] == ki && co.kj[e] == kj) {
+    const int2 k = co.key[e];
+    if (k.x == key.x && k.y == key.y) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         us[a] = co.us[a * cap + e];
         ur[a] = co.ur[a * cap + e];
       }
       *ut = co.ut[e];
-      return true;
+      return;
     }
   }
-  return false;
 }
 
 template <typename RT>
 __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur, Contacts old) {
   if (c.ctr->flags) return;
-  const int n = c.n;
   const int cap = c.cap_contacts;
   const int C = c.ctr->ncontacts;
-  // contiguous chunk of contacts per workgroup, chunks grouped per XCD
-  const int nb = gridDim.x;
-  const int lb = xcd_remap(blockIdx.x, nb);
-  const int per = ((C + nb - 1) / nb + (int)blockDim.x - 1) / (int)blockDim.x * (int)blockDim.x;
-  const int e0 = lb * per;
-  const int e1 = min(C, e0 + per);
-  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+  // each XCD (workgroup b runs on XCD b % 8) takes one contiguous eighth of
+  // the contacts, so neighbouring records share that XCD's L2; its
+  // workgroups stride through the eighth
+  const int xcd = blockIdx.x & 7, nbx = gridDim.x >> 3;
+  const int e0 = (int)(((long long)C * xcd) >> 3), e1 = (int)(((long long)C * (xcd + 1)) >> 3);
+  for (int e = e0 + (blockIdx.x >> 3) * blockDim.x + threadIdx.x; e < e1;
+       e += nbx * blockDim.x) {
     const int a = cur.a[e], b = cur.b[e];
-    const int ki = cur.ki[e], kj = cur.kj[e];
     const int sim = c.sim_of[a];
     const SimParams& P = c.sp[sim];
     const bool wall = b < 0;
-    // canonical orientation: body I carries the lower id (a for walls)
+    const double4 pa = S.xr[a];
+    const int ida = S.pid[a];
+    // canonical orientation: body I carries the lower id (the particle for walls)
+    double4 pi = pa, pj;
     int I = a, J = b;
-    if (!wall && S.pid[a] > S.pid[b]) {
-      I = b;
-      J = a;
-    }
-    const double xi = S.x[I], yi = S.x[n + I], zi = S.x[2 * n + I], Ri = S.R[I];
-    double xj, yj, zj, Rj;
-    double vjx = 0.0, vjy = 0.0, vjz = 0.0, wjx = 0.0, wjy = 0.0, wjz = 0.0;
+    bool swap = false;
+    int2 key;
     if (!wall) {
-      xj = S.x[J];
-      yj = S.x[n + J];
-      zj = S.x[2 * n + J];
-      Rj = S.R[J];
-      vjx = S.v[J];
-      vjy = S.v[n + J];
-      vjz = S.v[2 * n + J];
-      wjx = S.w[J];
-      wjy = S.w[n + J];
-      wjz = S.w[2 * n + J];
+      pj = S.xr[b];
+      const int idb = S.pid[b];
+      swap = ida > idb;
+      if (swap) {
+        pi = pj;
+        pj = pa;
+        I = b;
+        J = a;
+      }
+      key = make_int2(swap ? idb : ida, swap ? ida : idb);
     } else {
       const int m = -1 - b;
-      const double p[3] = {xi, yi, zi};
+      const double p[3] = {pa.x, pa.y, pa.z};
       double cp[3];
       closest_on_triangle(p, c.tri + 9 * m, cp);
-      xj = cp[0];
-      yj = cp[1];
-      zj = cp[2];
-      Rj = c.rmesh[m];
+      pj = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
+      key = make_int2(ida, -(m - P.tri0));
     }
+    const double Ri = pi.w, Rj = pj.w;
     double dx, dy, dz, d;
-    const double delta = pair_gap(xi, yi, zi, Ri, xj, yj, zj, Rj, &dx, &dy, &dz, &d);
+    const double delta = pair_gap(pi.x, pi.y, pi.z, Ri, pj.x, pj.y, pj.z, Rj, &dx, &dy, &dz, &d);
     const double invd = 1.0 / d;
     const RT nrm[3] = {(RT)(dx * invd), (RT)(dy * invd), (RT)(dz * invd)};
     const double ri = Ri - 0.5 * delta;
     const double mi = sphere_mass(P.rho, Ri);
+    const double* vwi = S.vw + 6 * (size_t)I;
+    const double vix = vwi[0], viy = vwi[1], viz = vwi[2];
+    const double wix = vwi[3], wiy = vwi[4], wiz = vwi[5];
     double rj, Rs, ms, Es, Gs, reff;
     double vrel[3], om[3];
-    const double vix = S.v[I], viy = S.v[n + I], viz = S.v[2 * n + I];
-    const double wix = S.w[I], wiy = S.w[n + I], wiz = S.w[2 * n + I];
+    const double n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
     if (!wall) {
+      const double* vwj = S.vw + 6 * (size_t)J;
+      const double vjx = vwj[0], vjy = vwj[1], vjz = vwj[2];
+      const double wjx = vwj[3], wjy = vwj[4], wjz = vwj[5];
       rj = Rj - 0.5 * delta;
       const double mj = sphere_mass(P.rho, Rj);
       Rs = 1.0 / (1.0 / Ri + 1.0 / Rj);
@@ -664,7 +689,6 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
       reff = 1.0 / (1.0 / ri + 1.0 / rj);
       // v = v_i - v_j + n x (r_i w_i + r_j w_j)
       const double rx = ri * wix + rj * wjx, ry = ri * wiy + rj * wjy, rz = ri * wiz + rj * wjz;
-      const double n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
       vrel[0] = (vix - vjx) + (n1 * rz - n2 * ry);
       vrel[1] = (viy - vjy) + (n2 * rx - n0 * rz);
       vrel[2] = (viz - vjz) + (n0 * ry - n1 * rx);
@@ -678,20 +702,19 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
       Es = P.Es_pw;
       Gs = P.Gs_pw;
       reff = ri;
-      double vw[3] = {0.0, 0.0, 0.0};
-      if (P.rotating) {  // wall material velocity at the contact point c = p + R_m n
-        const double px = xj + Rj * (double)nrm[0] - P.ctr[0];
-        const double py = yj + Rj * (double)nrm[1] - P.ctr[1];
-        const double pz = zj + Rj * (double)nrm[2] - P.ctr[2];
-        vw[0] = P.om[1] * pz - P.om[2] * py;
-        vw[1] = P.om[2] * px - P.om[0] * pz;
-        vw[2] = P.om[0] * py - P.om[1] * px;
+      double vw0 = 0.0, vw1 = 0.0, vw2 = 0.0;
+      if (P.rotating) {  // wall material velocity at the contact point p + R_m n
+        const double px = pj.x + Rj * n0 - P.ctr[0];
+        const double py = pj.y + Rj * n1 - P.ctr[1];
+        const double pz = pj.z + Rj * n2 - P.ctr[2];
+        vw0 = P.om[1] * pz - P.om[2] * py;
+        vw1 = P.om[2] * px - P.om[0] * pz;
+        vw2 = P.om[0] * py - P.om[1] * px;
       }
-      const double n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
       const double rx = ri * wix, ry = ri * wiy, rz = ri * wiz;
-      vrel[0] = (vix - vw[0]) + (n1 * rz - n2 * ry);
-      vrel[1] = (viy - vw[1]) + (n2 * rx - n0 * rz);
-      vrel[2] = (viz - vw[2]) + (n0 * ry - n1 * rx);
+      vrel[0] = (vix - vw0) + (n1 * rz - n2 * ry);
+      vrel[1] = (viy - vw1) + (n2 * rx - n0 * rz);
+      vrel[2] = (viz - vw2) + (n0 * ry - n1 * rx);
       om[0] = wix - P.om[0];
       om[1] = wiy - P.om[1];
       om[2] = wiz - P.om[2];
@@ -719,21 +742,23 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
     // springs of the previous step (zero for a new contact)
     double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
     {
-      const int pa = S.src[a];
-      const int po = wall ? pa : min(pa, S.src[b]);
-      find_old(old, po, ki, kj, us, ur, &ut, cap);
+      const int sa = S.src[a];
+      const int po = wall ? sa : min(sa, S.src[b]);
+      find_old(old, po, key, us, ur, &ut, cap);
     }
     RT fs[3], fr[3], ft;
     friction_vec<RT>(nrm, ks, cs, (RT)P.mu_s * fnl, P.dt, vs, us, fs);
     friction_vec<RT>(nrm, kn, cn, (RT)P.mu_r * fnl, P.dt, vr, ur, fr);
     friction_scalar<RT>(ks, cs, (RT)P.mu_t * fnl, P.dt, vt, &ut, &ft);
+    cur.key[e] = key;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       cur.us[k * cap + e] = us[k];
       cur.ur[k * cap + e] = ur[k];
     }
     cur.ut[e] = ut;
-    // torques: tau_s = r_i f_s x n, tau_r = R* n x f_r, tau_t = f_t R* n
+    // torques: tau_s = r_i f_s x n, tau_r = R* n x f_r, tau_t = f_t R* n;
+    // body j: -f, r_j f_s x n - tau_r - tau_t (Eq. antisymm_*)
     const RT fsxn[3] = {fs[1] * nrm[2] - fs[2] * nrm[1], fs[2] * nrm[0] - fs[0] * nrm[2],
                         fs[0] * nrm[1] - fs[1] * nrm[0]};
     const RT rs = (RT)Rs;
@@ -741,25 +766,26 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
                       rs * (nrm[0] * fr[1] - nrm[1] * fr[0])};
     const RT ftr = ft * rs;
     const RT rif = (RT)ri, rjf = (RT)rj;
+    double* res = c.res;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double f = (double)fn[k] + (double)fs[k];
       const double ttr = (double)tr[k] + (double)(ftr * nrm[k]);
       const double ti = (double)(rif * fsxn[k]) + ttr;
-      fatomic_add(&c.F[k * n + I], f);
-      fatomic_add(&c.T[k * n + I], ti);
-      if (!wall) {
-        const double tj = (double)(rjf * fsxn[k]) - ttr;
-        fatomic_add(&c.F[k * n + J], -f);
-        fatomic_add(&c.T[k * n + J], tj);
-      }
+      const double tj = wall ? 0.0 : (double)(rjf * fsxn[k]) - ttr;
+      // per-contact results for the owner slot a and the partner b
+      res[(size_t)k * cap + e] = swap ? -f : f;
+      res[(size_t)(3 + k) * cap + e] = swap ? tj : ti;
+      res[(size_t)(6 + k) * cap + e] = swap ? ti : tj;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// 7. integration: semi-implicit Euler (Eq. v, x), SPIRAL (Eq. spiral) with
-//    the old angular velocity, then Eq. w; Stokes drag (Section 2.1)
+// 7. integration: gather the contact sums of each particle in a fixed order
+//    (owned contacts in record order, then partner contacts by ascending
+//    owner slot), then semi-implicit Euler (Eq. v, x), SPIRAL (Eq. spiral)
+//    with the old angular velocity, then Eq. w; Stokes drag (Section 2.1)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void qmul(const double a[4], const double b[4], double o[4]) {
   const double s = a[0] * b[0] - ((a[1] * b[1] + a[2] * b[2]) + a[3] * b[3]);
@@ -772,69 +798,144 @@ __device__ __forceinline__ void qmul(const double a[4], const double b[4], doubl
   o[3] = z;
 }
 
-__global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S) {
+__global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts cur) {
   if (c.ctr->flags) return;
   const int n = c.n;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const SimParams& P = c.sp[c.sim_of[i]];
-    const double R = S.R[i];
-    const double m = sphere_mass(P.rho, R);
-    const double I = 0.4 * m * R * R;
-    const double cd = 9.0 * P.eta / (2.0 * P.rho * R * R);
-    const double gd = (10.0 / 3.0) * cd;
-    const double dt = P.dt;
-    double v[3], x[3], w[3], al[3];
-    bool ok = true;
+  if (i >= n) return;
+  const size_t cap = (size_t)c.cap_contacts;
+  const double* res = c.res;
+  double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+  {
+    const int e0 = cur.off[i], e1 = e0 + cur.cnt[i];
+    for (int e = e0; e < e1; ++e) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      v[k] = S.v[k * n + i];
-      x[k] = S.x[k * n + i];
-      w[k] = S.w[k * n + i];
-      const double a = (c.F[k * n + i] / m + P.g[k]) - cd * v[k];
-      al[k] = c.T[k * n + i] / I - gd * w[k];
-      v[k] = v[k] + dt * a;
-      x[k] = x[k] + dt * v[k];
+      for (int k = 0; k < 3; ++k) {
+        F[k] += res[k * cap + e];
+        T[k] += res[(3 + k) * cap + e];
+      }
     }
-    double q[4] = {S.q[i], S.q[n + i], S.q[2 * n + i], S.q[3 * n + i]};
-    const double wl = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
-    if (wl > 0.0) {
-      const double phi = 0.5 * dt * wl;
-      double sp, cp;
-      sincos(phi, &sp, &cp);
-      sp /= wl;
-      const double r[4] = {cp, sp * w[0], sp * w[1], sp * w[2]};
-      double o[4];
-      qmul(q, r, o);
-      q[0] = o[0]; q[1] = o[1]; q[2] = o[2]; q[3] = o[3];
-    }
-    const double alen = sqrt((al[0] * al[0] + al[1] * al[1]) + al[2] * al[2]);
-    if (alen > 0.0) {
-      const double th = (0.5 * dt) * (0.5 * dt) * alen;
-      double st, ct;
-      sincos(th, &st, &ct);
-      st /= alen;
-      const double r[4] = {ct, st * al[0], st * al[1], st * al[2]};
-      double o[4];
-      qmul(q, r, o);
-      q[0] = o[0]; q[1] = o[1]; q[2] = o[2]; q[3] = o[3];
-    }
+    const int m = min(c.pcnt[i], kMaxRev);
+    const int* pl = c.plist + (size_t)i * kMaxRev;
+    if (m <= 8) {
+      // sort (owner slot, record) pairs with a fixed compare-exchange network
+      int ka[8], ke[8];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      w[k] = w[k] + dt * al[k];
-      ok = ok && isfinite(x[k]) && isfinite(v[k]) && isfinite(w[k]);
-      S.v[k * n + i] = v[k];
-      S.x[k * n + i] = x[k];
-      S.w[k * n + i] = w[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) S.q[k * n + i] = q[k];
-    if (!ok) atomicOr(&c.ctr->flags, kFlagNonFinite);
+      for (int j = 0; j < 8; ++j) {
+        ke[j] = j < m ? pl[j] : -1;
+        ka[j] = j < m ? cur.a[ke[j]] : 0x7fffffff;
+      }
+#define SDEM_CX(x, y)                                    \
+  if (ka[y] < ka[x]) {                                  \
+    const int ta = ka[x], te = ke[x];                   \
+    ka[x] = ka[y];                                      \
+    ke[x] = ke[y];                                      \
+    ka[y] = ta;                                         \
+    ke[y] = te;                                         \
   }
+      SDEM_CX(0, 1) SDEM_CX(2, 3) SDEM_CX(4, 5) SDEM_CX(6, 7)
+      SDEM_CX(0, 2) SDEM_CX(1, 3) SDEM_CX(4, 6) SDEM_CX(5, 7)
+      SDEM_CX(1, 2) SDEM_CX(5, 6) SDEM_CX(0, 4) SDEM_CX(3, 7)
+      SDEM_CX(1, 5) SDEM_CX(2, 6)
+      SDEM_CX(1, 4) SDEM_CX(3, 6)
+      SDEM_CX(2, 4) SDEM_CX(3, 5)
+      SDEM_CX(3, 4)
+#undef SDEM_CX
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < m) {
+          const int e = ke[j];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            F[k] -= res[k * cap + e];
+            T[k] += res[(6 + k) * cap + e];
+          }
+        }
+      }
+    } else {
+      int last = -1;
+      for (int it = 0; it < m; ++it) {  // ascending owner slot (owners are distinct)
+        int best = -1, ba = 0x7fffffff;
+        for (int j = 0; j < m; ++j) {
+          const int e = pl[j];
+          const int a = cur.a[e];
+          if (a > last && a < ba) {
+            ba = a;
+            best = e;
+          }
+        }
+        if (best < 0) break;
+        last = ba;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          F[k] -= res[k * cap + best];
+          T[k] += res[(6 + k) * cap + best];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    c.F[k * n + i] = F[k];
+    c.T[k * n + i] = T[k];
+  }
+  const SimParams& P = c.sp[c.sim_of[i]];
+  const double4 xr = S.xr[i];
+  const double R = xr.w;
+  const double m = sphere_mass(P.rho, R);
+  const double I = 0.4 * m * R * R;
+  const double cd = 9.0 * P.eta / (2.0 * P.rho * R * R);
+  const double gd = (10.0 / 3.0) * cd;
+  const double dt = P.dt;
+  double* vwp = S.vw + 6 * (size_t)i;
+  double v[3] = {vwp[0], vwp[1], vwp[2]}, w[3] = {vwp[3], vwp[4], vwp[5]};
+  double x[3] = {xr.x, xr.y, xr.z}, al[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double a = (F[k] / m + P.g[k]) - cd * v[k];
+    al[k] = T[k] / I - gd * w[k];
+    v[k] = v[k] + dt * a;
+    x[k] = x[k] + dt * v[k];
+  }
+  const double4 q4 = S.q[i];
+  double q[4] = {q4.x, q4.y, q4.z, q4.w};
+  const double wl = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+  if (wl > 0.0) {
+    const double phi = 0.5 * dt * wl;
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    sp /= wl;
+    const double r[4] = {cp, sp * w[0], sp * w[1], sp * w[2]};
+    double o[4];
+    qmul(q, r, o);
+    q[0] = o[0]; q[1] = o[1]; q[2] = o[2]; q[3] = o[3];
+  }
+  const double alen = sqrt((al[0] * al[0] + al[1] * al[1]) + al[2] * al[2]);
+  if (alen > 0.0) {
+    const double th = (0.5 * dt) * (0.5 * dt) * alen;
+    double st, ct;
+    sincos(th, &st, &ct);
+    st /= alen;
+    const double r[4] = {ct, st * al[0], st * al[1], st * al[2]};
+    double o[4];
+    qmul(q, r, o);
+    q[0] = o[0]; q[1] = o[1]; q[2] = o[2]; q[3] = o[3];
+  }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w[k] = w[k] + dt * al[k];
+    ok = ok && isfinite(x[k]) && isfinite(v[k]) && isfinite(w[k]);
+    vwp[k] = v[k];
+    vwp[3 + k] = w[k];
+  }
+  S.xr[i] = make_double4(x[0], x[1], x[2], R);
+  S.q[i] = make_double4(q[0], q[1], q[2], q[3]);
+  if (!ok) raise_flag(c.ctr, kFlagNonFinite);
 }
 
 // ---------------------------------------------------------------------------
-// reads: scatter a state buffer back to persistent-id order
+// state transfer between the caller's SoA arrays and the packed slots
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_scatter_state(Ctx c, State S, double* x, double* v,
                                                             double* w, double* q, double* F,
@@ -843,18 +944,50 @@ __global__ __launch_bounds__(kThreads) void k_scatter_state(Ctx c, State S, doub
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int id = S.pid[i];
+  const double4 p = S.xr[i];
+  const double* vw = S.vw + 6 * (size_t)i;
+  if (x) {
+    x[id] = p.x;
+    x[n + id] = p.y;
+    x[2 * n + id] = p.z;
+  }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (x) x[k * n + id] = S.x[k * n + i];
-    if (v) v[k * n + id] = S.v[k * n + i];
-    if (w) w[k * n + id] = S.w[k * n + i];
+    if (v) v[k * n + id] = vw[k];
+    if (w) w[k * n + id] = vw[3 + k];
     if (F) F[k * n + id] = c.F[k * n + i];
     if (T) T[k * n + id] = c.T[k * n + i];
   }
   if (q) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) q[k * n + id] = S.q[k * n + i];
+    const double4 qq = S.q[i];
+    q[id] = qq.x;
+    q[n + id] = qq.y;
+    q[2 * n + id] = qq.z;
+    q[3 * n + id] = qq.w;
   }
+}
+
+// slot i <- caller's particle i (identity order); v, w, q may be null
+__global__ __launch_bounds__(kThreads) void k_pack_state(Ctx c, State S, const double* x,
+                                                         const double* v, const double* w,
+                                                         const double* q, const double* R) {
+  const int n = c.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  S.xr[i] = make_double4(x[i], x[n + i], x[2 * n + i], R[i]);
+  double* vw = S.vw + 6 * (size_t)i;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    vw[k] = v ? v[k * n + i] : 0.0;
+    vw[3 + k] = w ? w[k * n + i] : 0.0;
+  }
+  S.q[i] = q ? make_double4(q[i], q[n + i], q[2 * n + i], q[3 * n + i])
+             : make_double4(1.0, 0.0, 0.0, 0.0);
+  S.pid[i] = i;
+  S.src[i] = i;
+  S.key[i] = 0;
+  c.F[i] = c.F[n + i] = c.F[2 * n + i] = 0.0;
+  c.T[i] = c.T[n + i] = c.T[2 * n + i] = 0.0;
 }
 
 __global__ void k_selftest(int64_t n, const double* in, const double* in2, double* out) {
@@ -869,46 +1002,34 @@ __global__ void k_selftest(int64_t n, const double* in, const double* in2, doubl
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int n, int t) { return n > 0 ? (n + t - 1) / t : 1; }
 
-static hipError_t scan(int* in, int* out, const int* len_dev, int len_host, int* total,
-                       int clear_input, Counters* ctr, int cap, int* tmp, hipStream_t s) {
-  k_scan_reduce<<<kScanBlocks, kScanThreads, 0, s>>>(in, len_dev, len_host, tmp, ctr);
-  k_scan_top<<<1, kScanThreads, 0, s>>>(tmp, total, ctr, cap);
-  k_scan_down<<<kScanBlocks, kScanThreads, 0, s>>>(in, out, len_dev, len_host, tmp, clear_input,
-                                                   ctr);
-  k_scan_end<<<1, 64, 0, s>>>(len_dev, len_host, out, total, ctr);
-  return hipGetLastError();
-}
-
 hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
                        const Contacts& cnew, int precision, hipStream_t s, hipEvent_t* ev) {
   // ev (optional): kPhases + 1 events recorded at the phase boundaries
-  const int n = c.n;
-  const int nbp = blocks_for(n, kThreads);
+  const int nbp = blocks_for(c.n, kThreads);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (c.nchunks > 0) k_bbox_part<<<c.nchunks, kThreads, 0, s>>>(c, A);
   k_grid<<<1, kGridThreads, 0, s>>>(c);
   if (ev) (void)hipEventRecord(ev[1], s);
   k_keys<<<nbp, kThreads, 0, s>>>(c, A);
-  // cell starts; clears the counts for the next step; total = n
-  hipError_t e = scan(c.cell_cnt, c.cell_start, &c.ctr->ncells, 0, c.scan_tmp + kScanBlocks, 1,
-                      c.ctr, -1, c.scan_tmp, s);
-  if (e) return e;
+  if (c.cap_cells <= kScanSmall) {
+    k_scan_small<<<1, kScanOne, 0, s>>>(c);
+  } else {
+    k_scan_reduce<<<kScanBlocks, kScanThreads, 0, s>>>(c);
+    k_scan_top<<<1, kScanThreads, 0, s>>>(c);
+    k_scan_down<<<kScanBlocks, kScanThreads, 0, s>>>(c);
+  }
   k_scatter<<<nbp, kThreads, 0, s>>>(c);
   k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B);
-  if (c.ntri > 0) k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
+  if (c.any_rotating) k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
   if (ev) (void)hipEventRecord(ev[2], s);
-  k_detect<false><<<nbp, kThreads, 0, s>>>(c, B, cnew);
-  e = scan(cnew.cnt, cnew.off, nullptr, n, &c.ctr->ncontacts, 0, c.ctr, c.cap_contacts,
-           c.scan_tmp, s);
-  if (e) return e;
-  k_detect<true><<<nbp, kThreads, 0, s>>>(c, B, cnew);
+  k_detect<<<nbp, kThreads, 0, s>>>(c, B, cnew);
   if (ev) (void)hipEventRecord(ev[3], s);
   if (precision == SDEM_MIXED)
-    k_force<float><<<kForceBlocks, kThreads, 0, s>>>(c, B, cnew, cold);
+    k_force<float><<<c.force_blocks, kThreads, 0, s>>>(c, B, cnew, cold);
   else
-    k_force<double><<<kForceBlocks, kThreads, 0, s>>>(c, B, cnew, cold);
+    k_force<double><<<c.force_blocks, kThreads, 0, s>>>(c, B, cnew, cold);
   if (ev) (void)hipEventRecord(ev[4], s);
-  k_integrate<<<nbp, kThreads, 0, s>>>(c, B);
+  k_integrate<<<nbp, kThreads, 0, s>>>(c, B, cnew);
   if (ev) (void)hipEventRecord(ev[5], s);
   return hipGetLastError();
 }
@@ -917,6 +1038,13 @@ hipError_t launch_scatter_state(const Ctx& c, const State& S, double* x, double*
                                 double* q, double* F, double* T, hipStream_t s) {
   if (c.n > 0)
     k_scatter_state<<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, S, x, v, w, q, F, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_state(const Ctx& c, const State& S, const double* x, const double* v,
+                             const double* w, const double* q, const double* R, hipStream_t s) {
+  if (c.n > 0)
+    k_pack_state<<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, S, x, v, w, q, R);
   return hipGetLastError();
 }
 

@@ -100,6 +100,9 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.rank = L.take<int32_t>(N);
   cc.perm = L.take<int32_t>(N);
   cc.scan_tmp = L.take<int32_t>(kScanBlocks + 1);
+  cc.pcnt = L.take<int32_t>(N);
+  cc.plist = L.take<int32_t>(N * kMaxRev);
+  cc.res = L.take<double>(9 * Cm);
   cc.F = L.take<double>(3 * N);
   cc.T = L.take<double>(3 * N);
   cc.tri_ref = L.take<double>(9 * M);
@@ -109,11 +112,9 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.tri_sim = L.take<int32_t>(M);
   for (int b = 0; b < 2; ++b) {
     State s{};
-    s.x = L.take<double>(3 * N);
-    s.v = L.take<double>(3 * N);
-    s.w = L.take<double>(3 * N);
-    s.q = L.take<double>(4 * N);
-    s.R = L.take<double>(N);
+    s.xr = L.take<double4>(N);
+    s.vw = L.take<double>(6 * N);
+    s.q = L.take<double4>(N);
     s.pid = L.take<int32_t>(N);
     s.key = L.take<int32_t>(N);
     s.src = L.take<int32_t>(N);
@@ -121,12 +122,11 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   }
   for (int b = 0; b < 2; ++b) {
     Contacts k{};
-    k.cnt = L.take<int32_t>(N + 1);
-    k.off = L.take<int32_t>(N + 1);
+    k.cnt = L.take<int32_t>(N);
+    k.off = L.take<int32_t>(N);
     k.a = L.take<int32_t>(Cm);
     k.b = L.take<int32_t>(Cm);
-    k.ki = L.take<int32_t>(Cm);
-    k.kj = L.take<int32_t>(Cm);
+    k.key = L.take<int2>(Cm);
     k.us = L.take<double>(3 * Cm);
     k.ur = L.take<double>(3 * Cm);
     k.ut = L.take<double>(Cm);
@@ -228,6 +228,9 @@ static int upload_params(sdem_ctx* x) {
     sp[s].ntri = (int32_t)x->mesh_r[s].size();
     tri0 += sp[s].ntri;
   }
+  x->c.any_rotating = 0;
+  for (int s = 0; s < x->nsims; ++s)
+    if (sp[s].rotating && sp[s].ntri > 0) x->c.any_rotating = 1;
   HIP_TRY(hipMemcpyAsync(x->c.sp, sp.data(), sizeof(SimParams) * x->nsims, hipMemcpyHostToDevice,
                          x->stream));
   HIP_TRY(hipStreamSynchronize(x->stream));
@@ -301,6 +304,15 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   c.ntri = 0;
   c.cap_contacts = (int32_t)cfg.contacts_max;
   c.cap_cells = (int32_t)cfg.cells_max;
+  {
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+    (void)hipGetLastError();
+    // a multiple of 8 so that every XCD gets the same number of workgroups
+    c.force_blocks = std::max(8, (ncu * kForceBlocksPerCU + 7) / 8 * 8);
+  }
 
   auto bail = [&](int code) {
     delete X;
@@ -320,38 +332,41 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   }
   chunk0[nsims] = (int32_t)(chunks.size() / 3);
   c.nchunks = chunk0[nsims];
-  std::vector<int32_t> iota((size_t)std::max<int64_t>(n, 1));
-  for (int64_t i = 0; i < n; ++i) iota[i] = (int32_t)i;
 
   auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, st) : hipSuccess;
   };
-  const size_t v3 = sizeof(double) * 3 * n;
-  State& A = X->st[0];
+  // caller arrays that are not device memory are staged through the scratch
+  const double* in[5] = {x, v, w, q, R};
+  const size_t words[5] = {3, 3, 3, 4, 1};
+  const double* dev_in[5];
   hipError_t e = hipSuccess;
+  size_t at = 0;
+  for (int k = 0; k < 5 && !e; ++k) {
+    dev_in[k] = nullptr;
+    if (in[k] && n) {
+      if (is_device_ptr(in[k])) {
+        dev_in[k] = in[k];
+      } else {
+        double* d = X->scratch + at * n;
+        e = cp(d, in[k], sizeof(double) * words[k] * n);
+        dev_in[k] = d;
+      }
+    }
+    at += words[k];
+  }
   if (!e) e = hipMemsetAsync(c.ctr, 0, sizeof(Counters), st);
   if (!e) e = hipMemsetAsync(c.cell_cnt, 0, sizeof(int32_t) * cfg.cells_max, st);
   for (int b = 0; b < 2 && !e; ++b) {
-    e = hipMemsetAsync(X->ct[b].cnt, 0, sizeof(int32_t) * (n + 1), st);
-    if (!e) e = hipMemsetAsync(X->ct[b].off, 0, sizeof(int32_t) * (n + 1), st);
+    e = hipMemsetAsync(X->ct[b].cnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
+    if (!e) e = hipMemsetAsync(X->ct[b].off, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
   }
-  if (!e) e = hipMemsetAsync(c.F, 0, v3 ? v3 : 8, st);
-  if (!e) e = hipMemsetAsync(c.T, 0, v3 ? v3 : 8, st);
-  if (!e) e = cp(A.x, x, v3);
-  if (!e) e = v ? cp(A.v, v, v3) : hipMemsetAsync(A.v, 0, v3 ? v3 : 8, st);
-  if (!e) e = w ? cp(A.w, w, v3) : hipMemsetAsync(A.w, 0, v3 ? v3 : 8, st);
-  if (!e && q) e = cp(A.q, q, 4 * sizeof(double) * n);
-  if (!e && !q && n) {
-    std::vector<double> qi((size_t)4 * n, 0.0);
-    for (int64_t i = 0; i < n; ++i) qi[i] = 1.0;
-    e = hipMemcpy(A.q, qi.data(), qi.size() * sizeof(double), hipMemcpyHostToDevice);
-  }
-  if (!e) e = cp(A.R, R, sizeof(double) * n);
-  if (!e) e = cp(A.pid, iota.data(), sizeof(int32_t) * n);
-  if (!e) e = cp(A.src, iota.data(), sizeof(int32_t) * n);
+  if (!e) e = hipMemsetAsync(c.pcnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
   if (!e) e = cp(c.sim_of, sim_of.data(), sizeof(int32_t) * n);
   if (!e) e = cp(c.chunks, chunks.data(), sizeof(int32_t) * chunks.size());
   if (!e) e = cp(c.chunk0, chunk0.data(), sizeof(int32_t) * chunk0.size());
+  if (!e) e = launch_pack_state(c, X->st[0], dev_in[0], dev_in[1], dev_in[2], dev_in[3],
+                                dev_in[4], st);
   if (!e) e = hipStreamSynchronize(st);
   if (e) {
     fail(SDEM_EHIP, "init copies failed: %s", hipGetErrorString(e));
@@ -447,17 +462,16 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
     }
   }
   // group by owner slot (counting sort)
-  std::vector<int32_t> cnt((size_t)n + 1, 0), off((size_t)n + 1, 0);
+  std::vector<int32_t> cnt((size_t)std::max<int64_t>(n, 1), 0), off((size_t)n + 1, 0);
   for (int64_t e = 0; e < nc; ++e) ++cnt[owner[e]];
   for (int64_t s = 0; s < n; ++s) off[s + 1] = off[s] + cnt[s];
   std::vector<int32_t> pos(off.begin(), off.end());
   const size_t cap = (size_t)X->cfg.contacts_max;
-  std::vector<int32_t> K1((size_t)nc), K2((size_t)nc);
+  std::vector<int2> K((size_t)std::max<int64_t>(nc, 1));
   std::vector<double> U((size_t)3 * nc), V((size_t)3 * nc), Wt((size_t)nc);
   for (int64_t e = 0; e < nc; ++e) {
     const int32_t d = pos[owner[e]]++;
-    K1[d] = ki[e];
-    K2[d] = kj[e];
+    K[d] = make_int2(ki[e], kj[e]);
     for (int k = 0; k < 3; ++k) {
       U[(size_t)k * nc + d] = us[3 * e + k];
       V[(size_t)k * nc + d] = ur[3 * e + k];
@@ -465,11 +479,12 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
     Wt[d] = ut[e];
   }
   Contacts& C = X->ct[X->cur];
-  HIP_TRY(hipMemcpy(C.cnt, cnt.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(C.off, off.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+  if (n) {
+    HIP_TRY(hipMemcpy(C.cnt, cnt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(C.off, off.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  }
   if (nc) {
-    HIP_TRY(hipMemcpy(C.ki, K1.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(C.kj, K2.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(C.key, K.data(), sizeof(int2) * nc, hipMemcpyHostToDevice));
     for (int k = 0; k < 3; ++k) {
       HIP_TRY(hipMemcpy(C.us + k * cap, U.data() + (size_t)k * nc, sizeof(double) * nc,
                         hipMemcpyHostToDevice));
@@ -479,6 +494,32 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
     HIP_TRY(hipMemcpy(C.ut, Wt.data(), sizeof(double) * nc, hipMemcpyHostToDevice));
   }
   return SDEM_OK;
+}
+
+// After a batch of steps: read the counters, locate a failed step, report.
+static int finish_steps(sdem_ctx* X, const Counters& before, int start) {
+  Counters after;
+  HIP_TRY(hipMemcpyAsync(&after, X->c.ctr, sizeof after, hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  if (!after.flags) return SDEM_OK;
+  const int64_t done = (int64_t)(after.steps - before.steps) - 1;  // the failed one counted
+  X->cur = (int)((start + done) & 1);
+  X->failed = true;
+  const long long at = (long long)(before.steps + done);
+  if (after.flags & kFlagCapCells)
+    return fail(SDEM_ECAPACITY,
+                "step %lld: the grid needs %d cells, cells_max is %lld (particles spread too "
+                "far; confine them with a mesh or raise cells_max)",
+                at, after.need_cells, (long long)X->cfg.cells_max);
+  if (after.flags & kFlagCapContacts)
+    return fail(SDEM_ECAPACITY, "step %lld: %d contacts exceed contacts_max = %lld", at,
+                after.ncontacts, (long long)X->cfg.contacts_max);
+  if (after.flags & kFlagCapPerParticle)
+    return fail(SDEM_ECAPACITY,
+                "step %lld: a particle has more than %d contacts of one kind (owned or "
+                "partnered)",
+                at, kMaxOwn);
+  return fail(SDEM_ENONFINITE, "step %lld: non-finite position, velocity or spin", at);
 }
 
 static hipError_t enqueue_steps(sdem_ctx* X, int k) {
@@ -539,27 +580,7 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
     HIP_TRY(enqueue_steps(X, 1));
     X->cur ^= 1;
   }
-  Counters after;
-  HIP_TRY(hipMemcpyAsync(&after, X->c.ctr, sizeof after, hipMemcpyDeviceToHost, X->stream));
-  HIP_TRY(hipStreamSynchronize(X->stream));
-  if (after.flags) {
-    const int64_t done = (int64_t)(after.steps - before.steps) - 1;  // the failed one counted
-    X->cur = (int)((start + done) & 1);
-    X->failed = true;
-    if (after.flags & kFlagCapCells)
-      return fail(SDEM_ECAPACITY,
-                  "step %lld: the grid needs %d cells, cells_max is %lld (particles spread too "
-                  "far; confine them with a mesh or raise cells_max)",
-                  (long long)(before.steps + done), after.need_cells,
-                  (long long)X->cfg.cells_max);
-    if (after.flags & kFlagCapContacts)
-      return fail(SDEM_ECAPACITY, "step %lld: %d contacts exceed contacts_max = %lld",
-                  (long long)(before.steps + done), after.need_contacts,
-                  (long long)X->cfg.contacts_max);
-    return fail(SDEM_ENONFINITE, "step %lld: non-finite position, velocity or spin",
-                (long long)(before.steps + done));
-  }
-  return SDEM_OK;
+  return finish_steps(X, before, start);
 }
 
 int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
@@ -591,18 +612,7 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
   for (int k = 0; k <= kPhases; ++k) (void)hipEventDestroy(ev[k]);
   if (err) return fail(SDEM_EHIP, "profiled step failed: %s", hipGetErrorString(err));
   for (int k = 0; k < kPhases; ++k) phase_ms[k] /= (double)nsteps;
-  Counters after;
-  HIP_TRY(hipMemcpyAsync(&after, X->c.ctr, sizeof after, hipMemcpyDeviceToHost, X->stream));
-  HIP_TRY(hipStreamSynchronize(X->stream));
-  if (after.flags) {
-    const int64_t done = (int64_t)(after.steps - before.steps) - 1;
-    X->cur = (int)((start + done) & 1);
-    X->failed = true;
-    return fail(after.flags & kFlagNonFinite ? SDEM_ENONFINITE : SDEM_ECAPACITY,
-                "profiled step %lld failed (flags %d)", (long long)(before.steps + done),
-                after.flags);
-  }
-  return SDEM_OK;
+  return finish_steps(X, before, start);
 }
 
 int sdem_read_state(sdem_ctx* X, double* x, double* v, double* w, double* q, double* F,
@@ -642,15 +652,24 @@ int sdem_read_contacts(sdem_ctx* X, int64_t cap, int64_t* n_out, int32_t* ki, in
   const Contacts& C = X->ct[X->cur];
   hipStream_t st = X->stream;
   HIP_TRY(hipStreamSynchronize(st));
+  // records of a completed step (or loaded history) fill [0, sum of counts)
   int32_t total = 0;
-  if (n) HIP_TRY(hipMemcpy(&total, C.off + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (n) {
+    std::vector<int32_t> cnt((size_t)n);
+    HIP_TRY(hipMemcpy(cnt.data(), C.cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    for (int32_t v : cnt) total += v;
+  }
   if (n_out) *n_out = total;
   if (!total) return SDEM_OK;
   const size_t ccap = (size_t)X->cfg.contacts_max;
+  std::vector<int2> KK(total);
   std::vector<int32_t> K1(total), K2(total);
   std::vector<double> S((size_t)7 * total);
-  HIP_TRY(hipMemcpy(K1.data(), C.ki, sizeof(int32_t) * total, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(K2.data(), C.kj, sizeof(int32_t) * total, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(KK.data(), C.key, sizeof(int2) * total, hipMemcpyDeviceToHost));
+  for (int32_t e = 0; e < total; ++e) {
+    K1[e] = KK[e].x;
+    K2[e] = KK[e].y;
+  }
   for (int k = 0; k < 3; ++k) {
     HIP_TRY(hipMemcpy(S.data() + (size_t)k * total, C.us + k * ccap, sizeof(double) * total,
                       hipMemcpyDeviceToHost));

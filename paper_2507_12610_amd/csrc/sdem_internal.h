@@ -8,16 +8,19 @@
 
 namespace sdem {
 
-constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scans
+constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scan
 constexpr int kScanThreads = 256;
 constexpr int kBboxChunk = 4096;    // particles per bounding-box partial
 constexpr int kThreads = 256;       // threads per workgroup of the particle kernels
-constexpr int kForceBlocks = 4096;  // fixed grid of the contact kernel (grid stride)
+constexpr int kForceBlocksPerCU = 4;  // grid of the contact kernel: 4 workgroups per CU
+constexpr int kMaxOwn = 32;         // contacts one particle may own in a step
+constexpr int kMaxRev = 32;         // contacts one particle may take part in as partner
 
 enum : int {
   kFlagCapContacts = 1,
   kFlagCapCells = 2,
   kFlagNonFinite = 4,
+  kFlagCapPerParticle = 8,
 };
 
 // Per-simulation constants, derived on the host at init.
@@ -47,23 +50,21 @@ struct SimGrid {
 // Device-side counters and flags of a context.
 struct Counters {
   int32_t flags;
-  int32_t ncontacts;     // contacts of the step in progress
+  int32_t ncontacts;     // contacts of the step in progress (allocation counter)
   int32_t ncells;        // cells of the step in progress (all sims)
-  int32_t need_contacts; // last required contact capacity (diagnostic)
-  int32_t need_cells;
+  int32_t need_cells;    // last required cell capacity (diagnostic)
+  uint32_t scan_ticket;  // last-block detection of the scan
   int32_t pad;
-  unsigned long long steps;
+  unsigned long long steps;  // steps started (a failed one included)
   unsigned long long pp_sum, pw_sum;
 };
 
-// One buffer of per-particle state, in cell-sorted order; vectors are SoA
-// with stride n.
+// One buffer of per-particle state in cell-sorted order, packed per particle
+// so that a gather of one particle is a few 16-byte loads.
 struct State {
-  double* x;     // [3][n]
-  double* v;     // [3][n]
-  double* w;     // [3][n]
-  double* q;     // [4][n]
-  double* R;     // [n]
+  double4* xr;   // [n] centre x, y, z and radius R
+  double* vw;    // [n][6] velocity then angular velocity
+  double4* q;    // [n] orientation quaternion, scalar first
   int32_t* pid;  // persistent id
   int32_t* key;  // cell key of this slot (written by the reorder)
   int32_t* src;  // slot of the same particle in the previous step's order
@@ -71,13 +72,12 @@ struct State {
 
 // One buffer of contacts, grouped by owner slot (owner = lower slot).
 struct Contacts {
-  int32_t* cnt;  // [n+1] contacts per owner slot
-  int32_t* off;  // [n+1] exclusive prefix of cnt
+  int32_t* cnt;  // [n] contacts per owner slot
+  int32_t* off;  // [n] first contact of each owner slot
   int32_t* a;    // owner slot
   int32_t* b;    // partner slot (>= 0) or -1 - global triangle index
-  int32_t* ki;   // key: lower persistent id (particle pairs) or the particle's id
-  int32_t* kj;   // key: higher persistent id, or -(local triangle index)
-  double* us;    // [3][cap] sliding spring, orientation of body ki
+  int2* key;     // (lower persistent id, higher id) or (id, -local triangle index)
+  double* us;    // [3][cap] sliding spring, orientation of body key.x
   double* ur;    // [3][cap] rolling spring
   double* ut;    // [cap] twisting spring
 };
@@ -85,6 +85,7 @@ struct Contacts {
 // Everything a step's kernels read or write.
 struct Ctx {
   int32_t n, nsims, ntri, cap_contacts, cap_cells, nchunks;
+  int32_t any_rotating, force_blocks;
   SimParams* sp;      // [nsims]
   SimGrid* sg;        // [nsims]
   int32_t* sim_of;    // [n] simulation of each slot (fixed)
@@ -97,8 +98,12 @@ struct Ctx {
   int32_t* rank;      // [n] arrival rank in the cell
   int32_t* perm;      // [n] new slot -> previous slot (unstable within a cell)
   int32_t* scan_tmp;  // [kScanBlocks+1]
-  double* F;          // [3][n] contact force of the last step
-  double* T;          // [3][n] contact torque of the last step
+  int32_t* pcnt;      // [n] contacts in which the slot is the partner
+  int32_t* plist;     // [n][kMaxRev] those contacts
+  double* res;        // [9][cap] per contact: force on the owner, torque on
+                      // the owner, torque on the partner
+  double* F;          // [3][n] contact force of the last step, by slot
+  double* T;          // [3][n] contact torque of the last step, by slot
   double* tri_ref;    // [ntri][9] vertices at t = 0
   double* tri;        // [ntri][9] vertices at the current step
   double* tri_pl;     // [ntri][4] unit normal and offset of the plane
@@ -199,6 +204,8 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
                        hipEvent_t* ev = nullptr);
 hipError_t launch_scatter_state(const Ctx& c, const State& S, double* x, double* v, double* w,
                                 double* q, double* F, double* T, hipStream_t s);
+hipError_t launch_pack_state(const Ctx& c, const State& S, const double* x, const double* v,
+                             const double* w, const double* q, const double* R, hipStream_t s);
 hipError_t launch_mesh_planes(const Ctx& c, hipStream_t s);
 hipError_t launch_selftest(int64_t n, const double* in, const double* in2, double* out,
                            hipStream_t s);

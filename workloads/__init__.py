@@ -211,9 +211,9 @@ def cfg2(seed=202, n=200_000, phi_rsa=0.35, shrink=0.93):
     vol = float(np.sum(4.0 / 3.0 * np.pi * (shrink * R) ** 3))
     L = 60 * MM
     H = vol / (phi_rsa * L * L)
+    # the bottom layer starts slightly pressed into the floor, like the
+    # overlapping neighbours inside the packing
     x = rsa_place(shrink * R, [-L / 2, -L / 2, 0.0], [L / 2, L / 2, H], seed)
-    # lift so that no sphere starts below the floor at its true radius
-    x[:, 2] += (1.0 - shrink) * R.max()
     tri = floor_mesh(0.0, 0.0, 300 * MM, 0.0)
     return _finish("cfg2_column_collapse_200k", default_params(dt=5e-7), x, R, rng, tri, 20000)
 
