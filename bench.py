@@ -62,6 +62,10 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cell-factor", type=float, default=None,
+                    help="cell edge / (2 R_max); default: autotuned")
+    ap.add_argument("--detect-lanes", type=int, default=None,
+                    help="lanes per particle in the contact search; default: autotuned")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -71,13 +75,21 @@ def main():
     import torch
 
     import workloads as W
-    from paper_2507_12610_amd import Solver
+    from paper_2507_12610_amd import Solver, autotune
 
     w = W.cfg2()
     n = len(w["R"])
     print(f"[bench] workload {w['name']}: N={n}, {len(w['tri'])} triangles", file=sys.stderr,
           flush=True)
-    s = Solver(w, precision=args.precision, device="cuda:0")
+    tuned = None
+    if args.cell_factor is None or args.detect_lanes is None:
+        best, timings = autotune(w, precision=args.precision)
+        tuned = {"chosen": best, "trials": timings}
+        print(f"[bench] autotuned: {best}", file=sys.stderr, flush=True)
+        cf, lanes = best["cell_factor"], best["detect_lanes"]
+    else:
+        cf, lanes = args.cell_factor, args.detect_lanes
+    s = Solver(w, precision=args.precision, device="cuda:0", cell_factor=cf, detect_lanes=lanes)
     s.step(args.warmup)
     torch.cuda.synchronize()
     st0 = s.stats()
@@ -117,10 +129,15 @@ def main():
            "config": {"workload": w["name"], "particles": n, "triangles": len(w["tri"]),
                       "dt": w["params"]["dt"], "precision": args.precision,
                       "radii": "lognormal, median 1 mm, sigma 0.2",
-                      "friction": [w["params"]["mu_s"], w["params"]["mu_r"], w["params"]["mu_t"]]},
+                      "friction": [w["params"]["mu_s"], w["params"]["mu_r"], w["params"]["mu_t"]],
+                      "cell_factor": cf, "detect_lanes": lanes},
            "contacts_per_s": round(contacts / wall, 1),
            "contacts_per_step": round(contacts / args.steps, 1),
+           "pair_contacts_per_step": round((st1["pp"] - st0["pp"]) / args.steps, 1),
+           "wall_contacts_per_step": round((st1["pw"] - st0["pw"]) / args.steps, 1),
            "roofline": roofline}
+    if tuned is not None:
+        out["autotune"] = tuned
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

@@ -85,12 +85,18 @@ typedef struct {
  *                force and torque arithmetic in float, with double for
  *                positions, velocities, differences, the contact test,
  *                springs, force sums and integration
- *  block         threads per workgroup for particle and contact kernels, a
- *                multiple of 64 in [64, 1024]; 0 selects 256
- *  cell_factor   cell edge = cell_factor * 2 * R_max, >= 1; 0 selects 1 */
+ *  block         reserved: 0 or a multiple of 64 in [64, 1024] (workgroups
+ *                are 256 threads)
+ *  detect_lanes  lanes that share one particle's contact search: 1, 2, 4 or
+ *                8; 0 selects 4
+ *  cell_factor   cell edge = cell_factor * 2 * R_max, >= 0.125; 0 selects 1.
+ *                Each particle searches the cells within R_i + R_max of its
+ *                centre, so the contact set does not depend on this value;
+ *                below 1 it trades more cell ranges for fewer candidates
+ *                (polydisperse systems) */
 typedef struct {
   int64_t n_max, contacts_max, cells_max, tri_max;
-  int32_t nsims_max, precision, block, reserved;
+  int32_t nsims_max, precision, block, detect_lanes;
   double cell_factor;
 } sdem_config;
 

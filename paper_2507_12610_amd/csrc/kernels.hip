@@ -129,7 +129,6 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
   if (threadIdx.x == 0) {
     bad_total = 0;
     atomicAdd(&c.ctr->steps, 1ull);  // steps started (the host discounts a failed one)
-    c.ctr->ncontacts = 0;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kGridThreads / 64;
@@ -181,6 +180,33 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
       if (bad) bad_total = 1;
     }
   }
+  // fold the previous step's per-group contact counts into the totals
+  if (c.ctr->stats_pending) {
+    unsigned long long a = 0, b = 0;
+    for (int q = threadIdx.x; q < c.ngroups; q += kGridThreads) {
+      a += (unsigned)c.gstat[2 * q];
+      b += (unsigned)c.gstat[2 * q + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 64);
+      b += __shfl_xor(b, o, 64);
+    }
+    __shared__ unsigned long long wsum[2][kGridThreads / 64];
+    if (lane == 0) {
+      wsum[0][wv] = a;
+      wsum[1][wv] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < nw; ++w) {
+        wsum[0][0] += wsum[0][w];
+        wsum[1][0] += wsum[1][w];
+      }
+      c.ctr->pp_sum += wsum[0][0];
+      c.ctr->pw_sum += wsum[1][0];
+      c.ctr->stats_pending = 0;
+    }
+  }
   __syncthreads();
   block_exclusive_scan_ll(ncell, c.nsims, &total);
   for (int s = threadIdx.x; s < c.nsims; s += kGridThreads) {
@@ -225,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_keys(Ctx c, State A) {
 // the next step and writing the end entry.  Tables of up to kScanSmall cells:
 // one workgroup; larger: block sums, a one-workgroup scan of them, downsweep.
 // ---------------------------------------------------------------------------
-constexpr int kScanSmall = 1 << 18;
+constexpr int kScanSmall = 1 << 15;
 constexpr int kScanOne = 1024;  // threads of the one-workgroup scan
 
 __global__ __launch_bounds__(kScanOne) void k_scan_small(Ctx c) {
@@ -379,6 +405,7 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B) {
   B.key[d] = k;
   B.src[d] = so;
   c.pcnt[d] = 0;
+  if ((d & (kGroup - 1)) == 0) c.gcnt[d >> kGroupShift] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -434,32 +461,36 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all) {
 }
 
 // ---------------------------------------------------------------------------
-// 5. narrow phase (Section 3.3), one pass.  Each lane (one particle slot)
-//    tests the triangles of its simulation, then the particles in the upper
-//    half of its 27-cell neighbourhood.  With cells in (z, y, x) row order
-//    the three cells cx-1..cx+1 of a row are one contiguous slot range, so the
-//    half shell is five ranges: the rest of the own row (slots after this
-//    one), the row at (y+1, z) and the three rows at z+1.  Each pair is found
-//    once, by its lower slot (the owner).  Hits go to a per-lane list in LDS;
-//    a wave prefix scan gives every lane its place and one atomic per wave
-//    reserves the wave's records.  Pair records are also entered in the
-//    partner's list (one integer atomic per pair).
+// 5. narrow phase (Section 3.3), one pass.  SUB adjacent lanes share one
+//    particle slot s and split its search (every SUB-th triangle of its
+//    simulation and every SUB-th candidate of each cell row), which
+//    multiplies the loads in flight for the latency-bound search.  Partners
+//    are the particles with a higher slot in the cells within R_s + R_max of
+//    x_s on each axis: with cells in (z, y, x) row order each row of that box
+//    is one contiguous slot range, and rows before the own row hold only
+//    lower slots.  Each pair is thus found once, by its lower slot (the
+//    owner).  Hits go to a per-lane list in LDS; a wave prefix scan gives
+//    every lane its place (a slot's SUB lists end up adjacent) and one atomic
+//    per wave reserves the wave's records.  Pair records are also entered in
+//    the partner's list (one integer atomic per pair).
 // ---------------------------------------------------------------------------
+template <int SUB>
 __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn) {
   if (c.ctr->flags) return;
   __shared__ int hits[kThreads / 64][kMaxOwn][64];
   const int n = c.n;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int s = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int g = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int s = g / SUB, sub = g % SUB;
   int npp = 0, npw = 0;
   if (s < n) {
     const int sim = c.sim_of[s];
-    const SimGrid g = c.sg[sim];
+    const SimGrid gr = c.sg[sim];
     const int tri0 = c.sp[sim].tri0, ntri = c.sp[sim].ntri;
     const double4 ps = S.xr[s];
     const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
     // ---- triangles
-    for (int m = tri0; m < tri0 + ntri; ++m) {
+    for (int m = tri0 + sub; m < tri0 + ntri; m += SUB) {
       const double* pl = c.tri_pl + 4 * m;
       const double reach = Rs + c.rmesh[m];
       const double pd = (pl[0] * xs + pl[1] * ys + pl[2] * zs) - pl[3];
@@ -470,60 +501,75 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
       double dx, dy, dz, d;
       const double delta = pair_gap(xs, ys, zs, Rs, cp[0], cp[1], cp[2], c.rmesh[m], &dx, &dy, &dz, &d);
       if (delta >= 0.0) {
-        if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = -1 - m;
+        if (npw < kMaxOwn) hits[wv][npw][lane] = -1 - m;
         ++npw;
       }
     }
-    // ---- particles
-    const int loc = S.key[s] - g.cell_off;
-    const int nx = g.dim[0], ny = g.dim[1], nz = g.dim[2];
+    // ---- particles (the margin on the box covers rounding of its ends)
+    const int loc = S.key[s] - gr.cell_off;
+    const int nx = gr.dim[0], ny = gr.dim[1], nz = gr.dim[2];
     const int cx = loc % nx, cyz = loc / nx, cy = cyz % ny, cz = cyz / ny;
-    const int xlo = cx > 0 ? cx - 1 : 0, xhi = cx + 1 < nx ? cx + 1 : nx - 1;
-    for (int r = 0; r < 5; ++r) {
-      const int yy = r == 0 ? cy : (r == 1 ? cy + 1 : cy + (r - 3));
-      const int zz = r <= 1 ? cz : cz + 1;
-      if (yy < 0 || yy >= ny || zz >= nz) continue;
-      const int row = g.cell_off + (zz * ny + yy) * nx;
-      const int t0 = (r == 0) ? s + 1 : c.cell_start[row + xlo];
-      const int t1 = c.cell_start[row + xhi + 1];
-      // four candidates per iteration so that four loads are in flight
-      for (int t = t0; t < t1; t += 4) {
-        double4 pt[4];
+    (void)cx;
+    const double reach = (Rs + c.sp[sim].rmax) * (1.0 + 1e-9);
+    const int x0 = cell_coord(xs - reach, gr.lo[0], gr.inv_h, nx);
+    const int x1 = cell_coord(xs + reach, gr.lo[0], gr.inv_h, nx);
+    const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, ny);
+    const int y1 = cell_coord(ys + reach, gr.lo[1], gr.inv_h, ny);
+    const int z1 = cell_coord(zs + reach, gr.lo[2], gr.inv_h, nz);
+    for (int zz = cz; zz <= z1; ++zz) {
+      for (int yy = (zz == cz ? cy : y0); yy <= y1; ++yy) {
+        const int row = gr.cell_off + (zz * ny + yy) * nx;
+        const int t0 = ((zz == cz && yy == cy) ? s + 1 : c.cell_start[row + x0]) + sub;
+        const int t1 = c.cell_start[row + x1 + 1];
+        // four candidates per iteration so that four loads are in flight
+        for (int t = t0; t < t1; t += 4 * SUB) {
+          double4 pt[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u < t1 ? t + u : t];
+          for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u * SUB < t1 ? t + u * SUB : t];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (t + u >= t1) break;
-          const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
-          const double sr = Rs + pt[u].w;
-          // cheap conservative reject before the exactly rounded test
-          if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) continue;
-          double dx, dy, dz, d;
-          const double delta =
-              pair_gap(xs, ys, zs, Rs, pt[u].x, pt[u].y, pt[u].z, pt[u].w, &dx, &dy, &dz, &d);
-          if (delta >= 0.0) {
-            if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = t + u;
-            ++npp;
+          for (int u = 0; u < 4; ++u) {
+            if (t + u * SUB >= t1) break;
+            const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
+            const double sr = Rs + pt[u].w;
+            // cheap conservative reject before the exactly rounded test
+            if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) continue;
+            double dx, dy, dz, d;
+            const double delta =
+                pair_gap(xs, ys, zs, Rs, pt[u].x, pt[u].y, pt[u].z, pt[u].w, &dx, &dy, &dz, &d);
+            if (delta >= 0.0) {
+              if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = t + u * SUB;
+              ++npp;
+            }
           }
         }
       }
     }
   }
-  // wave compaction: prefix scan of the per-lane counts, one atomic per wave
+  // wave compaction: prefix scan of the per-lane counts, then one atomic per
+  // wave on the counter of the wave's slot group (a wave's slots lie in one
+  // group, and a group's counter sees at most 4*SUB waves)
   const int total_hits = npw + npp;
   const int mine = total_hits < kMaxOwn ? total_hits : kMaxOwn;
   const int incl = wave_incl_scan(mine, lane);
   const int wtot = __shfl(incl, 63, 64);
+  const int grp = __shfl(g / SUB, 0, 64) >> kGroupShift;
   int base = 0;
-  if (lane == 63 && wtot > 0) base = atomicAdd(&c.ctr->ncontacts, wtot);
+  if (lane == 63 && wtot > 0 && grp < c.ngroups) base = atomicAdd(&c.gcnt[grp], wtot);
   base = __shfl(base, 63, 64);
-  const int first = base + incl - mine;
+  const int first = grp * c.gcap + base + incl - mine;
+  // end of this slot's records: the last of its SUB lanes
+  const int slot_end = __shfl(first + mine, (lane | (SUB - 1)), 64);
   if (total_hits > kMaxOwn) raise_flag(c.ctr, kFlagCapPerParticle);
-  const bool fits = (long long)base + wtot <= (long long)c.cap_contacts;
-  if (!fits && lane == 63) raise_flag(c.ctr, kFlagCapContacts);
+  const bool fits = base + wtot <= c.gcap;
+  if (!fits && lane == 63) {
+    atomicMax(&c.ctr->need_group, base + wtot);
+    raise_flag(c.ctr, kFlagCapContacts);
+  }
   if (s < n && fits) {
-    cn.off[s] = first;
-    cn.cnt[s] = mine;
+    if (sub == 0) {
+      cn.off[s] = first;
+      cn.cnt[s] = slot_end - first;
+    }
     for (int k = 0; k < mine; ++k) {
       const int e = first + k;
       const int t = hits[wv][k][lane];
@@ -537,12 +583,6 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
           raise_flag(c.ctr, kFlagCapPerParticle);
       }
     }
-  }
-  // contact counts for the statistics: one 64-bit atomic per wave
-  const int a = wave_sum_i32(npp), b = wave_sum_i32(npw);
-  if (lane == 0 && (a | b)) {
-    atomicAdd(&c.ctr->pp_sum, (unsigned long long)a);
-    atomicAdd(&c.ctr->pw_sum, (unsigned long long)b);
   }
 }
 
@@ -605,17 +645,20 @@ __device__ __forceinline__ double sphere_mass(double rho, double R) {
 // Springs of key (ki, kj) among the previous step's contacts of the previous
 // owner slot po; zero if the pair was not in contact.
 __device__ __forceinline__ void find_old(const Contacts& co, int po, int2 key, double us[3],
-                                         double ur[3], double* ut, int cap) {
+                                         double ur[3], double* ut) {
   const int b0 = co.off[po], b1 = b0 + co.cnt[po];
   for (int e = b0; e < b1; ++e) {
     const int2 k = co.key[e];
     if (k.x == key.x && k.y == key.y) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        us[a] = co.us[a * cap + e];
-        ur[a] = co.ur[a * cap + e];
-      }
-      *ut = co.ut[e];
+      const double2* r = reinterpret_cast<const double2*>(co.spr + (size_t)kSpr * e);
+      const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+      us[0] = r0.x;
+      us[1] = r0.y;
+      us[2] = r1.x;
+      ur[0] = r1.y;
+      ur[1] = r2.x;
+      ur[2] = r2.y;
+      *ut = r3.x;
       return;
     }
   }
@@ -624,15 +667,13 @@ __device__ __forceinline__ void find_old(const Contacts& co, int po, int2 key, d
 template <typename RT>
 __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur, Contacts old) {
   if (c.ctr->flags) return;
-  const int cap = c.cap_contacts;
-  const int C = c.ctr->ncontacts;
-  // each XCD (workgroup b runs on XCD b % 8) takes one contiguous eighth of
-  // the contacts, so neighbouring records share that XCD's L2; its
-  // workgroups stride through the eighth
-  const int xcd = blockIdx.x & 7, nbx = gridDim.x >> 3;
-  const int e0 = (int)(((long long)C * xcd) >> 3), e1 = (int)(((long long)C * (xcd + 1)) >> 3);
-  for (int e = e0 + (blockIdx.x >> 3) * blockDim.x + threadIdx.x; e < e1;
-       e += nbx * blockDim.x) {
+  // one workgroup per slot group (consecutive groups on one XCD share its L2)
+  const int grp = xcd_remap(blockIdx.x, gridDim.x);
+  const int cnt = min(c.gcnt[grp], c.gcap);
+  const int gbase = grp * c.gcap;
+  int npp = 0, npw = 0;
+  for (int l = threadIdx.x; l < cnt; l += blockDim.x) {
+    const int e = gbase + l;
     const int a = cur.a[e], b = cur.b[e];
     const int sim = c.sim_of[a];
     const SimParams& P = c.sp[sim];
@@ -744,19 +785,20 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
     {
       const int sa = S.src[a];
       const int po = wall ? sa : min(sa, S.src[b]);
-      find_old(old, po, key, us, ur, &ut, cap);
+      find_old(old, po, key, us, ur, &ut);
     }
     RT fs[3], fr[3], ft;
     friction_vec<RT>(nrm, ks, cs, (RT)P.mu_s * fnl, P.dt, vs, us, fs);
     friction_vec<RT>(nrm, kn, cn, (RT)P.mu_r * fnl, P.dt, vr, ur, fr);
     friction_scalar<RT>(ks, cs, (RT)P.mu_t * fnl, P.dt, vt, &ut, &ft);
     cur.key[e] = key;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      cur.us[k * cap + e] = us[k];
-      cur.ur[k * cap + e] = ur[k];
+    {
+      double2* r = reinterpret_cast<double2*>(cur.spr + (size_t)kSpr * e);
+      r[0] = make_double2(us[0], us[1]);
+      r[1] = make_double2(us[2], ur[0]);
+      r[2] = make_double2(ur[1], ur[2]);
+      r[3] = make_double2(ut, 0.0);
     }
-    cur.ut[e] = ut;
     // torques: tau_s = r_i f_s x n, tau_r = R* n x f_r, tau_t = f_t R* n;
     // body j: -f, r_j f_s x n - tau_r - tau_t (Eq. antisymm_*)
     const RT fsxn[3] = {fs[1] * nrm[2] - fs[2] * nrm[1], fs[2] * nrm[0] - fs[0] * nrm[2],
@@ -766,7 +808,9 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
                       rs * (nrm[0] * fr[1] - nrm[1] * fr[0])};
     const RT ftr = ft * rs;
     const RT rif = (RT)ri, rjf = (RT)rj;
-    double* res = c.res;
+    npp += wall ? 0 : 1;
+    npw += wall ? 1 : 0;
+    double o[kRes];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double f = (double)fn[k] + (double)fs[k];
@@ -774,10 +818,32 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
       const double ti = (double)(rif * fsxn[k]) + ttr;
       const double tj = wall ? 0.0 : (double)(rjf * fsxn[k]) - ttr;
       // per-contact results for the owner slot a and the partner b
-      res[(size_t)k * cap + e] = swap ? -f : f;
-      res[(size_t)(3 + k) * cap + e] = swap ? tj : ti;
-      res[(size_t)(6 + k) * cap + e] = swap ? ti : tj;
+      o[k] = swap ? -f : f;
+      o[3 + k] = swap ? tj : ti;
+      o[6 + k] = swap ? ti : tj;
     }
+    o[9] = 0.0;
+    double2* r = reinterpret_cast<double2*>(c.res + (size_t)kRes * e);
+#pragma unroll
+    for (int k = 0; k < kRes / 2; ++k) r[k] = make_double2(o[2 * k], o[2 * k + 1]);
+  }
+  // contact counts of the group for the statistics (summed by the next step's
+  // grid kernel or by the host)
+  __shared__ int red[2][kThreads / 64];
+  const int a = wave_sum_i32(npp), b = wave_sum_i32(npw);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ta = 0, tb = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      ta += red[0][w];
+      tb += red[1][w];
+    }
+    c.gstat[2 * grp] = ta;
+    c.gstat[2 * grp + 1] = tb;
   }
 }
 
@@ -803,16 +869,16 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   const int n = c.n;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const size_t cap = (size_t)c.cap_contacts;
   const double* res = c.res;
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   {
     const int e0 = cur.off[i], e1 = e0 + cur.cnt[i];
     for (int e = e0; e < e1; ++e) {
+      const double* r = res + (size_t)kRes * e;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        F[k] += res[k * cap + e];
-        T[k] += res[(3 + k) * cap + e];
+        F[k] += r[k];
+        T[k] += r[3 + k];
       }
     }
     const int m = min(c.pcnt[i], kMaxRev);
@@ -844,11 +910,11 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (j < m) {
-          const int e = ke[j];
+          const double* r = res + (size_t)kRes * ke[j];
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            F[k] -= res[k * cap + e];
-            T[k] += res[(6 + k) * cap + e];
+            F[k] -= r[k];
+            T[k] += r[6 + k];
           }
         }
       }
@@ -866,10 +932,11 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
         }
         if (best < 0) break;
         last = ba;
+        const double* r = res + (size_t)kRes * best;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          F[k] -= res[k * cap + best];
-          T[k] += res[(6 + k) * cap + best];
+          F[k] -= r[k];
+          T[k] += r[6 + k];
         }
       }
     }
@@ -932,6 +999,7 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   S.xr[i] = make_double4(x[0], x[1], x[2], R);
   S.q[i] = make_double4(q[0], q[1], q[2], q[3]);
   if (!ok) raise_flag(c.ctr, kFlagNonFinite);
+  if (i == 0) c.ctr->stats_pending = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1022,12 +1090,17 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
   k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B);
   if (c.any_rotating) k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
   if (ev) (void)hipEventRecord(ev[2], s);
-  k_detect<<<nbp, kThreads, 0, s>>>(c, B, cnew);
+  switch (c.detect_sub) {
+    case 1: k_detect<1><<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
+    case 2: k_detect<2><<<blocks_for(2 * c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
+    case 8: k_detect<8><<<blocks_for(8 * c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
+    default: k_detect<4><<<blocks_for(4 * c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
+  }
   if (ev) (void)hipEventRecord(ev[3], s);
   if (precision == SDEM_MIXED)
-    k_force<float><<<c.force_blocks, kThreads, 0, s>>>(c, B, cnew, cold);
+    k_force<float><<<c.ngroups, kThreads, 0, s>>>(c, B, cnew, cold);
   else
-    k_force<double><<<c.force_blocks, kThreads, 0, s>>>(c, B, cnew, cold);
+    k_force<double><<<c.ngroups, kThreads, 0, s>>>(c, B, cnew, cold);
   if (ev) (void)hipEventRecord(ev[4], s);
   k_integrate<<<nbp, kThreads, 0, s>>>(c, B, cnew);
   if (ev) (void)hipEventRecord(ev[5], s);

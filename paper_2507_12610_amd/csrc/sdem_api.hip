@@ -76,12 +76,21 @@ struct sdem_ctx {
   bool graph_failed = false;
 };
 
+// contact records are allocated per group of kGroup slots: gcap each
+static int64_t groups_of(const sdem_config& cfg) {
+  return (std::max<int64_t>(cfg.n_max, 1) + kGroup - 1) / kGroup;
+}
+static int64_t group_cap(const sdem_config& cfg) {
+  return std::max<int64_t>(1, (cfg.contacts_max + groups_of(cfg) - 1) / groups_of(cfg));
+}
+
 static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Contacts ct[2],
                     double** scratch) {
   Layout L;
   L.base = base;
   const size_t N = (size_t)std::max<int64_t>(cfg.n_max, 1);
-  const size_t Cm = (size_t)std::max<int64_t>(cfg.contacts_max, 1);
+  const size_t G = (size_t)groups_of(cfg);
+  const size_t Cm = G * (size_t)group_cap(cfg);
   const size_t Gm = (size_t)std::max<int64_t>(cfg.cells_max, 1);
   const size_t M = (size_t)std::max<int64_t>(cfg.tri_max, 1);
   const size_t S = (size_t)std::max<int32_t>(cfg.nsims_max, 1);
@@ -101,8 +110,10 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.perm = L.take<int32_t>(N);
   cc.scan_tmp = L.take<int32_t>(kScanBlocks + 1);
   cc.pcnt = L.take<int32_t>(N);
+  cc.gcnt = L.take<int32_t>(G);
+  cc.gstat = L.take<int32_t>(2 * G);
   cc.plist = L.take<int32_t>(N * kMaxRev);
-  cc.res = L.take<double>(9 * Cm);
+  cc.res = L.take<double>(kRes * Cm);
   cc.F = L.take<double>(3 * N);
   cc.T = L.take<double>(3 * N);
   cc.tri_ref = L.take<double>(9 * M);
@@ -127,9 +138,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
     k.a = L.take<int32_t>(Cm);
     k.b = L.take<int32_t>(Cm);
     k.key = L.take<int2>(Cm);
-    k.us = L.take<double>(3 * Cm);
-    k.ur = L.take<double>(3 * Cm);
-    k.ut = L.take<double>(Cm);
+    k.spr = L.take<double>(kSpr * Cm);
     if (ct) ct[b] = k;
   }
   double* scr = L.take<double>(19 * N);
@@ -144,6 +153,8 @@ static int check_config(const sdem_config* cfg) {
   if (cfg->n_max < 0 || cfg->n_max > 0x3fffffff) return fail(SDEM_EINVAL, "n_max out of range");
   if (cfg->contacts_max < 0 || cfg->contacts_max > 0x3fffffff)
     return fail(SDEM_EINVAL, "contacts_max out of range");
+  if (groups_of(*cfg) * group_cap(*cfg) > 0x7fffffffLL)
+    return fail(SDEM_EINVAL, "contacts_max too large");
   if (cfg->cells_max < 1 || cfg->cells_max > 0x3fffffff)
     return fail(SDEM_EINVAL, "cells_max out of range");
   if (cfg->tri_max < 0 || cfg->tri_max > 0x3fffffff) return fail(SDEM_EINVAL, "tri_max out of range");
@@ -153,8 +164,11 @@ static int check_config(const sdem_config* cfg) {
     return fail(SDEM_EINVAL, "unknown precision %d", cfg->precision);
   if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64))
     return fail(SDEM_EINVAL, "block must be a multiple of 64 in [64, 1024]");
-  if (!(cfg->cell_factor == 0.0 || cfg->cell_factor >= 1.0) || !isfinite(cfg->cell_factor))
-    return fail(SDEM_EINVAL, "cell_factor must be >= 1");
+  if (cfg->detect_lanes != 0 && cfg->detect_lanes != 1 && cfg->detect_lanes != 2 &&
+      cfg->detect_lanes != 4 && cfg->detect_lanes != 8)
+    return fail(SDEM_EINVAL, "detect_lanes must be 0, 1, 2, 4 or 8");
+  if (!(cfg->cell_factor == 0.0 || cfg->cell_factor >= 0.125) || !isfinite(cfg->cell_factor))
+    return fail(SDEM_EINVAL, "cell_factor must be >= 0.125 (0 selects 1)");
   return SDEM_OK;
 }
 
@@ -212,7 +226,8 @@ static SimParams derive(const sdem_params& p, double cell_factor, double rmax) {
   // cell edge >= 2 R_max; the small margin keeps neighbours within one cell
   // index of each other despite rounding of the cell coordinate
   const double rm = rmax > 0 ? rmax : 1.0;
-  d.h = cell_factor * 2.0 * rm * (1.0 + 1e-9);
+  d.rmax = rm;
+  d.h = cell_factor * 2.0 * rm;
   d.rotating = (p.mesh_omega[0] != 0.0 || p.mesh_omega[1] != 0.0 || p.mesh_omega[2] != 0.0);
   return d;
 }
@@ -313,6 +328,9 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
     // a multiple of 8 so that every XCD gets the same number of workgroups
     c.force_blocks = std::max(8, (ncu * kForceBlocksPerCU + 7) / 8 * 8);
   }
+  c.detect_sub = cfg.detect_lanes ? cfg.detect_lanes : 4;
+  c.ngroups = (int32_t)((std::max<int64_t>(n, 1) + kGroup - 1) / kGroup);
+  c.gcap = (int32_t)group_cap(cfg);
 
   auto bail = [&](int code) {
     delete X;
@@ -362,6 +380,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
     if (!e) e = hipMemsetAsync(X->ct[b].off, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
   }
   if (!e) e = hipMemsetAsync(c.pcnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
+  if (!e) e = hipMemsetAsync(c.gcnt, 0, sizeof(int32_t) * c.ngroups, st);
   if (!e) e = cp(c.sim_of, sim_of.data(), sizeof(int32_t) * n);
   if (!e) e = cp(c.chunks, chunks.data(), sizeof(int32_t) * chunks.size());
   if (!e) e = cp(c.chunk0, chunk0.data(), sizeof(int32_t) * chunk0.size());
@@ -461,22 +480,32 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
       owner[e] = slot[ki[e]];
     }
   }
-  // group by owner slot (counting sort)
-  std::vector<int32_t> cnt((size_t)std::max<int64_t>(n, 1), 0), off((size_t)n + 1, 0);
+  // group by owner slot (counting sort); records of slot group g start at
+  // g * gcap, each owner's records contiguous
+  std::vector<int32_t> cnt((size_t)std::max<int64_t>(n, 1), 0), off((size_t)std::max<int64_t>(n, 1), 0);
   for (int64_t e = 0; e < nc; ++e) ++cnt[owner[e]];
-  for (int64_t s = 0; s < n; ++s) off[s + 1] = off[s] + cnt[s];
+  const int64_t gcap = X->c.gcap;
+  std::vector<int32_t> used((size_t)X->c.ngroups, 0);
+  for (int64_t s = 0; s < n; ++s) {
+    const int64_t g = s >> kGroupShift;
+    off[s] = (int32_t)(g * gcap + used[g]);
+    used[g] += cnt[s];
+    if (used[g] > gcap)
+      return fail(SDEM_ECAPACITY, "history: slot group %lld needs more than its %lld records",
+                  (long long)g, (long long)gcap);
+  }
   std::vector<int32_t> pos(off.begin(), off.end());
-  const size_t cap = (size_t)X->cfg.contacts_max;
-  std::vector<int2> K((size_t)std::max<int64_t>(nc, 1));
-  std::vector<double> U((size_t)3 * nc), V((size_t)3 * nc), Wt((size_t)nc);
+  const size_t Ctot = (size_t)X->c.ngroups * (size_t)gcap;
+  std::vector<int2> K(Ctot);
+  std::vector<double> SP((size_t)kSpr * Ctot, 0.0);
   for (int64_t e = 0; e < nc; ++e) {
     const int32_t d = pos[owner[e]]++;
     K[d] = make_int2(ki[e], kj[e]);
     for (int k = 0; k < 3; ++k) {
-      U[(size_t)k * nc + d] = us[3 * e + k];
-      V[(size_t)k * nc + d] = ur[3 * e + k];
+      SP[(size_t)kSpr * d + k] = us[3 * e + k];
+      SP[(size_t)kSpr * d + 3 + k] = ur[3 * e + k];
     }
-    Wt[d] = ut[e];
+    SP[(size_t)kSpr * d + 6] = ut[e];
   }
   Contacts& C = X->ct[X->cur];
   if (n) {
@@ -484,14 +513,8 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
     HIP_TRY(hipMemcpy(C.off, off.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   }
   if (nc) {
-    HIP_TRY(hipMemcpy(C.key, K.data(), sizeof(int2) * nc, hipMemcpyHostToDevice));
-    for (int k = 0; k < 3; ++k) {
-      HIP_TRY(hipMemcpy(C.us + k * cap, U.data() + (size_t)k * nc, sizeof(double) * nc,
-                        hipMemcpyHostToDevice));
-      HIP_TRY(hipMemcpy(C.ur + k * cap, V.data() + (size_t)k * nc, sizeof(double) * nc,
-                        hipMemcpyHostToDevice));
-    }
-    HIP_TRY(hipMemcpy(C.ut, Wt.data(), sizeof(double) * nc, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(C.key, K.data(), sizeof(int2) * Ctot, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(C.spr, SP.data(), sizeof(double) * kSpr * Ctot, hipMemcpyHostToDevice));
   }
   return SDEM_OK;
 }
@@ -512,8 +535,10 @@ static int finish_steps(sdem_ctx* X, const Counters& before, int start) {
                 "far; confine them with a mesh or raise cells_max)",
                 at, after.need_cells, (long long)X->cfg.cells_max);
   if (after.flags & kFlagCapContacts)
-    return fail(SDEM_ECAPACITY, "step %lld: %d contacts exceed contacts_max = %lld", at,
-                after.ncontacts, (long long)X->cfg.contacts_max);
+    return fail(SDEM_ECAPACITY,
+                "step %lld: a group of %d particle slots needed %d contact records, its share "
+                "of contacts_max = %lld is %d; raise contacts_max",
+                at, kGroup, after.need_group, (long long)X->cfg.contacts_max, X->c.gcap);
   if (after.flags & kFlagCapPerParticle)
     return fail(SDEM_ECAPACITY,
                 "step %lld: a particle has more than %d contacts of one kind (owned or "
@@ -652,32 +677,33 @@ int sdem_read_contacts(sdem_ctx* X, int64_t cap, int64_t* n_out, int32_t* ki, in
   const Contacts& C = X->ct[X->cur];
   hipStream_t st = X->stream;
   HIP_TRY(hipStreamSynchronize(st));
-  // records of a completed step (or loaded history) fill [0, sum of counts)
+  // records of a completed step (or loaded history): [off[s], off[s]+cnt[s])
   int32_t total = 0;
+  std::vector<int32_t> cnt((size_t)std::max<int64_t>(n, 1)), off((size_t)std::max<int64_t>(n, 1));
   if (n) {
-    std::vector<int32_t> cnt((size_t)n);
     HIP_TRY(hipMemcpy(cnt.data(), C.cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
-    for (int32_t v : cnt) total += v;
+    HIP_TRY(hipMemcpy(off.data(), C.off, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    for (int64_t s = 0; s < n; ++s) total += cnt[s];
   }
   if (n_out) *n_out = total;
   if (!total) return SDEM_OK;
-  const size_t ccap = (size_t)X->cfg.contacts_max;
-  std::vector<int2> KK(total);
+  const size_t Ctot = (size_t)X->c.ngroups * (size_t)X->c.gcap;
+  std::vector<int2> KA(Ctot);
+  std::vector<double> SA((size_t)kSpr * Ctot);
+  HIP_TRY(hipMemcpy(KA.data(), C.key, sizeof(int2) * Ctot, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(SA.data(), C.spr, sizeof(double) * kSpr * Ctot, hipMemcpyDeviceToHost));
   std::vector<int32_t> K1(total), K2(total);
-  std::vector<double> S((size_t)7 * total);
-  HIP_TRY(hipMemcpy(KK.data(), C.key, sizeof(int2) * total, hipMemcpyDeviceToHost));
-  for (int32_t e = 0; e < total; ++e) {
-    K1[e] = KK[e].x;
-    K2[e] = KK[e].y;
+  std::vector<double> SP((size_t)kSpr * total);
+  {
+    int32_t w = 0;
+    for (int64_t s = 0; s < n; ++s)
+      for (int32_t k = 0; k < cnt[s]; ++k, ++w) {
+        const size_t e = (size_t)off[s] + k;
+        K1[w] = KA[e].x;
+        K2[w] = KA[e].y;
+        for (int j = 0; j < kSpr; ++j) SP[(size_t)kSpr * w + j] = SA[kSpr * e + j];
+      }
   }
-  for (int k = 0; k < 3; ++k) {
-    HIP_TRY(hipMemcpy(S.data() + (size_t)k * total, C.us + k * ccap, sizeof(double) * total,
-                      hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(S.data() + (size_t)(3 + k) * total, C.ur + k * ccap,
-                      sizeof(double) * total, hipMemcpyDeviceToHost));
-  }
-  HIP_TRY(hipMemcpy(S.data() + (size_t)6 * total, C.ut, sizeof(double) * total,
-                    hipMemcpyDeviceToHost));
   std::vector<int32_t> order(total);
   for (int32_t e = 0; e < total; ++e) order[e] = e;
   std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
@@ -691,10 +717,10 @@ int sdem_read_contacts(sdem_ctx* X, int64_t cap, int64_t* n_out, int32_t* ki, in
     o1[r] = K1[e];
     o2[r] = K2[e];
     for (int k = 0; k < 3; ++k) {
-      ous[3 * r + k] = S[(size_t)k * total + e];
-      our[3 * r + k] = S[(size_t)(3 + k) * total + e];
+      ous[3 * r + k] = SP[(size_t)kSpr * e + k];
+      our[3 * r + k] = SP[(size_t)kSpr * e + 3 + k];
     }
-    out[r] = S[(size_t)6 * total + e];
+    out[r] = SP[(size_t)kSpr * e + 6];
   }
   if (m) {
     if (ki) HIP_TRY(hipMemcpy(ki, o1.data(), sizeof(int32_t) * m, hipMemcpyDefault));
@@ -712,9 +738,18 @@ int sdem_stats(sdem_ctx* X, int64_t* steps, int64_t* pp, int64_t* pw) {
   HIP_TRY(hipMemcpyAsync(&h, X->c.ctr, sizeof h, hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipStreamSynchronize(X->stream));
   const int64_t done = (int64_t)h.steps - (h.flags ? 1 : 0);
+  int64_t a = (int64_t)h.pp_sum, b = (int64_t)h.pw_sum;
+  if (h.stats_pending) {  // the last step's counts are still per group
+    std::vector<int32_t> gs((size_t)2 * X->c.ngroups);
+    HIP_TRY(hipMemcpy(gs.data(), X->c.gstat, sizeof(int32_t) * gs.size(), hipMemcpyDeviceToHost));
+    for (int32_t q = 0; q < X->c.ngroups; ++q) {
+      a += gs[2 * q];
+      b += gs[2 * q + 1];
+    }
+  }
   if (steps) *steps = done;
-  if (pp) *pp = (int64_t)h.pp_sum;
-  if (pw) *pw = (int64_t)h.pw_sum;
+  if (pp) *pp = a;
+  if (pw) *pw = b;
   return SDEM_OK;
 }
 

@@ -10,11 +10,15 @@ namespace sdem {
 
 constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scan
 constexpr int kScanThreads = 256;
-constexpr int kBboxChunk = 4096;    // particles per bounding-box partial
+constexpr int kBboxChunk = 1024;    // particles per bounding-box partial
+constexpr int kSpr = 8;             // doubles per contact spring record
+constexpr int kRes = 10;            // doubles per contact result record
 constexpr int kThreads = 256;       // threads per workgroup of the particle kernels
 constexpr int kForceBlocksPerCU = 4;  // grid of the contact kernel: 4 workgroups per CU
 constexpr int kMaxOwn = 32;         // contacts one particle may own in a step
 constexpr int kMaxRev = 32;         // contacts one particle may take part in as partner
+constexpr int kGroupShift = 8;      // contact records are allocated per group of
+constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots
 
 enum : int {
   kFlagCapContacts = 1,
@@ -33,6 +37,7 @@ struct SimParams {
   double Es_pp, Gs_pp;         // uniform material, two spheres
   double Es_pw, Gs_pw;         // sphere against a rigid wall
   double h;                    // cell edge
+  double rmax;                 // largest radius of the simulation
   int32_t rotating;            // mesh rotates (|om| > 0)
   int32_t tri0, ntri;          // global triangle range
   int32_t p0, np;              // particle range (fixed positions in sorted order)
@@ -50,7 +55,8 @@ struct SimGrid {
 // Device-side counters and flags of a context.
 struct Counters {
   int32_t flags;
-  int32_t ncontacts;     // contacts of the step in progress (allocation counter)
+  int32_t need_group;    // contacts a slot group needed beyond its share (diagnostic)
+  int32_t stats_pending; // per-group contact counts of the last step not yet summed
   int32_t ncells;        // cells of the step in progress (all sims)
   int32_t need_cells;    // last required cell capacity (diagnostic)
   uint32_t scan_ticket;  // last-block detection of the scan
@@ -70,22 +76,27 @@ struct State {
   int32_t* src;  // slot of the same particle in the previous step's order
 };
 
-// One buffer of contacts, grouped by owner slot (owner = lower slot).
+// One buffer of contacts, grouped by owner slot (owner = lower slot).  The
+// records of slot group g (slots g*256 .. g*256+255) live in
+// [g*gcap, g*gcap + gcnt[g]).
 struct Contacts {
   int32_t* cnt;  // [n] contacts per owner slot
   int32_t* off;  // [n] first contact of each owner slot
   int32_t* a;    // owner slot
   int32_t* b;    // partner slot (>= 0) or -1 - global triangle index
   int2* key;     // (lower persistent id, higher id) or (id, -local triangle index)
-  double* us;    // [3][cap] sliding spring, orientation of body key.x
-  double* ur;    // [3][cap] rolling spring
-  double* ut;    // [cap] twisting spring
+  double* spr;   // [cap][kSpr] sliding spring (3), rolling spring (3), twisting
+                 // spring (1), in the orientation of body key.x; one pad
 };
 
 // Everything a step's kernels read or write.
 struct Ctx {
   int32_t n, nsims, ntri, cap_contacts, cap_cells, nchunks;
   int32_t any_rotating, force_blocks;
+  int32_t detect_sub;        // lanes per particle in the narrow phase (1, 2, 4, 8)
+  int32_t ngroups, gcap;     // slot groups, contact records per group
+  int32_t* gcnt;             // [ngroups] contact records used by each group
+  int32_t* gstat;            // [ngroups][2] pair and wall contacts of each group
   SimParams* sp;      // [nsims]
   SimGrid* sg;        // [nsims]
   int32_t* sim_of;    // [n] simulation of each slot (fixed)
@@ -100,8 +111,8 @@ struct Ctx {
   int32_t* scan_tmp;  // [kScanBlocks+1]
   int32_t* pcnt;      // [n] contacts in which the slot is the partner
   int32_t* plist;     // [n][kMaxRev] those contacts
-  double* res;        // [9][cap] per contact: force on the owner, torque on
-                      // the owner, torque on the partner
+  double* res;        // [cap][kRes] per contact: force on the owner (3), torque
+                      // on the owner (3), torque on the partner (3), pad
   double* F;          // [3][n] contact force of the last step, by slot
   double* T;          // [3][n] contact torque of the last step, by slot
   double* tri_ref;    // [ntri][9] vertices at t = 0

@@ -44,7 +44,7 @@ class Params(C.Structure):
 class Config(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("contacts_max", C.c_int64), ("cells_max", C.c_int64),
                 ("tri_max", C.c_int64), ("nsims_max", C.c_int32), ("precision", C.c_int32),
-                ("block", C.c_int32), ("reserved", C.c_int32), ("cell_factor", C.c_double)]
+                ("block", C.c_int32), ("detect_lanes", C.c_int32), ("cell_factor", C.c_double)]
 
 
 _lib = None
@@ -118,6 +118,34 @@ def _grid_cells(x, h):
     return int(np.prod(np.floor(ext / h) + 1))
 
 
+def autotune(sims, candidates=None, steps=20, warmup=6, precision="fp64", device="cuda:0",
+             **kw):
+    """Picks the cell edge factor and the number of lanes per particle in the
+    contact search by timing a few steps of each candidate on the given
+    workload (each trial runs on its own copy of the state).  Returns
+    (best, timings) with best = {"cell_factor", "detect_lanes", "ms_per_step"}."""
+    import time
+
+    import torch
+    if candidates is None:
+        candidates = [(1.0, 1), (1.0, 2), (0.7, 1), (0.5, 1), (0.5, 2), (0.4, 1), (0.33, 1)]
+    timings = []
+    for cf, lanes in candidates:
+        s = Solver(sims, precision=precision, device=device, cell_factor=cf, detect_lanes=lanes,
+                   **kw)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        s.close()
+        del s
+        timings.append({"cell_factor": cf, "detect_lanes": lanes, "ms_per_step": ms})
+    best = min(timings, key=lambda r: r["ms_per_step"])
+    return dict(best), timings
+
+
 class Solver:
     """One context of the HIP solver holding one or several simulations.
 
@@ -126,7 +154,7 @@ class Solver:
     """
 
     def __init__(self, sims, precision="fp64", device="cuda:0", contacts_max=None,
-                 cells_max=None, cell_factor=1.0, block=0, cell_slack=8.0):
+                 cells_max=None, cell_factor=1.0, block=0, cell_slack=8.0, detect_lanes=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("sdem needs a GPU: torch.cuda.is_available() is False")
@@ -151,8 +179,8 @@ class Solver:
         if contacts_max is None:
             contacts_max = int(max(4096, 8 * n))
         self.cfg = Config(max(n, 1), contacts_max, cells_max, max(ntri, 1), self.nsims,
-                          SDEM_MIXED if precision == "mixed" else SDEM_FP64, block, 0,
-                          float(cell_factor))
+                          SDEM_MIXED if precision == "mixed" else SDEM_FP64, block,
+                          int(detect_lanes), float(cell_factor))
         nbytes = L.sdem_workspace_bytes(C.byref(self.cfg))
         if nbytes == 0:
             _check(SDEM_EINVAL)
