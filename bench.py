@@ -35,6 +35,27 @@ def force_bytes(n, c):
     return 128.0 * n + 120.0 * c
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_force_cfg2_column_200k_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per contact-force launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when
+    the kernel source changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and
+                  line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"))
+    src = b"".join(open(os.path.join(ROOT, "paper_2507_12610_amd", "csrc", f), "rb").read()
+                   for f in ("kernels.hip", "sdem_internal.h"))
+    if hashlib.sha256(src).hexdigest()[:16] != fields.get("kernel_source_sha256_16", "").strip():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, budget_s=12.0, max_steps=40):
     import oracle
     o = oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"],
@@ -66,6 +87,8 @@ def main():
                     help="cell edge / (2 R_max); default: autotuned")
     ap.add_argument("--detect-lanes", type=int, default=None,
                     help="lanes per particle in the contact search; default: autotuned")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -76,6 +99,18 @@ def main():
 
     import workloads as W
     from paper_2507_12610_amd import Solver, autotune
+
+    if args.copy_calibration_mib:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel
+        # calibrate the counters read on the solver's kernels
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 copies of {nb} bytes", file=sys.stderr, flush=True)
+        del src, dst
 
     w = W.cfg2()
     n = len(w["R"])
@@ -115,7 +150,7 @@ def main():
     dominant = max(phases, key=phases.get)
     roofline = {"kernel": "k_force (contact forces, torques, spring carry-over)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "mean_ms": round(fms, 5), "algorithmic_bytes": force_bytes(n, c_prof),
                 "contacts_per_launch": round(c_prof, 1),
                 "phase_ms": {k: round(v, 5) for k, v in phases.items()},

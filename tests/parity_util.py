@@ -33,6 +33,15 @@ def force_err(Fg, Fo, scale):
     return float((d / s).max()) if len(d) else 0.0
 
 
+def torque_err(Tg, To, Tscale, Fscale, R):
+    """Per-particle torque error scaled by sum_c |torque| + (sum_c |force| +
+    m|g|) R_i: a rounding error in a force direction shows up as a torque
+    of that size even where the reference torques vanish."""
+    d = np.linalg.norm(np.asarray(Tg) - np.asarray(To), axis=1)
+    s = np.maximum(np.asarray(Tscale) + np.asarray(Fscale) * np.asarray(R), 1e-300)
+    return float((d / s).max()) if len(d) else 0.0
+
+
 def keys(c):
     return np.stack([c["ki"], c["kj"]], 1) if len(c["ki"]) else np.zeros((0, 2), np.int32)
 

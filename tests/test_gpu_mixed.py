@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.parity_util import force_err, keys, oracle_from, oracle_resync, rel, rel_w, spring_err
+from tests.parity_util import force_err, keys, torque_err, oracle_from, oracle_resync, rel, rel_w, spring_err
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,7 @@ def errors(g, o, w):
     sg, so, fo = g.state(), o.state(), o.forces()
     e = dict(spring_err(cg, co))
     e["F"] = force_err(sg["F"], fo["F"], fo["Fscale"])
-    e["T"] = force_err(sg["T"], fo["T"], fo["Tscale"])
+    e["T"] = torque_err(sg["T"], fo["T"], fo["Tscale"], fo["Fscale"], w["R"])
     e["v"] = rel(sg["v"], so["v"])
     e["w"] = rel_w(sg["w"], so["w"], w["R"], so["v"])
     e["q"] = rel(sg["q"], so["q"])

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity_util import (force_err, keys, oracle_from, oracle_resync, rel, rel_w,
+from tests.parity_util import (force_err, keys, torque_err, oracle_from, oracle_resync, rel, rel_w,
                                spring_err)
 
 pytestmark = pytest.mark.gpu
@@ -56,7 +56,7 @@ def compare_one_step(w, tol=TOL64, **skw):
     sg, so = g.state(), o.state()
     fo = o.forces()
     assert force_err(sg["F"], fo["F"], fo["Fscale"]) < tol
-    assert force_err(sg["T"], fo["T"], fo["Tscale"]) < tol
+    assert torque_err(sg["T"], fo["T"], fo["Tscale"], fo["Fscale"], w["R"]) < tol
     for k in ("v", "w", "q"):
         assert rel(sg[k], so[k]) < tol, k
     assert rel(sg["x"] - w["x"], so["x"] - w["x"]) < tol
