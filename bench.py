@@ -75,6 +75,82 @@ def cpu_baseline(w, budget_s=12.0, max_steps=40):
                       f"{total:.1f} s"}
 
 
+def sim_slice(w, st, c, lo, hi):
+    """Workload dict of particles [lo, hi) of a batched state, with its contacts
+    (keys made local) for sdem_set_history."""
+    d = dict(w)
+    d.update(x=st["x"][lo:hi].copy(), v=st["v"][lo:hi].copy(), w=st["w"][lo:hi].copy(),
+             q=st["q"][lo:hi].copy())
+    m = (c["ki"] >= lo) & (c["ki"] < hi)
+    kj = c["kj"][m]
+    hist = (c["ki"][m] - lo, kj.copy(), c["us"][m], c["ur"][m], c["ut"][m])
+    hist[1][kj > 0] -= lo
+    return d, hist
+
+
+def batched_forms(landing_steps, steps, precision_list=("fp64", "mixed")):
+    """Configuration 4: 256 box drops of uneven size in one context, timed after
+    the sims have landed, against the same 256 states stepped one simulation
+    after another (separate contexts, plain FP64), all on the GPU."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2507_12610_amd import Solver, autotune
+    sims = W.cfg4()
+    total = sum(len(s["R"]) for s in sims)
+    print(f"[bench] batched: {len(sims)} sims, {total} particles", file=sys.stderr, flush=True)
+    best, _ = autotune(sims, candidates=[(1.0, 1), (0.7, 1), (0.5, 1)], steps=10, warmup=4)
+    cf = best["cell_factor"]
+    b = Solver(sims, cell_factor=cf, detect_lanes=1)
+    b.step(landing_steps)
+    st, c = b.state(forces=False), b.contacts()
+    out = {"workload": "cfg4_256_box_drops", "sims": len(sims), "particles": total,
+           "landing_steps": landing_steps, "steps": steps, "cell_factor": cf}
+    res = {}
+    for prec in precision_list:
+        parts = [sim_slice(sims[k], st, c, b.offsets[k], b.offsets[k + 1])
+                 for k in range(len(sims))]
+        g = Solver([p[0] for p in parts], precision=prec, cell_factor=cf, detect_lanes=1)
+        g.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])
+        g.step(2)
+        torch.cuda.synchronize()
+        s0 = g.stats()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s1 = g.stats()
+        cont = (s1["pp"] - s0["pp"]) + (s1["pw"] - s0["pw"])
+        res[prec] = {"ms_per_step": 1e3 * dt / steps, "particle_steps_per_s": total * steps / dt,
+                     "contacts_per_s": cont / dt, "contacts_per_step": cont / steps}
+        g.close()
+    # the same 256 states, one simulation after another (plain FP64)
+    seq = []
+    for k in range(len(sims)):
+        d, h = sim_slice(sims[k], st, c, b.offsets[k], b.offsets[k + 1])
+        g = Solver(d, cell_factor=cf, detect_lanes=1)
+        g.set_history(*h)
+        seq.append(g)
+    for g in seq:
+        g.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in seq:
+        g.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for g in seq:
+        g.close()
+    res["sequential_fp64"] = {"ms_per_step": 1e3 * dt / steps,
+                              "particle_steps_per_s": total * steps / dt}
+    for prec in precision_list:
+        res[prec]["speedup_vs_sequential_fp64"] = (res["sequential_fp64"]["ms_per_step"] /
+                                                   res[prec]["ms_per_step"])
+    out.update(res)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +163,10 @@ def main():
                     help="cell edge / (2 R_max); default: autotuned")
     ap.add_argument("--detect-lanes", type=int, default=None,
                     help="lanes per particle in the contact search; default: autotuned")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision and batched forms")
+    ap.add_argument("--batch-landing-steps", type=int, default=1500)
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -173,6 +253,23 @@ def main():
            "roofline": roofline}
     if tuned is not None:
         out["autotune"] = tuned
+    if not args.no_forms:
+        forms = {}
+        other = "mixed" if args.precision == "fp64" else "fp64"
+        g = Solver(w, precision=other, device="cuda:0", cell_factor=cf, detect_lanes=lanes)
+        g.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(args.steps)
+        torch.cuda.synchronize()
+        ms_other = 1e3 * (time.perf_counter() - t0) / args.steps
+        g.close()
+        forms[other] = {"workload": w["name"], "ms_per_step": round(ms_other, 5),
+                        "particle_steps_per_s": round(n * 1e3 / ms_other, 1),
+                        "speedup_vs_" + args.precision: round(ms_per_step / ms_other, 4),
+                        "tolerance": 1e-5 if other == "mixed" else 1e-12}
+        forms["batched"] = batched_forms(args.batch_landing_steps, args.batch_steps)
+        out["forms"] = forms
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

@@ -245,8 +245,9 @@ def cfg3(seed=303, n=2_000_000, phi_rsa=0.36, shrink=0.92):
 def cfg4_sim(s, n_s, seed=404):
     """One simulation of the batched sweep: a 'box drop' of n_s spheres,
     R ~ U[0.8, 1.2] mm, on an n x n lattice of pitch 2.5 mm (n = ceil(n_s^1/3))
-    layered upward from mid-height of a 12-triangle cube of side 5n mm,
-    horizontally centred; mu_s = 0.1 + 0.8 s/255, mu_r = mu_t = 0.1."""
+    layered upward from 1.5 mm above the floor of a 12-triangle cube of side
+    5n mm, horizontally centred, so the layers land one after another within
+    the first ~1,500 steps; mu_s = 0.1 + 0.8 s/255, mu_r = mu_t = 0.1."""
     rng = np.random.Generator(np.random.PCG64(404_000 + s))
     nl = int(math.ceil(n_s ** (1.0 / 3.0) - 1e-9))
     Ls = 5.0 * nl * MM
@@ -254,7 +255,7 @@ def cfg4_sim(s, n_s, seed=404):
     k = np.arange(n_s)
     ix, iy, iz = k % nl, (k // nl) % nl, k // (nl * nl)
     off = (Ls - (nl - 1) * 2.5 * MM) / 2.0
-    x = np.stack([off + ix * 2.5 * MM, off + iy * 2.5 * MM, Ls / 2 + iz * 2.5 * MM], axis=1)
+    x = np.stack([off + ix * 2.5 * MM, off + iy * 2.5 * MM, 1.5 * MM + iz * 2.5 * MM], axis=1)
     tri = cube_mesh([0, 0, 0], [Ls] * 3)
     p = default_params(dt=dt_eq(0.8 * MM, 2500.0, 1e6, 0.3), mu_s=0.1 + 0.8 * s / 255.0)
     return _finish(f"cfg4_sim{s}", p, x, R, rng, tri, 5000, R_max=1.2 * MM)
