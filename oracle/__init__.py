@@ -108,6 +108,8 @@ def lib():
         L.orc_get_mesh.argtypes = [C.c_void_p, _D]
         L.orc_sample_step.argtypes = [C.c_void_p, C.c_int64, _I64, _D, _D, _D, _D, _I64, _D, _D,
                                       _D, _D]
+        L.orc_sample_keys.restype = C.c_int64
+        L.orc_sample_keys.argtypes = [C.c_void_p, C.c_int64, _I64, C.c_int64, _I64, _I32, _I32]
         L.orc_contact_keys.restype = C.c_int64
         L.orc_contact_keys.argtypes = [C.c_void_p, C.c_int64, _I32, _I32]
         _lib = L
@@ -295,6 +297,23 @@ class Sim:
         kj = np.zeros(max(n, 1), np.int32)
         lib().orc_contact_keys(self._h, n, ki.ctypes.data_as(_I32), kj.ctypes.data_as(_I32))
         return ki[:n], kj[:n]
+
+    def sample_keys(self, idx):
+        """Keys of every contact each listed particle takes part in, at the
+        current state: (ki, kj, counts), one particle after another, each in
+        key order."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        cnt = np.zeros(len(idx), np.int64)
+        tot = lib().orc_sample_keys(self._h, len(idx), idx.ctypes.data_as(_I64), 0,
+                                    cnt.ctypes.data_as(_I64), None, None)
+        if tot < 0:
+            raise IndexError("sample index out of range")
+        ki = np.zeros(max(tot, 1), np.int32)
+        kj = np.zeros(max(tot, 1), np.int32)
+        lib().orc_sample_keys(self._h, len(idx), idx.ctypes.data_as(_I64), tot,
+                              cnt.ctypes.data_as(_I64), ki.ctypes.data_as(_I32),
+                              kj.ctypes.data_as(_I32))
+        return ki[:tot], kj[:tot], cnt
 
     def sample_step(self, idx):
         """Net force/torque on each listed particle at the current state and

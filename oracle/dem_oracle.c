@@ -853,6 +853,65 @@ int64_t orc_contact_keys(orc_sim* s, int64_t cap, int32_t* ki, int32_t* kj) {
   return nc;
 }
 
+int64_t orc_sample_keys(orc_sim* s, int64_t ns, const int64_t* idx, int64_t cap, int64_t* cnt,
+                        int32_t* ki, int32_t* kj) {
+  if (s->n > 0) build_cells(s);
+  int32_t saved_mode = s->search_mode;
+  s->search_mode = 1;
+  int64_t* nb = NULL;
+  int64_t nbcap = 0, total = 0;
+  for (int64_t a = 0; a < ns; ++a) {
+    int64_t p = idx[a];
+    if (p < 0 || p >= s->n) {
+      s->search_mode = saved_mode;
+      free(nb);
+      return -1;
+    }
+    int64_t c0 = total;
+    int64_t nn = neighbours(s, p, 0, &nb, &nbcap);
+    /* key order: pairs (j, p) with j < p, then (p, -m) for m descending,
+     * then pairs (p, j) with j > p */
+    for (int pass = 0; pass < 3; ++pass) {
+      if (pass == 1) {
+        for (int64_t m = s->ntri - 1; m >= 0; --m) {
+          const double* t = s->tri + 9 * m;
+          double cp[3], dv[3];
+          orc_closest_point_triangle(s->x + 3 * p, t, t + 3, t + 6, cp);
+          sub3(s->x + 3 * p, cp, dv);
+          double d = sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
+          if ((s->R[p] + s->rmesh[m]) - d >= 0.0) {
+            if (total < cap) {
+              ki[total] = (int32_t)p;
+              kj[total] = (int32_t)-m;
+            }
+            ++total;
+          }
+        }
+        continue;
+      }
+      for (int64_t b = 0; b < nn; ++b) {
+        int64_t j = nb[b];
+        if ((pass == 0) != (j < p)) continue;
+        int64_t i0 = j < p ? j : p, j0 = j < p ? p : j;
+        double dv[3];
+        sub3(s->x + 3 * i0, s->x + 3 * j0, dv);
+        double d = sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
+        if ((s->R[i0] + s->R[j0]) - d >= 0.0) {
+          if (total < cap) {
+            ki[total] = (int32_t)i0;
+            kj[total] = (int32_t)j0;
+          }
+          ++total;
+        }
+      }
+    }
+    if (cnt) cnt[a] = total - c0;
+  }
+  free(nb);
+  s->search_mode = saved_mode;
+  return total;
+}
+
 int orc_sample_step(orc_sim* s, int64_t ns, const int64_t* idx, double* F, double* T,
                     double* Fscale, double* Tscale, int64_t* ncont, double* x1, double* v1,
                     double* w1, double* q1) {

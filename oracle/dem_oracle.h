@@ -119,6 +119,14 @@ int orc_sample_step(orc_sim* s, int64_t ns, const int64_t* idx, double* F, doubl
                     double* Fscale, double* Tscale, int64_t* ncont, double* x1, double* v1,
                     double* w1, double* q1);
 
+/* Contact keys of listed particles at the current state (Section 3.3
+ * definition; linked-cell search for pairs, every triangle for walls): for
+ * each idx[a], the keys of all contacts it takes part in, in key order,
+ * written one particle after another (up to cap in total); cnt[a] receives
+ * the particle's count.  Returns the total, or -1 on an index out of range. */
+int64_t orc_sample_keys(orc_sim* s, int64_t ns, const int64_t* idx, int64_t cap, int64_t* cnt,
+                        int32_t* ki, int32_t* kj);
+
 /* Contact set only (Section 3.3 definition): writes up to cap keys, returns
  * the total number of contacts of the current state. */
 int64_t orc_contact_keys(orc_sim* s, int64_t cap, int32_t* ki, int32_t* kj);

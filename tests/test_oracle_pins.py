@@ -624,6 +624,49 @@ def test_contact_set_brute_force_and_cells(seed):
         assert np.array_equal(order, np.arange(len(ki)))
 
 
+def test_sampled_keys_are_the_brute_force_set_per_particle():
+    """The per-particle key lists used for full-size checks are the
+    brute-force contact set restricted to each listed particle, in key
+    order (Section 3.3 contact definition)."""
+    w = W.random_cluster(300, 4, box=20e-3, overlap=0.2, r_lo=0.5e-3, r_hi=1.5e-3)
+    tri = W.cube_mesh([0.3e-3] * 3, [19.7e-3] * 3)
+    s = O.Sim(P(), w["x"], R=w["R"], tri=tri)
+    ref = reference_contact_set(w["x"], w["R"], tri)
+    idx = np.arange(300)[::-1]
+    ki, kj, cnt = s.sample_keys(idx)
+    assert cnt.sum() == len(ki) > 200
+    pos = 0
+    for a, p in enumerate(idx):
+        mine = sorted(k for k in ref if k[0] == p or (k[1] > 0 and k[1] == p))
+        got = list(zip(ki[pos:pos + cnt[a]].tolist(), kj[pos:pos + cnt[a]].tolist()))
+        assert got == mine, p
+        pos += cnt[a]
+
+
+def test_sampled_step_equals_the_full_step():
+    """The sampled one-step evaluation gives each listed particle the net
+    force, torque and next state of a full step (Section 2.3 forces with the
+    carried springs, Section 2.1 integration), here after 30 steps so that
+    the springs are loaded and some contacts are kinetic."""
+    tri = W.cube_mesh([-0.2e-3] * 3, [14.2e-3] * 3)
+    w = W.random_cluster(200, 7, box=14e-3, tri=tri)
+    s = O.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"], tri=tri)
+    s.step(30)
+    assert len(s.contacts()["ki"]) > 100
+    idx = np.array([0, 3, 50, 99, 150, 199])
+    smp = s.sample_step(idx)
+    s.step(1)
+    f, st = s.forces(), s.state()
+    for k, key in (("F", "Fscale"), ("T", "Tscale")):
+        d = np.linalg.norm(smp[k] - f[k][idx], axis=1)
+        sc = f[key][idx] + (f["Fscale"][idx] * w["R"][idx] if k == "T" else 0.0)
+        assert np.all(d <= 1e-13 * sc), k
+    assert np.array_equal(smp["ncont"] > 0, np.linalg.norm(f["F"][idx], axis=1) > 0)
+    for k in ("x", "v", "w", "q"):
+        sc = np.abs(st[k]).max()
+        assert np.abs(smp[k] - st[k][idx]).max() <= 1e-13 * sc, k
+
+
 def test_contact_set_edge_cases():
     # exactly touching (delta = 0) counts; a hair apart does not
     s = O.Sim(P(), [[0, 0, 0], [2e-3, 0, 0], [4e-3 + 1e-12, 0, 0]], R=[1e-3, 1e-3, 1e-3])

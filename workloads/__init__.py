@@ -218,26 +218,43 @@ def cfg2(seed=202, n=200_000, phi_rsa=0.35, shrink=0.93):
     return _finish("cfg2_column_collapse_200k", default_params(dt=5e-7), x, R, rng, tri, 20000)
 
 
-def cfg3(seed=303, n=2_000_000, phi_rsa=0.36, shrink=0.92):
+def fcc_sites(lo, hi, a_nn):
+    """Face-centred cubic lattice sites (nearest-neighbour distance a_nn)
+    inside the box [lo, hi], in (k, j, i, basis) generation order."""
+    a = a_nn * math.sqrt(2.0)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    cnt = np.floor((hi - lo) / a).astype(np.int64) + 1
+    g = np.stack(np.meshgrid(np.arange(cnt[0]), np.arange(cnt[1]), np.arange(cnt[2]),
+                             indexing="ij"), axis=-1).reshape(-1, 3)
+    basis = np.array([[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]])
+    pts = (lo + a * (g[:, None, :] + basis[None, :, :])).reshape(-1, 3)
+    inside = np.all((pts >= lo) & (pts <= hi), axis=1)
+    return pts[inside]
+
+
+def cfg3(seed=303, n=2_000_000, a_nn=2.22 * MM, jitter=0.005 * MM):
     """2,000,000 spheres, R ~ U[0.9, 1.1] mm, in a rotating drum (radius
-    0.15 m, axis y, length 0.40 m, 8,192 triangles, 1 rad/s), filled to the
-    level needed by random sequential addition below the axis region;
-    dt from Eq. dt at R_min = 0.9 mm."""
+    0.15 m, axis y, length 0.40 m, 8,192 triangles, 1 rad/s about y through
+    the origin); dt from Eq. dt at R_min = 0.9 mm.
+
+    Start: the n lowest sites of a face-centred cubic lattice (nearest
+    neighbours 2.22 mm apart, +-0.005 mm jitter per coordinate, so no two
+    spheres touch) that lie at least R_max + 0.05 mm inside the drum's
+    polygonal shell and end caps; zero velocity, random orientation.  The bed
+    fills about half the drum and settles onto the shell within ~50 steps."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    Rd, Ld, nseg = 0.15, 0.40, 128
     R = rng.uniform(0.9 * MM, 1.1 * MM, n)
-    Rd, Ld = 0.15, 0.40
-    vol = float(np.sum(4.0 / 3.0 * np.pi * (shrink * R) ** 3))
-    # fill height: the circular segment below z = zf holds vol/phi_rsa
-    target = vol / (phi_rsa * (Ld - 4 * MM))
-    lo_z, hi_z = -Rd, Rd
-    for _ in range(80):
-        zf = 0.5 * (lo_z + hi_z)
-        a = math.acos(max(-1.0, min(1.0, -zf / Rd)))
-        area = Rd * Rd * (a - math.sin(a) * math.cos(a))
-        lo_z, hi_z = (zf, hi_z) if area < target else (lo_z, zf)
-    x = rsa_place(shrink * R, [-Rd, -Ld / 2 + 2 * MM, -Rd], [Rd, Ld / 2 - 2 * MM, zf], seed,
-                  shape=1, cyl=(0.0, 0.0, Rd - 1.5 * MM, zf))
-    tri = drum_mesh(Rd, Ld)
+    clear = 1.1 * MM + 0.05 * MM
+    r_in = Rd * math.cos(math.pi / nseg) - clear  # inscribed radius of the shell
+    pts = fcc_sites([-r_in, -Ld / 2 + clear, -r_in], [r_in, Ld / 2 - clear, r_in], a_nn)
+    pts = pts[pts[:, 0] ** 2 + pts[:, 2] ** 2 <= r_in * r_in]
+    if len(pts) < n:
+        raise ValueError(f"the drum holds {len(pts)} lattice sites, fewer than {n}")
+    pts = pts[np.argsort(pts[:, 2], kind="stable")[:n]]
+    x = pts + rng.uniform(-jitter, jitter, (n, 3))
+    tri = drum_mesh(Rd, Ld, nseg)
     p = default_params(dt=dt_eq(0.9 * MM, 2500.0, 1e6, 0.3), mesh_omega=(0.0, 1.0, 0.0))
     return _finish("cfg3_rotating_drum_2M", p, x, R, rng, tri, 2000, R_max=1.1 * MM)
 
@@ -269,17 +286,26 @@ def cfg4(nsims=256, seed=404, sizes=None):
     return [cfg4_sim(s, int(sizes[s]), seed) for s in range(nsims)]
 
 
-def cfg5(seed=505, n=8_000_000, phi_rsa=0.38, shrink=0.85):
-    """8,000,000 spheres, half R = 1.0 mm and half 1.4 mm (seeded shuffle), a
-    dense packing in a closed 12-triangle cube: random sequential addition at
-    shrunk radii, then the true radii (packing fraction ~0.62); full
-    friction, g on, eta = 0, dt from Eq. dt at 1.0 mm."""
+def cfg5(seed=505, n=8_000_000, pitch=2.38 * MM, jitter=0.004 * MM):
+    """8,000,000 spheres, half R = 1.0 mm and half 1.4 mm, a pre-compressed
+    packing in a closed 12-triangle cube; full friction, g on, eta = 0, dt
+    from Eq. dt at 1.0 mm, 10,000 relaxation steps.
+
+    Start: a rock-salt arrangement on a simple cubic lattice of pitch 2.38 mm
+    (k^3 sites, k = ceil(n^1/3), the first n in (z, y, x) order), large
+    spheres where i + j + k is even, +-0.004 mm jitter per coordinate.  Every
+    face-neighbour pair is large-small and overlaps by 0.02 +- 0.01 mm; the
+    next shells are out of reach, so each sphere starts with exactly six
+    contacts (coordination number 6).  The walls sit 1.39 mm beyond the
+    outermost centres (large spheres there overlap them by 0.01 mm)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    R = np.where(rng.permutation(n) < n // 2, 1.0 * MM, 1.4 * MM)
-    vol = float(np.sum(4.0 / 3.0 * np.pi * (shrink * R) ** 3))
-    L = (vol / phi_rsa) ** (1.0 / 3.0)
-    x = rsa_place(shrink * R, [0.0, 0.0, 0.0], [L, L, L], seed)
-    tri = cube_mesh([-0.5 * MM] * 3, [L + 0.5 * MM] * 3)
+    k1 = int(math.ceil(n ** (1.0 / 3.0) - 1e-9))
+    idx = np.arange(n, dtype=np.int64)
+    i, j, k = idx % k1, (idx // k1) % k1, idx // (k1 * k1)
+    R = np.where((i + j + k) % 2 == 0, 1.4 * MM, 1.0 * MM)
+    x = np.stack([i, j, k], axis=1) * pitch + rng.uniform(-jitter, jitter, (n, 3))
+    top = (k1 - 1) * pitch
+    tri = cube_mesh([-1.39 * MM] * 3, [top + 1.39 * MM] * 3)
     p = default_params(dt=dt_eq(1.0 * MM, 2500.0, 1e6, 0.3))
     return _finish("cfg5_dense_packing_8M", p, x, R, rng, tri, 10000, R_max=1.4 * MM)
 
