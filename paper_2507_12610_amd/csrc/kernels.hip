@@ -460,6 +460,109 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all) {
   }
 }
 
+// Triangle bins (the triangle side of the broad phase): count, scan, fill and
+// sort the (bin, triangle) pairs.  A triangle enters every bin of its grid
+// that its vertex bounding box, grown by R_max + R_m of its simulation,
+// overlaps; the margin on the growth covers rounding of the box ends, so a
+// particle centre within R_i + R_m of the triangle lies in one of them.
+__device__ __forceinline__ void tri_bins(const Ctx& c, int m, const MeshGrid& G, int i0[3],
+                                         int i1[3]) {
+  const double* t = c.tri + 9 * m;
+  const double reach = (c.sp[c.tri_sim[m]].rmax + c.rmesh[m]) * (1.0 + 1e-9);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double a = t[k], b = t[3 + k], e = t[6 + k];
+    const double mn = fmin(a, fmin(b, e)), mx = fmax(a, fmax(b, e));
+    const double pad = reach + 1e-12 * (fabs(mn) + fabs(mx));
+    const double f0 = ((mn - pad) - G.lo[k]) * G.inv_h;
+    const double f1 = ((mx + pad) - G.lo[k]) * G.inv_h;
+    const int d = G.dim[k];
+    i0[k] = f0 <= 0.0 ? 0 : (f0 >= (double)d ? d - 1 : (int)f0);
+    i1[k] = f1 <= 0.0 ? 0 : (f1 >= (double)d ? d - 1 : (int)f1);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bin_count(Ctx c) {
+  if (c.ctr->flags) return;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= c.ntri) return;
+  const MeshGrid G = c.mg[c.tri_sim[m]];
+  int i0[3], i1[3];
+  tri_bins(c, m, G, i0, i1);
+  for (int z = i0[2]; z <= i1[2]; ++z)
+    for (int y = i0[1]; y <= i1[1]; ++y)
+      for (int x = i0[0]; x <= i1[0]; ++x)
+        atomicAdd(&c.bin_cnt[G.off + (z * G.dim[1] + y) * G.dim[0] + x], 1);
+}
+
+// Exclusive scan of the bin counts by one workgroup (a contiguous run of
+// bins per thread); clears the counts for the fill.
+__global__ __launch_bounds__(kBinScanThreads) void k_bin_scan(Ctx c) {
+  if (c.ctr->flags) return;
+  __shared__ int wsum[kBinScanThreads / 64];
+  const int nb = c.nbins;
+  const int per = (nb + kBinScanThreads - 1) / kBinScanThreads;
+  const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += c.bin_cnt[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int incl = wave_incl_scan(sum, lane);
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    int v = lane < kBinScanThreads / 64 ? wsum[lane] : 0;
+    v = wave_incl_scan(v, lane);
+    if (lane < kBinScanThreads / 64) wsum[lane] = v;
+  }
+  __syncthreads();
+  int run = (incl - sum) + (w > 0 ? wsum[w - 1] : 0);
+  for (int b = b0; b < b1; ++b) {
+    const int k = c.bin_cnt[b];
+    c.bin_start[b] = run;
+    c.bin_cnt[b] = 0;
+    run += k;
+  }
+  if (threadIdx.x == kBinScanThreads - 1) {
+    c.bin_start[nb] = run;
+    if (run > c.cap_bin_entries) raise_flag(c.ctr, kFlagCapBins);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bin_fill(Ctx c) {
+  if (c.ctr->flags) return;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= c.ntri) return;
+  const MeshGrid G = c.mg[c.tri_sim[m]];
+  int i0[3], i1[3];
+  tri_bins(c, m, G, i0, i1);
+  for (int z = i0[2]; z <= i1[2]; ++z)
+    for (int y = i0[1]; y <= i1[1]; ++y)
+      for (int x = i0[0]; x <= i1[0]; ++x) {
+        const int b = G.off + (z * G.dim[1] + y) * G.dim[0] + x;
+        const int pos = c.bin_start[b] + atomicAdd(&c.bin_cnt[b], 1);
+        if (pos < c.cap_bin_entries) c.bin_tri[pos] = m;
+      }
+}
+
+// Ascending triangle order within each bin (the fill order is arbitrary), so
+// that the narrow phase visits triangles in the same order every run.
+__global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
+  if (c.ctr->flags) return;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= c.nbins) return;
+  const int s0 = c.bin_start[b], s1 = c.bin_start[b + 1];
+  for (int i = s0 + 1; i < s1; ++i) {
+    const int v = c.bin_tri[i];
+    int j = i - 1;
+    while (j >= s0 && c.bin_tri[j] > v) {
+      c.bin_tri[j + 1] = c.bin_tri[j];
+      --j;
+    }
+    c.bin_tri[j + 1] = v;
+  }
+  c.bin_cnt[b] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // 5. narrow phase (Section 3.3), one pass.  SUB adjacent lanes share one
 //    particle slot s and split its search (every SUB-th triangle of its
@@ -486,11 +589,23 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
   if (s < n) {
     const int sim = c.sim_of[s];
     const SimGrid gr = c.sg[sim];
-    const int tri0 = c.sp[sim].tri0, ntri = c.sp[sim].ntri;
     const double4 ps = S.xr[s];
     const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
-    // ---- triangles
-    for (int m = tri0 + sub; m < tri0 + ntri; m += SUB) {
+    // ---- triangles listed in the bin of x_s
+    int k0 = 0, k1 = 0;
+    if (c.sp[sim].ntri > 0) {
+      const MeshGrid G = c.mg[sim];
+      const double fx = (xs - G.lo[0]) * G.inv_h, fy = (ys - G.lo[1]) * G.inv_h,
+                   fz = (zs - G.lo[2]) * G.inv_h;
+      if (fx >= 0.0 && fy >= 0.0 && fz >= 0.0 && fx < (double)G.dim[0] &&
+          fy < (double)G.dim[1] && fz < (double)G.dim[2]) {
+        const int b = G.off + ((int)fz * G.dim[1] + (int)fy) * G.dim[0] + (int)fx;
+        k0 = c.bin_start[b];
+        k1 = c.bin_start[b + 1];
+      }
+    }
+    for (int k = k0 + sub; k < k1; k += SUB) {
+      const int m = c.bin_tri[k];
       const double* pl = c.tri_pl + 4 * m;
       const double reach = Rs + c.rmesh[m];
       const double pd = (pl[0] * xs + pl[1] * ys + pl[2] * zs) - pl[3];
@@ -1088,7 +1203,10 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
   }
   k_scatter<<<nbp, kThreads, 0, s>>>(c);
   k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B);
-  if (c.any_rotating) k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
+  if (c.any_rotating) {
+    k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
+    (void)launch_mesh_bins(c, s);
+  }
   if (ev) (void)hipEventRecord(ev[2], s);
   switch (c.detect_sub) {
     case 1: k_detect<1><<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
@@ -1123,6 +1241,16 @@ hipError_t launch_pack_state(const Ctx& c, const State& S, const double* x, cons
 
 hipError_t launch_mesh_planes(const Ctx& c, hipStream_t s) {
   if (c.ntri > 0) k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_bins(const Ctx& c, hipStream_t s) {
+  if (c.ntri > 0 && c.nbins > 0) {
+    k_bin_count<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c);
+    k_bin_scan<<<1, kBinScanThreads, 0, s>>>(c);
+    k_bin_fill<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c);
+    k_bin_sort<<<blocks_for(c.nbins, kThreads), kThreads, 0, s>>>(c);
+  }
   return hipGetLastError();
 }
 

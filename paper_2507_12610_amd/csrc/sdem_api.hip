@@ -54,6 +54,15 @@ int64_t nchunks_max(const sdem_config& c) {
   return (c.n_max + kBboxChunk - 1) / kBboxChunk + c.nsims_max;
 }
 
+// Triangle bin tables sized from tri_max: 32 bins and 256 (bin, triangle)
+// entries per triangle, within fixed ceilings.
+int64_t bins_cap(const sdem_config& c) {
+  return c.tri_max > 0 ? std::min<int64_t>(std::max<int64_t>(4096, 32 * c.tri_max), 1 << 22) : 0;
+}
+int64_t bin_entries_cap(const sdem_config& c) {
+  return c.tri_max > 0 ? std::min<int64_t>(256 * c.tri_max + 4096, 1 << 27) : 0;
+}
+
 }  // namespace
 
 struct sdem_ctx {
@@ -121,6 +130,10 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.tri_pl = L.take<double>(4 * M);
   cc.rmesh = L.take<double>(M);
   cc.tri_sim = L.take<int32_t>(M);
+  cc.mg = L.take<MeshGrid>(S);
+  cc.bin_cnt = L.take<int32_t>((size_t)std::max<int64_t>(bins_cap(cfg), 1));
+  cc.bin_start = L.take<int32_t>((size_t)bins_cap(cfg) + 1);
+  cc.bin_tri = L.take<int32_t>((size_t)std::max<int64_t>(bin_entries_cap(cfg), 1));
   for (int b = 0; b < 2; ++b) {
     State s{};
     s.xr = L.take<double4>(N);
@@ -405,6 +418,99 @@ int sdem_init(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params,
                          hip_stream);
 }
 
+// Bin grid of one simulation's mesh.  The grid spans the vertex bounding box
+// grown by reach = R_max + max R_m (a static mesh) or the ball that holds the
+// mesh at every rotation angle about its centre (a rotating one).  The bin
+// edge starts at the larger of 2 reach and half the median triangle extent
+// and grows until the bins, and a bound on the (bin, triangle) entries that
+// holds at any orientation, fit this simulation's share of the tables.
+static MeshGrid mesh_grid(const std::vector<double>& tri, const std::vector<double>& rm,
+                          double rmax, bool rotating, const double* ctr, int64_t bins_budget,
+                          int64_t entries_budget, int32_t off) {
+  MeshGrid G{};
+  const size_t nt = rm.size();
+  double rmesh_max = 0.0;
+  for (double r : rm) rmesh_max = std::max(rmesh_max, r);
+  const double reach = (rmax + rmesh_max) * (1.0 + 1e-6);
+  double lo[3], hi[3];
+  if (rotating) {
+    double rv = 0.0;
+    for (size_t k = 0; k < 3 * nt; ++k) {
+      const double* v = tri.data() + 3 * k;
+      const double dx = v[0] - ctr[0], dy = v[1] - ctr[1], dz = v[2] - ctr[2];
+      rv = std::max(rv, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = ctr[a] - (rv + reach);
+      hi[a] = ctr[a] + (rv + reach);
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = HUGE_VAL;
+      hi[a] = -HUGE_VAL;
+    }
+    for (size_t k = 0; k < 3 * nt; ++k)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], tri[3 * k + a] - reach);
+        hi[a] = std::max(hi[a], tri[3 * k + a] + reach);
+      }
+  }
+  double span[3], smax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double pad = 1e-6 * (hi[a] - lo[a]) + 1e-9 * (fabs(lo[a]) + fabs(hi[a])) + 1e-12;
+    lo[a] -= pad;
+    hi[a] += pad;
+    span[a] = hi[a] - lo[a];
+    smax = std::max(smax, span[a]);
+  }
+  // per triangle: largest vertex distance from the centroid (rotation
+  // invariant) and largest box edge
+  std::vector<double> rb(nt), ext(nt);
+  for (size_t m = 0; m < nt; ++m) {
+    const double* t = tri.data() + 9 * m;
+    double c3[3], e = 0.0, r = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      c3[a] = (t[a] + t[3 + a] + t[6 + a]) / 3.0;
+      const double mn = std::min(t[a], std::min(t[3 + a], t[6 + a]));
+      const double mx = std::max(t[a], std::max(t[3 + a], t[6 + a]));
+      e = std::max(e, mx - mn);
+    }
+    for (int v = 0; v < 3; ++v) {
+      const double dx = t[3 * v] - c3[0], dy = t[3 * v + 1] - c3[1], dz = t[3 * v + 2] - c3[2];
+      r = std::max(r, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    rb[m] = r * (1.0 + 1e-6) + (rmax + rm[m]) * (1.0 + 1e-6);
+    ext[m] = e;
+  }
+  std::vector<double> es = ext;
+  std::nth_element(es.begin(), es.begin() + es.size() / 2, es.end());
+  double h = std::max({2.0 * reach, 0.5 * es[es.size() / 2], smax * 1e-6});
+  for (int it = 0; it < 400; ++it, h *= 1.25) {
+    int64_t dims[3], bins = 1;
+    for (int a = 0; a < 3; ++a) {
+      dims[a] = (int64_t)floor(span[a] / h) + 1;
+      bins *= dims[a];
+    }
+    if (bins > bins_budget) continue;
+    int64_t entries = 0;
+    for (size_t m = 0; m < nt && entries <= entries_budget; ++m) {
+      int64_t per = 1;
+      for (int a = 0; a < 3; ++a) per *= std::min<int64_t>(dims[a], (int64_t)floor(2.0 * rb[m] / h) + 2);
+      entries += per;
+    }
+    if (entries > entries_budget) continue;
+    for (int a = 0; a < 3; ++a) {
+      G.lo[a] = lo[a];
+      G.dim[a] = (int32_t)dims[a];
+    }
+    G.inv_h = 1.0 / h;
+    G.off = off;
+    return G;
+  }
+  G.dim[0] = 0;  // no grid fits (cannot happen for budgets >= 8 per triangle)
+  return G;
+}
+
 int sdem_add_mesh(sdem_ctx* X, int32_t sim, int64_t ntri, const double* tri, const double* rmesh) {
   if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
   if (X->stepped) return fail(SDEM_ESTATE, "meshes are fixed once stepping has started");
@@ -445,8 +551,36 @@ int sdem_add_mesh(sdem_ctx* X, int32_t sim, int64_t ntri, const double* tri, con
   }
   int rc = upload_params(X);
   if (rc) return rc;
+  // triangle bins: each simulation gets a share of the tables in proportion
+  // to its triangles
+  std::vector<MeshGrid> mg(X->nsims);
+  int64_t nbins = 0;
+  const int64_t tmax = std::max<int64_t>(X->cfg.tri_max, 1);
+  for (int s = 0; s < X->nsims; ++s) {
+    const int64_t nt = (int64_t)X->mesh_r[s].size();
+    mg[s] = MeshGrid{};
+    mg[s].off = (int32_t)nbins;
+    if (!nt) continue;
+    const int64_t bb = bins_cap(X->cfg) * nt / tmax, eb = bin_entries_cap(X->cfg) * nt / tmax;
+    mg[s] = mesh_grid(X->mesh_tri[s], X->mesh_r[s], X->rmax[s], derive(X->params[s], 1.0, X->rmax[s]).rotating,
+                      X->params[s].mesh_center, std::max<int64_t>(bb, 1), eb, (int32_t)nbins);
+    if (mg[s].dim[0] <= 0) return fail(SDEM_ECAPACITY, "no triangle bin grid fits simulation %d", s);
+    nbins += (int64_t)mg[s].dim[0] * mg[s].dim[1] * mg[s].dim[2];
+  }
+  c.nbins = (int32_t)nbins;
+  c.cap_bin_entries = (int32_t)bin_entries_cap(X->cfg);
+  HIP_TRY(hipMemcpyAsync(c.mg, mg.data(), sizeof(MeshGrid) * X->nsims, hipMemcpyHostToDevice, st));
+  if (nbins) HIP_TRY(hipMemsetAsync(c.bin_cnt, 0, sizeof(int32_t) * nbins, st));
   HIP_TRY(launch_mesh_planes(c, st));
+  HIP_TRY(launch_mesh_bins(c, st));
+  Counters ctr;
+  HIP_TRY(hipMemcpyAsync(&ctr, c.ctr, sizeof ctr, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (ctr.flags & kFlagCapBins) {
+    X->failed = true;
+    return fail(SDEM_ECAPACITY, "the triangle bins overflowed their table of %d entries",
+                c.cap_bin_entries);
+  }
   return SDEM_OK;
 }
 
@@ -539,6 +673,9 @@ static int finish_steps(sdem_ctx* X, const Counters& before, int start) {
                 "step %lld: a group of %d particle slots needed %d contact records, its share "
                 "of contacts_max = %lld is %d; raise contacts_max",
                 at, kGroup, after.need_group, (long long)X->cfg.contacts_max, X->c.gcap);
+  if (after.flags & kFlagCapBins)
+    return fail(SDEM_ECAPACITY, "step %lld: the triangle bins overflowed their table of %d "
+                "entries", at, X->c.cap_bin_entries);
   if (after.flags & kFlagCapPerParticle)
     return fail(SDEM_ECAPACITY,
                 "step %lld: a particle has more than %d contacts of one kind (owned or "

@@ -19,12 +19,14 @@ constexpr int kMaxOwn = 32;         // contacts one particle may own in a step
 constexpr int kMaxRev = 32;         // contacts one particle may take part in as partner
 constexpr int kGroupShift = 8;      // contact records are allocated per group of
 constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots
+constexpr int kBinScanThreads = 1024;  // one workgroup scans the triangle bins
 
 enum : int {
   kFlagCapContacts = 1,
   kFlagCapCells = 2,
   kFlagNonFinite = 4,
   kFlagCapPerParticle = 8,
+  kFlagCapBins = 16,
 };
 
 // Per-simulation constants, derived on the host at init.
@@ -50,6 +52,17 @@ struct SimGrid {
   double inv_h;
   int32_t dim[3];
   int32_t cell_off;
+};
+
+// Per-simulation uniform grid of triangle bins, fixed at set-up.  Bin b lists
+// every triangle whose bounding box, grown by R_max + R_m, overlaps it; the
+// grid covers all such boxes (for a rotating mesh, at every angle), so a
+// particle outside it touches no triangle.
+struct MeshGrid {
+  double lo[3];
+  double inv_h;
+  int32_t dim[3];
+  int32_t off;  // first bin of this simulation in the bin tables
 };
 
 // Device-side counters and flags of a context.
@@ -95,6 +108,7 @@ struct Ctx {
   int32_t any_rotating, force_blocks;
   int32_t detect_sub;        // lanes per particle in the narrow phase (1, 2, 4, 8)
   int32_t ngroups, gcap;     // slot groups, contact records per group
+  int32_t nbins, cap_bin_entries;  // triangle bins (all sims), capacity of bin_tri
   int32_t* gcnt;             // [ngroups] contact records used by each group
   int32_t* gstat;            // [ngroups][2] pair and wall contacts of each group
   SimParams* sp;      // [nsims]
@@ -120,6 +134,10 @@ struct Ctx {
   double* tri_pl;     // [ntri][4] unit normal and offset of the plane
   double* rmesh;      // [ntri]
   int32_t* tri_sim;   // [ntri]
+  MeshGrid* mg;       // [nsims]
+  int32_t* bin_cnt;   // [nbins] zero between builds
+  int32_t* bin_start; // [nbins+1]
+  int32_t* bin_tri;   // [cap_bin_entries] triangles of each bin, ascending
   Counters* ctr;
 };
 
@@ -218,6 +236,7 @@ hipError_t launch_scatter_state(const Ctx& c, const State& S, double* x, double*
 hipError_t launch_pack_state(const Ctx& c, const State& S, const double* x, const double* v,
                              const double* w, const double* q, const double* R, hipStream_t s);
 hipError_t launch_mesh_planes(const Ctx& c, hipStream_t s);
+hipError_t launch_mesh_bins(const Ctx& c, hipStream_t s);
 hipError_t launch_selftest(int64_t n, const double* in, const double* in2, double* out,
                            hipStream_t s);
 

@@ -70,3 +70,44 @@ def spring_err(cg, co):
         out[k] = rel(cg[k], co[k])
     out["ut"] = rel(cg["ut"], co["ut"])
     return out
+
+
+def keys_per_particle(c, idx):
+    """Keys of the contacts (ki, kj arrays in key order) that each listed
+    particle takes part in, one particle after another: (ki, kj, counts)."""
+    ki, kj = np.asarray(c["ki"]), np.asarray(c["kj"])
+    idx = np.asarray(idx)
+    sel = np.isin(ki, idx) | ((kj > 0) & np.isin(kj, idx))
+    ks, js = ki[sel], kj[sel]
+    oi, oj, cnt = [], [], []
+    for p in idx:
+        m = (ks == p) | ((js > 0) & (js == p))
+        oi.append(ks[m])
+        oj.append(js[m])
+        cnt.append(int(m.sum()))
+    cat = (lambda a: np.concatenate(a) if a else np.zeros(0, np.int32))
+    return cat(oi), cat(oj), np.array(cnt, np.int64)
+
+
+def sampled_errors(g, w, st, hist, t, idx):
+    """Steps the GPU context g once from the state st / springs hist it holds
+    at time t, and checks the listed particles against the oracle's sampled
+    step from the same point: returns (keys equal, contacts of the sample,
+    dict of per-quantity errors)."""
+    o = oracle_resync(w, st, hist, t)
+    oki, okj, ocnt = o.sample_keys(idx)
+    smp = o.sample_step(idx)
+    g.step(1)
+    sg, cg = g.state(), g.contacts()
+    gki, gkj, gcnt = keys_per_particle(cg, idx)
+    same = (np.array_equal(ocnt, gcnt) and np.array_equal(oki, gki) and np.array_equal(okj, gkj))
+    R = w["R"][idx]
+    err = {
+        "F": force_err(sg["F"][idx], smp["F"], smp["Fscale"]),
+        "T": torque_err(sg["T"][idx], smp["T"], smp["Tscale"], smp["Fscale"], R),
+        "x": rel(sg["x"][idx], smp["x"]),
+        "v": rel(sg["v"][idx], smp["v"]),
+        "q": rel(sg["q"][idx], smp["q"]),
+        "w": rel_w(sg["w"][idx], smp["w"], R, smp["v"]),
+    }
+    return same, int(ocnt.sum()), err

@@ -8,17 +8,25 @@ autotuner for the column, 1.0 as the reference stencil).
   springs).
 * 256 uneven box drops in one context: after 1,500 steps (all landed), eight
   simulations re-synced and compared one step later.
+* 2,000,000 spheres in the rotating 8,192-triangle drum, FP64 and mixed
+  precision: after 600 steps (the bed has landed on the shell), the oracle
+  restarted from the GPU state and springs evaluates one step for sampled
+  particles (half of them in contact): their contact keys bit for bit, and
+  their force, torque and next state.
+* 8,000,000 spheres in the pre-compressed packing, FP64 and mixed: the same
+  sampled check at the first step and again after 50 steps.
 """
 import numpy as np
 import pytest
 
 import workloads as W
 from tests.parity_util import (force_err, keys, oracle_from, oracle_resync, rel, rel_w,
-                               spring_err, torque_err)
+                               sampled_errors, spring_err, torque_err)
 
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
+TOL32 = 1e-5
 
 
 def solver(w, **kw):
@@ -97,3 +105,62 @@ def test_batch_256_after_landing():
         fo = o.forces()
         assert force_err(sg["F"][lo:hi], fo["F"], fo["Fscale"]) < TOL64, k
     assert total > 1000
+
+
+def sample_ids(n, c, seed, k=3000):
+    """k random particles, k random particles in contact, and the ends."""
+    rng = np.random.default_rng(seed)
+    touched = np.unique(np.concatenate([c["ki"], c["kj"][c["kj"] > 0]])) if len(c["ki"]) else []
+    pick = [rng.choice(n, k, replace=False)]
+    if len(touched):
+        pick.append(rng.choice(touched, min(k, len(touched)), replace=False))
+    return np.unique(np.concatenate(pick + [[0, n - 1]])).astype(np.int64)
+
+
+@pytest.fixture(scope="module")
+def drum():
+    return W.cfg3()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", TOL32)])
+def test_drum_2M_sampled(drum, precision, tol):
+    w = drum
+    g = solver(w, precision=precision, cell_factor=0.5, detect_lanes=1)
+    k = 600
+    g.step(k)
+    st, c = g.state(forces=False), g.contacts()
+    assert (c["kj"] <= 0).sum() > 10_000  # the bed rests on the shell
+    idx = sample_ids(len(w["R"]), c, 3)
+    same, nc, err = sampled_errors(g, w, st, c, k * w["params"]["dt"], idx)
+    print(precision, "sampled contacts", nc, {q: f"{e:.2e}" for q, e in err.items()})
+    assert same
+    assert nc > 3000
+    assert max(err.values()) < tol, err
+
+
+@pytest.fixture(scope="module")
+def packing():
+    return W.cfg5()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", TOL32)])
+def test_packing_8M_sampled(packing, precision, tol):
+    w = packing
+    n = len(w["R"])
+    g = solver(w, precision=precision, cell_factor=1.0, detect_lanes=1)
+    empty = {"ki": np.zeros(0, np.int32), "kj": np.zeros(0, np.int32)}
+    idx = sample_ids(n, empty, 5)
+    st0 = {k: w[k] for k in ("x", "v", "w", "q")}
+    same, nc, err = sampled_errors(g, w, st0, empty, 0.0, idx)
+    print(precision, "step 1 sampled contacts", nc, {q: f"{e:.2e}" for q, e in err.items()})
+    assert same and nc >= 5 * len(idx)
+    assert max(err.values()) < tol, err
+    g.step(49)
+    st, c = g.state(forces=False), g.contacts()
+    assert len(c["ki"]) > 20_000_000
+    idx = sample_ids(n, c, 6)
+    same, nc, err = sampled_errors(g, w, st, c, 50 * w["params"]["dt"], idx)
+    print(precision, "step 51 sampled contacts", nc, {q: f"{e:.2e}" for q, e in err.items()})
+    assert same
+    assert max(err.values()) < tol, err
+    g.close()
