@@ -384,28 +384,53 @@ __global__ __launch_bounds__(kThreads) void k_scatter(Ctx c) {
 // cell start plus the number of the cell's particles that came from a lower
 // previous slot, so the order within a cell is the previous order (stable and
 // deterministic).  Moves the whole state record.
-__global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B) {
+__global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, Contacts cold) {
   if (c.ctr->flags) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= c.n) return;
-  const int so = c.perm[p];
-  const int k = c.key_tmp[so];
-  const int cs = c.cell_start[k], ce = c.cell_start[k + 1];
-  int r = 0;
-  for (int t = cs; t < ce; ++t) r += (c.perm[t] < so) ? 1 : 0;
-  const int d = cs + r;
-  B.xr[d] = A.xr[so];
-  const double2* vin = reinterpret_cast<const double2*>(A.vw + 6 * (size_t)so);
-  double2* vout = reinterpret_cast<double2*>(B.vw + 6 * (size_t)d);
-  vout[0] = vin[0];
-  vout[1] = vin[1];
-  vout[2] = vin[2];
-  B.q[d] = A.q[so];
-  B.pid[d] = A.pid[so];
-  B.key[d] = k;
-  B.src[d] = so;
-  c.pcnt[d] = 0;
-  if ((d & (kGroup - 1)) == 0) c.gcnt[d >> kGroupShift] = 0;
+  // Thread d fills new slot d.  The scatter put the particles of each cell in
+  // arrival order; slot d of cell k takes the particle whose previous slot
+  // ranks d - cell_start[k] among them (stable order within a cell).
+  const int d0 = blockIdx.x * kThreads;
+  const int d = d0 + (int)threadIdx.x;
+  __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
+  if (d < c.n) {
+    const int k = c.key_tmp[c.perm[d]];
+    const int cs = c.cell_start[k], ce = c.cell_start[k + 1];
+    const int want = d - cs;
+    int so = c.perm[d];
+    for (int t = cs; t < ce; ++t) {
+      const int v = c.perm[t];
+      int r = 0;
+      for (int u = cs; u < ce; ++u) r += (c.perm[u] < v) ? 1 : 0;
+      if (r == want) {
+        so = v;
+        break;
+      }
+    }
+    const double4 xr = A.xr[so], q = A.q[so];
+    const double2* vin = reinterpret_cast<const double2*>(A.vw + 6 * (size_t)so);
+    const int t = threadIdx.x;
+    st_x[2 * t] = make_double2(xr.x, xr.y);
+    st_x[2 * t + 1] = make_double2(xr.z, xr.w);
+    st_v[3 * t] = vin[0];
+    st_v[3 * t + 1] = vin[1];
+    st_v[3 * t + 2] = vin[2];
+    st_q[2 * t] = make_double2(q.x, q.y);
+    st_q[2 * t + 1] = make_double2(q.z, q.w);
+    const int id = A.pid[so];
+    B.pid[d] = id;
+    B.key[d] = k;
+    B.os[d] = make_int4(so, cold.off[so], cold.cnt[so], id);
+    c.pcnt[d] = 0;
+    if ((d & (kGroup - 1)) == 0) c.gcnt[d >> kGroupShift] = 0;
+  }
+  __syncthreads();
+  const int np = min(c.n - d0, kThreads);
+  double2* gx = reinterpret_cast<double2*>(B.xr + d0);
+  double2* gv = reinterpret_cast<double2*>(B.vw + 6 * (size_t)d0);
+  double2* gq = reinterpret_cast<double2*>(B.q + d0);
+  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gx[k] = st_x[k];
+  for (int k = threadIdx.x; k < 3 * np; k += kThreads) gv[k] = st_v[k];
+  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gq[k] = st_q[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -693,7 +718,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
       if (t >= 0) {
         const int r = atomicAdd(&c.pcnt[t], 1);
         if (r < kMaxRev)
-          c.plist[(size_t)t * kMaxRev + r] = e;
+          c.plist[(size_t)t * kMaxRev + r] = make_int2(s, e);
         else
           raise_flag(c.ctr, kFlagCapPerParticle);
       }
@@ -757,26 +782,19 @@ __device__ __forceinline__ double sphere_mass(double rho, double R) {
   return (4.0 / 3.0) * kPi * rho * (R * R * R);
 }
 
-// Springs of key (ki, kj) among the previous step's contacts of the previous
-// owner slot po; zero if the pair was not in contact.
-__device__ __forceinline__ void find_old(const Contacts& co, int po, int2 key, double us[3],
-                                         double ur[3], double* ut) {
-  const int b0 = co.off[po], b1 = b0 + co.cnt[po];
-  for (int e = b0; e < b1; ++e) {
-    const int2 k = co.key[e];
-    if (k.x == key.x && k.y == key.y) {
-      const double2* r = reinterpret_cast<const double2*>(co.spr + (size_t)kSpr * e);
-      const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-      us[0] = r0.x;
-      us[1] = r0.y;
-      us[2] = r1.x;
-      ur[0] = r1.y;
-      ur[1] = r2.x;
-      ur[2] = r2.y;
-      *ut = r3.x;
-      return;
-    }
+// Record of key (ki, kj) among the n contacts that the previous owner slot
+// owned in the previous step (records b0 ..), or -1 if the pair was not in
+// contact.  Keys are probed four at a time so that their loads overlap.
+__device__ __forceinline__ int find_old(const Contacts& co, int b0, int n, int2 key) {
+  for (int base = 0; base < n; base += 4) {
+    int2 k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) k[u] = base + u < n ? co.key[b0 + base + u] : make_int2(-1, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (base + u < n && k[u].x == key.x && k[u].y == key.y) return b0 + base + u;
   }
+  return -1;
 }
 
 template <typename RT>
@@ -787,37 +805,65 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
   const int cnt = min(c.gcnt[grp], c.gcap);
   const int gbase = grp * c.gcap;
   int npp = 0, npw = 0;
-  for (int l = threadIdx.x; l < cnt; l += blockDim.x) {
+  // the spring and result records of one pass are staged in LDS and written
+  // out as contiguous runs (per-lane 64- and 80-byte records written
+  // directly would make every store instruction scatter)
+  __shared__ double2 st_spr[kThreads * kSpr / 2];
+  __shared__ double2 st_res[kThreads * kRes / 2];
+  for (int base = 0; base < cnt; base += kThreads) {
+  const int l = base + (int)threadIdx.x;
+  if (l < cnt) {
     const int e = gbase + l;
     const int a = cur.a[e], b = cur.b[e];
-    const int sim = c.sim_of[a];
-    const SimParams& P = c.sp[sim];
     const bool wall = b < 0;
+    const SimParams& P = c.sp[c.sim_of[a]];
+    // both bodies are gathered at once; the canonical orientation is then
+    // chosen in registers
     const double4 pa = S.xr[a];
-    const int ida = S.pid[a];
-    // canonical orientation: body I carries the lower id (the particle for walls)
-    double4 pi = pa, pj;
-    int I = a, J = b;
-    bool swap = false;
-    int2 key;
+    const int4 oa = S.os[a];
+    const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
+    const double2 va0 = va[0], va1 = va[1], va2 = va[2];
+    double4 pb;
+    int4 ob = oa;
+    double2 vb0 = make_double2(0.0, 0.0), vb1 = vb0, vb2 = vb0;
+    int m = 0;
     if (!wall) {
-      pj = S.xr[b];
-      const int idb = S.pid[b];
-      swap = ida > idb;
-      if (swap) {
-        pi = pj;
-        pj = pa;
-        I = b;
-        J = a;
-      }
-      key = make_int2(swap ? idb : ida, swap ? ida : idb);
+      pb = S.xr[b];
+      ob = S.os[b];
+      const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
+      vb0 = vb[0];
+      vb1 = vb[1];
+      vb2 = vb[2];
     } else {
-      const int m = -1 - b;
+      m = -1 - b;
       const double p[3] = {pa.x, pa.y, pa.z};
       double cp[3];
       closest_on_triangle(p, c.tri + 9 * m, cp);
-      pj = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
-      key = make_int2(ida, -(m - P.tri0));
+      pb = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
+    }
+    // canonical orientation: body I carries the lower id (the particle for walls)
+    const int ida = oa.w, idb = ob.w;
+    const bool swap = !wall && ida > idb;
+    const double4 pi = swap ? pb : pa, pj = swap ? pa : pb;
+    const int2 key = wall ? make_int2(ida, -(m - P.tri0))
+                          : make_int2(swap ? idb : ida, swap ? ida : idb);
+    // springs of the previous step (zero for a new contact), looked up among
+    // the records of the previous owner: the lower previous slot of the two
+    double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
+    {
+      const bool bown = !wall && ob.x < oa.x;
+      const int eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
+      if (eo >= 0) {
+        const double2* r = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
+        const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+        us[0] = r0.x;
+        us[1] = r0.y;
+        us[2] = r1.x;
+        ur[0] = r1.y;
+        ur[1] = r2.x;
+        ur[2] = r2.y;
+        ut = r3.x;
+      }
     }
     const double Ri = pi.w, Rj = pj.w;
     double dx, dy, dz, d;
@@ -826,16 +872,16 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
     const RT nrm[3] = {(RT)(dx * invd), (RT)(dy * invd), (RT)(dz * invd)};
     const double ri = Ri - 0.5 * delta;
     const double mi = sphere_mass(P.rho, Ri);
-    const double* vwi = S.vw + 6 * (size_t)I;
-    const double vix = vwi[0], viy = vwi[1], viz = vwi[2];
-    const double wix = vwi[3], wiy = vwi[4], wiz = vwi[5];
+    const double2 vi0 = swap ? vb0 : va0, vi1 = swap ? vb1 : va1, vi2 = swap ? vb2 : va2;
+    const double vix = vi0.x, viy = vi0.y, viz = vi1.x;
+    const double wix = vi1.y, wiy = vi2.x, wiz = vi2.y;
     double rj, Rs, ms, Es, Gs, reff;
     double vrel[3], om[3];
     const double n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
     if (!wall) {
-      const double* vwj = S.vw + 6 * (size_t)J;
-      const double vjx = vwj[0], vjy = vwj[1], vjz = vwj[2];
-      const double wjx = vwj[3], wjy = vwj[4], wjz = vwj[5];
+      const double2 vj0 = swap ? va0 : vb0, vj1 = swap ? va1 : vb1, vj2 = swap ? va2 : vb2;
+      const double vjx = vj0.x, vjy = vj0.y, vjz = vj1.x;
+      const double wjx = vj1.y, wjy = vj2.x, wjz = vj2.y;
       rj = Rj - 0.5 * delta;
       const double mj = sphere_mass(P.rho, Rj);
       Rs = 1.0 / (1.0 / Ri + 1.0 / Rj);
@@ -895,20 +941,13 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
     const RT kd = kn * (RT)delta;
     const RT fn[3] = {kd * nrm[0] - cn * vn[0], kd * nrm[1] - cn * vn[1], kd * nrm[2] - cn * vn[2]};
     const RT fnl = sqrt((fn[0] * fn[0] + fn[1] * fn[1]) + fn[2] * fn[2]);
-    // springs of the previous step (zero for a new contact)
-    double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
-    {
-      const int sa = S.src[a];
-      const int po = wall ? sa : min(sa, S.src[b]);
-      find_old(old, po, key, us, ur, &ut);
-    }
     RT fs[3], fr[3], ft;
     friction_vec<RT>(nrm, ks, cs, (RT)P.mu_s * fnl, P.dt, vs, us, fs);
     friction_vec<RT>(nrm, kn, cn, (RT)P.mu_r * fnl, P.dt, vr, ur, fr);
     friction_scalar<RT>(ks, cs, (RT)P.mu_t * fnl, P.dt, vt, &ut, &ft);
     cur.key[e] = key;
     {
-      double2* r = reinterpret_cast<double2*>(cur.spr + (size_t)kSpr * e);
+      double2* r = st_spr + (kSpr / 2) * threadIdx.x;
       r[0] = make_double2(us[0], us[1]);
       r[1] = make_double2(us[2], ur[0]);
       r[2] = make_double2(ur[1], ur[2]);
@@ -938,9 +977,19 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
       o[6 + k] = swap ? ti : tj;
     }
     o[9] = 0.0;
-    double2* r = reinterpret_cast<double2*>(c.res + (size_t)kRes * e);
+    double2* r = st_res + (kRes / 2) * threadIdx.x;
 #pragma unroll
     for (int k = 0; k < kRes / 2; ++k) r[k] = make_double2(o[2 * k], o[2 * k + 1]);
+  }
+  __syncthreads();
+  {
+    const int nrec = min(cnt - base, kThreads);
+    double2* gs = reinterpret_cast<double2*>(cur.spr + (size_t)kSpr * (gbase + base));
+    for (int k = threadIdx.x; k < nrec * (kSpr / 2); k += kThreads) gs[k] = st_spr[k];
+    double2* gr = reinterpret_cast<double2*>(c.res + (size_t)kRes * (gbase + base));
+    for (int k = threadIdx.x; k < nrec * (kRes / 2); k += kThreads) gr[k] = st_res[k];
+  }
+  __syncthreads();
   }
   // contact counts of the group for the statistics (summed by the next step's
   // grid kernel or by the host)
@@ -982,29 +1031,56 @@ __device__ __forceinline__ void qmul(const double a[4], const double b[4], doubl
 __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts cur) {
   if (c.ctr->flags) return;
   const int n = c.n;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int i0 = blockIdx.x * kThreads;
+  const int i = i0 + (int)threadIdx.x;
+  // new states are staged in LDS and written out as contiguous runs
+  __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
+  if (i < n) {
   const double* res = c.res;
+  // the particle's own state first, so that its loads overlap the gathers
+  const SimParams& P = c.sp[c.sim_of[i]];
+  const double4 xr = S.xr[i];
+  const double4 q4 = S.q[i];
+  double* vwp = S.vw + 6 * (size_t)i;
+  const double2* vw2 = reinterpret_cast<const double2*>(vwp);
+  const double2 s0 = vw2[0], s1 = vw2[1], s2 = vw2[2];
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   {
+    // owned contacts in record order, four records in flight
     const int e0 = cur.off[i], e1 = e0 + cur.cnt[i];
-    for (int e = e0; e < e1; ++e) {
-      const double* r = res + (size_t)kRes * e;
+    const int m = min(c.pcnt[i], kMaxRev);
+    for (int e = e0; e < e1; e += 4) {
+      double2 f[4][3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        F[k] += r[k];
-        T[k] += r[3 + k];
+      for (int u = 0; u < 4; ++u) {
+        const double2* r = reinterpret_cast<const double2*>(res + (size_t)kRes * (e + u < e1 ? e + u : e));
+        f[u][0] = r[0];
+        f[u][1] = r[1];
+        f[u][2] = r[2];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (e + u < e1) {
+          F[0] += f[u][0].x;
+          F[1] += f[u][0].y;
+          F[2] += f[u][1].x;
+          T[0] += f[u][1].y;
+          T[1] += f[u][2].x;
+          T[2] += f[u][2].y;
+        }
       }
     }
-    const int m = min(c.pcnt[i], kMaxRev);
-    const int* pl = c.plist + (size_t)i * kMaxRev;
+    // contacts owned by others, in ascending owner slot (the partner lists
+    // hold (owner slot, record); owners of one partner are distinct)
+    const int2* pl = c.plist + (size_t)i * kMaxRev;
     if (m <= 8) {
-      // sort (owner slot, record) pairs with a fixed compare-exchange network
+      // sort with a fixed compare-exchange network
       int ka[8], ke[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        ke[j] = j < m ? pl[j] : -1;
-        ka[j] = j < m ? cur.a[ke[j]] : 0x7fffffff;
+        const int2 v = j < m ? pl[j] : make_int2(0x7fffffff, -1);
+        ka[j] = v.x;
+        ke[j] = v.y;
       }
 #define SDEM_CX(x, y)                                    \
   if (ka[y] < ka[x]) {                                  \
@@ -1022,27 +1098,38 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
       SDEM_CX(2, 4) SDEM_CX(3, 5)
       SDEM_CX(3, 4)
 #undef SDEM_CX
+      // force on the owner (doubles 0..2) and torque on the partner (6..8)
+      double2 g[8][4];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (j < m) {
-          const double* r = res + (size_t)kRes * ke[j];
+          const double2* r = reinterpret_cast<const double2*>(res + (size_t)kRes * ke[j]);
+          g[j][0] = r[0];
+          g[j][1] = r[1];
+          g[j][2] = r[3];
+          g[j][3] = r[4];
+        }
+      }
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            F[k] -= r[k];
-            T[k] += r[6 + k];
-          }
+      for (int j = 0; j < 8; ++j) {
+        if (j < m) {
+          F[0] -= g[j][0].x;
+          F[1] -= g[j][0].y;
+          F[2] -= g[j][1].x;
+          T[0] += g[j][2].x;
+          T[1] += g[j][2].y;
+          T[2] += g[j][3].x;
         }
       }
     } else {
       int last = -1;
-      for (int it = 0; it < m; ++it) {  // ascending owner slot (owners are distinct)
+      for (int it = 0; it < m; ++it) {  // ascending owner slot
         int best = -1, ba = 0x7fffffff;
         for (int j = 0; j < m; ++j) {
-          const int e = pl[j];
-          const int a = cur.a[e];
-          if (a > last && a < ba) {
-            ba = a;
-            best = e;
+          const int2 v = pl[j];
+          if (v.x > last && v.x < ba) {
+            ba = v.x;
+            best = v.y;
           }
         }
         if (best < 0) break;
@@ -1061,16 +1148,13 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
     c.F[k * n + i] = F[k];
     c.T[k * n + i] = T[k];
   }
-  const SimParams& P = c.sp[c.sim_of[i]];
-  const double4 xr = S.xr[i];
   const double R = xr.w;
   const double m = sphere_mass(P.rho, R);
   const double I = 0.4 * m * R * R;
   const double cd = 9.0 * P.eta / (2.0 * P.rho * R * R);
   const double gd = (10.0 / 3.0) * cd;
   const double dt = P.dt;
-  double* vwp = S.vw + 6 * (size_t)i;
-  double v[3] = {vwp[0], vwp[1], vwp[2]}, w[3] = {vwp[3], vwp[4], vwp[5]};
+  double v[3] = {s0.x, s0.y, s1.x}, w[3] = {s1.y, s2.x, s2.y};
   double x[3] = {xr.x, xr.y, xr.z}, al[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -1079,7 +1163,6 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
     v[k] = v[k] + dt * a;
     x[k] = x[k] + dt * v[k];
   }
-  const double4 q4 = S.q[i];
   double q[4] = {q4.x, q4.y, q4.z, q4.w};
   const double wl = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
   if (wl > 0.0) {
@@ -1108,13 +1191,26 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   for (int k = 0; k < 3; ++k) {
     w[k] = w[k] + dt * al[k];
     ok = ok && isfinite(x[k]) && isfinite(v[k]) && isfinite(w[k]);
-    vwp[k] = v[k];
-    vwp[3 + k] = w[k];
   }
-  S.xr[i] = make_double4(x[0], x[1], x[2], R);
-  S.q[i] = make_double4(q[0], q[1], q[2], q[3]);
+  const int t = threadIdx.x;
+  st_x[2 * t] = make_double2(x[0], x[1]);
+  st_x[2 * t + 1] = make_double2(x[2], R);
+  st_v[3 * t] = make_double2(v[0], v[1]);
+  st_v[3 * t + 1] = make_double2(v[2], w[0]);
+  st_v[3 * t + 2] = make_double2(w[1], w[2]);
+  st_q[2 * t] = make_double2(q[0], q[1]);
+  st_q[2 * t + 1] = make_double2(q[2], q[3]);
   if (!ok) raise_flag(c.ctr, kFlagNonFinite);
   if (i == 0) c.ctr->stats_pending = 1;
+  }
+  __syncthreads();
+  const int np = min(n - i0, kThreads);
+  double2* gx = reinterpret_cast<double2*>(S.xr + i0);
+  double2* gv = reinterpret_cast<double2*>(S.vw + 6 * (size_t)i0);
+  double2* gq = reinterpret_cast<double2*>(S.q + i0);
+  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gx[k] = st_x[k];
+  for (int k = threadIdx.x; k < 3 * np; k += kThreads) gv[k] = st_v[k];
+  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gq[k] = st_q[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -1167,7 +1263,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_state(Ctx c, State S, const d
   S.q[i] = q ? make_double4(q[i], q[n + i], q[2 * n + i], q[3 * n + i])
              : make_double4(1.0, 0.0, 0.0, 0.0);
   S.pid[i] = i;
-  S.src[i] = i;
+  S.os[i] = make_int4(i, 0, 0, i);
   S.key[i] = 0;
   c.F[i] = c.F[n + i] = c.F[2 * n + i] = 0.0;
   c.T[i] = c.T[n + i] = c.T[2 * n + i] = 0.0;
@@ -1202,7 +1298,7 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
     k_scan_down<<<kScanBlocks, kScanThreads, 0, s>>>(c);
   }
   k_scatter<<<nbp, kThreads, 0, s>>>(c);
-  k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B);
+  k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B, cold);
   if (c.any_rotating) {
     k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
     (void)launch_mesh_bins(c, s);

@@ -121,7 +121,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.pcnt = L.take<int32_t>(N);
   cc.gcnt = L.take<int32_t>(G);
   cc.gstat = L.take<int32_t>(2 * G);
-  cc.plist = L.take<int32_t>(N * kMaxRev);
+  cc.plist = L.take<int2>(N * kMaxRev);
   cc.res = L.take<double>(kRes * Cm);
   cc.F = L.take<double>(3 * N);
   cc.T = L.take<double>(3 * N);
@@ -141,7 +141,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
     s.q = L.take<double4>(N);
     s.pid = L.take<int32_t>(N);
     s.key = L.take<int32_t>(N);
-    s.src = L.take<int32_t>(N);
+    s.os = L.take<int4>(N);
     if (st) st[b] = s;
   }
   for (int b = 0; b < 2; ++b) {

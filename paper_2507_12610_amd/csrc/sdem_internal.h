@@ -86,7 +86,8 @@ struct State {
   double4* q;    // [n] orientation quaternion, scalar first
   int32_t* pid;  // persistent id
   int32_t* key;  // cell key of this slot (written by the reorder)
-  int32_t* src;  // slot of the same particle in the previous step's order
+  int4* os;      // (slot in the previous step's order, first and number of the
+                 // contacts it owned in the previous step, persistent id)
 };
 
 // One buffer of contacts, grouped by owner slot (owner = lower slot).  The
@@ -124,7 +125,7 @@ struct Ctx {
   int32_t* perm;      // [n] new slot -> previous slot (unstable within a cell)
   int32_t* scan_tmp;  // [kScanBlocks+1]
   int32_t* pcnt;      // [n] contacts in which the slot is the partner
-  int32_t* plist;     // [n][kMaxRev] those contacts
+  int2* plist;        // [n][kMaxRev] those contacts: (owner slot, record)
   double* res;        // [cap][kRes] per contact: force on the owner (3), torque
                       // on the owner (3), torque on the partner (3), pad
   double* F;          // [3][n] contact force of the last step, by slot
