@@ -244,6 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_keys(Ctx c, State A) {
   const int key = g.cell_off + (cz * g.dim[1] + cy) * g.dim[0] + cx;
   c.key_tmp[i] = key;
   c.rank[i] = atomicAdd(&c.cell_cnt[key], 1);
+  c.rowmax[key - cx] = 0ull;  // the reorder takes the maxima of occupied rows
 }
 
 // ---------------------------------------------------------------------------
@@ -392,6 +393,8 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
   const int d0 = blockIdx.x * kThreads;
   const int d = d0 + (int)threadIdx.x;
   __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
+  int rk = -1 - (int)threadIdx.x;  // row of the slot's cell (unique dummy if none)
+  double rr = 0.0;
   if (d < c.n) {
     const int k = c.key_tmp[c.perm[d]];
     const int cs = c.cell_start[k], ce = c.cell_start[k + 1];
@@ -416,12 +419,31 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
     st_v[3 * t + 2] = vin[2];
     st_q[2 * t] = make_double2(q.x, q.y);
     st_q[2 * t + 1] = make_double2(q.z, q.w);
+    {
+      const SimGrid g = c.sg[c.sim_of[d]];
+      rk = k - (k - g.cell_off) % g.dim[0];
+      rr = xr.w;
+    }
     const int id = A.pid[so];
     B.pid[d] = id;
     B.key[d] = k;
     B.os[d] = make_int4(so, cold.off[so], cold.cnt[so], id);
     c.pcnt[d] = 0;
     if ((d & (kGroup - 1)) == 0) c.gcnt[d >> kGroupShift] = 0;
+  }
+  // largest radius per cell row: slots are in row order, so a wave's rows
+  // are runs of lanes; a segmented maximum leaves one atomic per run
+  {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double ov = __shfl_down(rr, o, 64);
+      const int ok = __shfl_down(rk, o, 64);
+      if (lane + o < 64 && ok == rk) rr = fmax(rr, ov);
+    }
+    const int prev = __shfl_up(rk, 1, 64);
+    if (rk >= 0 && (lane == 0 || prev != rk))
+      atomicMax(&c.rowmax[rk], (unsigned long long)__double_as_longlong(rr));
   }
   __syncthreads();
   const int np = min(c.n - d0, kThreads);
@@ -590,9 +612,9 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
 
 // ---------------------------------------------------------------------------
 // 5. narrow phase (Section 3.3), one pass.  SUB adjacent lanes share one
-//    particle slot s and split its search (every SUB-th triangle of its
-//    simulation and every SUB-th candidate of each cell row), which
-//    multiplies the loads in flight for the latency-bound search.  Partners
+//    particle slot s and split its search (every SUB-th triangle of its bin
+//    and every SUB-th cell row of its search box), which shortens each
+//    lane's chain of dependent loads in the latency-bound search.  Partners
 //    are the particles with a higher slot in the cells within R_s + R_max of
 //    x_s on each axis: with cells in (z, y, x) row order each row of that box
 //    is one contiguous slot range, and rows before the own row hold only
@@ -645,41 +667,99 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
         ++npw;
       }
     }
-    // ---- particles (the margin on the box covers rounding of its ends)
+    // ---- particles.  The half-shell rows run from the own row through the
+    // rest of the own (y, z) plane, then over the full planes above; lane
+    // `sub` takes every SUB-th of them.  A row is searched over the x cells
+    // within rho = R_s + (largest radius in the row) of x_s, given its (y, z)
+    // distance from x_s; rows farther than rho are skipped.  The row geometry
+    // is done in cell units relative to the own cell, in float, with margins
+    // (1e-5 cell, 1e-6 relative) far above its rounding, so the search only
+    // ever widens.  The largest radius of a row is loaded two rows ahead and
+    // the slot range one row ahead of the candidates being examined.
     const int loc = S.key[s] - gr.cell_off;
     const int nx = gr.dim[0], ny = gr.dim[1], nz = gr.dim[2];
     const int cx = loc % nx, cyz = loc / nx, cy = cyz % ny, cz = cyz / ny;
-    (void)cx;
+    const float fx = (float)((xs - gr.lo[0]) * gr.inv_h - cx);
+    const float fy = (float)((ys - gr.lo[1]) * gr.inv_h - cy);
+    const float fz = (float)((zs - gr.lo[2]) * gr.inv_h - cz);
     const double reach = (Rs + c.sp[sim].rmax) * (1.0 + 1e-9);
-    const int x0 = cell_coord(xs - reach, gr.lo[0], gr.inv_h, nx);
-    const int x1 = cell_coord(xs + reach, gr.lo[0], gr.inv_h, nx);
     const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, ny);
     const int y1 = cell_coord(ys + reach, gr.lo[1], gr.inv_h, ny);
     const int z1 = cell_coord(zs + reach, gr.lo[2], gr.inv_h, nz);
-    for (int zz = cz; zz <= z1; ++zz) {
-      for (int yy = (zz == cz ? cy : y0); yy <= y1; ++yy) {
-        const int row = gr.cell_off + (zz * ny + yy) * nx;
-        const int t0 = ((zz == cz && yy == cy) ? s + 1 : c.cell_start[row + x0]) + sub;
-        const int t1 = c.cell_start[row + x1 + 1];
-        // four candidates per iteration so that four loads are in flight
-        for (int t = t0; t < t1; t += 4 * SUB) {
-          double4 pt[4];
+    auto step1 = [&](int* zz, int* yy) {
+      if (++*yy > y1) {
+        ++*zz;
+        *yy = y0;
+      }
+    };
+    auto advance = [&](int* zz, int* yy) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u * SUB < t1 ? t + u * SUB : t];
+      for (int k = 0; k < SUB; ++k) step1(zz, yy);
+    };
+    auto row_at = [&](int zz, int yy) { return gr.cell_off + (zz * ny + yy) * nx; };
+    auto load_rm = [&](int zz, int yy) {
+      return zz <= z1 ? __longlong_as_double((long long)c.rowmax[row_at(zz, yy)]) : 0.0;
+    };
+    auto bounds = [&](int zz, int yy, double rm, int* t0, int* t1) {
+      *t0 = 0;
+      *t1 = 0;
+      if (zz > z1) return;
+      const float ry = (float)(yy - cy), rz = (float)(zz - cz);
+      const float dy = fmaxf(fmaxf(ry - fy, fy - (ry + 1.0f)) - 1e-5f, 0.0f);
+      const float dz = fmaxf(fmaxf(rz - fz, fz - (rz + 1.0f)) - 1e-5f, 0.0f);
+      const float rho = (float)((Rs + rm) * gr.inv_h) * (1.0f + 1e-6f) + 1e-5f;
+      const float d2 = dy * dy + dz * dz;
+      if (d2 > rho * rho) return;
+      const float xr = sqrtf(rho * rho - d2) * (1.0f + 1e-6f) + 1e-5f;
+      const int x0 = max(0, cx + (int)floorf(fx - xr));
+      const int x1 = min(nx - 1, cx + (int)floorf(fx + xr));
+      if (x1 < x0) return;
+      const int row = row_at(zz, yy);
+      *t0 = (zz == cz && yy == cy) ? s + 1 : c.cell_start[row + x0];
+      *t1 = c.cell_start[row + x1 + 1];
+    };
+    // rows: C (candidates now), B (slot range next), A (largest radius next)
+    int zA = cz, yA = cy;
+    for (int k = 0; k < sub; ++k) step1(&zA, &yA);
+    int zB = zA, yB = yA;
+    double rmB = load_rm(zB, yB);
+    advance(&zA, &yA);
+    double rmA = load_rm(zA, yA);
+    int t0n, t1n;
+    bounds(zB, yB, rmB, &t0n, &t1n);
+    int zC = zB;
+    zB = zA;
+    yB = yA;
+    rmB = rmA;
+    advance(&zA, &yA);
+    rmA = load_rm(zA, yA);
+    while (zC <= z1) {
+      const int t0 = t0n, t1 = t1n;
+      bounds(zB, yB, rmB, &t0n, &t1n);
+      zC = zB;
+      zB = zA;
+      yB = yA;
+      rmB = rmA;
+      advance(&zA, &yA);
+      rmA = load_rm(zA, yA);
+      // four candidates per iteration so that four loads are in flight
+      for (int t = t0; t < t1; t += 4) {
+        double4 pt[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (t + u * SUB >= t1) break;
-            const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
-            const double sr = Rs + pt[u].w;
-            // cheap conservative reject before the exactly rounded test
-            if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) continue;
-            double dx, dy, dz, d;
-            const double delta =
-                pair_gap(xs, ys, zs, Rs, pt[u].x, pt[u].y, pt[u].z, pt[u].w, &dx, &dy, &dz, &d);
-            if (delta >= 0.0) {
-              if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = t + u * SUB;
-              ++npp;
-            }
+        for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u < t1 ? t + u : t];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (t + u >= t1) break;
+          const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
+          const double sr = Rs + pt[u].w;
+          // cheap conservative reject before the exactly rounded test
+          if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) continue;
+          double dx, dy, dz, d;
+          const double delta =
+              pair_gap(xs, ys, zs, Rs, pt[u].x, pt[u].y, pt[u].z, pt[u].w, &dx, &dy, &dz, &d);
+          if (delta >= 0.0) {
+            if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = t + u;
+            ++npp;
           }
         }
       }

@@ -114,6 +114,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.part = L.take<double>(6 * NC);
   cc.cell_cnt = L.take<int32_t>(Gm);
   cc.cell_start = L.take<int32_t>(Gm + 1);
+  cc.rowmax = L.take<unsigned long long>(Gm);
   cc.key_tmp = L.take<int32_t>(N);
   cc.rank = L.take<int32_t>(N);
   cc.perm = L.take<int32_t>(N);
@@ -388,6 +389,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   }
   if (!e) e = hipMemsetAsync(c.ctr, 0, sizeof(Counters), st);
   if (!e) e = hipMemsetAsync(c.cell_cnt, 0, sizeof(int32_t) * cfg.cells_max, st);
+  if (!e) e = hipMemsetAsync(c.rowmax, 0, sizeof(unsigned long long) * cfg.cells_max, st);
   for (int b = 0; b < 2 && !e; ++b) {
     e = hipMemsetAsync(X->ct[b].cnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
     if (!e) e = hipMemsetAsync(X->ct[b].off, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);

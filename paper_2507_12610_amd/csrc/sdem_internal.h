@@ -120,6 +120,9 @@ struct Ctx {
   double* part;       // [nchunks][6] bounding-box partials
   int32_t* cell_cnt;  // [cap_cells] zero between steps
   int32_t* cell_start;// [cap_cells+1]
+  unsigned long long* rowmax;  // [cap_cells] at the first cell of each cell row:
+                      // largest radius in that row (bits of a positive double);
+                      // rows without particles hold stale values >= 0
   int32_t* key_tmp;   // [n] cell key by previous slot
   int32_t* rank;      // [n] arrival rank in the cell
   int32_t* perm;      // [n] new slot -> previous slot (unstable within a cell)
