@@ -840,8 +840,9 @@ __device__ __forceinline__ void friction_vec(const RT n[3], RT k, RT cdmp, RT li
     const RT sc = lim / fl;
 #pragma unroll
     for (int a = 0; a < 3; ++a) f[a] = f[a] * sc;
+    const double ik = 1.0 / (double)k;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = -((double)f[a] + (double)cdmp * (double)vm[a]) / (double)k;
+    for (int a = 0; a < 3; ++a) u[a] = -((double)f[a] + (double)cdmp * (double)vm[a]) * ik;
   }
 }
 
@@ -955,7 +956,7 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
     const double2 vi0 = swap ? vb0 : va0, vi1 = swap ? vb1 : va1, vi2 = swap ? vb2 : va2;
     const double vix = vi0.x, viy = vi0.y, viz = vi1.x;
     const double wix = vi1.y, wiy = vi2.x, wiz = vi2.y;
-    double rj, Rs, ms, Es, Gs, reff;
+    double rj, Rs, ms, Es, Gs, cnf, csf, reff;
     double vrel[3], om[3];
     const double n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
     if (!wall) {
@@ -964,11 +965,14 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
       const double wjx = vj1.y, wjy = vj2.x, wjz = vj2.y;
       rj = Rj - 0.5 * delta;
       const double mj = sphere_mass(P.rho, Rj);
-      Rs = 1.0 / (1.0 / Ri + 1.0 / Rj);
-      ms = 1.0 / (1.0 / mi + 1.0 / mj);
+      // effective radius and mass 1/(1/a + 1/b) written as a b / (a + b)
+      Rs = (Ri * Rj) / (Ri + Rj);
+      ms = (mi * mj) / (mi + mj);
+      cnf = P.cnf_pp;
+      csf = P.csf_pp;
       Es = P.Es_pp;
       Gs = P.Gs_pp;
-      reff = 1.0 / (1.0 / ri + 1.0 / rj);
+      reff = (ri * rj) / (ri + rj);
       // v = v_i - v_j + n x (r_i w_i + r_j w_j)
       const double rx = ri * wix + rj * wjx, ry = ri * wiy + rj * wjy, rz = ri * wiz + rj * wjz;
       vrel[0] = (vix - vjx) + (n1 * rz - n2 * ry);
@@ -981,6 +985,8 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
       rj = 0.0;
       Rs = Ri;
       ms = mi;
+      cnf = P.cnf_pw;
+      csf = P.csf_pw;
       Es = P.Es_pw;
       Gs = P.Gs_pw;
       reff = ri;
@@ -1002,11 +1008,14 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
       om[2] = wiz - P.om[2];
     }
     // coefficients (Eq. ks, cn, cs; k_r = k_n, c_r = c_n, k_t = k_s, c_t = c_s)
+    // with k_n = 4/3 E* a and k_s = 8 G* a: c_n = beta sqrt(20/3 E*) sqrt(m* a)
+    // and c_s = beta sqrt(4/3 G*) sqrt(m* a), the constant factors per simulation
     const RT ac = (RT)sqrt(Rs * delta);
     const RT kn = (RT)(4.0 / 3.0) * (RT)Es * ac;
     const RT ks = (RT)8.0 * (RT)Gs * ac;
-    const RT cn = sqrt((RT)5.0 * (RT)ms * kn) * (RT)P.beta;
-    const RT cs = sqrt((RT)ms * ks / (RT)6.0) * (RT)P.beta;
+    const RT sm = sqrt((RT)ms * ac);
+    const RT cn = (RT)cnf * sm;
+    const RT cs = (RT)csf * sm;
     // relative velocities
     const RT v0 = (RT)vrel[0], v1 = (RT)vrel[1], v2 = (RT)vrel[2];
     const RT vnn = (v0 * nrm[0] + v1 * nrm[1]) + v2 * nrm[2];

@@ -237,6 +237,12 @@ static SimParams derive(const sdem_params& p, double cell_factor, double rmax) {
   d.Gs_pp = E / (4.0 * (2.0 - nu) * (1.0 + nu));
   d.Es_pw = E / (1.0 - nu * nu);
   d.Gs_pw = E / (2.0 * (1.0 + nu) * (2.0 - nu));
+  // c_n = sqrt(5 m* k_n) beta with k_n = 4/3 E* a; c_s = sqrt(m* k_s / 6) beta
+  // with k_s = 8 G* a (Eq. cn, cs)
+  d.cnf_pp = d.beta * sqrt(20.0 / 3.0 * d.Es_pp);
+  d.csf_pp = d.beta * sqrt(4.0 / 3.0 * d.Gs_pp);
+  d.cnf_pw = d.beta * sqrt(20.0 / 3.0 * d.Es_pw);
+  d.csf_pw = d.beta * sqrt(4.0 / 3.0 * d.Gs_pw);
   // cell edge >= 2 R_max; the small margin keeps neighbours within one cell
   // index of each other despite rounding of the cell coordinate
   const double rm = rmax > 0 ? rmax : 1.0;

@@ -38,6 +38,8 @@ struct SimParams {
   double beta;                 // 1/sqrt(1 + (pi/ln e_n)^2)
   double Es_pp, Gs_pp;         // uniform material, two spheres
   double Es_pw, Gs_pw;         // sphere against a rigid wall
+  double cnf_pp, csf_pp;       // beta sqrt(20/3 E*), beta sqrt(4/3 G*): damping
+  double cnf_pw, csf_pw;       // coefficients per sqrt(m* a), two spheres / wall
   double h;                    // cell edge
   double rmax;                 // largest radius of the simulation
   int32_t rotating;            // mesh rotates (|om| > 0)
