@@ -39,54 +39,77 @@ __device__ __forceinline__ void raise_flag(Counters* ctr, int f) { atomicOr(&ctr
 // ---------------------------------------------------------------------------
 // 1. bounding box of the centres, per simulation (Section 3.3)
 // ---------------------------------------------------------------------------
+// Bounding-box partials of one wave of slots (Section 3.3: cells over the
+// bounding box of the centres): one partial per (wave, simulation) segment,
+// written by the segment's first lane.  Must be called by every lane of a
+// wave that holds at least one slot; `valid` is false past the last slot.  A
+// non-finite coordinate turns the partial's minimum into NaN, which the grid
+// kernel reports.
+__device__ __forceinline__ void wave_bbox(const Ctx& c, int i, bool valid, double x, double y,
+                                          double z) {
+  const int lane = threadIdx.x & 63;
+  const int sim = valid ? c.sim_of[i] : 0x7fffffff;
+  double v[6] = {x, y, z, -x, -y, -z};  // minima of (x, y, z) and of (-x, -y, -z)
+  const bool bad = valid && !(isfinite(x) && isfinite(y) && isfinite(z));
+  if (!valid) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = INFINITY;
+  }
+  const int s0 = __shfl(sim, 0, 64);
+  const int first = c.wchunk[i >> 6];
+  if (__all(!valid || sim == s0)) {
+    // the whole wave is one simulation: butterfly minimum
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      for (int o = 32; o > 0; o >>= 1) v[k] = fmin(v[k], __shfl_xor(v[k], o, 64));
+    const bool anybad = __any(bad);
+    if (lane == 0) {
+      double* p = c.part + 6 * (size_t)first;
+      p[0] = anybad ? NAN : v[0];
+      p[1] = v[1];
+      p[2] = v[2];
+      p[3] = -v[3];
+      p[4] = -v[4];
+      p[5] = -v[5];
+    }
+  } else {
+    // several simulations: segmented minimum over runs of equal sim
+    int nb = bad ? 1 : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int os = __shfl_down(sim, o, 64);
+      const int ob = __shfl_down(nb, o, 64);
+      const bool same = lane + o < 64 && os == sim;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const double ov = __shfl_down(v[k], o, 64);
+        if (same) v[k] = fmin(v[k], ov);
+      }
+      if (same) nb |= ob;
+    }
+    const int prev = __shfl_up(sim, 1, 64);
+    const bool head = valid && (lane == 0 || prev != sim);
+    const unsigned long long heads = __ballot(head);
+    if (head) {
+      const int k = first + __popcll(heads & ((1ull << lane) - 1ull));
+      double* p = c.part + 6 * (size_t)k;
+      p[0] = nb ? NAN : v[0];
+      p[1] = v[1];
+      p[2] = v[2];
+      p[3] = -v[3];
+      p[4] = -v[4];
+      p[5] = -v[5];
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_bbox_part(Ctx c, State A) {
   if (c.ctr->flags) return;
-  const int ch = blockIdx.x;
-  const int b0 = c.chunks[3 * ch + 1], b1 = c.chunks[3 * ch + 2];
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  bool bad = false;
-  for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-    const double4 p = A.xr[i];
-    const double xv[3] = {p.x, p.y, p.z};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = fmin(lo[k], xv[k]);
-      hi[k] = fmax(hi[k], xv[k]);
-      bad = bad || !isfinite(xv[k]);
-    }
-  }
-  __shared__ double red[6][kThreads / 64];
-  __shared__ int any_bad;
-  if (threadIdx.x == 0) any_bad = 0;
-  __syncthreads();
-  if (bad) any_bad = 1;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    double a = lo[k], b = hi[k];
-    for (int o = 32; o > 0; o >>= 1) {
-      a = fmin(a, __shfl_xor(a, o, 64));
-      b = fmax(b, __shfl_xor(b, o, 64));
-    }
-    if (lane == 0) {
-      red[k][wv] = a;
-      red[3 + k][wv] = b;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = blockDim.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      double a = red[k][0], b = red[3 + k][0];
-      for (int w = 1; w < nw; ++w) {
-        a = fmin(a, red[k][w]);
-        b = fmax(b, red[3 + k][w]);
-      }
-      c.part[6 * ch + k] = any_bad ? NAN : a;
-      c.part[6 * ch + 3 + k] = b;
-    }
-  }
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const bool valid = i < c.n;
+  double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (valid) p = A.xr[i];
+  if (i - (int)(threadIdx.x & 63) < c.n) wave_bbox(c, i, valid, p.x, p.y, p.z);
 }
 
 // One workgroup of kGridThreads: one wave per simulation reduces that
@@ -132,52 +155,99 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kGridThreads / 64;
-  for (int s = wv; s < c.nsims; s += nw) {
-    const int q0 = c.chunk0[s], q1 = c.chunk0[s + 1];
-    double L[3] = {INFINITY, INFINITY, INFINITY}, H[3] = {-INFINITY, -INFINITY, -INFINITY};
-    bool bad = false;
-    for (int q = q0 + lane; q < q1; q += 64) {
-#pragma unroll
+  // grid of simulation s from the reduced bounding box (L, H)
+  auto set_grid = [&](int s, const double* L, const double* H, bool bad) {
+    SimGrid g;
+    const double h = c.sp[s].h;
+    long long nc = 1;
+    for (int k = 0; k < 3; ++k) {
+      g.lo[k] = 0.0;
+      g.dim[k] = 1;
+    }
+    if (c.sp[s].np > 0) {
       for (int k = 0; k < 3; ++k) {
-        const double a = c.part[6 * q + k];
-        bad = bad || isnan(a);
-        L[k] = fmin(L[k], a);
-        H[k] = fmax(H[k], c.part[6 * q + 3 + k]);
+        const double ext = (H[k] - L[k]) / h;
+        if (bad || !(ext >= 0.0) || !(ext < 1e30)) {
+          bad = true;
+        } else {
+          const double dm = floor(ext) + 1.0;
+          g.dim[k] = dm > 1048576.0 ? 1048576 : (int)dm;
+          g.lo[k] = L[k];
+        }
+        nc *= (long long)g.dim[k];
       }
     }
+    g.inv_h = 1.0 / h;
+    g.cell_off = 0;
+    c.sg[s] = g;
+    ncell[s] = nc;
+    if (bad) bad_total = 1;
+  };
+  if (c.nsims <= nw) {
+    // few simulations: the whole workgroup reduces each one's partials
+    __shared__ double red[kGridThreads / 64][6];
+    __shared__ int redbad;
+    for (int s = 0; s < c.nsims; ++s) {
+      const int q0 = c.chunk0[s], q1 = c.chunk0[s + 1];
+      double v[6] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
+      bool bad = false;
+      if (threadIdx.x == 0) redbad = 0;
+      for (int q = q0 + (int)threadIdx.x; q < q1; q += kGridThreads) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      for (int o = 32; o > 0; o >>= 1) {
-        L[k] = fmin(L[k], __shfl_xor(L[k], o, 64));
-        H[k] = fmax(H[k], __shfl_xor(H[k], o, 64));
-      }
-    bad = __any(bad);
-    if (lane == 0) {
-      SimGrid g;
-      const double h = c.sp[s].h;
-      long long nc = 1;
-      for (int k = 0; k < 3; ++k) {
-        g.lo[k] = 0.0;
-        g.dim[k] = 1;
-      }
-      if (c.sp[s].np > 0) {
         for (int k = 0; k < 3; ++k) {
-          const double ext = (H[k] - L[k]) / h;
-          if (bad || !(ext >= 0.0) || !(ext < 1e30)) {
-            bad = true;
-          } else {
-            const double dm = floor(ext) + 1.0;
-            g.dim[k] = dm > 1048576.0 ? 1048576 : (int)dm;
-            g.lo[k] = L[k];
-          }
-          nc *= (long long)g.dim[k];
+          const double a = c.part[6 * q + k];
+          bad = bad || isnan(a);
+          v[k] = fmin(v[k], a);
+          v[3 + k] = fmin(v[3 + k], -c.part[6 * q + 3 + k]);
         }
       }
-      g.inv_h = 1.0 / h;
-      g.cell_off = 0;
-      c.sg[s] = g;
-      ncell[s] = nc;
-      if (bad) bad_total = 1;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] = fmin(v[k], __shfl_xor(v[k], o, 64));
+      bad = __any(bad);
+      __syncthreads();
+      if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) red[wv][k] = v[k];
+        if (bad) redbad = 1;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double L[3], H[3];
+        for (int k = 0; k < 3; ++k) {
+          double a = red[0][k], b = red[0][3 + k];
+          for (int w = 1; w < nw; ++w) {
+            a = fmin(a, red[w][k]);
+            b = fmin(b, red[w][3 + k]);
+          }
+          L[k] = a;
+          H[k] = -b;
+        }
+        set_grid(s, L, H, redbad != 0);
+      }
+    }
+  } else {
+    for (int s = wv; s < c.nsims; s += nw) {
+      const int q0 = c.chunk0[s], q1 = c.chunk0[s + 1];
+      double L[3] = {INFINITY, INFINITY, INFINITY}, H[3] = {-INFINITY, -INFINITY, -INFINITY};
+      bool bad = false;
+      for (int q = q0 + lane; q < q1; q += 64) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double a = c.part[6 * q + k];
+          bad = bad || isnan(a);
+          L[k] = fmin(L[k], a);
+          H[k] = fmax(H[k], c.part[6 * q + 3 + k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        for (int o = 32; o > 0; o >>= 1) {
+          L[k] = fmin(L[k], __shfl_xor(L[k], o, 64));
+          H[k] = fmax(H[k], __shfl_xor(H[k], o, 64));
+        }
+      bad = __any(bad);
+      if (lane == 0) set_grid(s, L, H, bad);
     }
   }
   // fold the previous step's per-group contact counts into the totals
@@ -1106,6 +1176,23 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
 //    owner slot), then semi-implicit Euler (Eq. v, x), SPIRAL (Eq. spiral)
 //    with the old angular velocity, then Eq. w; Stokes drag (Section 2.1)
 // ---------------------------------------------------------------------------
+// sin(x)/x and cos(x).  The rotation angles of one step are tiny (|x| of
+// order 1e-5), where the Taylor polynomials below are exact to far below one
+// rounding (first omitted terms x^8/9! and x^10/10!, < 1e-24 relative for
+// |x| < 2^-8); larger angles use the library.
+__device__ __forceinline__ void sinc_cos(double x, double* sx, double* cx) {
+  if (fabs(x) < 0.00390625) {
+    const double x2 = x * x;
+    *sx = 1.0 - x2 * (1.0 / 6.0 - x2 * (1.0 / 120.0 - x2 * (1.0 / 5040.0)));
+    *cx = 1.0 - x2 * (0.5 - x2 * (1.0 / 24.0 - x2 * (1.0 / 720.0 - x2 * (1.0 / 40320.0))));
+  } else {
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    *sx = sn / x;
+    *cx = cs;
+  }
+}
+
 __device__ __forceinline__ void qmul(const double a[4], const double b[4], double o[4]) {
   const double s = a[0] * b[0] - ((a[1] * b[1] + a[2] * b[2]) + a[3] * b[3]);
   const double x = (a[0] * b[1] + b[0] * a[1]) + (a[2] * b[3] - a[3] * b[2]);
@@ -1124,6 +1211,7 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   const int i = i0 + (int)threadIdx.x;
   // new states are staged in LDS and written out as contiguous runs
   __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
+  double nx3[3] = {0.0, 0.0, 0.0};  // new centre, for the next step's bounding box
   if (i < n) {
   const double* res = c.res;
   // the particle's own state first, so that its loads overlap the gathers
@@ -1255,10 +1343,11 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   double q[4] = {q4.x, q4.y, q4.z, q4.w};
   const double wl = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
   if (wl > 0.0) {
+    // sin(phi)/|w| = (dt/2) sin(phi)/phi
     const double phi = 0.5 * dt * wl;
-    double sp, cp;
-    sincos(phi, &sp, &cp);
-    sp /= wl;
+    double sc, cp;
+    sinc_cos(phi, &sc, &cp);
+    const double sp = (0.5 * dt) * sc;
     const double r[4] = {cp, sp * w[0], sp * w[1], sp * w[2]};
     double o[4];
     qmul(q, r, o);
@@ -1266,10 +1355,12 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   }
   const double alen = sqrt((al[0] * al[0] + al[1] * al[1]) + al[2] * al[2]);
   if (alen > 0.0) {
-    const double th = (0.5 * dt) * (0.5 * dt) * alen;
-    double st, ct;
-    sincos(th, &st, &ct);
-    st /= alen;
+    // sin(theta)/|alpha| = (dt/2)^2 sin(theta)/theta
+    const double h2 = (0.5 * dt) * (0.5 * dt);
+    const double th = h2 * alen;
+    double sc, ct;
+    sinc_cos(th, &sc, &ct);
+    const double st = h2 * sc;
     const double r[4] = {ct, st * al[0], st * al[1], st * al[2]};
     double o[4];
     qmul(q, r, o);
@@ -1282,6 +1373,9 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
     ok = ok && isfinite(x[k]) && isfinite(v[k]) && isfinite(w[k]);
   }
   const int t = threadIdx.x;
+  nx3[0] = x[0];
+  nx3[1] = x[1];
+  nx3[2] = x[2];
   st_x[2 * t] = make_double2(x[0], x[1]);
   st_x[2 * t + 1] = make_double2(x[2], R);
   st_v[3 * t] = make_double2(v[0], v[1]);
@@ -1292,6 +1386,7 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   if (!ok) raise_flag(c.ctr, kFlagNonFinite);
   if (i == 0) c.ctr->stats_pending = 1;
   }
+  if (i - (int)(threadIdx.x & 63) < n) wave_bbox(c, i, i < n, nx3[0], nx3[1], nx3[2]);
   __syncthreads();
   const int np = min(n - i0, kThreads);
   double2* gx = reinterpret_cast<double2*>(S.xr + i0);
@@ -1375,7 +1470,8 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
   // ev (optional): kPhases + 1 events recorded at the phase boundaries
   const int nbp = blocks_for(c.n, kThreads);
   if (ev) (void)hipEventRecord(ev[0], s);
-  if (c.nchunks > 0) k_bbox_part<<<c.nchunks, kThreads, 0, s>>>(c, A);
+  // the bounding-box partials of A were written by the previous step's
+  // integration (or at set-up)
   k_grid<<<1, kGridThreads, 0, s>>>(c);
   if (ev) (void)hipEventRecord(ev[1], s);
   k_keys<<<nbp, kThreads, 0, s>>>(c, A);
@@ -1407,6 +1503,11 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
   if (ev) (void)hipEventRecord(ev[4], s);
   k_integrate<<<nbp, kThreads, 0, s>>>(c, B, cnew);
   if (ev) (void)hipEventRecord(ev[5], s);
+  return hipGetLastError();
+}
+
+hipError_t launch_bbox(const Ctx& c, const State& S, hipStream_t s) {
+  if (c.n > 0) k_bbox_part<<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, S);
   return hipGetLastError();
 }
 

@@ -50,9 +50,8 @@ struct Layout {
   }
 };
 
-int64_t nchunks_max(const sdem_config& c) {
-  return (c.n_max + kBboxChunk - 1) / kBboxChunk + c.nsims_max;
-}
+int64_t nwaves_max(const sdem_config& c) { return (c.n_max + kWave - 1) / kWave + 1; }
+int64_t nchunks_max(const sdem_config& c) { return nwaves_max(c) + c.nsims_max; }
 
 // Triangle bin tables sized from tri_max: 32 bins and 256 (bin, triangle)
 // entries per triangle, within fixed ceilings.
@@ -109,7 +108,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.sp = L.take<SimParams>(S);
   cc.sg = L.take<SimGrid>(S);
   cc.sim_of = L.take<int32_t>(N);
-  cc.chunks = L.take<int32_t>(3 * NC);
+  cc.wchunk = L.take<int32_t>((size_t)nwaves_max(cfg));
   cc.chunk0 = L.take<int32_t>(S + 1);
   cc.part = L.take<double>(6 * NC);
   cc.cell_cnt = L.take<int32_t>(Gm);
@@ -357,19 +356,24 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
     return code;
   };
   hipStream_t st = X->stream;
-  // per-slot simulation id and bounding-box chunks
-  std::vector<int32_t> sim_of((size_t)std::max<int64_t>(n, 1)), chunks, chunk0(nsims + 1);
-  for (int s = 0; s < nsims; ++s) {
-    chunk0[s] = (int32_t)(chunks.size() / 3);
+  // per-slot simulation id; bounding-box chunks = (wave of 64 slots,
+  // simulation) segments, in slot order (so simulations ascend)
+  std::vector<int32_t> sim_of((size_t)std::max<int64_t>(n, 1)), chunk0(nsims + 1);
+  std::vector<int32_t> wchunk((size_t)std::max<int64_t>((n + kWave - 1) / kWave, 1), 0), chunk_sim;
+  for (int s = 0; s < nsims; ++s)
     for (int64_t i = offsets[s]; i < offsets[s + 1]; ++i) sim_of[i] = s;
-    for (int64_t b = offsets[s]; b < offsets[s + 1]; b += kBboxChunk) {
-      chunks.push_back(s);
-      chunks.push_back((int32_t)b);
-      chunks.push_back((int32_t)std::min<int64_t>(offsets[s + 1], b + kBboxChunk));
-    }
+  for (int64_t w = 0; w * kWave < n; ++w) {
+    wchunk[w] = (int32_t)chunk_sim.size();
+    int prev = -1;
+    for (int64_t i = w * kWave; i < std::min<int64_t>(n, (w + 1) * kWave); ++i)
+      if (sim_of[i] != prev) {
+        prev = sim_of[i];
+        chunk_sim.push_back(prev);
+      }
   }
-  chunk0[nsims] = (int32_t)(chunks.size() / 3);
-  c.nchunks = chunk0[nsims];
+  for (int s = 0; s <= nsims; ++s)
+    chunk0[s] = (int32_t)(std::lower_bound(chunk_sim.begin(), chunk_sim.end(), s) - chunk_sim.begin());
+  c.nchunks = (int32_t)chunk_sim.size();
 
   auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, st) : hipSuccess;
@@ -403,10 +407,13 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   if (!e) e = hipMemsetAsync(c.pcnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
   if (!e) e = hipMemsetAsync(c.gcnt, 0, sizeof(int32_t) * c.ngroups, st);
   if (!e) e = cp(c.sim_of, sim_of.data(), sizeof(int32_t) * n);
-  if (!e) e = cp(c.chunks, chunks.data(), sizeof(int32_t) * chunks.size());
+  if (!e) e = cp(c.wchunk, wchunk.data(), sizeof(int32_t) * wchunk.size());
   if (!e) e = cp(c.chunk0, chunk0.data(), sizeof(int32_t) * chunk0.size());
   if (!e) e = launch_pack_state(c, X->st[0], dev_in[0], dev_in[1], dev_in[2], dev_in[3],
                                 dev_in[4], st);
+  // bounding-box partials of the initial state (each step's integration
+  // writes those of the next)
+  if (!e) e = launch_bbox(c, X->st[0], st);
   if (!e) e = hipStreamSynchronize(st);
   if (e) {
     fail(SDEM_EHIP, "init copies failed: %s", hipGetErrorString(e));

@@ -10,7 +10,8 @@ namespace sdem {
 
 constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scan
 constexpr int kScanThreads = 256;
-constexpr int kBboxChunk = 1024;    // particles per bounding-box partial
+constexpr int kWave = 64;           // slots per wave; bounding-box partials are
+                                    // per (wave of slots, simulation)
 constexpr int kSpr = 8;             // doubles per contact spring record
 constexpr int kRes = 10;            // doubles per contact result record
 constexpr int kThreads = 256;       // threads per workgroup of the particle kernels
@@ -117,9 +118,10 @@ struct Ctx {
   SimParams* sp;      // [nsims]
   SimGrid* sg;        // [nsims]
   int32_t* sim_of;    // [n] simulation of each slot (fixed)
-  int32_t* chunks;    // [nchunks][3] (sim, begin, end) for the bounding box
+  int32_t* wchunk;    // [n/64] first bounding-box chunk of each wave of slots
   int32_t* chunk0;    // [nsims+1] first chunk of each simulation
-  double* part;       // [nchunks][6] bounding-box partials
+  double* part;       // [nchunks][6] bounding-box partials (min xyz, max xyz),
+                      // one per (wave, simulation) segment, simulations ascending
   int32_t* cell_cnt;  // [cap_cells] zero between steps
   int32_t* cell_start;// [cap_cells+1]
   unsigned long long* rowmax;  // [cap_cells] at the first cell of each cell row:
@@ -239,6 +241,7 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
                        hipEvent_t* ev = nullptr);
 hipError_t launch_scatter_state(const Ctx& c, const State& S, double* x, double* v, double* w,
                                 double* q, double* F, double* T, hipStream_t s);
+hipError_t launch_bbox(const Ctx& c, const State& S, hipStream_t s);
 hipError_t launch_pack_state(const Ctx& c, const State& S, const double* x, const double* v,
                              const double* w, const double* q, const double* R, hipStream_t s);
 hipError_t launch_mesh_planes(const Ctx& c, hipStream_t s);
