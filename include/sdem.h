@@ -93,11 +93,24 @@ typedef struct {
  *                Each particle searches the cells within R_i + R_max of its
  *                centre, so the contact set does not depend on this value;
  *                below 1 it trades more cell ranges for fewer candidates
- *                (polydisperse systems) */
+ *                (polydisperse systems)
+ *  skin          >= 0, in units of R_max of each simulation.  0: the cells are
+ *                rebuilt every step (Section 3.3).  s > 0: the cells and the
+ *                particle order are kept between rebuilds, and every search
+ *                reaches s R_max / 2 further (plus, should a particle drift
+ *                farther than that from where it was binned, the excess,
+ *                measured every step).  The cells are rebuilt every
+ *                rebuild_every steps and at the first step of an sdem_step
+ *                call after such a drift.  The contact set is the same for
+ *                every value; only the work per step changes
+ *  rebuild_every with skin > 0: steps between rebuilds, >= 1; 0 selects 64 */
 typedef struct {
   int64_t n_max, contacts_max, cells_max, tri_max;
   int32_t nsims_max, precision, block, detect_lanes;
   double cell_factor;
+  double skin;
+  int32_t rebuild_every;
+  int32_t reserved;  /* 0 */
 } sdem_config;
 
 /* Bytes of device workspace a context with these capacities needs. */
@@ -139,10 +152,13 @@ int sdem_step(sdem_ctx* ctx, int64_t nsteps);
 
 /* Measurement aid: like sdem_step, but launches each step's kernels directly
  * (no graph) with HIP events between its phases on the context's stream,
- * and returns the mean time per step of each phase in phase_ms[5]:
- *   0 bounding box and grid, 1 cell sort and state reorder (and mesh
- *   motion), 2 narrow phase (contact counts, scan, records), 3 contact forces
- *   and torques with the spring carry-over, 4 integration.
+ * and returns the mean time per step of each phase in phase_ms[0..4], and in
+ * phase_ms[5] the mean duration of the contact-force kernel alone, from start
+ * and stop events attached to its dispatch (hipExtLaunchKernel):
+ *   0 grid (from the bounding box reduced by the previous integration),
+ *   1 cell sort and state reorder (and mesh motion), 2 narrow phase (contact
+ *   records), 3 contact forces and torques with the spring carry-over,
+ *   4 integration.
  * Results are identical to sdem_step's. */
 int sdem_step_profiled(sdem_ctx* ctx, int64_t nsteps, double* phase_ms);
 
@@ -159,10 +175,12 @@ int sdem_read_state(sdem_ctx* ctx, double* x, double* v, double* w, double* q, d
 int sdem_read_contacts(sdem_ctx* ctx, int64_t cap, int64_t* n_out, int32_t* ki, int32_t* kj,
                        double* us, double* ur, double* ut);
 
-/* Steps completed, and the sums over those steps of particle-pair and
- * particle-triangle contact counts (for contacts/s).  Any pointer may be
+/* Steps completed, the sums over those steps of particle-pair and
+ * particle-triangle contact counts (for contacts/s), and the number of steps
+ * that rebuilt the cells (all of them when skin = 0).  Any pointer may be
  * NULL.  Synchronises the stream. */
-int sdem_stats(sdem_ctx* ctx, int64_t* steps, int64_t* pp_contacts, int64_t* pw_contacts);
+int sdem_stats(sdem_ctx* ctx, int64_t* steps, int64_t* pp_contacts, int64_t* pw_contacts,
+               int64_t* rebuilds);
 
 /* Releases the host-side context (the workspace stays the caller's). */
 int sdem_destroy(sdem_ctx* ctx);

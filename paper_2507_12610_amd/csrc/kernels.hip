@@ -12,6 +12,8 @@
 // previous step's buffers untouched.
 #include <math.h>
 
+#include <hip/hip_ext.h>
+
 #include "sdem_internal.h"
 
 namespace sdem {
@@ -46,31 +48,33 @@ __device__ __forceinline__ void raise_flag(Counters* ctr, int f) { atomicOr(&ctr
 // non-finite coordinate turns the partial's minimum into NaN, which the grid
 // kernel reports.
 __device__ __forceinline__ void wave_bbox(const Ctx& c, int i, bool valid, double x, double y,
-                                          double z) {
+                                          double z, double drift = 0.0) {
   const int lane = threadIdx.x & 63;
   const int sim = valid ? c.sim_of[i] : 0x7fffffff;
-  double v[6] = {x, y, z, -x, -y, -z};  // minima of (x, y, z) and of (-x, -y, -z)
+  // minima of (x, y, z), of (-x, -y, -z) and of -drift
+  double v[7] = {x, y, z, -x, -y, -z, -drift};
   const bool bad = valid && !(isfinite(x) && isfinite(y) && isfinite(z));
   if (!valid) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = INFINITY;
+    for (int k = 0; k < 7; ++k) v[k] = INFINITY;
   }
   const int s0 = __shfl(sim, 0, 64);
   const int first = c.wchunk[i >> 6];
   if (__all(!valid || sim == s0)) {
     // the whole wave is one simulation: butterfly minimum
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 7; ++k)
       for (int o = 32; o > 0; o >>= 1) v[k] = fmin(v[k], __shfl_xor(v[k], o, 64));
     const bool anybad = __any(bad);
     if (lane == 0) {
-      double* p = c.part + 6 * (size_t)first;
+      double* p = c.part + kPart * (size_t)first;
       p[0] = anybad ? NAN : v[0];
       p[1] = v[1];
       p[2] = v[2];
       p[3] = -v[3];
       p[4] = -v[4];
       p[5] = -v[5];
+      p[6] = -v[6];
     }
   } else {
     // several simulations: segmented minimum over runs of equal sim
@@ -81,7 +85,7 @@ __device__ __forceinline__ void wave_bbox(const Ctx& c, int i, bool valid, doubl
       const int ob = __shfl_down(nb, o, 64);
       const bool same = lane + o < 64 && os == sim;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
+      for (int k = 0; k < 7; ++k) {
         const double ov = __shfl_down(v[k], o, 64);
         if (same) v[k] = fmin(v[k], ov);
       }
@@ -92,13 +96,14 @@ __device__ __forceinline__ void wave_bbox(const Ctx& c, int i, bool valid, doubl
     const unsigned long long heads = __ballot(head);
     if (head) {
       const int k = first + __popcll(heads & ((1ull << lane) - 1ull));
-      double* p = c.part + 6 * (size_t)k;
+      double* p = c.part + kPart * (size_t)k;
       p[0] = nb ? NAN : v[0];
       p[1] = v[1];
       p[2] = v[2];
       p[3] = -v[3];
       p[4] = -v[4];
       p[5] = -v[5];
+      p[6] = -v[6];
     }
   }
 }
@@ -144,14 +149,22 @@ __device__ __forceinline__ void block_exclusive_scan_ll(long long* buf, int len,
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
+__global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c, int rebuild) {
   if (c.ctr->flags) return;
   __shared__ long long ncell[kMaxSims];
   __shared__ long long total;
   __shared__ int bad_total;
+  // contact record counters of the slot groups, filled by the narrow phase
+  for (int q = threadIdx.x; q < c.ngroups; q += kGridThreads) c.gcnt[q] = 0;
+  __shared__ int drifted;
   if (threadIdx.x == 0) {
     bad_total = 0;
     atomicAdd(&c.ctr->steps, 1ull);  // steps started (the host discounts a failed one)
+    drifted = c.ctr->rebuild_next;
+    if (rebuild) {
+      c.ctr->rebuild_next = 0;
+      c.ctr->rebuilds += 1ull;
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kGridThreads / 64;
@@ -179,11 +192,28 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
     }
     g.inv_h = 1.0 / h;
     g.cell_off = 0;
+    g.extra = 0.0;
     c.sg[s] = g;
     ncell[s] = nc;
     if (bad) bad_total = 1;
   };
-  if (c.nsims <= nw) {
+  if (!rebuild) {
+    // The grid of the last rebuild stays.  If a particle drifted beyond half
+    // the skin, every search of this step reaches by the excess further: the
+    // largest drift of each simulation, from the integration's partials.
+    if (drifted) {
+      for (int s = wv; s < c.nsims; s += nw) {
+        const int q0 = c.chunk0[s], q1 = c.chunk0[s + 1];
+        double dmax = 0.0;
+        for (int q = q0 + lane; q < q1; q += 64) dmax = fmax(dmax, c.part[kPart * q + 6]);
+        for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+        if (lane == 0) {
+          const double ex = dmax - c.sp[s].half_skin;
+          c.sg[s].extra = ex > 0.0 ? ex * (1.0 + 1e-6) : 0.0;
+        }
+      }
+    }
+  } else if (c.nsims <= nw) {
     // few simulations: the whole workgroup reduces each one's partials
     __shared__ double red[kGridThreads / 64][6];
     __shared__ int redbad;
@@ -195,10 +225,10 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
       for (int q = q0 + (int)threadIdx.x; q < q1; q += kGridThreads) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const double a = c.part[6 * q + k];
+          const double a = c.part[kPart * q + k];
           bad = bad || isnan(a);
           v[k] = fmin(v[k], a);
-          v[3 + k] = fmin(v[3 + k], -c.part[6 * q + 3 + k]);
+          v[3 + k] = fmin(v[3 + k], -c.part[kPart * q + 3 + k]);
         }
       }
 #pragma unroll
@@ -234,10 +264,10 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
       for (int q = q0 + lane; q < q1; q += 64) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const double a = c.part[6 * q + k];
+          const double a = c.part[kPart * q + k];
           bad = bad || isnan(a);
           L[k] = fmin(L[k], a);
-          H[k] = fmax(H[k], c.part[6 * q + 3 + k]);
+          H[k] = fmax(H[k], c.part[kPart * q + 3 + k]);
         }
       }
 #pragma unroll
@@ -278,6 +308,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
     }
   }
   __syncthreads();
+  if (!rebuild) return;
   block_exclusive_scan_ll(ncell, c.nsims, &total);
   for (int s = threadIdx.x; s < c.nsims; s += kGridThreads) {
     const long long off = ncell[s];
@@ -480,6 +511,7 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
       }
     }
     const double4 xr = A.xr[so], q = A.q[so];
+    B.xb[d] = make_double4(xr.x, xr.y, xr.z, 0.0);  // binned centre
     const double2* vin = reinterpret_cast<const double2*>(A.vw + 6 * (size_t)so);
     const int t = threadIdx.x;
     st_x[2 * t] = make_double2(xr.x, xr.y);
@@ -498,8 +530,6 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
     B.pid[d] = id;
     B.key[d] = k;
     B.os[d] = make_int4(so, cold.off[so], cold.cnt[so], id);
-    c.pcnt[d] = 0;
-    if ((d & (kGroup - 1)) == 0) c.gcnt[d >> kGroupShift] = 0;
   }
   // largest radius per cell row: slots are in row order, so a wave's rows
   // are runs of lanes; a segmented maximum leaves one atomic per run
@@ -695,8 +725,11 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
 //    the partner's list (one integer atomic per pair).
 // ---------------------------------------------------------------------------
 template <int SUB>
-__global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn) {
+__global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Contacts cn,
+                                                    int rebuilt) {
   if (c.ctr->flags) return;
+  // the sorted copy when this step rebuilt the cells, else the kept order
+  const State S = rebuilt ? B : A;
   __shared__ int hits[kThreads / 64][kMaxOwn][64];
   const int n = c.n;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -752,7 +785,9 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
     const float fx = (float)((xs - gr.lo[0]) * gr.inv_h - cx);
     const float fy = (float)((ys - gr.lo[1]) * gr.inv_h - cy);
     const float fz = (float)((zs - gr.lo[2]) * gr.inv_h - cz);
-    const double reach = (Rs + c.sp[sim].rmax) * (1.0 + 1e-9);
+    // drift allowed since the cells were built (plus any excess measured)
+    const double hs = c.sp[sim].half_skin + gr.extra;
+    const double reach = ((Rs + c.sp[sim].rmax) + hs) * (1.0 + 1e-9);
     const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, ny);
     const int y1 = cell_coord(ys + reach, gr.lo[1], gr.inv_h, ny);
     const int z1 = cell_coord(zs + reach, gr.lo[2], gr.inv_h, nz);
@@ -777,7 +812,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State S, Contacts cn
       const float ry = (float)(yy - cy), rz = (float)(zz - cz);
       const float dy = fmaxf(fmaxf(ry - fy, fy - (ry + 1.0f)) - 1e-5f, 0.0f);
       const float dz = fmaxf(fmaxf(rz - fz, fz - (rz + 1.0f)) - 1e-5f, 0.0f);
-      const float rho = (float)((Rs + rm) * gr.inv_h) * (1.0f + 1e-6f) + 1e-5f;
+      const float rho = (float)(((Rs + rm) + hs) * gr.inv_h) * (1.0f + 1e-6f) + 1e-5f;
       const float d2 = dy * dy + dz * dz;
       if (d2 > rho * rho) return;
       const float xr = sqrtf(rho * rho - d2) * (1.0f + 1e-6f) + 1e-5f;
@@ -949,8 +984,15 @@ __device__ __forceinline__ int find_old(const Contacts& co, int b0, int n, int2 
 }
 
 template <typename RT>
-__global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur, Contacts old) {
+__global__ __launch_bounds__(kThreads) void k_force(Ctx c, State A, State B, Contacts cur,
+                                                   Contacts old, int rebuilt) {
   if (c.ctr->flags) return;
+  const State S = rebuilt ? B : A;
+  // (previous slot, its previous contact segment, id): carried by the
+  // reorder, or the slot itself when the order was kept
+  auto origin = [&](int p) {
+    return rebuilt ? S.os[p] : make_int4(p, old.off[p], old.cnt[p], S.pid[p]);
+  };
   // one workgroup per slot group (consecutive groups on one XCD share its L2)
   const int grp = xcd_remap(blockIdx.x, gridDim.x);
   const int cnt = min(c.gcnt[grp], c.gcap);
@@ -971,7 +1013,7 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
     // both bodies are gathered at once; the canonical orientation is then
     // chosen in registers
     const double4 pa = S.xr[a];
-    const int4 oa = S.os[a];
+    const int4 oa = origin(a);
     const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
     const double2 va0 = va[0], va1 = va[1], va2 = va[2];
     double4 pb;
@@ -980,7 +1022,7 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State S, Contacts cur
     int m = 0;
     if (!wall) {
       pb = S.xr[b];
-      ob = S.os[b];
+      ob = origin(b);
       const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
       vb0 = vb[0];
       vb1 = vb[1];
@@ -1204,14 +1246,20 @@ __device__ __forceinline__ void qmul(const double a[4], const double b[4], doubl
   o[3] = z;
 }
 
-__global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts cur) {
+__global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B, Contacts cur,
+                                                       int rebuilt) {
   if (c.ctr->flags) return;
+  // reads the step's state (the sorted copy B, or A when the order was
+  // kept) and writes the new state to B
+  const State S = rebuilt ? B : A;
   const int n = c.n;
   const int i0 = blockIdx.x * kThreads;
   const int i = i0 + (int)threadIdx.x;
   // new states are staged in LDS and written out as contiguous runs
   __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
   double nx3[3] = {0.0, 0.0, 0.0};  // new centre, for the next step's bounding box
+  bool drift = false;
+  double ddrift = 0.0;
   if (i < n) {
   const double* res = c.res;
   // the particle's own state first, so that its loads overlap the gathers
@@ -1226,6 +1274,7 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
     // owned contacts in record order, four records in flight
     const int e0 = cur.off[i], e1 = e0 + cur.cnt[i];
     const int m = min(c.pcnt[i], kMaxRev);
+    c.pcnt[i] = 0;  // cleared for the next step's narrow phase
     for (int e = e0; e < e1; e += 4) {
       double2 f[4][3];
 #pragma unroll
@@ -1376,6 +1425,18 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   nx3[0] = x[0];
   nx3[1] = x[1];
   nx3[2] = x[2];
+  if (!rebuilt) {  // the kept order: carry the slot's labels over to B
+    B.key[i] = A.key[i];
+    B.pid[i] = A.pid[i];
+    B.xb[i] = A.xb[i];
+  }
+  if (c.skin_on) {  // drift from the binned centre, and whether beyond half the skin
+    const double4 xb = S.xb[i];
+    const double ex = x[0] - xb.x, ey = x[1] - xb.y, ez = x[2] - xb.z;
+    const double d2 = (ex * ex + ey * ey) + ez * ez;
+    ddrift = sqrt(d2) * (1.0 + 1e-12);
+    drift = d2 > P.half_skin * P.half_skin;
+  }
   st_x[2 * t] = make_double2(x[0], x[1]);
   st_x[2 * t + 1] = make_double2(x[2], R);
   st_v[3 * t] = make_double2(v[0], v[1]);
@@ -1386,12 +1447,13 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State S, Contacts
   if (!ok) raise_flag(c.ctr, kFlagNonFinite);
   if (i == 0) c.ctr->stats_pending = 1;
   }
-  if (i - (int)(threadIdx.x & 63) < n) wave_bbox(c, i, i < n, nx3[0], nx3[1], nx3[2]);
+  if (i - (int)(threadIdx.x & 63) < n) wave_bbox(c, i, i < n, nx3[0], nx3[1], nx3[2], ddrift);
+  if (__any(drift) && (threadIdx.x & 63) == 0) atomicOr(&c.ctr->rebuild_next, 1);
   __syncthreads();
   const int np = min(n - i0, kThreads);
-  double2* gx = reinterpret_cast<double2*>(S.xr + i0);
-  double2* gv = reinterpret_cast<double2*>(S.vw + 6 * (size_t)i0);
-  double2* gq = reinterpret_cast<double2*>(S.q + i0);
+  double2* gx = reinterpret_cast<double2*>(B.xr + i0);
+  double2* gv = reinterpret_cast<double2*>(B.vw + 6 * (size_t)i0);
+  double2* gq = reinterpret_cast<double2*>(B.q + i0);
   for (int k = threadIdx.x; k < 2 * np; k += kThreads) gx[k] = st_x[k];
   for (int k = threadIdx.x; k < 3 * np; k += kThreads) gv[k] = st_v[k];
   for (int k = threadIdx.x; k < 2 * np; k += kThreads) gq[k] = st_q[k];
@@ -1448,6 +1510,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_state(Ctx c, State S, const d
              : make_double4(1.0, 0.0, 0.0, 0.0);
   S.pid[i] = i;
   S.os[i] = make_int4(i, 0, 0, i);
+  S.xb[i] = make_double4(x[i], x[n + i], x[2 * n + i], 0.0);
   S.key[i] = 0;
   c.F[i] = c.F[n + i] = c.F[2 * n + i] = 0.0;
   c.T[i] = c.T[n + i] = c.T[2 * n + i] = 0.0;
@@ -1466,42 +1529,55 @@ __global__ void k_selftest(int64_t n, const double* in, const double* in2, doubl
 static inline int blocks_for(int n, int t) { return n > 0 ? (n + t - 1) / t : 1; }
 
 hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
-                       const Contacts& cnew, int precision, hipStream_t s, hipEvent_t* ev) {
-  // ev (optional): kPhases + 1 events recorded at the phase boundaries
+                       const Contacts& cnew, int precision, int rebuild, hipStream_t s,
+                       hipEvent_t* ev) {
+  // rebuild: sort the particles into fresh cells (A -> B); otherwise the
+  // cells and the slot order of A are kept and only the narrow phase, the
+  // forces and the integration (A -> B) run.  ev (optional): kEvents events,
+  // the phase boundaries and the force kernel's own start/stop.
   const int nbp = blocks_for(c.n, kThreads);
   if (ev) (void)hipEventRecord(ev[0], s);
-  // the bounding-box partials of A were written by the previous step's
-  // integration (or at set-up)
-  k_grid<<<1, kGridThreads, 0, s>>>(c);
+  k_grid<<<1, kGridThreads, 0, s>>>(c, rebuild);
   if (ev) (void)hipEventRecord(ev[1], s);
-  k_keys<<<nbp, kThreads, 0, s>>>(c, A);
-  if (c.cap_cells <= kScanSmall) {
-    k_scan_small<<<1, kScanOne, 0, s>>>(c);
-  } else {
-    k_scan_reduce<<<kScanBlocks, kScanThreads, 0, s>>>(c);
-    k_scan_top<<<1, kScanThreads, 0, s>>>(c);
-    k_scan_down<<<kScanBlocks, kScanThreads, 0, s>>>(c);
+  if (rebuild) {
+    k_keys<<<nbp, kThreads, 0, s>>>(c, A);
+    if (c.cap_cells <= kScanSmall) {
+      k_scan_small<<<1, kScanOne, 0, s>>>(c);
+    } else {
+      k_scan_reduce<<<kScanBlocks, kScanThreads, 0, s>>>(c);
+      k_scan_top<<<1, kScanThreads, 0, s>>>(c);
+      k_scan_down<<<kScanBlocks, kScanThreads, 0, s>>>(c);
+    }
+    k_scatter<<<nbp, kThreads, 0, s>>>(c);
+    k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B, cold);
   }
-  k_scatter<<<nbp, kThreads, 0, s>>>(c);
-  k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B, cold);
   if (c.any_rotating) {
     k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
     (void)launch_mesh_bins(c, s);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
   switch (c.detect_sub) {
-    case 1: k_detect<1><<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
-    case 2: k_detect<2><<<blocks_for(2 * c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
-    case 8: k_detect<8><<<blocks_for(8 * c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
-    default: k_detect<4><<<blocks_for(4 * c.n, kThreads), kThreads, 0, s>>>(c, B, cnew); break;
+    case 1: k_detect<1><<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
+    case 2: k_detect<2><<<blocks_for(2 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
+    case 8: k_detect<8><<<blocks_for(8 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
+    default: k_detect<4><<<blocks_for(4 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
   }
   if (ev) (void)hipEventRecord(ev[3], s);
-  if (precision == SDEM_MIXED)
-    k_force<float><<<c.ngroups, kThreads, 0, s>>>(c, B, cnew, cold);
-  else
-    k_force<double><<<c.ngroups, kThreads, 0, s>>>(c, B, cnew, cold);
+  if (ev) {
+    // profiled: the dispatch itself records start and stop of the kernel
+    if (precision == SDEM_MIXED)
+      hipExtLaunchKernelGGL(k_force<float>, dim3(c.ngroups), dim3(kThreads), 0, s, ev[kPhases + 1],
+                            ev[kPhases + 2], 0, c, A, B, cnew, cold, rebuild);
+    else
+      hipExtLaunchKernelGGL(k_force<double>, dim3(c.ngroups), dim3(kThreads), 0, s, ev[kPhases + 1],
+                            ev[kPhases + 2], 0, c, A, B, cnew, cold, rebuild);
+  } else if (precision == SDEM_MIXED) {
+    k_force<float><<<c.ngroups, kThreads, 0, s>>>(c, A, B, cnew, cold, rebuild);
+  } else {
+    k_force<double><<<c.ngroups, kThreads, 0, s>>>(c, A, B, cnew, cold, rebuild);
+  }
   if (ev) (void)hipEventRecord(ev[4], s);
-  k_integrate<<<nbp, kThreads, 0, s>>>(c, B, cnew);
+  k_integrate<<<nbp, kThreads, 0, s>>>(c, A, B, cnew, rebuild);
   if (ev) (void)hipEventRecord(ev[5], s);
   return hipGetLastError();
 }

@@ -80,8 +80,15 @@ struct sdem_ctx {
   std::vector<int64_t> offsets;
   std::vector<std::vector<double>> mesh_tri, mesh_r;
   std::vector<double> rmax;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // graphs by pattern and starting buffer parity: two full steps, one full
+  // step, one step keeping the cells, eight steps keeping the cells
+  hipGraphExec_t graph[4][2] = {};
   bool graph_failed = false;
+  // rebuild schedule (skin > 0): steps since the last rebuild, and a drift
+  // past half the skin seen at the last synchronisation (or no rebuild yet)
+  int64_t since = 0;
+  bool need_rebuild = true;
+  int rebuild_every = 1;
 };
 
 // contact records are allocated per group of kGroup slots: gcap each
@@ -110,7 +117,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.sim_of = L.take<int32_t>(N);
   cc.wchunk = L.take<int32_t>((size_t)nwaves_max(cfg));
   cc.chunk0 = L.take<int32_t>(S + 1);
-  cc.part = L.take<double>(6 * NC);
+  cc.part = L.take<double>(kPart * NC);
   cc.cell_cnt = L.take<int32_t>(Gm);
   cc.cell_start = L.take<int32_t>(Gm + 1);
   cc.rowmax = L.take<unsigned long long>(Gm);
@@ -142,6 +149,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
     s.pid = L.take<int32_t>(N);
     s.key = L.take<int32_t>(N);
     s.os = L.take<int4>(N);
+    s.xb = L.take<double4>(N);
     if (st) st[b] = s;
   }
   for (int b = 0; b < 2; ++b) {
@@ -182,6 +190,9 @@ static int check_config(const sdem_config* cfg) {
     return fail(SDEM_EINVAL, "detect_lanes must be 0, 1, 2, 4 or 8");
   if (!(cfg->cell_factor == 0.0 || cfg->cell_factor >= 0.125) || !isfinite(cfg->cell_factor))
     return fail(SDEM_EINVAL, "cell_factor must be >= 0.125 (0 selects 1)");
+  if (!(cfg->skin >= 0.0) || !(cfg->skin <= 100.0))
+    return fail(SDEM_EINVAL, "skin must be in [0, 100]");
+  if (cfg->rebuild_every < 0) return fail(SDEM_EINVAL, "rebuild_every must be >= 0");
   return SDEM_OK;
 }
 
@@ -213,7 +224,7 @@ static bool is_device_ptr(const void* p) {
          a.type == hipMemoryTypeUnified;
 }
 
-static SimParams derive(const sdem_params& p, double cell_factor, double rmax) {
+static SimParams derive(const sdem_params& p, double cell_factor, double rmax, double skin = 0.0) {
   SimParams d{};
   d.rho = p.rho;
   d.E = p.E;
@@ -247,6 +258,7 @@ static SimParams derive(const sdem_params& p, double cell_factor, double rmax) {
   const double rm = rmax > 0 ? rmax : 1.0;
   d.rmax = rm;
   d.h = cell_factor * 2.0 * rm;
+  d.half_skin = 0.5 * skin * rm;
   d.rotating = (p.mesh_omega[0] != 0.0 || p.mesh_omega[1] != 0.0 || p.mesh_omega[2] != 0.0);
   return d;
 }
@@ -255,7 +267,7 @@ static int upload_params(sdem_ctx* x) {
   std::vector<SimParams> sp(x->nsims);
   int tri0 = 0;
   for (int s = 0; s < x->nsims; ++s) {
-    sp[s] = derive(x->params[s], x->cfg.cell_factor, x->rmax[s]);
+    sp[s] = derive(x->params[s], x->cfg.cell_factor, x->rmax[s], x->cfg.skin);
     sp[s].p0 = (int32_t)x->offsets[s];
     sp[s].np = (int32_t)(x->offsets[s + 1] - x->offsets[s]);
     sp[s].tri0 = tri0;
@@ -289,6 +301,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   sdem_config cfg = *cfg_in;
   if (cfg.cell_factor == 0.0) cfg.cell_factor = 1.0;
   if (cfg.block == 0) cfg.block = kThreads;
+  cfg.reserved = 0;
   if (nsims < 1 || nsims > cfg.nsims_max)
     return fail(SDEM_ECAPACITY, "nsims %d outside [1, nsims_max=%d]", nsims, cfg.nsims_max);
   if (!params || !offsets) return fail(SDEM_EINVAL, "params and offsets are required");
@@ -348,6 +361,8 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
     c.force_blocks = std::max(8, (ncu * kForceBlocksPerCU + 7) / 8 * 8);
   }
   c.detect_sub = cfg.detect_lanes ? cfg.detect_lanes : 4;
+  c.skin_on = cfg.skin > 0.0 ? 1 : 0;
+  X->rebuild_every = c.skin_on ? (cfg.rebuild_every > 0 ? cfg.rebuild_every : 64) : 1;
   c.ngroups = (int32_t)((std::max<int64_t>(n, 1) + kGroup - 1) / kGroup);
   c.gcap = (int32_t)group_cap(cfg);
 
@@ -673,6 +688,7 @@ static int finish_steps(sdem_ctx* X, const Counters& before, int start) {
   Counters after;
   HIP_TRY(hipMemcpyAsync(&after, X->c.ctr, sizeof after, hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipStreamSynchronize(X->stream));
+  if (after.rebuild_next) X->need_rebuild = true;
   if (!after.flags) return SDEM_OK;
   const int64_t done = (int64_t)(after.steps - before.steps) - 1;  // the failed one counted
   X->cur = (int)((start + done) & 1);
@@ -699,28 +715,47 @@ static int finish_steps(sdem_ctx* X, const Counters& before, int start) {
   return fail(SDEM_ENONFINITE, "step %lld: non-finite position, velocity or spin", at);
 }
 
-static hipError_t enqueue_steps(sdem_ctx* X, int k) {
+// Steps keep the cells when a skin is set, except every rebuild_every-th
+// step and the first step after a drift past half the skin was seen.
+static bool rebuild_now(const sdem_ctx* X) {
+  return !X->c.skin_on || X->need_rebuild || X->since >= X->rebuild_every;
+}
+static void count_step(sdem_ctx* X, bool rebuild) {
+  if (rebuild) {
+    X->since = 1;
+    X->need_rebuild = false;
+  } else {
+    ++X->since;
+  }
+}
+
+// k steps from the current buffer parity, all rebuilding or all keeping the
+// cells (the parity is not advanced here)
+static hipError_t enqueue_steps(sdem_ctx* X, int k, bool rebuild, hipEvent_t* ev = nullptr) {
   for (int i = 0; i < k; ++i) {
     const int a = (X->cur + i) & 1;
     hipError_t e = launch_step(X->c, X->st[a], X->st[a ^ 1], X->ct[a], X->ct[a ^ 1],
-                               X->cfg.precision, X->stream);
+                               X->cfg.precision, rebuild ? 1 : 0, X->stream, ev);
     if (e) return e;
   }
   return hipSuccess;
 }
 
-// A graph of two steps starting from buffer parity p (the pointers of both
-// buffers are baked in; after two steps the parity is p again).
-static hipGraphExec_t pair_graph(sdem_ctx* X) {
+// Graph patterns: {steps, rebuild}.  A graph bakes in the pointers of both
+// buffers for its starting parity.
+constexpr int kPatSteps[4] = {2, 1, 1, 8};
+constexpr bool kPatRebuild[4] = {true, true, false, false};
+
+static hipGraphExec_t step_graph(sdem_ctx* X, int pat) {
   const int p = X->cur;
-  if (X->graph[p] || X->graph_failed || !X->stream) return X->graph[p];
+  if (X->graph[pat][p] || X->graph_failed || !X->stream) return X->graph[pat][p];
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(X->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     X->graph_failed = true;
     return nullptr;
   }
-  hipError_t e = enqueue_steps(X, 2);
+  hipError_t e = enqueue_steps(X, kPatSteps[pat], kPatRebuild[pat]);
   hipError_t e2 = hipStreamEndCapture(X->stream, &g);
   hipGraphExec_t ex = nullptr;
   if (e || e2 || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
@@ -729,8 +764,17 @@ static hipGraphExec_t pair_graph(sdem_ctx* X) {
     ex = nullptr;
   }
   if (g) (void)hipGraphDestroy(g);
-  X->graph[p] = ex;
+  X->graph[pat][p] = ex;
   return ex;
+}
+
+static hipError_t run_pattern(sdem_ctx* X, int pat) {
+  hipGraphExec_t g = step_graph(X, pat);
+  hipError_t e = g ? hipGraphLaunch(g, X->stream) : enqueue_steps(X, kPatSteps[pat], kPatRebuild[pat]);
+  if (e) return e;
+  for (int i = 0; i < kPatSteps[pat]; ++i) count_step(X, kPatRebuild[pat]);
+  if (kPatSteps[pat] & 1) X->cur ^= 1;
+  return hipSuccess;
 }
 
 int sdem_step(sdem_ctx* X, int64_t nsteps) {
@@ -744,18 +788,19 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
   HIP_TRY(hipStreamSynchronize(X->stream));
   const int start = X->cur;
   int64_t left = nsteps;
-  while (left >= 2) {
-    hipGraphExec_t g = pair_graph(X);
-    if (g) {
-      HIP_TRY(hipGraphLaunch(g, X->stream));
+  while (left > 0) {
+    int pat;
+    if (!X->c.skin_on) {
+      pat = left >= 2 ? 0 : 1;
+    } else if (rebuild_now(X)) {
+      pat = 1;
+    } else if (left >= 8 && X->since + 8 <= X->rebuild_every) {
+      pat = 3;
     } else {
-      HIP_TRY(enqueue_steps(X, 2));
+      pat = 2;
     }
-    left -= 2;
-  }
-  if (left) {
-    HIP_TRY(enqueue_steps(X, 1));
-    X->cur ^= 1;
+    HIP_TRY(run_pattern(X, pat));
+    left -= kPatSteps[pat];
   }
   return finish_steps(X, before, start);
 }
@@ -764,20 +809,20 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
   if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
   if (X->failed) return fail(SDEM_ESTATE, "context failed in an earlier step; read it and re-init");
   if (nsteps < 0 || !phase_ms) return fail(SDEM_EINVAL, "bad arguments");
-  for (int k = 0; k < kPhases; ++k) phase_ms[k] = 0.0;
+  for (int k = 0; k <= kPhases; ++k) phase_ms[k] = 0.0;
   if (nsteps == 0) return SDEM_OK;
   X->stepped = true;
-  hipEvent_t ev[kPhases + 1];
-  for (int k = 0; k <= kPhases; ++k) HIP_TRY(hipEventCreate(&ev[k]));
+  hipEvent_t ev[kEvents];
+  for (int k = 0; k < kEvents; ++k) HIP_TRY(hipEventCreate(&ev[k]));
   Counters before;
   HIP_TRY(hipMemcpyAsync(&before, X->c.ctr, sizeof before, hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipStreamSynchronize(X->stream));
   const int start = X->cur;
   hipError_t err = hipSuccess;
   for (int64_t i = 0; i < nsteps && !err; ++i) {
-    const int a = X->cur;
-    err = launch_step(X->c, X->st[a], X->st[a ^ 1], X->ct[a], X->ct[a ^ 1], X->cfg.precision,
-                      X->stream, ev);
+    const bool rb = rebuild_now(X);
+    err = enqueue_steps(X, 1, rb, ev);
+    count_step(X, rb);
     X->cur ^= 1;
     if (!err) err = hipEventSynchronize(ev[kPhases]);
     for (int k = 0; k < kPhases && !err; ++k) {
@@ -785,10 +830,15 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
       err = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
       phase_ms[k] += ms;
     }
+    if (!err) {
+      float ms = 0.f;
+      err = hipEventElapsedTime(&ms, ev[kPhases + 1], ev[kPhases + 2]);
+      phase_ms[kPhases] += ms;
+    }
   }
-  for (int k = 0; k <= kPhases; ++k) (void)hipEventDestroy(ev[k]);
+  for (int k = 0; k < kEvents; ++k) (void)hipEventDestroy(ev[k]);
   if (err) return fail(SDEM_EHIP, "profiled step failed: %s", hipGetErrorString(err));
-  for (int k = 0; k < kPhases; ++k) phase_ms[k] /= (double)nsteps;
+  for (int k = 0; k <= kPhases; ++k) phase_ms[k] /= (double)nsteps;
   return finish_steps(X, before, start);
 }
 
@@ -884,7 +934,7 @@ int sdem_read_contacts(sdem_ctx* X, int64_t cap, int64_t* n_out, int32_t* ki, in
   return SDEM_OK;
 }
 
-int sdem_stats(sdem_ctx* X, int64_t* steps, int64_t* pp, int64_t* pw) {
+int sdem_stats(sdem_ctx* X, int64_t* steps, int64_t* pp, int64_t* pw, int64_t* rebuilds) {
   if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
   Counters h;
   HIP_TRY(hipMemcpyAsync(&h, X->c.ctr, sizeof h, hipMemcpyDeviceToHost, X->stream));
@@ -902,6 +952,7 @@ int sdem_stats(sdem_ctx* X, int64_t* steps, int64_t* pp, int64_t* pw) {
   if (steps) *steps = done;
   if (pp) *pp = a;
   if (pw) *pw = b;
+  if (rebuilds) *rebuilds = (int64_t)h.rebuilds;
   return SDEM_OK;
 }
 
@@ -909,7 +960,8 @@ int sdem_destroy(sdem_ctx* X) {
   if (!X) return SDEM_OK;
   if (X->stream) (void)hipStreamSynchronize(X->stream);
   for (int p = 0; p < 2; ++p)
-    if (X->graph[p]) (void)hipGraphExecDestroy(X->graph[p]);
+    for (int q = 0; q < 4; ++q)
+      if (X->graph[q][p]) (void)hipGraphExecDestroy(X->graph[q][p]);
   delete X;
   return SDEM_OK;
 }

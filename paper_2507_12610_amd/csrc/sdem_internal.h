@@ -10,6 +10,8 @@ namespace sdem {
 
 constexpr int kScanBlocks = 1024;   // fixed grid of the device-wide scan
 constexpr int kScanThreads = 256;
+constexpr int kPart = 7;            // doubles per bounding-box partial: min xyz, max xyz,
+                                    // largest drift from the binned centre
 constexpr int kWave = 64;           // slots per wave; bounding-box partials are
                                     // per (wave of slots, simulation)
 constexpr int kSpr = 8;             // doubles per contact spring record
@@ -43,6 +45,7 @@ struct SimParams {
   double cnf_pw, csf_pw;       // coefficients per sqrt(m* a), two spheres / wall
   double h;                    // cell edge
   double rmax;                 // largest radius of the simulation
+  double half_skin;            // skin * rmax / 2: allowed drift from the binned position
   int32_t rotating;            // mesh rotates (|om| > 0)
   int32_t tri0, ntri;          // global triangle range
   int32_t p0, np;              // particle range (fixed positions in sorted order)
@@ -55,6 +58,7 @@ struct SimGrid {
   double inv_h;
   int32_t dim[3];
   int32_t cell_off;
+  double extra;  // search reach beyond half the skin (drift measured past it)
 };
 
 // Per-simulation uniform grid of triangle bins, fixed at set-up.  Bin b lists
@@ -76,9 +80,12 @@ struct Counters {
   int32_t ncells;        // cells of the step in progress (all sims)
   int32_t need_cells;    // last required cell capacity (diagnostic)
   uint32_t scan_ticket;  // last-block detection of the scan
+  int32_t rebuild_next;  // a particle drifted beyond half the skin since the last rebuild
+  int32_t pad2;
   int32_t pad;
   unsigned long long steps;  // steps started (a failed one included)
   unsigned long long pp_sum, pw_sum;
+  unsigned long long rebuilds;  // steps that rebuilt the cells
 };
 
 // One buffer of per-particle state in cell-sorted order, packed per particle
@@ -91,6 +98,7 @@ struct State {
   int32_t* key;  // cell key of this slot (written by the reorder)
   int4* os;      // (slot in the previous step's order, first and number of the
                  // contacts it owned in the previous step, persistent id)
+  double4* xb;   // centre when the cells were last built (w unused)
 };
 
 // One buffer of contacts, grouped by owner slot (owner = lower slot).  The
@@ -110,6 +118,7 @@ struct Contacts {
 struct Ctx {
   int32_t n, nsims, ntri, cap_contacts, cap_cells, nchunks;
   int32_t any_rotating, force_blocks;
+  int32_t skin_on;           // cells are kept between steps (skin > 0)
   int32_t detect_sub;        // lanes per particle in the narrow phase (1, 2, 4, 8)
   int32_t ngroups, gcap;     // slot groups, contact records per group
   int32_t nbins, cap_bin_entries;  // triangle bins (all sims), capacity of bin_tri
@@ -120,7 +129,7 @@ struct Ctx {
   int32_t* sim_of;    // [n] simulation of each slot (fixed)
   int32_t* wchunk;    // [n/64] first bounding-box chunk of each wave of slots
   int32_t* chunk0;    // [nsims+1] first chunk of each simulation
-  double* part;       // [nchunks][6] bounding-box partials (min xyz, max xyz),
+  double* part;       // [nchunks][kPart] bounding-box partials (min xyz, max xyz, drift),
                       // one per (wave, simulation) segment, simulations ascending
   int32_t* cell_cnt;  // [cap_cells] zero between steps
   int32_t* cell_start;// [cap_cells+1]
@@ -236,8 +245,9 @@ __device__ __forceinline__ void closest_on_triangle(const double p[3], const dou
 // Phases of a step as timed by sdem_step_profiled: grid, sort+reorder (+mesh),
 // narrow phase, contact forces, integration.
 constexpr int kPhases = 5;
+constexpr int kEvents = kPhases + 3;  // phase boundaries, then the force kernel's own pair
 hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
-                       const Contacts& cnew, int precision, hipStream_t s,
+                       const Contacts& cnew, int precision, int rebuild, hipStream_t s,
                        hipEvent_t* ev = nullptr);
 hipError_t launch_scatter_state(const Ctx& c, const State& S, double* x, double* v, double* w,
                                 double* q, double* F, double* T, hipStream_t s);

@@ -24,7 +24,7 @@ _NAMES = {SDEM_EINVAL: "EINVAL", SDEM_ECAPACITY: "ECAPACITY", SDEM_ENONFINITE: "
 EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_batch", "sdem_add_mesh",
            "sdem_set_history", "sdem_step", "sdem_read_state", "sdem_read_contacts", "sdem_stats",
            "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding", "sdem_step_profiled")
-PHASES = ("grid", "sort", "detect", "force", "integrate")
+PHASES = ("grid", "sort", "detect", "force", "integrate", "force_kernel")
 
 
 class SdemError(RuntimeError):
@@ -44,7 +44,8 @@ class Params(C.Structure):
 class Config(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("contacts_max", C.c_int64), ("cells_max", C.c_int64),
                 ("tri_max", C.c_int64), ("nsims_max", C.c_int32), ("precision", C.c_int32),
-                ("block", C.c_int32), ("detect_lanes", C.c_int32), ("cell_factor", C.c_double)]
+                ("block", C.c_int32), ("detect_lanes", C.c_int32), ("cell_factor", C.c_double),
+                ("skin", C.c_double), ("rebuild_every", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -74,7 +75,7 @@ def lib():
         L.sdem_step_profiled.argtypes = [_VP, C.c_int64, _D]
         L.sdem_read_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP]
         L.sdem_read_contacts.argtypes = [_VP, C.c_int64, _I64, _VP, _VP, _VP, _VP, _VP]
-        L.sdem_stats.argtypes = [_VP, _I64, _I64, _I64]
+        L.sdem_stats.argtypes = [_VP, _I64, _I64, _I64, _I64]
         L.sdem_destroy.argtypes = [_VP]
         L.sdem_last_error.restype = C.c_char_p
         L.sdem_last_error.argtypes = []
@@ -120,19 +121,24 @@ def _grid_cells(x, h):
 
 def autotune(sims, candidates=None, steps=20, warmup=6, precision="fp64", device="cuda:0",
              **kw):
-    """Picks the cell edge factor and the number of lanes per particle in the
-    contact search by timing a few steps of each candidate on the given
-    workload (each trial runs on its own copy of the state).  Returns
-    (best, timings) with best = {"cell_factor", "detect_lanes", "ms_per_step"}."""
+    """Picks the cell edge factor, the number of lanes per particle in the
+    contact search and the skin by timing a few steps of each candidate
+    (cell_factor, detect_lanes[, skin]) on the given workload (each trial runs
+    on its own copy of the state).  Returns (best, timings) with best =
+    {"cell_factor", "detect_lanes", "skin", "ms_per_step"}."""
     import time
 
     import torch
     if candidates is None:
         candidates = [(1.0, 1), (1.0, 2), (0.7, 1), (0.5, 1), (0.5, 2), (0.4, 1), (0.33, 1)]
     timings = []
-    for cf, lanes in candidates:
+    for cand in candidates:
+        cf, lanes = cand[0], cand[1]
+        skin = cand[2] if len(cand) > 2 else kw.get("skin", 0.0)
+        opts = dict(kw)
+        opts["skin"] = skin
         s = Solver(sims, precision=precision, device=device, cell_factor=cf, detect_lanes=lanes,
-                   **kw)
+                   **opts)
         s.step(warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -141,7 +147,8 @@ def autotune(sims, candidates=None, steps=20, warmup=6, precision="fp64", device
         ms = 1e3 * (time.perf_counter() - t0) / steps
         s.close()
         del s
-        timings.append({"cell_factor": cf, "detect_lanes": lanes, "ms_per_step": ms})
+        timings.append({"cell_factor": cf, "detect_lanes": lanes, "skin": skin,
+                        "ms_per_step": ms})
     best = min(timings, key=lambda r: r["ms_per_step"])
     return dict(best), timings
 
@@ -154,7 +161,8 @@ class Solver:
     """
 
     def __init__(self, sims, precision="fp64", device="cuda:0", contacts_max=None,
-                 cells_max=None, cell_factor=1.0, block=0, cell_slack=8.0, detect_lanes=0):
+                 cells_max=None, cell_factor=1.0, block=0, cell_slack=8.0, detect_lanes=0,
+                 skin=0.0, rebuild_every=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("sdem needs a GPU: torch.cuda.is_available() is False")
@@ -180,7 +188,8 @@ class Solver:
             contacts_max = int(max(4096, 8 * n))
         self.cfg = Config(max(n, 1), contacts_max, cells_max, max(ntri, 1), self.nsims,
                           SDEM_MIXED if precision == "mixed" else SDEM_FP64, block,
-                          int(detect_lanes), float(cell_factor))
+                          int(detect_lanes), float(cell_factor), float(skin),
+                          int(rebuild_every), 0)
         nbytes = L.sdem_workspace_bytes(C.byref(self.cfg))
         if nbytes == 0:
             _check(SDEM_EINVAL)
@@ -267,6 +276,6 @@ class Solver:
         return {"ki": ki[:m], "kj": kj[:m], "us": us[:m], "ur": ur[:m], "ut": ut[:m]}
 
     def stats(self):
-        s, pp, pw = C.c_int64(), C.c_int64(), C.c_int64()
-        _check(lib().sdem_stats(self._h, C.byref(s), C.byref(pp), C.byref(pw)))
-        return {"steps": s.value, "pp": pp.value, "pw": pw.value}
+        s, pp, pw, rb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().sdem_stats(self._h, C.byref(s), C.byref(pp), C.byref(pw), C.byref(rb)))
+        return {"steps": s.value, "pp": pp.value, "pw": pw.value, "rebuilds": rb.value}

@@ -49,6 +49,10 @@ def test_workspace_bytes_and_config_checks():
                 sdem.Config(1000, 8000, 10000, 12, 0, 0, 0, 0, 1.0),
                 sdem.Config(1000, 8000, 10000, 12, 1, 7, 0, 0, 1.0),
                 sdem.Config(1000, 8000, 10000, 12, 1, 0, 65, 0, 1.0),
+                sdem.Config(1000, 8000, 10000, 12, 1, 0, 0, 0, 1.0, -1.0),
                 sdem.Config(1000, 8000, 10000, 12, 1, 0, 0, 0, 0.1)):
         assert L.sdem_workspace_bytes(ctypes.byref(bad)) == 0
     assert b"cell_factor" in L.sdem_last_error()
+    assert L.sdem_workspace_bytes(ctypes.byref(sdem.Config(1000, 8000, 10000, 12, 1, 0, 0, 0, 1.0,
+                                                           -1.0))) == 0
+    assert b"skin" in L.sdem_last_error()
