@@ -88,6 +88,36 @@ def sim_slice(w, st, c, lo, hi):
     return d, hist
 
 
+def mixed_vs_fp64(w, cf, lanes, skin, steps_before=200):
+    """One step of the mixed path and of the FP64 path from the same state
+    and springs (taken after steps_before FP64 steps): per quantity, the
+    largest difference relative to the largest FP64 value (for x, relative
+    to the largest displacement of the step)."""
+    import numpy as np
+    from paper_2507_12610_amd import Solver
+    a = Solver(w, precision="fp64", cell_factor=cf, detect_lanes=lanes, skin=skin)
+    a.step(steps_before)
+    st, c = a.state(forces=False), a.contacts()
+    d = dict(w)
+    d.update({k: st[k] for k in ("x", "v", "w", "q")})
+    b = Solver(d, precision="mixed", cell_factor=cf, detect_lanes=lanes, skin=skin)
+    b.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])
+    a.step(1)
+    b.step(1)
+    sa, sb = a.state(), b.state()
+    a.close()
+    b.close()
+
+    def rel(x, y):
+        den = float(np.abs(y).max())
+        return float(np.abs(x - y).max() / den) if den > 0 else float(np.abs(x).max())
+
+    out = {k: rel(sb[k], sa[k]) for k in ("F", "T", "v", "w", "q")}
+    out["x"] = rel(sb["x"] - st["x"], sa["x"] - st["x"])
+    return {"after_fp64_steps": steps_before, "contacts": int(len(c["ki"])),
+            "max_rel_diff": {k: float(f"{v:.3e}") for k, v in out.items()}}
+
+
 # (cell_factor, detect_lanes, skin) tried by the autotuner on the bench workload
 TUNE_CANDIDATES = [(0.4, 1, 0.05), (0.5, 1, 0.05), (0.33, 1, 0.05), (0.7, 1, 0.05), (0.4, 2, 0.05),
                    (0.4, 1, 0.1), (0.4, 1, 0.02), (0.4, 1, 0.0)]
@@ -280,6 +310,7 @@ def main():
                         "particle_steps_per_s": round(n * 1e3 / ms_other, 1),
                         "speedup_vs_" + args.precision: round(ms_per_step / ms_other, 4),
                         "tolerance": 1e-5 if other == "mixed" else 1e-12}
+        forms["mixed_vs_fp64_one_step"] = mixed_vs_fp64(w, cf, lanes, skin)
         if skin > 0:
             # the paper's scheme, cells rebuilt every step, same workload
             g = Solver(w, precision=args.precision, device="cuda:0", cell_factor=cf,

@@ -116,3 +116,29 @@ def test_batch_with_skin():
         assert force_err(sg["F"][lo:hi], fo["F"], fo["Fscale"]) < TOL64, k
     assert total > 300
     assert g.stats()["rebuilds"] < 801
+
+
+def test_drift_past_the_skin_within_one_call():
+    """A skin far too small for the speeds and no scheduled rebuild inside one
+    call of 60 steps: after the first step every search must widen by the
+    measured drift beyond half the skin.  The contact set and the state at the
+    end match the oracle, and only the first step rebuilt the cells."""
+    tri = W.cube_mesh([-0.2e-3] * 3, [18.2e-3] * 3)
+    w = W.random_cluster(600, 43, box=18e-3, overlap=0.2, r_lo=0.4e-3, r_hi=1.4e-3, vel=0.5,
+                         spin=200.0, tri=tri)
+    w["params"].update(g=(0.0, 0.0, -9.81), dt=2e-6)
+    g = solver(w, cell_factor=0.5, detect_lanes=1, skin=0.001, rebuild_every=100000)
+    o = oracle_from(w)
+    g.step(60)
+    o.step(60)
+    assert g.stats()["rebuilds"] == 1
+    cg, co = g.contacts(), o.contacts()
+    assert np.array_equal(keys(cg), keys(co))
+    assert len(co["ki"]) > 200
+    sg, so = g.state(), o.state()
+    for k in ("v", "q"):
+        assert rel(sg[k], so[k]) < TOL64, k
+    assert rel_w(sg["w"], so["w"], w["R"], so["v"]) < TOL64
+    # the next call starts with a rebuild and stays exact
+    check_resync(g, w, every=10, checks=3, t0=60 * w["params"]["dt"])
+    assert g.stats()["rebuilds"] >= 2
