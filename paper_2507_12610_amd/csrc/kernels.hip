@@ -770,7 +770,39 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
         ++npw;
       }
     }
-    // ---- particles.  The half-shell rows run from the own row through the
+    // ---- particles.  Between rebuilds, with no drift past half the skin in
+    // this simulation, the candidates recorded at the last rebuild suffice:
+    // every pair within R_s + R_t + 2 (half skin) of each other then.
+    const double hsk = c.sp[sim].half_skin;
+    const bool listed = c.skin_on && !rebuilt && gr.extra == 0.0;
+    int* vl = c.vlist + (size_t)g * kCand;
+    const int nlist = listed ? c.vcnt[g] : -1;
+    auto test = [&](int t, const double4& pt) {
+      const double ex = xs - pt.x, ey = ys - pt.y, ez = zs - pt.z;
+      const double sr = Rs + pt.w;
+      // cheap conservative reject before the exactly rounded test
+      if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) return;
+      double dx, dy, dz, d;
+      const double delta = pair_gap(xs, ys, zs, Rs, pt.x, pt.y, pt.z, pt.w, &dx, &dy, &dz, &d);
+      if (delta >= 0.0) {
+        if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = t;
+        ++npp;
+      }
+    };
+    if (nlist >= 0) {
+      for (int k = 0; k < nlist; k += 4) {
+        int tt[4];
+        double4 pt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tt[u] = vl[k + u < nlist ? k + u : k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pt[u] = S.xr[tt[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k + u < nlist) test(tt[u], pt[u]);
+      }
+    } else {
+    // The half-shell rows run from the own row through the
     // rest of the own (y, z) plane, then over the full planes above; lane
     // `sub` takes every SUB-th of them.  A row is searched over the x cells
     // within rho = R_s + (largest radius in the row) of x_s, given its (y, z)
@@ -785,8 +817,11 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     const float fx = (float)((xs - gr.lo[0]) * gr.inv_h - cx);
     const float fy = (float)((ys - gr.lo[1]) * gr.inv_h - cy);
     const float fz = (float)((zs - gr.lo[2]) * gr.inv_h - cz);
-    // drift allowed since the cells were built (plus any excess measured)
-    const double hs = c.sp[sim].half_skin + gr.extra;
+    // drift allowed since the cells were built (plus any excess measured);
+    // a rebuild step looks twice as far to record the candidates
+    const bool record = c.skin_on && rebuilt;
+    const double hs = record ? 2.0 * hsk : hsk + gr.extra;
+    int ncand = 0;
     const double reach = ((Rs + c.sp[sim].rmax) + hs) * (1.0 + 1e-9);
     const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, ny);
     const int y1 = cell_coord(ys + reach, gr.lo[1], gr.inv_h, ny);
@@ -855,19 +890,19 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (t + u >= t1) break;
-          const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
-          const double sr = Rs + pt[u].w;
-          // cheap conservative reject before the exactly rounded test
-          if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) continue;
-          double dx, dy, dz, d;
-          const double delta =
-              pair_gap(xs, ys, zs, Rs, pt[u].x, pt[u].y, pt[u].z, pt[u].w, &dx, &dy, &dz, &d);
-          if (delta >= 0.0) {
-            if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = t + u;
-            ++npp;
+          if (record) {
+            const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
+            const double sr = (Rs + pt[u].w) + 2.0 * hsk;
+            if ((ex * ex + ey * ey) + ez * ez <= sr * sr * (1.0 + 1e-9)) {
+              if (ncand < kCand) vl[ncand] = t + u;
+              ++ncand;
+            }
           }
+          test(t + u, pt[u]);
         }
       }
+    }
+    if (record) c.vcnt[g] = ncand <= kCand ? ncand : -1;  // -1: search the cells
     }
   }
   // wave compaction: prefix scan of the per-lane counts, then one atomic per

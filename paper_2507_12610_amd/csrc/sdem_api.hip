@@ -129,6 +129,13 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.gcnt = L.take<int32_t>(G);
   cc.gstat = L.take<int32_t>(2 * G);
   cc.plist = L.take<int2>(N * kMaxRev);
+  {
+    // candidate lists of the search lanes, kept between rebuilds (skin > 0)
+    const size_t lanes = (size_t)(cfg.detect_lanes ? cfg.detect_lanes : 4);
+    const size_t NL = cfg.skin > 0.0 ? N * lanes : 1;
+    cc.vcnt = L.take<int32_t>(NL);
+    cc.vlist = L.take<int32_t>(NL * kCand);
+  }
   cc.res = L.take<double>(kRes * Cm);
   cc.F = L.take<double>(3 * N);
   cc.T = L.take<double>(3 * N);

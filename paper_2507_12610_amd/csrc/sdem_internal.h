@@ -20,6 +20,7 @@ constexpr int kThreads = 256;       // threads per workgroup of the particle ker
 constexpr int kForceBlocksPerCU = 4;  // grid of the contact kernel: 4 workgroups per CU
 constexpr int kMaxOwn = 32;         // contacts one particle may own in a step
 constexpr int kMaxRev = 32;         // contacts one particle may take part in as partner
+constexpr int kCand = 32;           // candidates one search lane records at a rebuild
 constexpr int kGroupShift = 8;      // contact records are allocated per group of
 constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots
 constexpr int kBinScanThreads = 1024;  // one workgroup scans the triangle bins
@@ -142,6 +143,9 @@ struct Ctx {
   int32_t* scan_tmp;  // [kScanBlocks+1]
   int32_t* pcnt;      // [n] contacts in which the slot is the partner
   int2* plist;        // [n][kMaxRev] those contacts: (owner slot, record)
+  int32_t* vcnt;      // [n * lanes] candidates recorded by each search lane at the last
+                      // rebuild (-1: more than kCand, search the cells)
+  int32_t* vlist;     // [n * lanes][kCand] their slots, in search order
   double* res;        // [cap][kRes] per contact: force on the owner (3), torque
                       // on the owner (3), torque on the partner (3), pad
   double* F;          // [3][n] contact force of the last step, by slot
