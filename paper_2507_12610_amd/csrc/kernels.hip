@@ -41,71 +41,73 @@ __device__ __forceinline__ void raise_flag(Counters* ctr, int f) { atomicOr(&ctr
 // ---------------------------------------------------------------------------
 // 1. bounding box of the centres, per simulation (Section 3.3)
 // ---------------------------------------------------------------------------
-// Bounding-box partials of one wave of slots (Section 3.3: cells over the
-// bounding box of the centres): one partial per (wave, simulation) segment,
-// written by the segment's first lane.  Must be called by every lane of a
-// wave that holds at least one slot; `valid` is false past the last slot.  A
-// non-finite coordinate turns the partial's minimum into NaN, which the grid
-// kernel reports.
-__device__ __forceinline__ void wave_bbox(const Ctx& c, int i, bool valid, double x, double y,
-                                          double z, double drift = 0.0) {
+// Per-wave segmented minimum of v[0..K) over runs of lanes with equal
+// simulation; the first lane of each run gets the run's minima and the index
+// of its partial: one partial per (wave, simulation) segment, in slot order.
+// Must be called by every lane of a wave that holds at least one slot.
+template <int K>
+__device__ __forceinline__ bool wave_segment_min(const Ctx& c, int i, bool valid, double v[K],
+                                                 int* bad, int* chunk) {
   const int lane = threadIdx.x & 63;
   const int sim = valid ? c.sim_of[i] : 0x7fffffff;
-  // minima of (x, y, z), of (-x, -y, -z) and of -drift
-  double v[7] = {x, y, z, -x, -y, -z, -drift};
-  const bool bad = valid && !(isfinite(x) && isfinite(y) && isfinite(z));
   if (!valid) {
 #pragma unroll
-    for (int k = 0; k < 7; ++k) v[k] = INFINITY;
+    for (int k = 0; k < K; ++k) v[k] = INFINITY;
   }
   const int s0 = __shfl(sim, 0, 64);
   const int first = c.wchunk[i >> 6];
   if (__all(!valid || sim == s0)) {
     // the whole wave is one simulation: butterfly minimum
 #pragma unroll
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < K; ++k)
       for (int o = 32; o > 0; o >>= 1) v[k] = fmin(v[k], __shfl_xor(v[k], o, 64));
-    const bool anybad = __any(bad);
-    if (lane == 0) {
-      double* p = c.part + kPart * (size_t)first;
-      p[0] = anybad ? NAN : v[0];
-      p[1] = v[1];
-      p[2] = v[2];
-      p[3] = -v[3];
-      p[4] = -v[4];
-      p[5] = -v[5];
-      p[6] = -v[6];
-    }
-  } else {
-    // several simulations: segmented minimum over runs of equal sim
-    int nb = bad ? 1 : 0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int os = __shfl_down(sim, o, 64);
-      const int ob = __shfl_down(nb, o, 64);
-      const bool same = lane + o < 64 && os == sim;
-#pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        const double ov = __shfl_down(v[k], o, 64);
-        if (same) v[k] = fmin(v[k], ov);
-      }
-      if (same) nb |= ob;
-    }
-    const int prev = __shfl_up(sim, 1, 64);
-    const bool head = valid && (lane == 0 || prev != sim);
-    const unsigned long long heads = __ballot(head);
-    if (head) {
-      const int k = first + __popcll(heads & ((1ull << lane) - 1ull));
-      double* p = c.part + kPart * (size_t)k;
-      p[0] = nb ? NAN : v[0];
-      p[1] = v[1];
-      p[2] = v[2];
-      p[3] = -v[3];
-      p[4] = -v[4];
-      p[5] = -v[5];
-      p[6] = -v[6];
-    }
+    *bad = __any(*bad) ? 1 : 0;
+    *chunk = first;
+    return lane == 0;
   }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int os = __shfl_down(sim, o, 64);
+    const int ob = __shfl_down(*bad, o, 64);
+    const bool same = lane + o < 64 && os == sim;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double ov = __shfl_down(v[k], o, 64);
+      if (same) v[k] = fmin(v[k], ov);
+    }
+    if (same) *bad |= ob;
+  }
+  const int prev = __shfl_up(sim, 1, 64);
+  const bool head = valid && (lane == 0 || prev != sim);
+  const unsigned long long heads = __ballot(head);
+  *chunk = first + __popcll(heads & ((1ull << lane) - 1ull));
+  return head;
+}
+
+// Bounding-box partials (Section 3.3: cells over the bounding box of the
+// centres) of one wave; a non-finite coordinate turns the partial's minimum
+// into NaN, which the grid kernel reports.
+__device__ __forceinline__ void wave_bbox(const Ctx& c, int i, bool valid, double x, double y,
+                                          double z) {
+  double v[6] = {x, y, z, -x, -y, -z};  // minima of (x, y, z) and of (-x, -y, -z)
+  int bad = valid && !(isfinite(x) && isfinite(y) && isfinite(z)) ? 1 : 0;
+  int chunk;
+  if (wave_segment_min<6>(c, i, valid, v, &bad, &chunk)) {
+    double* p = c.part + kPart * (size_t)chunk;
+    p[0] = bad ? NAN : v[0];
+    p[1] = v[1];
+    p[2] = v[2];
+    p[3] = -v[3];
+    p[4] = -v[4];
+    p[5] = -v[5];
+  }
+}
+
+// Largest drift from the binned centre over each (wave, simulation) segment.
+__device__ __forceinline__ void wave_drift(const Ctx& c, int i, bool valid, double drift) {
+  double v[1] = {-drift};
+  int bad = 0, chunk;
+  if (wave_segment_min<1>(c, i, valid, v, &bad, &chunk)) c.part[kPart * (size_t)chunk + 6] = -v[0];
 }
 
 __global__ __launch_bounds__(kThreads) void k_bbox_part(Ctx c, State A) {
@@ -309,6 +311,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c, int rebuild) {
   }
   __syncthreads();
   if (!rebuild) return;
+  for (int q = threadIdx.x; q < c.nchunks; q += kGridThreads) c.part[kPart * q + 6] = 0.0;
   block_exclusive_scan_ll(ncell, c.nsims, &total);
   for (int s = threadIdx.x; s < c.nsims; s += kGridThreads) {
     const long long off = ncell[s];
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
       }
     }
     const double4 xr = A.xr[so], q = A.q[so];
-    B.xb[d] = make_double4(xr.x, xr.y, xr.z, 0.0);  // binned centre
+    c.xb[d] = make_double4(xr.x, xr.y, xr.z, 0.0);  // binned centre
     const double2* vin = reinterpret_cast<const double2*>(A.vw + 6 * (size_t)so);
     const int t = threadIdx.x;
     st_x[2 * t] = make_double2(xr.x, xr.y);
@@ -528,8 +531,8 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
     }
     const int id = A.pid[so];
     B.pid[d] = id;
-    B.key[d] = k;
-    B.os[d] = make_int4(so, cold.off[so], cold.cnt[so], id);
+    c.key[d] = k;
+    c.os[d] = make_int4(so, cold.off[so], cold.cnt[so], id);
   }
   // largest radius per cell row: slots are in row order, so a wave's rows
   // are runs of lanes; a segmented maximum leaves one atomic per run
@@ -811,7 +814,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     // (1e-5 cell, 1e-6 relative) far above its rounding, so the search only
     // ever widens.  The largest radius of a row is loaded two rows ahead and
     // the slot range one row ahead of the candidates being examined.
-    const int loc = S.key[s] - gr.cell_off;
+    const int loc = c.key[s] - gr.cell_off;
     const int nx = gr.dim[0], ny = gr.dim[1], nz = gr.dim[2];
     const int cx = loc % nx, cyz = loc / nx, cy = cyz % ny, cz = cyz / ny;
     const float fx = (float)((xs - gr.lo[0]) * gr.inv_h - cx);
@@ -1026,7 +1029,7 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State A, State B, Con
   // (previous slot, its previous contact segment, id): carried by the
   // reorder, or the slot itself when the order was kept
   auto origin = [&](int p) {
-    return rebuilt ? S.os[p] : make_int4(p, old.off[p], old.cnt[p], S.pid[p]);
+    return rebuilt ? c.os[p] : make_int4(p, old.off[p], old.cnt[p], S.pid[p]);
   };
   // one workgroup per slot group (consecutive groups on one XCD share its L2)
   const int grp = xcd_remap(blockIdx.x, gridDim.x);
@@ -1292,7 +1295,6 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
   const int i = i0 + (int)threadIdx.x;
   // new states are staged in LDS and written out as contiguous runs
   __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
-  double nx3[3] = {0.0, 0.0, 0.0};  // new centre, for the next step's bounding box
   bool drift = false;
   double ddrift = 0.0;
   if (i < n) {
@@ -1457,16 +1459,11 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
     ok = ok && isfinite(x[k]) && isfinite(v[k]) && isfinite(w[k]);
   }
   const int t = threadIdx.x;
-  nx3[0] = x[0];
-  nx3[1] = x[1];
-  nx3[2] = x[2];
-  if (!rebuilt) {  // the kept order: carry the slot's labels over to B
-    B.key[i] = A.key[i];
+  if (!rebuilt) {  // the kept order: carry the slot's id over to B
     B.pid[i] = A.pid[i];
-    B.xb[i] = A.xb[i];
   }
   if (c.skin_on) {  // drift from the binned centre, and whether beyond half the skin
-    const double4 xb = S.xb[i];
+    const double4 xb = c.xb[i];
     const double ex = x[0] - xb.x, ey = x[1] - xb.y, ez = x[2] - xb.z;
     const double d2 = (ex * ex + ey * ey) + ez * ez;
     ddrift = sqrt(d2) * (1.0 + 1e-12);
@@ -1482,8 +1479,12 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
   if (!ok) raise_flag(c.ctr, kFlagNonFinite);
   if (i == 0) c.ctr->stats_pending = 1;
   }
-  if (i - (int)(threadIdx.x & 63) < n) wave_bbox(c, i, i < n, nx3[0], nx3[1], nx3[2], ddrift);
-  if (__any(drift) && (threadIdx.x & 63) == 0) atomicOr(&c.ctr->rebuild_next, 1);
+  // a wave where a particle drifted past half the skin records its largest
+  // drift (read by the next step's grid kernel) and raises the flag
+  if (i - (int)(threadIdx.x & 63) < n && __any(drift)) {
+    wave_drift(c, i, i < n, ddrift);
+    if ((threadIdx.x & 63) == 0) atomicOr(&c.ctr->rebuild_next, 1);
+  }
   __syncthreads();
   const int np = min(n - i0, kThreads);
   double2* gx = reinterpret_cast<double2*>(B.xr + i0);
@@ -1544,9 +1545,9 @@ __global__ __launch_bounds__(kThreads) void k_pack_state(Ctx c, State S, const d
   S.q[i] = q ? make_double4(q[i], q[n + i], q[2 * n + i], q[3 * n + i])
              : make_double4(1.0, 0.0, 0.0, 0.0);
   S.pid[i] = i;
-  S.os[i] = make_int4(i, 0, 0, i);
-  S.xb[i] = make_double4(x[i], x[n + i], x[2 * n + i], 0.0);
-  S.key[i] = 0;
+  c.os[i] = make_int4(i, 0, 0, i);
+  c.xb[i] = make_double4(x[i], x[n + i], x[2 * n + i], 0.0);
+  c.key[i] = 0;
   c.F[i] = c.F[n + i] = c.F[2 * n + i] = 0.0;
   c.T[i] = c.T[n + i] = c.T[2 * n + i] = 0.0;
 }
@@ -1572,6 +1573,7 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
   // the phase boundaries and the force kernel's own start/stop.
   const int nbp = blocks_for(c.n, kThreads);
   if (ev) (void)hipEventRecord(ev[0], s);
+  if (rebuild) k_bbox_part<<<nbp, kThreads, 0, s>>>(c, A);
   k_grid<<<1, kGridThreads, 0, s>>>(c, rebuild);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (rebuild) {

@@ -129,6 +129,9 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.gcnt = L.take<int32_t>(G);
   cc.gstat = L.take<int32_t>(2 * G);
   cc.plist = L.take<int2>(N * kMaxRev);
+  cc.key = L.take<int32_t>(N);
+  cc.os = L.take<int4>(N);
+  cc.xb = L.take<double4>(N);
   {
     // candidate lists of the search lanes, kept between rebuilds (skin > 0)
     const size_t lanes = (size_t)(cfg.detect_lanes ? cfg.detect_lanes : 4);
@@ -154,9 +157,6 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
     s.vw = L.take<double>(6 * N);
     s.q = L.take<double4>(N);
     s.pid = L.take<int32_t>(N);
-    s.key = L.take<int32_t>(N);
-    s.os = L.take<int4>(N);
-    s.xb = L.take<double4>(N);
     if (st) st[b] = s;
   }
   for (int b = 0; b < 2; ++b) {

@@ -96,10 +96,6 @@ struct State {
   double* vw;    // [n][6] velocity then angular velocity
   double4* q;    // [n] orientation quaternion, scalar first
   int32_t* pid;  // persistent id
-  int32_t* key;  // cell key of this slot (written by the reorder)
-  int4* os;      // (slot in the previous step's order, first and number of the
-                 // contacts it owned in the previous step, persistent id)
-  double4* xb;   // centre when the cells were last built (w unused)
 };
 
 // One buffer of contacts, grouped by owner slot (owner = lower slot).  The
@@ -143,6 +139,11 @@ struct Ctx {
   int32_t* scan_tmp;  // [kScanBlocks+1]
   int32_t* pcnt;      // [n] contacts in which the slot is the partner
   int2* plist;        // [n][kMaxRev] those contacts: (owner slot, record)
+  // per slot, written by the reorder at a rebuild and kept until the next:
+  int32_t* key;       // [n] cell key
+  int4* os;           // [n] (slot in the previous step's order, first and number of the
+                      // contacts it owned in the previous step, persistent id)
+  double4* xb;        // [n] centre when the cells were built (w unused)
   int32_t* vcnt;      // [n * lanes] candidates recorded by each search lane at the last
                       // rebuild (-1: more than kCand, search the cells)
   int32_t* vlist;     // [n * lanes][kCand] their slots, in search order
