@@ -151,22 +151,18 @@ __device__ __forceinline__ void block_exclusive_scan_ll(long long* buf, int len,
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c, int rebuild) {
+// Runs at the start of the steps that rebuild the cells (the first kernel
+// after the bounding-box partials): counts the step as started.
+__global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
   if (c.ctr->flags) return;
   __shared__ long long ncell[kMaxSims];
   __shared__ long long total;
   __shared__ int bad_total;
-  // contact record counters of the slot groups, filled by the narrow phase
-  for (int q = threadIdx.x; q < c.ngroups; q += kGridThreads) c.gcnt[q] = 0;
-  __shared__ int drifted;
   if (threadIdx.x == 0) {
     bad_total = 0;
     atomicAdd(&c.ctr->steps, 1ull);  // steps started (the host discounts a failed one)
-    drifted = c.ctr->rebuild_next;
-    if (rebuild) {
-      c.ctr->rebuild_next = 0;
-      c.ctr->rebuilds += 1ull;
-    }
+    c.ctr->rebuild_next = 0;
+    c.ctr->rebuilds += 1ull;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = kGridThreads / 64;
@@ -194,28 +190,11 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c, int rebuild) {
     }
     g.inv_h = 1.0 / h;
     g.cell_off = 0;
-    g.extra = 0.0;
     c.sg[s] = g;
     ncell[s] = nc;
     if (bad) bad_total = 1;
   };
-  if (!rebuild) {
-    // The grid of the last rebuild stays.  If a particle drifted beyond half
-    // the skin, every search of this step reaches by the excess further: the
-    // largest drift of each simulation, from the integration's partials.
-    if (drifted) {
-      for (int s = wv; s < c.nsims; s += nw) {
-        const int q0 = c.chunk0[s], q1 = c.chunk0[s + 1];
-        double dmax = 0.0;
-        for (int q = q0 + lane; q < q1; q += 64) dmax = fmax(dmax, c.part[kPart * q + 6]);
-        for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
-        if (lane == 0) {
-          const double ex = dmax - c.sp[s].half_skin;
-          c.sg[s].extra = ex > 0.0 ? ex * (1.0 + 1e-6) : 0.0;
-        }
-      }
-    }
-  } else if (c.nsims <= nw) {
+  if (c.nsims <= nw) {
     // few simulations: the whole workgroup reduces each one's partials
     __shared__ double red[kGridThreads / 64][6];
     __shared__ int redbad;
@@ -282,35 +261,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c, int rebuild) {
       if (lane == 0) set_grid(s, L, H, bad);
     }
   }
-  // fold the previous step's per-group contact counts into the totals
-  if (c.ctr->stats_pending) {
-    unsigned long long a = 0, b = 0;
-    for (int q = threadIdx.x; q < c.ngroups; q += kGridThreads) {
-      a += (unsigned)c.gstat[2 * q];
-      b += (unsigned)c.gstat[2 * q + 1];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      a += __shfl_xor(a, o, 64);
-      b += __shfl_xor(b, o, 64);
-    }
-    __shared__ unsigned long long wsum[2][kGridThreads / 64];
-    if (lane == 0) {
-      wsum[0][wv] = a;
-      wsum[1][wv] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int w = 1; w < nw; ++w) {
-        wsum[0][0] += wsum[0][w];
-        wsum[1][0] += wsum[1][w];
-      }
-      c.ctr->pp_sum += wsum[0][0];
-      c.ctr->pw_sum += wsum[1][0];
-      c.ctr->stats_pending = 0;
-    }
-  }
   __syncthreads();
-  if (!rebuild) return;
   for (int q = threadIdx.x; q < c.nchunks; q += kGridThreads) c.part[kPart * q + 6] = 0.0;
   block_exclusive_scan_ll(ncell, c.nsims, &total);
   for (int s = threadIdx.x; s < c.nsims; s += kGridThreads) {
@@ -561,7 +512,7 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
 // ---------------------------------------------------------------------------
 // 4. mesh: rigid rotation (extension for rotating drums) and plane data
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all) {
+__global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) {
 #pragma clang fp contract(off)
   if (c.ctr->flags) return;
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -573,10 +524,10 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all) {
     for (int k = 0; k < 9; ++k) t[k] = t0[k];
   } else if (P.rotating) {
     // rigid rotation by |om| t about the axis om/|om| through ctr, with t the
-    // time at the start of this step (steps already counts the current one)
+    // time at the start of this step (`started`: steps already counts it)
     const double wl = sqrt((P.om[0] * P.om[0] + P.om[1] * P.om[1]) + P.om[2] * P.om[2]);
     const double kx = P.om[0] / wl, ky = P.om[1] / wl, kz = P.om[2] / wl;
-    const double ang = wl * ((double)(c.ctr->steps - 1ull) * P.dt);
+    const double ang = wl * ((double)(c.ctr->steps - (unsigned long long)started) * P.dt);
     const double co = cos(ang), si = sin(ang);
     for (int v = 0; v < 3; ++v) {
       const double rx = t0[3 * v] - P.ctr[0], ry = t0[3 * v + 1] - P.ctr[1],
@@ -731,17 +682,48 @@ template <int SUB>
 __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Contacts cn,
                                                     int rebuilt) {
   if (c.ctr->flags) return;
+  // a step that keeps the cells starts here
+  if (!rebuilt && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&c.ctr->steps, 1ull);
   // the sorted copy when this step rebuilt the cells, else the kept order
   const State S = rebuilt ? B : A;
   __shared__ int hits[kThreads / 64][kMaxOwn][64];
   const int n = c.n;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int g = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int bg = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x;
+  const int g = bg + threadIdx.x;
   const int s = g / SUB, sub = g % SUB;
+  // If a particle drifted past half the skin since the cells were built,
+  // every search of this step reaches by the excess further: the largest
+  // drift of each simulation of this workgroup, from the integration's
+  // per-wave partials (a rare step; the others skip this).
+  __shared__ double xdrift[kThreads];
+  __shared__ double red[kThreads / 64];
+  int sim_lo = 0;
+  if (!rebuilt && c.ctr->rebuild_next && bg / SUB < n) {
+    sim_lo = c.sim_of[bg / SUB];
+    const int sim_hi = c.sim_of[min(n - 1, (bg + kThreads - 1) / SUB)];
+    for (int sm = sim_lo; sm <= sim_hi; ++sm) {
+      double dmax = 0.0;
+      for (int q = c.chunk0[sm] + threadIdx.x; q < c.chunk0[sm + 1]; q += kThreads)
+        dmax = fmax(dmax, c.part[kPart * q + 6]);
+      for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+      __syncthreads();
+      if (lane == 0) red[wv] = dmax;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, red[w]);
+        const double ex = m - c.sp[sm].half_skin;
+        xdrift[sm - sim_lo] = ex > 0.0 ? ex * (1.0 + 1e-6) : 0.0;
+      }
+    }
+    __syncthreads();
+  }
   int npp = 0, npw = 0;
   if (s < n) {
     const int sim = c.sim_of[s];
     const SimGrid gr = c.sg[sim];
+    const double extra = (!rebuilt && c.ctr->rebuild_next) ? xdrift[sim - sim_lo] : 0.0;
     const double4 ps = S.xr[s];
     const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
     // ---- triangles listed in the bin of x_s
@@ -777,7 +759,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     // this simulation, the candidates recorded at the last rebuild suffice:
     // every pair within R_s + R_t + 2 (half skin) of each other then.
     const double hsk = c.sp[sim].half_skin;
-    const bool listed = c.skin_on && !rebuilt && gr.extra == 0.0;
+    const bool listed = c.skin_on && !rebuilt && extra == 0.0;
     int* vl = c.vlist + (size_t)g * kCand;
     const int nlist = listed ? c.vcnt[g] : -1;
     auto test = [&](int t, const double4& pt) {
@@ -823,7 +805,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     // drift allowed since the cells were built (plus any excess measured);
     // a rebuild step looks twice as far to record the candidates
     const bool record = c.skin_on && rebuilt;
-    const double hs = record ? 2.0 * hsk : hsk + gr.extra;
+    const double hs = record ? 2.0 * hsk : hsk + extra;
     int ncand = 0;
     const double reach = ((Rs + c.sp[sim].rmax) + hs) * (1.0 + 1e-9);
     const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, ny);
@@ -1245,8 +1227,8 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State A, State B, Con
       ta += red[0][w];
       tb += red[1][w];
     }
-    c.gstat[2 * grp] = ta;
-    c.gstat[2 * grp + 1] = tb;
+    c.gstat[2 * grp] += (unsigned long long)ta;  // running sums, one writer per group
+    c.gstat[2 * grp + 1] += (unsigned long long)tb;
   }
 }
 
@@ -1477,7 +1459,7 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
   st_q[2 * t] = make_double2(q[0], q[1]);
   st_q[2 * t + 1] = make_double2(q[2], q[3]);
   if (!ok) raise_flag(c.ctr, kFlagNonFinite);
-  if (i == 0) c.ctr->stats_pending = 1;
+  if ((i & (kGroup - 1)) == 0) c.gcnt[i >> kGroupShift] = 0;  // for the next narrow phase
   }
   // a wave where a particle drifted past half the skin records its largest
   // drift (read by the next step's grid kernel) and raises the flag
@@ -1573,8 +1555,10 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
   // the phase boundaries and the force kernel's own start/stop.
   const int nbp = blocks_for(c.n, kThreads);
   if (ev) (void)hipEventRecord(ev[0], s);
-  if (rebuild) k_bbox_part<<<nbp, kThreads, 0, s>>>(c, A);
-  k_grid<<<1, kGridThreads, 0, s>>>(c, rebuild);
+  if (rebuild) {
+    k_bbox_part<<<nbp, kThreads, 0, s>>>(c, A);
+    k_grid<<<1, kGridThreads, 0, s>>>(c);
+  }
   if (ev) (void)hipEventRecord(ev[1], s);
   if (rebuild) {
     k_keys<<<nbp, kThreads, 0, s>>>(c, A);
@@ -1589,7 +1573,7 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
     k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B, cold);
   }
   if (c.any_rotating) {
-    k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0);
+    k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0, rebuild);
     (void)launch_mesh_bins(c, s);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
@@ -1639,7 +1623,7 @@ hipError_t launch_pack_state(const Ctx& c, const State& S, const double* x, cons
 }
 
 hipError_t launch_mesh_planes(const Ctx& c, hipStream_t s) {
-  if (c.ntri > 0) k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 1);
+  if (c.ntri > 0) k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 1, 0);
   return hipGetLastError();
 }
 

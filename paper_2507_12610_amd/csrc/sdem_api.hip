@@ -127,7 +127,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.scan_tmp = L.take<int32_t>(kScanBlocks + 1);
   cc.pcnt = L.take<int32_t>(N);
   cc.gcnt = L.take<int32_t>(G);
-  cc.gstat = L.take<int32_t>(2 * G);
+  cc.gstat = L.take<unsigned long long>(2 * G);
   cc.plist = L.take<int2>(N * kMaxRev);
   cc.key = L.take<int32_t>(N);
   cc.os = L.take<int4>(N);
@@ -428,6 +428,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   }
   if (!e) e = hipMemsetAsync(c.pcnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
   if (!e) e = hipMemsetAsync(c.gcnt, 0, sizeof(int32_t) * c.ngroups, st);
+  if (!e) e = hipMemsetAsync(c.gstat, 0, sizeof(unsigned long long) * 2 * c.ngroups, st);
   if (!e) e = cp(c.sim_of, sim_of.data(), sizeof(int32_t) * n);
   if (!e) e = cp(c.wchunk, wchunk.data(), sizeof(int32_t) * wchunk.size());
   if (!e) e = cp(c.chunk0, chunk0.data(), sizeof(int32_t) * chunk0.size());
@@ -947,13 +948,14 @@ int sdem_stats(sdem_ctx* X, int64_t* steps, int64_t* pp, int64_t* pw, int64_t* r
   HIP_TRY(hipMemcpyAsync(&h, X->c.ctr, sizeof h, hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipStreamSynchronize(X->stream));
   const int64_t done = (int64_t)h.steps - (h.flags ? 1 : 0);
-  int64_t a = (int64_t)h.pp_sum, b = (int64_t)h.pw_sum;
-  if (h.stats_pending) {  // the last step's counts are still per group
-    std::vector<int32_t> gs((size_t)2 * X->c.ngroups);
-    HIP_TRY(hipMemcpy(gs.data(), X->c.gstat, sizeof(int32_t) * gs.size(), hipMemcpyDeviceToHost));
+  int64_t a = 0, b = 0;
+  {
+    std::vector<unsigned long long> gs((size_t)2 * X->c.ngroups);
+    HIP_TRY(hipMemcpy(gs.data(), X->c.gstat, sizeof(unsigned long long) * gs.size(),
+                      hipMemcpyDeviceToHost));
     for (int32_t q = 0; q < X->c.ngroups; ++q) {
-      a += gs[2 * q];
-      b += gs[2 * q + 1];
+      a += (int64_t)gs[2 * q];
+      b += (int64_t)gs[2 * q + 1];
     }
   }
   if (steps) *steps = done;

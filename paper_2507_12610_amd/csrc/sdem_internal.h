@@ -59,7 +59,6 @@ struct SimGrid {
   double inv_h;
   int32_t dim[3];
   int32_t cell_off;
-  double extra;  // search reach beyond half the skin (drift measured past it)
 };
 
 // Per-simulation uniform grid of triangle bins, fixed at set-up.  Bin b lists
@@ -77,7 +76,7 @@ struct MeshGrid {
 struct Counters {
   int32_t flags;
   int32_t need_group;    // contacts a slot group needed beyond its share (diagnostic)
-  int32_t stats_pending; // per-group contact counts of the last step not yet summed
+  int32_t pad0;
   int32_t ncells;        // cells of the step in progress (all sims)
   int32_t need_cells;    // last required cell capacity (diagnostic)
   uint32_t scan_ticket;  // last-block detection of the scan
@@ -85,7 +84,6 @@ struct Counters {
   int32_t pad2;
   int32_t pad;
   unsigned long long steps;  // steps started (a failed one included)
-  unsigned long long pp_sum, pw_sum;
   unsigned long long rebuilds;  // steps that rebuilt the cells
 };
 
@@ -120,7 +118,8 @@ struct Ctx {
   int32_t ngroups, gcap;     // slot groups, contact records per group
   int32_t nbins, cap_bin_entries;  // triangle bins (all sims), capacity of bin_tri
   int32_t* gcnt;             // [ngroups] contact records used by each group
-  int32_t* gstat;            // [ngroups][2] pair and wall contacts of each group
+  unsigned long long* gstat; // [ngroups][2] pair and wall contacts of each group, summed
+                             // over the steps
   SimParams* sp;      // [nsims]
   SimGrid* sg;        // [nsims]
   int32_t* sim_of;    // [n] simulation of each slot (fixed)
