@@ -726,42 +726,29 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     const double extra = (!rebuilt && c.ctr->rebuild_next) ? xdrift[sim - sim_lo] : 0.0;
     const double4 ps = S.xr[s];
     const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
-    // ---- triangles listed in the bin of x_s
-    int k0 = 0, k1 = 0;
-    if (c.sp[sim].ntri > 0) {
-      const MeshGrid G = c.mg[sim];
-      const double fx = (xs - G.lo[0]) * G.inv_h, fy = (ys - G.lo[1]) * G.inv_h,
-                   fz = (zs - G.lo[2]) * G.inv_h;
-      if (fx >= 0.0 && fy >= 0.0 && fz >= 0.0 && fx < (double)G.dim[0] &&
-          fy < (double)G.dim[1] && fz < (double)G.dim[2]) {
-        const int b = G.off + ((int)fz * G.dim[1] + (int)fy) * G.dim[0] + (int)fx;
-        k0 = c.bin_start[b];
-        k1 = c.bin_start[b + 1];
-      }
-    }
-    for (int k = k0 + sub; k < k1; k += SUB) {
-      const int m = c.bin_tri[k];
-      const double* pl = c.tri_pl + 4 * m;
-      const double reach = Rs + c.rmesh[m];
-      const double pd = (pl[0] * xs + pl[1] * ys + pl[2] * zs) - pl[3];
-      if (fabs(pd) > reach * (1.0 + 1e-9) + 1e-300) continue;
+    // Between rebuilds, with no drift past half the skin in this simulation,
+    // the candidates recorded at the last rebuild suffice: every particle
+    // within R_s + R_t + 2 (half skin) of x_s then, and (static meshes) every
+    // triangle within R_s + R_m + half skin.
+    const double hsk = c.sp[sim].half_skin;
+    const bool listed = c.skin_on && !rebuilt && extra == 0.0;
+    const bool record = c.skin_on && rebuilt;
+    const bool tri_listed = !c.sp[sim].rotating;
+    int* vl = c.vlist + (size_t)g * kCand;
+    const int nlist = listed ? c.vcnt[g] : -1;
+    int ncand = 0;
+    auto test_wall = [&](int m) {
       const double p[3] = {xs, ys, zs};
       double cp[3];
       closest_on_triangle(p, c.tri + 9 * m, cp);
       double dx, dy, dz, d;
       const double delta = pair_gap(xs, ys, zs, Rs, cp[0], cp[1], cp[2], c.rmesh[m], &dx, &dy, &dz, &d);
       if (delta >= 0.0) {
-        if (npw < kMaxOwn) hits[wv][npw][lane] = -1 - m;
+        if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = -1 - m;
         ++npw;
       }
-    }
-    // ---- particles.  Between rebuilds, with no drift past half the skin in
-    // this simulation, the candidates recorded at the last rebuild suffice:
-    // every pair within R_s + R_t + 2 (half skin) of each other then.
-    const double hsk = c.sp[sim].half_skin;
-    const bool listed = c.skin_on && !rebuilt && extra == 0.0;
-    int* vl = c.vlist + (size_t)g * kCand;
-    const int nlist = listed ? c.vcnt[g] : -1;
+      return d;
+    };
     auto test = [&](int t, const double4& pt) {
       const double ex = xs - pt.x, ey = ys - pt.y, ez = zs - pt.z;
       const double sr = Rs + pt.w;
@@ -774,6 +761,35 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
         ++npp;
       }
     };
+    // ---- triangles listed in the bin of x_s (unless the list holds them)
+    if (!(nlist >= 0 && tri_listed)) {
+      int k0 = 0, k1 = 0;
+      if (c.sp[sim].ntri > 0) {
+        const MeshGrid G = c.mg[sim];
+        const double fx = (xs - G.lo[0]) * G.inv_h, fy = (ys - G.lo[1]) * G.inv_h,
+                     fz = (zs - G.lo[2]) * G.inv_h;
+        if (fx >= 0.0 && fy >= 0.0 && fz >= 0.0 && fx < (double)G.dim[0] &&
+            fy < (double)G.dim[1] && fz < (double)G.dim[2]) {
+          const int b = G.off + ((int)fz * G.dim[1] + (int)fy) * G.dim[0] + (int)fx;
+          k0 = c.bin_start[b];
+          k1 = c.bin_start[b + 1];
+        }
+      }
+      const bool rec_tri = record && tri_listed;
+      for (int k = k0 + sub; k < k1; k += SUB) {
+        const int m = c.bin_tri[k];
+        const double* pl = c.tri_pl + 4 * m;
+        const double reach = (Rs + c.rmesh[m]) + (rec_tri ? hsk : 0.0);
+        const double pd = (pl[0] * xs + pl[1] * ys + pl[2] * zs) - pl[3];
+        if (fabs(pd) > reach * (1.0 + 1e-9) + 1e-300) continue;
+        const double d = test_wall(m);
+        if (rec_tri && d <= reach * (1.0 + 1e-9)) {
+          if (ncand < kCand) vl[ncand] = -1 - m;
+          ++ncand;
+        }
+      }
+    }
+    // ---- particles (and listed triangles)
     if (nlist >= 0) {
       for (int k = 0; k < nlist; k += 4) {
         int tt[4];
@@ -781,10 +797,15 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
 #pragma unroll
         for (int u = 0; u < 4; ++u) tt[u] = vl[k + u < nlist ? k + u : k];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) pt[u] = S.xr[tt[u]];
+        for (int u = 0; u < 4; ++u) pt[u] = S.xr[tt[u] >= 0 ? tt[u] : s];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k + u < nlist) test(tt[u], pt[u]);
+        for (int u = 0; u < 4; ++u) {
+          if (k + u >= nlist) continue;
+          if (tt[u] >= 0)
+            test(tt[u], pt[u]);
+          else
+            (void)test_wall(-1 - tt[u]);
+        }
       }
     } else {
     // The half-shell rows run from the own row through the
@@ -804,9 +825,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     const float fz = (float)((zs - gr.lo[2]) * gr.inv_h - cz);
     // drift allowed since the cells were built (plus any excess measured);
     // a rebuild step looks twice as far to record the candidates
-    const bool record = c.skin_on && rebuilt;
     const double hs = record ? 2.0 * hsk : hsk + extra;
-    int ncand = 0;
     const double reach = ((Rs + c.sp[sim].rmax) + hs) * (1.0 + 1e-9);
     const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, ny);
     const int y1 = cell_coord(ys + reach, gr.lo[1], gr.inv_h, ny);
