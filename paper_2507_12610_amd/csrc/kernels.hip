@@ -918,8 +918,22 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
   const int wtot = __shfl(incl, 63, 64);
   const int grp = __shfl(g / SUB, 0, 64) >> kGroupShift;
   int base = 0;
-  if (lane == 63 && wtot > 0 && grp < c.ngroups) base = atomicAdd(&c.gcnt[grp], wtot);
-  base = __shfl(base, 63, 64);
+  if (SUB == 1) {
+    // one lane per slot: the workgroup is the slot group, so the waves'
+    // offsets come from a scan of their totals, in slot order
+    __shared__ int wtots[kThreads / 64];
+    if (lane == 63) wtots[wv] = wtot;
+    __syncthreads();
+    int tot = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      if (w < wv) base += wtots[w];
+      tot += wtots[w];
+    }
+    if (threadIdx.x == 0 && grp < c.ngroups) c.gcnt[grp] = tot;
+  } else {
+    if (lane == 63 && wtot > 0 && grp < c.ngroups) base = atomicAdd(&c.gcnt[grp], wtot);
+    base = __shfl(base, 63, 64);
+  }
   const int first = grp * c.gcap + base + incl - mine;
   // end of this slot's records: the last of its SUB lanes
   const int slot_end = __shfl(first + mine, (lane | (SUB - 1)), 64);
