@@ -682,8 +682,12 @@ template <int SUB>
 __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Contacts cn,
                                                     int rebuilt) {
   if (c.ctr->flags) return;
-  // a step that keeps the cells starts here
-  if (!rebuilt && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&c.ctr->steps, 1ull);
+  // a step that keeps the cells starts here (and is counted if its searches
+  // must reach past the skin)
+  if (!rebuilt && blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicAdd(&c.ctr->steps, 1ull);
+    if (c.ctr->rebuild_next) c.ctr->drift_steps += 1ull;
+  }
   // the sorted copy when this step rebuilt the cells, else the kept order
   const State S = rebuilt ? B : A;
   __shared__ int hits[kThreads / 64][kMaxOwn][64];
@@ -1495,10 +1499,11 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
   if ((i & (kGroup - 1)) == 0) c.gcnt[i >> kGroupShift] = 0;  // for the next narrow phase
   }
   // a wave where a particle drifted past half the skin records its largest
-  // drift (read by the next step's grid kernel) and raises the flag
+  // drift (read by the next step's narrow phase) and raises the flag
   if (i - (int)(threadIdx.x & 63) < n && __any(drift)) {
     wave_drift(c, i, i < n, ddrift);
-    if ((threadIdx.x & 63) == 0) atomicOr(&c.ctr->rebuild_next, 1);
+    // one write per wave, and none once the flag is up (a single address)
+    if ((threadIdx.x & 63) == 0 && !c.ctr->rebuild_next) atomicOr(&c.ctr->rebuild_next, 1);
   }
   __syncthreads();
   const int np = min(n - i0, kThreads);

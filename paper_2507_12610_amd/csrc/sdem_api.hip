@@ -88,7 +88,10 @@ struct sdem_ctx {
   // past half the skin seen at the last synchronisation (or no rebuild yet)
   int64_t since = 0;
   bool need_rebuild = true;
-  int rebuild_every = 1;
+  int rebuild_every = 1;  // the configured longest period
+  int period = 1;         // the current period: halved after a call in which
+                          // searches had to reach past the skin, doubled
+                          // (up to rebuild_every) after one without
 };
 
 // contact records are allocated per group of kGroup slots: gcap each
@@ -370,6 +373,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   c.detect_sub = cfg.detect_lanes ? cfg.detect_lanes : 4;
   c.skin_on = cfg.skin > 0.0 ? 1 : 0;
   X->rebuild_every = c.skin_on ? (cfg.rebuild_every > 0 ? cfg.rebuild_every : 64) : 1;
+  X->period = X->rebuild_every;
   c.ngroups = (int32_t)((std::max<int64_t>(n, 1) + kGroup - 1) / kGroup);
   c.gcap = (int32_t)group_cap(cfg);
 
@@ -726,7 +730,7 @@ static int finish_steps(sdem_ctx* X, const Counters& before, int start) {
 // Steps keep the cells when a skin is set, except every rebuild_every-th
 // step and the first step after a drift past half the skin was seen.
 static bool rebuild_now(const sdem_ctx* X) {
-  return !X->c.skin_on || X->need_rebuild || X->since >= X->rebuild_every;
+  return !X->c.skin_on || X->need_rebuild || X->since >= X->period;
 }
 static void count_step(sdem_ctx* X, bool rebuild) {
   if (rebuild) {
@@ -785,6 +789,24 @@ static hipError_t run_pattern(sdem_ctx* X, int pat) {
   return hipSuccess;
 }
 
+// At the end of a run of steps since the last rebuild (skin > 0): read the
+// drift counters and adapt the period.  A run whose searches had to reach
+// past the skin halves the period (down to 4 steps) and forces a rebuild; a
+// run without doubles it, up to rebuild_every.
+static int adapt_period(sdem_ctx* X, unsigned long long* drift0) {
+  Counters h;
+  HIP_TRY(hipMemcpyAsync(&h, X->c.ctr, sizeof h, hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  if (h.flags) return SDEM_OK;  // reported by the caller
+  if (h.rebuild_next) X->need_rebuild = true;
+  if (h.drift_steps > *drift0)
+    X->period = std::max(std::min(4, X->rebuild_every), X->period / 2);
+  else
+    X->period = std::min(X->rebuild_every, X->period * 2);
+  *drift0 = h.drift_steps;
+  return SDEM_OK;
+}
+
 int sdem_step(sdem_ctx* X, int64_t nsteps) {
   if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
   if (X->failed) return fail(SDEM_ESTATE, "context failed in an earlier step; read it and re-init");
@@ -795,17 +817,23 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
   HIP_TRY(hipMemcpyAsync(&before, X->c.ctr, sizeof before, hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipStreamSynchronize(X->stream));
   const int start = X->cur;
+  unsigned long long drift0 = before.drift_steps;
   int64_t left = nsteps;
   while (left > 0) {
     int pat;
     if (!X->c.skin_on) {
       pat = left >= 2 ? 0 : 1;
-    } else if (rebuild_now(X)) {
-      pat = 1;
-    } else if (left >= 8 && X->since + 8 <= X->rebuild_every) {
-      pat = 3;
     } else {
-      pat = 2;
+      if (X->since >= X->period && X->since > 0) {
+        const int rc = adapt_period(X, &drift0);
+        if (rc) return rc;
+      }
+      if (rebuild_now(X))
+        pat = 1;
+      else if (left >= 8 && X->since + 8 <= X->period)
+        pat = 3;
+      else
+        pat = 2;
     }
     HIP_TRY(run_pattern(X, pat));
     left -= kPatSteps[pat];

@@ -85,6 +85,7 @@ struct Counters {
   int32_t pad;
   unsigned long long steps;  // steps started (a failed one included)
   unsigned long long rebuilds;  // steps that rebuilt the cells
+  unsigned long long drift_steps;  // steps whose searches reached past the skin
 };
 
 // One buffer of per-particle state in cell-sorted order, packed per particle
