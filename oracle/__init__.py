@@ -81,6 +81,10 @@ def lib():
         L.orc_dt_default.restype = C.c_double
         L.orc_dt_default.argtypes = [C.c_double] * 4
         L.orc_closest_point_triangle.argtypes = [_D] * 5
+        L.orc_closest_point_segment.argtypes = [_D] * 4
+        L.orc_closest_point_rectangle.argtypes = [_D] * 6
+        L.orc_closest_point_element.argtypes = [_D, C.c_int32, _D, _D]
+        L.orc_set_mesh_elements.argtypes = [C.c_void_p, C.c_int64, _I32, _D, _D]
         L.orc_quat_mul.argtypes = [_D] * 3
         L.orc_validate.argtypes = [C.POINTER(Params)]
         L.orc_eval_pp.restype = C.c_int
@@ -158,6 +162,45 @@ def closest_point_triangle(p, a, b, c) -> np.ndarray:
     return out
 
 
+def closest_point_segment(p, a, b) -> np.ndarray:
+    out = np.zeros(3)
+    args = [_vec(v) for v in (p, a, b)]
+    lib().orc_closest_point_segment(*[_p(v) for v in args], _p(out))
+    return out
+
+
+def closest_point_rectangle(p, a, b, c, d) -> np.ndarray:
+    out = np.zeros(3)
+    args = [_vec(v) for v in (p, a, b, c, d)]
+    lib().orc_closest_point_rectangle(*[_p(v) for v in args], _p(out))
+    return out
+
+
+def closest_point_element(p, verts) -> np.ndarray:
+    """Closest point on an element given by its 1..4 vertices."""
+    v = np.asarray(verts, np.float64).reshape(-1, 3)
+    nv = len(v)
+    buf = np.zeros((4, 3))
+    buf[:nv] = v
+    buf[nv:] = v[-1]
+    out = np.zeros(3)
+    lib().orc_closest_point_element(_p(_vec(p)), nv, _p(buf), _p(out))
+    return out
+
+
+def pack_elements(elements):
+    """(nv [m] int32, verts [m][4][3]) from a list of 1..4-vertex arrays."""
+    m = len(elements)
+    nv = np.zeros(m, np.int32)
+    verts = np.zeros((m, 4, 3))
+    for k, e in enumerate(elements):
+        e = np.asarray(e, np.float64).reshape(-1, 3)
+        nv[k] = len(e)
+        verts[k, :len(e)] = e
+        verts[k, len(e):] = e[-1]
+    return nv, verts
+
+
 def quat_mul(a, b) -> np.ndarray:
     out = np.zeros(4)
     a = _vec(a)
@@ -201,7 +244,8 @@ def integrate(params, R, F, T, x, v, w, q):
 class Sim:
     """One simulation held by the oracle."""
 
-    def __init__(self, params, x, v=None, w=None, q=None, R=None, tri=None, rmesh=None):
+    def __init__(self, params, x, v=None, w=None, q=None, R=None, tri=None, rmesh=None,
+                 elements=None):
         x = _vec(x)
         n = x.shape[0]
         self.n = n
@@ -222,6 +266,8 @@ class Sim:
         self.ntri = 0
         if tri is not None:
             self.set_mesh(tri, rmesh)
+        if elements is not None:
+            self.set_mesh_elements(elements, rmesh)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -234,6 +280,23 @@ class Sim:
         m = tri.shape[0]
         rm = None if rmesh is None else np.ascontiguousarray(np.asarray(rmesh, np.float64).reshape(m))
         if lib().orc_set_mesh(self._h, m, _p(tri), _p(rm) if rm is not None else None) != 0:
+            raise ValueError("bad mesh")
+        self.ntri = m
+
+    def set_mesh_elements(self, elements, rmesh=None):
+        """Mesh of points, segments, triangles and rectangles: a list of
+        1..4-vertex arrays, or a pair (nv [m], verts [m][4][3])."""
+        if isinstance(elements, tuple):
+            nv, verts = elements
+            nv = np.ascontiguousarray(nv, np.int32)
+            verts = np.ascontiguousarray(np.asarray(verts, np.float64).reshape(len(nv), 12))
+        else:
+            nv, verts = pack_elements(elements)
+            verts = np.ascontiguousarray(verts.reshape(len(nv), 12))
+        m = len(nv)
+        rm = None if rmesh is None else np.ascontiguousarray(np.asarray(rmesh, np.float64).reshape(m))
+        if lib().orc_set_mesh_elements(self._h, m, nv.ctypes.data_as(_I32), _p(verts),
+                                       _p(rm) if rm is not None else None) != 0:
             raise ValueError("bad mesh")
         self.ntri = m
 
@@ -285,10 +348,12 @@ class Sim:
         return {"ki": ki, "kj": kj, "us": us, "ur": ur, "ut": ut, "f": f, "ti": ti, "tj": tj}
 
     def mesh(self):
-        tri = np.zeros((self.ntri, 3, 3))
+        """Current vertices [m][4][3] (slots past an element's own vertices
+        repeat its last one)."""
+        v = np.zeros((self.ntri, 4, 3))
         if self.ntri:
-            lib().orc_get_mesh(self._h, _p(tri))
-        return tri
+            lib().orc_get_mesh(self._h, _p(v))
+        return v
 
     def contact_keys(self):
         """Contact set of the current state (no forces, no advance)."""

@@ -144,6 +144,66 @@ void orc_closest_point_triangle(const double p[3], const double a[3], const doub
   for (int k = 0; k < 3; ++k) out[k] = (a[k] + ab[k] * v) + ac[k] * w;
 }
 
+/* Closest point on the line segment ab (Fig. 4B), Ericson Sec. 5.1.2: the
+ * projection parameter of p onto ab, clamped to the segment.  A segment of
+ * zero length gives a. */
+void orc_closest_point_segment(const double p[3], const double a[3], const double b[3],
+                               double out[3]) {
+  double ab[3], ap[3];
+  sub3(b, a, ab);
+  sub3(p, a, ap);
+  double t = dot3(ap, ab);
+  if (t <= 0.0) {
+    memcpy(out, a, 3 * sizeof(double));
+    return;
+  }
+  double dd = dot3(ab, ab);
+  if (t >= dd) {
+    memcpy(out, b, 3 * sizeof(double));
+    return;
+  }
+  double u = t / dd;
+  for (int k = 0; k < 3; ++k) out[k] = a[k] + u * ab[k];
+}
+
+/* Closest point on the rectangle with corners a, b, c, d in cyclic order
+ * (Fig. 4D), Ericson Sec. 5.1.4: p - a is expressed along the two edges
+ * e1 = b - a and e2 = d - a, which are orthogonal, and each coordinate is
+ * clamped to its edge on its own.  Corner c is implied (b + d - a) and not
+ * read. */
+void orc_closest_point_rectangle(const double p[3], const double a[3], const double b[3],
+                                 const double c[3], const double d[3], double out[3]) {
+  (void)c;
+  double e1[3], e2[3], ap[3];
+  sub3(b, a, e1);
+  sub3(d, a, e2);
+  sub3(p, a, ap);
+  double s1 = dot3(ap, e1), l1 = dot3(e1, e1);
+  double s2 = dot3(ap, e2), l2 = dot3(e2, e2);
+  double c1 = s1 >= l1 ? 1.0 : (s1 > 0.0 ? s1 / l1 : 0.0);
+  double c2 = s2 >= l2 ? 1.0 : (s2 > 0.0 ? s2 / l2 : 0.0);
+  for (int k = 0; k < 3; ++k) out[k] = (a[k] + c1 * e1[k]) + c2 * e2[k];
+}
+
+/* Closest point on mesh element v [4][3] with nv vertices (Section 3.3,
+ * Fig. 4A-D): the vertex itself, a segment, a triangle or a rectangle. */
+void orc_closest_point_element(const double p[3], int32_t nv, const double v[12], double out[3]) {
+  switch (nv) {
+    case 1:
+      memcpy(out, v, 3 * sizeof(double));
+      return;
+    case 2:
+      orc_closest_point_segment(p, v, v + 3, out);
+      return;
+    case 3:
+      orc_closest_point_triangle(p, v, v + 3, v + 6, out);
+      return;
+    default:
+      orc_closest_point_rectangle(p, v, v + 3, v + 6, v + 9, out);
+      return;
+  }
+}
+
 void orc_quat_mul(const double a[4], const double b[4], double out[4]) {
   /* (a0 b0 - av.bv, a0 bv + b0 av + av x bv) */
   double cr[3];
@@ -339,8 +399,10 @@ struct orc_sim {
   int64_t n;
   double *x, *v, *w, *q, *R, *m, *I;
   double *F, *T, *Fs, *Ts;
-  int64_t ntri;
-  double *tri0, *tri, *rmesh;
+  int64_t ntri;          /* mesh elements */
+  int32_t* nv;           /* vertices per element, 1..4 */
+  double *tri0, *tri;    /* vertices [ntri][4][3] at t = 0 and now */
+  double* rmesh;         /* element radii R_m */
   double t, t0;  /* t = t0 + nstep * dt */
   int64_t nstep;
   int32_t search_mode;
@@ -410,6 +472,7 @@ void orc_free(orc_sim* s) {
   free(s->tri0);
   free(s->tri);
   free(s->rmesh);
+  free(s->nv);
   free(s->hist);
   free(s->head);
   free(s->next);
@@ -418,21 +481,63 @@ void orc_free(orc_sim* s) {
 
 static void update_mesh(orc_sim* s);
 
-int orc_set_mesh(orc_sim* s, int64_t ntri, const double* tri, const double* rmesh) {
-  if (ntri < 0) return -1;
-  for (int64_t m = 0; m < ntri; ++m)
-    if (rmesh && !(rmesh[m] >= 0)) return -1;
+/* A rectangle's corners must have a right angle at corner 0 and corner 2 at
+ * corner 1 + corner 3 - corner 0, each to 1e-6 relative to the edges. */
+static int is_rectangle(const double* v) {
+  double e1[3], e2[3], g[3];
+  sub3(v + 3, v, e1);
+  sub3(v + 9, v, e2);
+  for (int k = 0; k < 3; ++k) g[k] = v[6 + k] - ((v[3 + k] + v[9 + k]) - v[k]);
+  double l1 = norm3(e1), l2 = norm3(e2);
+  if (fabs(dot3(e1, e2)) > 1e-6 * l1 * l2) return 0;
+  return norm3(g) <= 1e-6 * (l1 + l2);
+}
+
+int orc_set_mesh_elements(orc_sim* s, int64_t nel, const int32_t* nv, const double* verts,
+                          const double* rmesh) {
+  if (nel < 0) return -1;
+  for (int64_t m = 0; m < nel; ++m) {
+    if (nv[m] < 1 || nv[m] > 4) return -1;
+    for (int k = 0; k < 3 * nv[m]; ++k)
+      if (!isfinite(verts[12 * m + k])) return -1;
+    if (rmesh && !(rmesh[m] >= 0 && isfinite(rmesh[m]))) return -1;
+    if (nv[m] == 4 && !is_rectangle(verts + 12 * m)) return -1;
+  }
   free(s->tri0);
   free(s->tri);
   free(s->rmesh);
-  s->ntri = ntri;
-  s->tri0 = xmalloc((size_t)ntri * 9 * sizeof(double));
-  s->tri = xmalloc((size_t)ntri * 9 * sizeof(double));
-  s->rmesh = xmalloc((size_t)ntri * sizeof(double));
-  memcpy(s->tri0, tri, (size_t)ntri * 9 * sizeof(double));
-  for (int64_t m = 0; m < ntri; ++m) s->rmesh[m] = rmesh ? rmesh[m] : 0.0;
+  free(s->nv);
+  s->ntri = nel;
+  s->tri0 = xmalloc((size_t)nel * 12 * sizeof(double));
+  s->tri = xmalloc((size_t)nel * 12 * sizeof(double));
+  s->rmesh = xmalloc((size_t)nel * sizeof(double));
+  s->nv = xmalloc((size_t)nel * sizeof(int32_t));
+  for (int64_t m = 0; m < nel; ++m) {
+    s->nv[m] = nv[m];
+    /* slots past the element's own vertices repeat its last vertex */
+    for (int k = 0; k < 12; ++k) {
+      int slot = k / 3 < nv[m] ? k / 3 : nv[m] - 1;
+      s->tri0[12 * m + k] = verts[12 * m + 3 * slot + k % 3];
+    }
+    s->rmesh[m] = rmesh ? rmesh[m] : 0.0;
+  }
   update_mesh(s);
   return 0;
+}
+
+int orc_set_mesh(orc_sim* s, int64_t ntri, const double* tri, const double* rmesh) {
+  if (ntri < 0) return -1;
+  int32_t* nv = xmalloc((size_t)ntri * sizeof(int32_t));
+  double* v = xmalloc((size_t)ntri * 12 * sizeof(double));
+  for (int64_t m = 0; m < ntri; ++m) {
+    nv[m] = 3;
+    memcpy(v + 12 * m, tri + 9 * m, 9 * sizeof(double));
+    memcpy(v + 12 * m + 9, tri + 9 * m + 6, 3 * sizeof(double));
+  }
+  int rc = orc_set_mesh_elements(s, ntri, nv, v, rmesh);
+  free(nv);
+  free(v);
+  return rc;
 }
 
 static int key_less(int32_t ai, int32_t aj, int32_t bi, int32_t bj) {
@@ -485,13 +590,13 @@ static void update_mesh(orc_sim* s) {
   const double* om = s->p.mesh_omega;
   double wl = norm3(om);
   if (!(wl > 0.0)) {
-    if (s->ntri) memcpy(s->tri, s->tri0, (size_t)s->ntri * 9 * sizeof(double));
+    if (s->ntri) memcpy(s->tri, s->tri0, (size_t)s->ntri * 12 * sizeof(double));
     return;
   }
   double kx[3] = {om[0] / wl, om[1] / wl, om[2] / wl};
   double ang = wl * s->t;
   double co = cos(ang), si = sin(ang);
-  for (int64_t m = 0; m < s->ntri * 3; ++m) {
+  for (int64_t m = 0; m < s->ntri * 4; ++m) {
     double r[3];
     sub3(s->tri0 + 3 * m, s->p.mesh_center, r);
     double kxr[3];
@@ -615,9 +720,8 @@ static int64_t neighbours(const orc_sim* s, int64_t i, int only_greater, int64_t
 /* Evaluate particle-wall contact of particle i with element m, if any. */
 static int eval_wall(const orc_sim* s, int64_t i, int64_t m, const double* us, const double* ur,
                      double ut, orc_contact* o) {
-  const double* t = s->tri + 9 * m;
   double cp[3];
-  orc_closest_point_triangle(s->x + 3 * i, t, t + 3, t + 6, cp);
+  orc_closest_point_element(s->x + 3 * i, s->nv[m], s->tri + 12 * m, cp);
   /* contact test first, with no wall motion; motion needs the normal */
   double dv[3];
   sub3(s->x + 3 * i, cp, dv);
@@ -810,8 +914,8 @@ void orc_get_contacts(const orc_sim* s, int32_t* ki, int32_t* kj, double* us, do
   }
 }
 
-void orc_get_mesh(const orc_sim* s, double* tri) {
-  memcpy(tri, s->tri, (size_t)s->ntri * 9 * sizeof(double));
+void orc_get_mesh(const orc_sim* s, double* verts) {
+  memcpy(verts, s->tri, (size_t)s->ntri * 12 * sizeof(double));
 }
 
 int64_t orc_contact_keys(orc_sim* s, int64_t cap, int32_t* ki, int32_t* kj) {
@@ -821,9 +925,8 @@ int64_t orc_contact_keys(orc_sim* s, int64_t cap, int32_t* ki, int32_t* kj) {
   int64_t nbcap = 0;
   for (int64_t i = 0; i < s->n; ++i) {
     for (int64_t m = s->ntri - 1; m >= 0; --m) {
-      const double* t = s->tri + 9 * m;
       double cp[3], dv[3];
-      orc_closest_point_triangle(s->x + 3 * i, t, t + 3, t + 6, cp);
+      orc_closest_point_element(s->x + 3 * i, s->nv[m], s->tri + 12 * m, cp);
       sub3(s->x + 3 * i, cp, dv);
       double d = sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
       if ((s->R[i] + s->rmesh[m]) - d >= 0.0) {
@@ -874,9 +977,8 @@ int64_t orc_sample_keys(orc_sim* s, int64_t ns, const int64_t* idx, int64_t cap,
     for (int pass = 0; pass < 3; ++pass) {
       if (pass == 1) {
         for (int64_t m = s->ntri - 1; m >= 0; --m) {
-          const double* t = s->tri + 9 * m;
           double cp[3], dv[3];
-          orc_closest_point_triangle(s->x + 3 * p, t, t + 3, t + 6, cp);
+          orc_closest_point_element(s->x + 3 * p, s->nv[m], s->tri + 12 * m, cp);
           sub3(s->x + 3 * p, cp, dv);
           double d = sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
           if ((s->R[p] + s->rmesh[m]) - d >= 0.0) {

@@ -57,6 +57,14 @@ double orc_dt_default(double R_min, double rho, double E, double nu);
 /* Closest point on triangle abc to p (region method, Fig. 4C). */
 void orc_closest_point_triangle(const double p[3], const double a[3], const double b[3],
                                 const double c[3], double out[3]);
+/* Closest point on segment ab to p (Fig. 4B). */
+void orc_closest_point_segment(const double p[3], const double a[3], const double b[3],
+                               double out[3]);
+/* Closest point on rectangle abcd (corners in cyclic order, Fig. 4D). */
+void orc_closest_point_rectangle(const double p[3], const double a[3], const double b[3],
+                                 const double c[3], const double d[3], double out[3]);
+/* Closest point on a mesh element of nv = 1..4 vertices v[4][3]. */
+void orc_closest_point_element(const double p[3], int32_t nv, const double v[12], double out[3]);
 /* Hamilton product out = a*b, quaternions scalar first (Eq. spiral). */
 void orc_quat_mul(const double a[4], const double b[4], double out[4]);
 /* Validates parameters per Table 2 "Requirements"; returns 0 or -1. */
@@ -88,6 +96,15 @@ typedef struct orc_sim orc_sim;
 orc_sim* orc_create(const orc_params* p, int64_t n, const double* x, const double* v,
                     const double* w, const double* q, const double* R);
 void orc_free(orc_sim* s);
+/* Mesh elements with nv[m] = 1..4 vertices (point, segment, triangle,
+ * rectangle with corners in cyclic order), verts [nel][4][3] (slots past
+ * nv[m] ignored), radii rmesh [nel] >= 0 (NULL for 0).  Returns -1 for a
+ * bad count, coordinate or radius, or four corners that are not a
+ * rectangle (right angle at corner 0, corner 2 = corner 1 + corner 3 -
+ * corner 0, each to 1e-6 relative). */
+int orc_set_mesh_elements(orc_sim* s, int64_t nel, const int32_t* nv, const double* verts,
+                          const double* rmesh);
+/* Triangles only: tri [ntri][3][3]. */
 int orc_set_mesh(orc_sim* s, int64_t ntri, const double* tri, const double* rmesh);
 int orc_set_history(orc_sim* s, int64_t nc, const int32_t* ki, const int32_t* kj,
                     const double* us, const double* ur, const double* ut);
@@ -107,8 +124,9 @@ int64_t orc_num_contacts(const orc_sim* s);
  * and torques of each contact. */
 void orc_get_contacts(const orc_sim* s, int32_t* ki, int32_t* kj, double* us, double* ur,
                       double* ut, double* f, double* ti, double* tj);
-/* Current mesh vertices [ntri][3][3]. */
-void orc_get_mesh(const orc_sim* s, double* tri);
+/* Current mesh vertices [ntri][4][3] (slots past an element's own vertices
+ * repeat its last vertex). */
+void orc_get_mesh(const orc_sim* s, double* verts);
 
 /* Sampled one-step check for large systems: for each listed particle, find
  * every contact it takes part in at the current state (brute force over a

@@ -136,6 +136,54 @@ def floor_mesh(cx, cy, half, z=0.0):
     return np.ascontiguousarray(np.array([[a, b, c], [a, c, d]]))
 
 
+def primitive_mesh(box, seed):
+    """A container of side `box` built from every kind of mesh element
+    (Section 3.3, Fig. 4A-E), each with its own radius R_m:
+      - floor z = 0: four rectangles (R_m = 0);
+      - walls x = 0 and x = box: one rectangle each; walls y = 0 and
+        y = box: two triangles each (R_m = 0);
+      - a tilted rounded rectangle (R_m = 1 mm) and two tilted rounded
+        triangles (R_m = 0.8 mm) inside;
+      - six rounded segments (rails, R_m ~ U[0.3, 1.5] mm) and eight rounded
+        points (R_m ~ U[0.5, 2] mm) at random inside.
+    Returns (elements, rmesh): a list of 1..4-vertex arrays (rectangle
+    corners in cyclic order) and their radii."""
+    rng = np.random.Generator(np.random.PCG64(seed + 9000))
+    L = float(box)
+    h = L / 2
+    els, rm = [], []
+
+    def add(v, r):
+        els.append(np.asarray(v, float).reshape(-1, 3))
+        rm.append(float(r))
+
+    for x0 in (0.0, h):
+        for y0 in (0.0, h):
+            add([[x0, y0, 0], [x0 + h, y0, 0], [x0 + h, y0 + h, 0], [x0, y0 + h, 0]], 0.0)
+    for xw in (0.0, L):
+        add([[xw, 0, 0], [xw, L, 0], [xw, L, L], [xw, 0, L]], 0.0)
+    for yw in (0.0, L):
+        a, b, c, d = [0, yw, 0], [L, yw, 0], [L, yw, L], [0, yw, L]
+        add([a, b, c], 0.0)
+        add([a, c, d], 0.0)
+    # tilted rounded rectangle: corner, two orthogonal edges
+    c0 = np.array([0.3, 0.25, 0.45]) * L
+    e1 = np.array([0.4, 0.0, 0.1]) * L
+    e2 = np.cross(e1, [0.1, 1.0, 0.2])
+    e2 *= 0.3 * L / np.linalg.norm(e2)
+    add([c0, c0 + e1, c0 + e1 + e2, c0 + e2], 1.0 * MM)
+    for k in range(2):
+        t0 = rng.uniform(0.15, 0.85, 3) * L
+        add([t0, t0 + rng.normal(0, 0.2, 3) * L, t0 + rng.normal(0, 0.2, 3) * L], 0.8 * MM)
+    for k in range(6):
+        s0 = rng.uniform(0.1, 0.9, 3) * L
+        add([s0, np.clip(s0 + rng.normal(0, 0.3, 3) * L, 0.05 * L, 0.95 * L)],
+            rng.uniform(0.3, 1.5) * MM)
+    for k in range(8):
+        add([rng.uniform(0.1, 0.9, 3) * L], rng.uniform(0.5, 2.0) * MM)
+    return els, np.array(rm)
+
+
 def drum_mesh(radius, length, nseg=128, nring=31):
     """Closed drum around the y axis: nseg x nring x 2 shell triangles plus
     two end-cap fans of nseg triangles (8,192 for the defaults)."""
