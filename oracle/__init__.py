@@ -42,6 +42,28 @@ class Params(C.Structure):
                 ("mesh_center", C.c_double * 3)]
 
 
+class Spawn(C.Structure):
+    _fields_ = [("smin", C.c_double * 3), ("smax", C.c_double * 3), ("Rmin", C.c_double),
+                ("Rmax", C.c_double), ("v0", C.c_double * 3), ("w0", C.c_double * 3),
+                ("n_spawn", C.c_int64), ("n_max", C.c_int64), ("seed", C.c_uint64)]
+
+
+def make_spawn(smin, smax, Rmin, Rmax, v0=(0.0, 0.0, 0.0), w0=(0.0, 0.0, 0.0), n_spawn=100,
+               n_max=1000, seed=0) -> Spawn:
+    return Spawn((C.c_double * 3)(*smin), (C.c_double * 3)(*smax), float(Rmin), float(Rmax),
+                 (C.c_double * 3)(*v0), (C.c_double * 3)(*w0), int(n_spawn), int(n_max),
+                 int(seed))
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 output words for counter ctr[4] and key key[2]."""
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
 class Contact(C.Structure):
     _fields_ = [("delta", C.c_double), ("d", C.c_double), ("ri", C.c_double), ("rj", C.c_double),
                 ("n", C.c_double * 3), ("kn", C.c_double), ("ks", C.c_double),
@@ -106,6 +128,12 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_get_state.argtypes = [C.c_void_p, _D, _D, _D, _D]
         L.orc_get_forces.argtypes = [C.c_void_p, _D, _D, _D, _D]
+        L.orc_num_particles.restype = C.c_int64
+        L.orc_num_particles.argtypes = [C.c_void_p]
+        L.orc_get_radii.argtypes = [C.c_void_p, _D]
+        L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
+        L.orc_set_spawn.argtypes = [C.c_void_p, C.POINTER(Spawn)]
+        L.orc_spawn_status.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
         L.orc_num_contacts.restype = C.c_int64
         L.orc_num_contacts.argtypes = [C.c_void_p]
         L.orc_get_contacts.argtypes = [C.c_void_p, _I32, _I32, _D, _D, _D, _D, _D, _D]
@@ -322,6 +350,28 @@ class Sim:
     def step(self, nsteps: int = 1):
         if lib().orc_step(self._h, int(nsteps)) != 0:
             raise RuntimeError("oracle step failed")
+        self.n = int(lib().orc_num_particles(self._h))
+
+    def set_spawn(self, spawn=None, **kw):
+        """Particle spawning (Section 3.1): a Spawn structure or the keyword
+        arguments of make_spawn; None turns it off."""
+        if spawn is None and kw:
+            spawn = make_spawn(**kw)
+        if lib().orc_set_spawn(self._h, C.byref(spawn) if spawn is not None else None) != 0:
+            raise ValueError("bad spawn parameters")
+
+    def spawn_status(self):
+        a, r = C.c_uint64(), C.c_double()
+        lib().orc_spawn_status(self._h, C.byref(a), C.byref(r))
+        return int(a.value), float(r.value)
+
+    @property
+    def radii(self):
+        n = self.n
+        out = np.zeros(n)
+        if n:
+            lib().orc_get_radii(self._h, _p(out))
+        return out
 
     def state(self):
         n = self.n

@@ -36,6 +36,16 @@
  *       and stiffness in the constitutive laws (R* = R_i, m* = m_i,
  *       E* = E/(1-nu^2), G* = G/(2-nu)); r_i = R_i - delta/2 also for walls.
  *   R9  right-multiplication of the quaternion, no renormalisation.
+ *   S1  particle spawning (Section 3.1): at the start of each step, before
+ *       the contact search, up to N_spawn attempts, while n < N_max.  Attempt
+ *       a (counted over the whole run, from 0) draws four numbers from
+ *       Philox4x32-10 (counter (a_lo, a_hi, 0, 0), key (seed_lo, seed_hi)),
+ *       u = (k + 1/2) 2^-32: the centre s_min + u (s_max - s_min) per axis
+ *       and the radius R_min + u (R_max - R_min), unless a radius is carried
+ *       over from a failed attempt.  The candidate fails if it would touch
+ *       (delta >= 0, R2) any particle, including those spawned earlier in the
+ *       same step, or any mesh element; then its radius carries over.  New
+ *       particles take the next ids, velocity v0, spin w0, orientation 1.
  *   R14 rotating mesh (extension): vertices rotate rigidly about mesh_center
  *       by angle |Omega| t; the wall velocity at the contact point
  *       c = p + R_m n is Omega x (c - mesh_center) and the relative angular
@@ -387,6 +397,35 @@ int orc_eval_pw(const orc_params* p, const double xi[3], const double vi[3], con
   return 1;
 }
 
+/* ---- counter-based random numbers ---------------------------------------- */
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC 2011): each round multiplies words 0 and
+ * 2 by fixed odd constants, crosses the high and low halves with the other
+ * two words and the key, and bumps the key by the two Weyl constants. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+    uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
+    c0 = h1 ^ c1 ^ k0;
+    c1 = l1;
+    c2 = h0 ^ c3 ^ k1;
+    c3 = l0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* the uniform in (0, 1) of one 32-bit output: (k + 1/2) 2^-32, exact */
+static double unit_open(uint32_t k) { return ((double)k + 0.5) * (1.0 / 4294967296.0); }
+
 /* ---- simulation state ---------------------------------------------------- */
 typedef struct {
   int32_t ki, kj;
@@ -404,6 +443,12 @@ struct orc_sim {
   double *tri0, *tri;    /* vertices [ntri][4][3] at t = 0 and now */
   double* rmesh;         /* element radii R_m */
   double t, t0;  /* t = t0 + nstep * dt */
+  /* spawning (Section 3.1) */
+  int64_t cap;        /* allocated particles */
+  int32_t spawn_on;
+  orc_spawn sp;
+  uint64_t attempts;  /* spawn attempts made so far */
+  double carried;     /* radius carried over from a failed attempt, or 0 */
   int64_t nstep;
   int32_t search_mode;
   double cell_factor;
@@ -453,7 +498,107 @@ orc_sim* orc_create(const orc_params* p, int64_t n, const double* x, const doubl
   }
   s->search_mode = (n <= 2048) ? 0 : 1;
   s->cell_factor = 1.0;
+  s->cap = n;
   return s;
+}
+
+/* room for at least `need` particles in every per-particle array */
+static void ensure_cap(orc_sim* s, int64_t need) {
+  if (need <= s->cap) return;
+  int64_t c = 2 * s->cap + 64;
+  if (c < need) c = need;
+  size_t d = sizeof(double);
+  s->x = realloc(s->x, (size_t)c * 3 * d);
+  s->v = realloc(s->v, (size_t)c * 3 * d);
+  s->w = realloc(s->w, (size_t)c * 3 * d);
+  s->q = realloc(s->q, (size_t)c * 4 * d);
+  s->R = realloc(s->R, (size_t)c * d);
+  s->m = realloc(s->m, (size_t)c * d);
+  s->I = realloc(s->I, (size_t)c * d);
+  s->F = realloc(s->F, ((size_t)c * 3 + 1) * d);
+  s->T = realloc(s->T, ((size_t)c * 3 + 1) * d);
+  s->Fs = realloc(s->Fs, ((size_t)c + 1) * d);
+  s->Ts = realloc(s->Ts, ((size_t)c + 1) * d);
+  if (!s->x || !s->v || !s->w || !s->q || !s->R || !s->m || !s->I || !s->F || !s->T || !s->Fs ||
+      !s->Ts)
+    abort();
+  s->cap = c;
+}
+
+int orc_set_spawn(orc_sim* s, const orc_spawn* p) {
+  if (!p) {
+    s->spawn_on = 0;
+    return 0;
+  }
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(p->smin[k]) || !isfinite(p->smax[k]) || !(p->smax[k] >= p->smin[k]) ||
+        !isfinite(p->v0[k]) || !isfinite(p->w0[k]))
+      return -1;
+  if (!(p->Rmin > 0) || !(p->Rmax >= p->Rmin) || !isfinite(p->Rmax)) return -1;
+  if (p->n_spawn < 0 || p->n_max < 0) return -1;
+  s->sp = *p;
+  s->spawn_on = 1;
+  s->attempts = 0;
+  s->carried = 0.0;
+  return 0;
+}
+
+void orc_spawn_status(const orc_sim* s, uint64_t* attempts, double* carried) {
+  if (attempts) *attempts = s->attempts;
+  if (carried) *carried = s->carried;
+}
+
+/* would a sphere of radius r at c touch (delta >= 0) a particle or a mesh
+ * element? */
+static int spawn_blocked(const orc_sim* s, const double c[3], double r) {
+  for (int64_t i = 0; i < s->n; ++i) {
+    double dv[3];
+    sub3(s->x + 3 * i, c, dv);
+    double d = sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
+    if ((s->R[i] + r) - d >= 0.0) return 1;
+  }
+  for (int64_t m = 0; m < s->ntri; ++m) {
+    double cp[3], dv[3];
+    orc_closest_point_element(c, s->nv[m], s->tri + 12 * m, cp);
+    sub3(c, cp, dv);
+    double d = sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
+    if ((r + s->rmesh[m]) - d >= 0.0) return 1;
+  }
+  return 0;
+}
+
+/* the spawn attempts of one step (reading S1) */
+static void spawn_step(orc_sim* s) {
+  if (!s->spawn_on) return;
+  const orc_spawn* p = &s->sp;
+  const uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+  for (int64_t k = 0; k < p->n_spawn && s->n < p->n_max; ++k) {
+    uint64_t a = s->attempts++;
+    uint32_t ctr[4] = {(uint32_t)a, (uint32_t)(a >> 32), 0u, 0u}, o[4];
+    orc_philox4x32_10(ctr, key, o);
+    double c[3];
+    for (int d = 0; d < 3; ++d) c[d] = p->smin[d] + unit_open(o[d]) * (p->smax[d] - p->smin[d]);
+    double r = s->carried > 0.0 ? s->carried : p->Rmin + unit_open(o[3]) * (p->Rmax - p->Rmin);
+    if (spawn_blocked(s, c, r)) {
+      s->carried = r;
+      continue;
+    }
+    s->carried = 0.0;
+    ensure_cap(s, s->n + 1);
+    int64_t i = s->n++;
+    for (int d = 0; d < 3; ++d) {
+      s->x[3 * i + d] = c[d];
+      s->v[3 * i + d] = p->v0[d];
+      s->w[3 * i + d] = p->w0[d];
+    }
+    s->q[4 * i] = 1.0;
+    s->q[4 * i + 1] = 0.0;
+    s->q[4 * i + 2] = 0.0;
+    s->q[4 * i + 3] = 0.0;
+    s->R[i] = r;
+    s->m[i] = sphere_mass(s->p.rho, r);
+    s->I[i] = 2.0 / 5.0 * s->m[i] * r * r;
+  }
 }
 
 void orc_free(orc_sim* s) {
@@ -782,6 +927,7 @@ void orc_integrate(const orc_params* p, double R, const double F[3], const doubl
 static void add_scaled_norm(double* acc, const double v[3]) { *acc += norm3(v); }
 
 static int step_once(orc_sim* s) {
+  spawn_step(s);
   int64_t n = s->n;
   memset(s->F, 0, (size_t)n * 3 * sizeof(double));
   memset(s->T, 0, (size_t)n * 3 * sizeof(double));
@@ -894,6 +1040,10 @@ void orc_get_forces(const orc_sim* s, double* F, double* T, double* Fscale, doub
   if (Fscale) memcpy(Fscale, s->Fs, (size_t)s->n * sizeof(double));
   if (Tscale) memcpy(Tscale, s->Ts, (size_t)s->n * sizeof(double));
 }
+
+int64_t orc_num_particles(const orc_sim* s) { return s->n; }
+
+void orc_get_radii(const orc_sim* s, double* R) { memcpy(R, s->R, (size_t)s->n * sizeof(double)); }
 
 int64_t orc_num_contacts(const orc_sim* s) { return s->nhist; }
 

@@ -91,6 +91,19 @@ int orc_eval_pw(const orc_params* p, const double xi[3], const double vi[3], con
 void orc_integrate(const orc_params* p, double R, const double F[3], const double T[3],
                    double x[3], double v[3], double w[3], double q[4]);
 
+/* Philox4x32-10 counter-based generator (Salmon et al., SC 2011). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Particle spawning (Section 3.1): box [smin, smax], radii U[Rmin, Rmax],
+ * initial velocity v0 and spin w0, n_spawn attempts per step until n_max. */
+typedef struct {
+  double smin[3], smax[3];
+  double Rmin, Rmax;
+  double v0[3], w0[3];
+  int64_t n_spawn, n_max;
+  uint64_t seed;
+} orc_spawn;
+
 /* ---- whole simulations -------------------------------------------------- */
 typedef struct orc_sim orc_sim;
 orc_sim* orc_create(const orc_params* p, int64_t n, const double* x, const double* v,
@@ -108,6 +121,11 @@ int orc_set_mesh_elements(orc_sim* s, int64_t nel, const int32_t* nv, const doub
 int orc_set_mesh(orc_sim* s, int64_t ntri, const double* tri, const double* rmesh);
 int orc_set_history(orc_sim* s, int64_t nc, const int32_t* ki, const int32_t* kj,
                     const double* us, const double* ur, const double* ut);
+/* Turns spawning on (p != NULL; resets the attempt count and the carried
+ * radius) or off.  Returns -1 for a bad box, radius range or count. */
+int orc_set_spawn(orc_sim* s, const orc_spawn* p);
+/* Attempts made so far and the radius carried over (0 if none). */
+void orc_spawn_status(const orc_sim* s, uint64_t* attempts, double* carried);
 void orc_set_time(orc_sim* s, double t);
 double orc_get_time(const orc_sim* s);
 /* Contact search: 0 = brute force over all pairs, 1 = linked cells with
@@ -118,6 +136,8 @@ void orc_get_state(const orc_sim* s, double* x, double* v, double* w, double* q)
 /* Net force/torque of the last step, and the force scale
  * sum_c |contribution| + m|g| used to normalise per-particle errors. */
 void orc_get_forces(const orc_sim* s, double* F, double* T, double* Fscale, double* Tscale);
+int64_t orc_num_particles(const orc_sim* s);
+void orc_get_radii(const orc_sim* s, double* R);
 int64_t orc_num_contacts(const orc_sim* s);
 /* Contacts of the last step in key order (i ascending, then j ascending,
  * signed; j <= 0 labels mesh element -j), with their springs and the force
