@@ -7,8 +7,9 @@
  *   1. broad phase: bounding box of the particle centres, cubic cells of edge
  *      cell_factor * 2 R_max, particles sorted by cell;
  *   2. narrow phase: particle pairs with delta = R_i + R_j - d >= 0 in the
- *      27-cell neighbourhood, and particle-triangle pairs with
- *      delta = R_i + R_m - |x_i - closest point| >= 0 (Fig. 4C);
+ *      27-cell neighbourhood, and particle-mesh element pairs with
+ *      delta = R_i + R_m - |x_i - closest point| >= 0, the element being a
+ *      point, segment, triangle or rectangle of radius R_m (Fig. 4A-D);
  *   3. contact forces and torques: Hertz normal force with damping (Eq. fn,
  *      cn), Mindlin sliding, rolling and twisting springs with Coulomb limits
  *      (Eq. fs..ft, Coulombs/r/t, um..um_kinetic), torques, and the pairwise
@@ -25,8 +26,9 @@
  *  - The persistent id of a particle is its index in the arrays given to
  *    sdem_init / sdem_init_batch.  Every read returns data ordered by id.
  *  - Contact keys (Section 3.2): (ki, kj) with ki < kj the two particle ids
- *    for a particle pair, or kj = -m <= 0 for triangle m of the particle's own
- *    simulation (m counted from 0 in the order given to sdem_add_mesh).
+ *    for a particle pair, or kj = -m <= 0 for mesh element m of the
+ *    particle's own simulation (m counted from 0 in the order given to
+ *    sdem_add_mesh or sdem_add_mesh_elements).
  *  - Pointers passed to sdem_init, sdem_read_* may be device or host memory;
  *    the library copies, it never keeps a caller pointer.  Mesh and history
  *    arrays are host memory.
@@ -52,7 +54,7 @@ typedef struct sdem_ctx sdem_ctx;
 typedef enum {
   SDEM_OK = 0,
   SDEM_EINVAL = -1,     /* argument outside its documented range            */
-  SDEM_ECAPACITY = -2,  /* contacts, cells or triangles exceed the capacity */
+  SDEM_ECAPACITY = -2,  /* contacts, cells or elements exceed the capacity  */
   SDEM_ENONFINITE = -3, /* a position, velocity or spin became NaN or inf   */
   SDEM_EHIP = -4,       /* a HIP runtime call failed                        */
   SDEM_ESTATE = -5      /* call not allowed in the context's current state  */
@@ -79,7 +81,7 @@ typedef struct {
  *  contacts_max  contacts (particle pairs + particle-triangle) per step
  *  cells_max     grid cells per step over all simulations (the grid spans
  *                the bounding box of each simulation's centres)
- *  tri_max       triangles over all simulations
+ *  tri_max       mesh elements (of any kind) over all simulations
  *  nsims_max     simulations
  *  precision     SDEM_FP64: all arithmetic in double.  SDEM_MIXED: contact
  *                force and torque arithmetic in float, with double for
@@ -134,9 +136,84 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg, int32_t nsims,
 
 /* Sets the triangle mesh of simulation `sim` (replacing any earlier one):
  * tri [ntri][3][3] vertex coordinates (host), rmesh [ntri] element radii
- * R_m >= 0 (host, NULL for 0).  Allowed before the first step only. */
+ * R_m >= 0 (host, NULL for 0).  Allowed before the first step only.
+ * Equivalent to sdem_add_mesh_elements with every nverts[m] = 3. */
 int sdem_add_mesh(sdem_ctx* ctx, int32_t sim, int64_t ntri, const double* tri,
                   const double* rmesh);
+
+/* Sets the mesh of simulation `sim` (replacing any earlier one) from
+ * elements of one to four vertices (Section 3.3, Fig. 4A-E): a point, a line
+ * segment, a triangle or a rectangle, each thickened by its own radius
+ * R_m >= 0, so that a vertex acts as a sphere and an edge as a
+ * spherocylinder of that radius.  A particle touches element m when
+ * R_i + R_m - |x_i - closest point of the element| >= 0; the contact point
+ * lies R_m from the closest point towards the particle.  Elements touch any
+ * number of particles and a particle any number of elements (no merging
+ * across shared edges).
+ *   nverts [nel]      vertices of each element, 1..4 (host);
+ *   verts [nel][4][3] coordinates (host); slots past nverts[m] are not read;
+ *                     a rectangle gives its corners in cyclic order and must
+ *                     have a right angle at corner 0 and corner 2 at
+ *                     corner 1 + corner 3 - corner 0, each to 1e-6 relative
+ *                     to its edge lengths (corner 2 is then not used);
+ *   rmesh [nel]       radii R_m >= 0 (host, NULL for all 0).
+ * Keys kj = -m as in the conventions above.  Allowed before the first step
+ * only.  Returns SDEM_EINVAL for a vertex count outside 1..4, a non-finite
+ * coordinate, a negative radius or corners that are not a rectangle, and
+ * SDEM_ECAPACITY when the elements of all simulations exceed tri_max (or
+ * their bins the tables sized from it); the mesh is left unchanged then,
+ * except after a bin overflow, which fails the context. */
+int sdem_add_mesh_elements(sdem_ctx* ctx, int32_t sim, int64_t nel, const int32_t* nverts,
+                           const double* verts, const double* rmesh);
+
+/* Particle spawning (Section 3.1).  At the start of every step, before the
+ * broad phase, up to n_spawn attempts are made while the particle count is
+ * below n_max.  Attempt a (counted from 0 over the context's life, reset by
+ * sdem_set_spawn) takes the four 32-bit words of Philox4x32-10 (Salmon et
+ * al., SC 2011) for counter (a mod 2^32, a div 2^32, 0, 0) and key
+ * (seed mod 2^32, seed div 2^32); with u = (word + 1/2) 2^-32 the candidate
+ * centre is smin + u (smax - smin) per axis and its radius
+ * R_min + u (R_max - R_min), unless a radius carried over from the previous
+ * failed attempt is used instead.  The candidate fails if it would touch
+ * (R_j + r - d >= 0, the contact test) any particle, including one spawned
+ * earlier in the same step, or any mesh element; its radius then carries
+ * over (possibly to the next step).  A new particle gets the next id
+ * (ids stay dense: the count before it), velocity v0, spin w0, orientation
+ * (1, 0, 0, 0) and no contacts.  Only centres are confined to the box, so a
+ * flat box (smin = smax on an axis) spawns in a plane.  Steps that spawn run
+ * one at a time and wait for the count of new particles. */
+typedef struct {
+  double smin[3], smax[3];  /* spawn box of the centres, smin <= smax       */
+  double R_min, R_max;      /* radius range, 0 < R_min <= R_max             */
+  double v0[3], w0[3];      /* initial velocity and angular velocity        */
+  int64_t n_spawn;          /* attempts per step, 0..1024                   */
+  int64_t n_max;            /* spawn while the count is below this          */
+  uint64_t seed;            /* generator key                                */
+} sdem_spawn_params;
+
+/* Turns spawning on for simulation `sim` (p != NULL) or off (p == NULL).
+ * Spawning needs a context of one simulation (sim = 0) and n_max <= the
+ * context's n_max.  Resets the attempt counter and the carried radius.  A
+ * larger R_max than any initial radius widens the cells (edge
+ * cell_factor * 2 R_max) and the mesh reach from then on.  May be called
+ * between steps.  Returns SDEM_EINVAL for a bad box, radius range, count or
+ * context, SDEM_ECAPACITY for n_max above the context's n_max. */
+int sdem_set_spawn(sdem_ctx* ctx, int32_t sim, const sdem_spawn_params* p);
+
+/* Continues the spawn sequence at attempt `attempts` with a carried radius
+ * (0 for none, else within [R_min, R_max]), e.g. to resume a run.  Spawning
+ * must be on. */
+int sdem_set_spawn_status(sdem_ctx* ctx, uint64_t attempts, double carried);
+
+/* The particle count (host value, no wait), and if asked the attempts made
+ * so far and the radius carried over (0 if none; these wait for the
+ * stream). Any pointer may be NULL. */
+int sdem_spawn_status(sdem_ctx* ctx, int64_t* n, uint64_t* attempts, double* carried);
+
+/* Sets the step counter, and with it the clock t = steps * dt of moving
+ * meshes (the rotating-mesh extension), e.g. to resume a run at its time.
+ * The statistics of sdem_stats count from this value. */
+int sdem_set_clock(sdem_ctx* ctx, int64_t steps);
 
 /* Loads friction-spring history (host arrays): nc keys (ki, kj) as in the
  * conventions above, springs us[nc][3], ur[nc][3], ut[nc] in the orientation
@@ -168,6 +245,10 @@ int sdem_step_profiled(sdem_ctx* ctx, int64_t nsteps, double* phase_ms);
 int sdem_read_state(sdem_ctx* ctx, double* x, double* v, double* w, double* q, double* F,
                     double* T);
 
+/* Radii R [n] by persistent id (device or host memory; n from
+ * sdem_spawn_status, which grows with spawning). */
+int sdem_read_radii(sdem_ctx* ctx, double* R);
+
 /* Contacts of the last step in key order (ki ascending, then kj ascending,
  * signed) with their springs after that step: us, ur [cap][3], ut [cap].
  * *n_out receives the number of contacts; at most cap are written.  Any
@@ -194,6 +275,43 @@ const char* sdem_last_error(void);
  * and division are correctly rounded, as the host's are. */
 int sdem_selftest_rounding(int64_t n, const double* in, const double* in2, double* out,
                            void* hip_stream);
+
+/* ---- file formats (Section 6 of the paper) ------------------------------ */
+
+/* Reads a mesh in GeomView's Object File Format: "OFF", the vertex and face
+ * counts (a third count is ignored), the vertices, then per face its vertex
+ * count k (1..4: point, segment, triangle, rectangle with corners in cyclic
+ * order), k vertex indices and optionally an index into radii[n_radii], the
+ * list of mesh radii (0 when absent); '#' starts a comment.  Writes up to cap
+ * elements as sdem_add_mesh_elements takes them (nverts [cap], verts
+ * [cap][4][3], rmesh [cap]; any may be NULL) and the element count to
+ * *nel_out (call with cap = 0 to size the arrays).  SDEM_EINVAL, with the
+ * line, for a malformed file. */
+int sdem_read_off(const char* path, int32_t n_radii, const double* radii, int64_t cap,
+                  int64_t* nel_out, int32_t* nverts, double* verts, double* rmesh);
+
+/* Writes the state by id as CSV: a header "id,x,y,z,vx,vy,vz,wx,wy,wz,q0,q1,
+ * q2,q3,R" and one row per particle, every number to 17 significant digits
+ * (read back exactly).  Overwrites the file. */
+int sdem_write_csv(sdem_ctx* ctx, const char* path);
+
+/* Reads such a CSV: columns by header name in any order, x, y, z and R
+ * required, v and w zero and q the identity when absent; with an id column
+ * the rows go to their ids (a permutation of 0..n-1), else in file order.
+ * Arrays as sdem_init takes them (x, v, w [3][cap], q [4][cap], R [cap],
+ * host; any may be NULL); *n_out is the row count, and nothing is written
+ * when it exceeds cap. */
+int sdem_read_csv(const char* path, int64_t cap, int64_t* n_out, double* x, double* v, double* w,
+                  double* q, double* R);
+
+/* Writes the contacts of the last step with their springs as CSV
+ * ("ki,kj,usx,usy,usz,urx,ury,urz,ut", keys as in the conventions), and
+ * reads such a file into the arrays sdem_set_history takes (*nc_out rows; up
+ * to cap written).  With sdem_write_csv, sdem_set_clock and
+ * sdem_set_spawn_status this resumes a run with its friction history. */
+int sdem_write_contacts_csv(sdem_ctx* ctx, const char* path);
+int sdem_read_contacts_csv(const char* path, int64_t cap, int64_t* nc_out, int32_t* ki,
+                           int32_t* kj, double* us, double* ur, double* ut);
 
 #ifdef __cplusplus
 }

@@ -134,6 +134,7 @@ def lib():
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.orc_set_spawn.argtypes = [C.c_void_p, C.POINTER(Spawn)]
         L.orc_spawn_status.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
+        L.orc_set_spawn_status.argtypes = [C.c_void_p, C.c_uint64, C.c_double]
         L.orc_num_contacts.restype = C.c_int64
         L.orc_num_contacts.argtypes = [C.c_void_p]
         L.orc_get_contacts.argtypes = [C.c_void_p, _I32, _I32, _D, _D, _D, _D, _D, _D]
@@ -359,6 +360,9 @@ class Sim:
             spawn = make_spawn(**kw)
         if lib().orc_set_spawn(self._h, C.byref(spawn) if spawn is not None else None) != 0:
             raise ValueError("bad spawn parameters")
+
+    def set_spawn_status(self, attempts, carried):
+        lib().orc_set_spawn_status(self._h, int(attempts), float(carried))
 
     def spawn_status(self):
         a, r = C.c_uint64(), C.c_double()

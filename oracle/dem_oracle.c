@@ -543,6 +543,11 @@ int orc_set_spawn(orc_sim* s, const orc_spawn* p) {
   return 0;
 }
 
+void orc_set_spawn_status(orc_sim* s, uint64_t attempts, double carried) {
+  s->attempts = attempts;
+  s->carried = carried;
+}
+
 void orc_spawn_status(const orc_sim* s, uint64_t* attempts, double* carried) {
   if (attempts) *attempts = s->attempts;
   if (carried) *carried = s->carried;

@@ -124,6 +124,9 @@ int orc_set_history(orc_sim* s, int64_t nc, const int32_t* ki, const int32_t* kj
 /* Turns spawning on (p != NULL; resets the attempt count and the carried
  * radius) or off.  Returns -1 for a bad box, radius range or count. */
 int orc_set_spawn(orc_sim* s, const orc_spawn* p);
+/* Restarts the spawn sequence at attempt `attempts` with a carried radius
+ * (0 for none), e.g. to resume from another run's state. */
+void orc_set_spawn_status(orc_sim* s, uint64_t attempts, double carried);
 /* Attempts made so far and the radius carried over (0 if none). */
 void orc_spawn_status(const orc_sim* s, uint64_t* attempts, double* carried);
 void orc_set_time(orc_sim* s, double t);

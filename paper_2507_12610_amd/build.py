@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsdem.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "sdem_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f)
+           for f in ("kernels.hip", "spawn.hip", "sdem_api.hip", "sdem_io.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

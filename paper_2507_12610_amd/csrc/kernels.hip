@@ -510,7 +510,9 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
 }
 
 // ---------------------------------------------------------------------------
-// 4. mesh: rigid rotation (extension for rotating drums) and plane data
+// 4. mesh: rigid rotation (extension for rotating drums) and plane data (the
+//    plane through the stored slots 0, 1, 2: a triangle's, or a rectangle's
+//    through corners 0, 1 and 3)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) {
 #pragma clang fp contract(off)
@@ -553,7 +555,7 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) 
     c.tri_pl[4 * m + 1] = ny;
     c.tri_pl[4 * m + 2] = nz;
     c.tri_pl[4 * m + 3] = nx * t[0] + ny * t[1] + nz * t[2];
-  } else {  // degenerate element: no plane filter
+  } else {  // point, segment or degenerate element: no plane filter
     c.tri_pl[4 * m] = 0.0;
     c.tri_pl[4 * m + 1] = 0.0;
     c.tri_pl[4 * m + 2] = 0.0;
@@ -561,19 +563,25 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) 
   }
 }
 
-// Triangle bins (the triangle side of the broad phase): count, scan, fill and
-// sort the (bin, triangle) pairs.  A triangle enters every bin of its grid
+// Element bins (the mesh side of the broad phase): count, scan, fill and
+// sort the (bin, element) pairs.  An element enters every bin of its grid
 // that its vertex bounding box, grown by R_max + R_m of its simulation,
 // overlaps; the margin on the growth covers rounding of the box ends, so a
-// particle centre within R_i + R_m of the triangle lies in one of them.
+// particle centre within R_i + R_m of the element lies in one of them.
 __device__ __forceinline__ void tri_bins(const Ctx& c, int m, const MeshGrid& G, int i0[3],
                                          int i1[3]) {
   const double* t = c.tri + 9 * m;
+  const bool rect = c.tri_nv[m] == 4;
   const double reach = (c.sp[c.tri_sim[m]].rmax + c.rmesh[m]) * (1.0 + 1e-9);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double a = t[k], b = t[3 + k], e = t[6 + k];
-    const double mn = fmin(a, fmin(b, e)), mx = fmax(a, fmax(b, e));
+    double mn = fmin(a, fmin(b, e)), mx = fmax(a, fmax(b, e));
+    if (rect) {  // the implied fourth corner of a rectangle
+      const double f = (b + e) - a;
+      mn = fmin(mn, f);
+      mx = fmax(mx, f);
+    }
     const double pad = reach + 1e-12 * (fabs(mn) + fabs(mx));
     const double f0 = ((mn - pad) - G.lo[k]) * G.inv_h;
     const double f1 = ((mx + pad) - G.lo[k]) * G.inv_h;
@@ -744,7 +752,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     auto test_wall = [&](int m) {
       const double p[3] = {xs, ys, zs};
       double cp[3];
-      closest_on_triangle(p, c.tri + 9 * m, cp);
+      closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
       double dx, dy, dz, d;
       const double delta = pair_gap(xs, ys, zs, Rs, cp[0], cp[1], cp[2], c.rmesh[m], &dx, &dy, &dz, &d);
       if (delta >= 0.0) {
@@ -1088,7 +1096,7 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State A, State B, Con
       m = -1 - b;
       const double p[3] = {pa.x, pa.y, pa.z};
       double cp[3];
-      closest_on_triangle(p, c.tri + 9 * m, cp);
+      closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
       pb = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
     }
     // canonical orientation: body I carries the lower id (the particle for walls)
@@ -1638,6 +1646,14 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
   if (ev) (void)hipEventRecord(ev[4], s);
   k_integrate<<<nbp, kThreads, 0, s>>>(c, A, B, cnew, rebuild);
   if (ev) (void)hipEventRecord(ev[5], s);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_now(const Ctx& c, hipStream_t s) {
+  // a rotating mesh at the time of the step about to start (the step counter
+  // does not count it yet)
+  if (c.any_rotating && c.ntri > 0)
+    k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0, 0);
   return hipGetLastError();
 }
 

@@ -78,7 +78,8 @@ struct sdem_ctx {
   double* scratch = nullptr;  // [19][n] for reads into host memory
   std::vector<sdem_params> params;
   std::vector<int64_t> offsets;
-  std::vector<std::vector<double>> mesh_tri, mesh_r;
+  std::vector<std::vector<double>> mesh_tri, mesh_r;  // 9 doubles and R_m per element
+  std::vector<std::vector<int32_t>> mesh_nv;          // vertices per element
   std::vector<double> rmax;
   // graphs by pattern and starting buffer parity: two full steps, one full
   // step, one step keeping the cells, eight steps keeping the cells
@@ -92,7 +93,22 @@ struct sdem_ctx {
   int period = 1;         // the current period: halved after a call in which
                           // searches had to reach past the skin, doubled
                           // (up to rebuild_every) after one without
+  // particle spawning (one simulation per context)
+  bool spawn_on = false;
+  SpawnParams spawn{};
+  std::vector<int32_t> wchunk_host;  // first chunk of each wave (one simulation: the wave)
+  int32_t chunk_end = 0;
 };
+
+// Graphs bake the context by value: drop them when a field of it changes.
+static void drop_graphs(sdem_ctx* X) {
+  for (auto& row : X->graph)
+    for (auto& g : row)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+}
 
 // contact records are allocated per group of kGroup slots: gcap each
 static int64_t groups_of(const sdem_config& cfg) {
@@ -115,6 +131,9 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   const size_t NC = (size_t)nchunks_max(cfg);
   Ctx cc{};
   cc.ctr = L.take<Counters>(1);
+  cc.spawn = L.take<SpawnParams>(1);
+  cc.spawn_cand = L.take<double4>(kSpawnMax);
+  cc.spawn_thr = L.take<unsigned long long>(kSpawnMax);
   cc.sp = L.take<SimParams>(S);
   cc.sg = L.take<SimGrid>(S);
   cc.sim_of = L.take<int32_t>(N);
@@ -150,6 +169,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.tri_pl = L.take<double>(4 * M);
   cc.rmesh = L.take<double>(M);
   cc.tri_sim = L.take<int32_t>(M);
+  cc.tri_nv = L.take<int32_t>(M);
   cc.mg = L.take<MeshGrid>(S);
   cc.bin_cnt = L.take<int32_t>((size_t)std::max<int64_t>(bins_cap(cfg), 1));
   cc.bin_start = L.take<int32_t>((size_t)bins_cap(cfg) + 1);
@@ -293,6 +313,10 @@ static int upload_params(sdem_ctx* x) {
   return SDEM_OK;
 }
 
+namespace sdem {
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace sdem
+
 extern "C" {
 
 size_t sdem_workspace_bytes(const sdem_config* cfg) {
@@ -353,6 +377,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   X->offsets.assign(offsets, offsets + nsims + 1);
   X->mesh_tri.assign(nsims, {});
   X->mesh_r.assign(nsims, {});
+  X->mesh_nv.assign(nsims, {});
   X->rmax = rmax;
   carve(cfg, reinterpret_cast<char*>(workspace), &X->c, X->st, X->ct, &X->scratch);
   Ctx& c = X->c;
@@ -466,9 +491,22 @@ int sdem_init(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params,
 // edge starts at the larger of 2 reach and half the median triangle extent
 // and grows until the bins, and a bound on the (bin, triangle) entries that
 // holds at any orientation, fit this simulation's share of the tables.
-static MeshGrid mesh_grid(const std::vector<double>& tri, const std::vector<double>& rm,
-                          double rmax, bool rotating, const double* ctr, int64_t bins_budget,
-                          int64_t entries_budget, int32_t off) {
+// Corners of element m (its stored vertices, plus the implied fourth corner
+// of a rectangle); returns their number.
+static int element_corners(const std::vector<double>& tri, const std::vector<int32_t>& nv,
+                           size_t m, double out[4][3]) {
+  const double* t = tri.data() + 9 * m;
+  for (int v = 0; v < 3; ++v)
+    for (int a = 0; a < 3; ++a) out[v][a] = t[3 * v + a];
+  if (nv[m] != 4) return 3;
+  for (int a = 0; a < 3; ++a) out[3][a] = (t[3 + a] + t[6 + a]) - t[a];
+  return 4;
+}
+
+static MeshGrid mesh_grid(const std::vector<double>& tri, const std::vector<int32_t>& nv,
+                          const std::vector<double>& rm, double rmax, bool rotating,
+                          const double* ctr, int64_t bins_budget, int64_t entries_budget,
+                          int32_t off) {
   MeshGrid G{};
   const size_t nt = rm.size();
   double rmesh_max = 0.0;
@@ -477,10 +515,13 @@ static MeshGrid mesh_grid(const std::vector<double>& tri, const std::vector<doub
   double lo[3], hi[3];
   if (rotating) {
     double rv = 0.0;
-    for (size_t k = 0; k < 3 * nt; ++k) {
-      const double* v = tri.data() + 3 * k;
-      const double dx = v[0] - ctr[0], dy = v[1] - ctr[1], dz = v[2] - ctr[2];
-      rv = std::max(rv, sqrt(dx * dx + dy * dy + dz * dz));
+    for (size_t m = 0; m < nt; ++m) {
+      double cr[4][3];
+      const int k = element_corners(tri, nv, m, cr);
+      for (int v = 0; v < k; ++v) {
+        const double dx = cr[v][0] - ctr[0], dy = cr[v][1] - ctr[1], dz = cr[v][2] - ctr[2];
+        rv = std::max(rv, sqrt(dx * dx + dy * dy + dz * dz));
+      }
     }
     for (int a = 0; a < 3; ++a) {
       lo[a] = ctr[a] - (rv + reach);
@@ -491,11 +532,15 @@ static MeshGrid mesh_grid(const std::vector<double>& tri, const std::vector<doub
       lo[a] = HUGE_VAL;
       hi[a] = -HUGE_VAL;
     }
-    for (size_t k = 0; k < 3 * nt; ++k)
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = std::min(lo[a], tri[3 * k + a] - reach);
-        hi[a] = std::max(hi[a], tri[3 * k + a] + reach);
-      }
+    for (size_t m = 0; m < nt; ++m) {
+      double cr[4][3];
+      const int k = element_corners(tri, nv, m, cr);
+      for (int v = 0; v < k; ++v)
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::min(lo[a], cr[v][a] - reach);
+          hi[a] = std::max(hi[a], cr[v][a] + reach);
+        }
+    }
   }
   double span[3], smax = 0.0;
   for (int a = 0; a < 3; ++a) {
@@ -505,20 +550,25 @@ static MeshGrid mesh_grid(const std::vector<double>& tri, const std::vector<doub
     span[a] = hi[a] - lo[a];
     smax = std::max(smax, span[a]);
   }
-  // per triangle: largest vertex distance from the centroid (rotation
+  // per element: largest corner distance from the corners' mean (rotation
   // invariant) and largest box edge
   std::vector<double> rb(nt), ext(nt);
   for (size_t m = 0; m < nt; ++m) {
-    const double* t = tri.data() + 9 * m;
+    double cr[4][3];
+    const int k = element_corners(tri, nv, m, cr);
     double c3[3], e = 0.0, r = 0.0;
     for (int a = 0; a < 3; ++a) {
-      c3[a] = (t[a] + t[3 + a] + t[6 + a]) / 3.0;
-      const double mn = std::min(t[a], std::min(t[3 + a], t[6 + a]));
-      const double mx = std::max(t[a], std::max(t[3 + a], t[6 + a]));
+      double sum = 0.0, mn = cr[0][a], mx = cr[0][a];
+      for (int v = 0; v < k; ++v) {
+        sum += cr[v][a];
+        mn = std::min(mn, cr[v][a]);
+        mx = std::max(mx, cr[v][a]);
+      }
+      c3[a] = sum / k;
       e = std::max(e, mx - mn);
     }
-    for (int v = 0; v < 3; ++v) {
-      const double dx = t[3 * v] - c3[0], dy = t[3 * v + 1] - c3[1], dz = t[3 * v + 2] - c3[2];
+    for (int v = 0; v < k; ++v) {
+      const double dx = cr[v][0] - c3[0], dy = cr[v][1] - c3[1], dz = cr[v][2] - c3[2];
       r = std::max(r, sqrt(dx * dx + dy * dy + dz * dz));
     }
     rb[m] = r * (1.0 + 1e-6) + (rmax + rm[m]) * (1.0 + 1e-6);
@@ -553,31 +603,80 @@ static MeshGrid mesh_grid(const std::vector<double>& tri, const std::vector<doub
   return G;
 }
 
-int sdem_add_mesh(sdem_ctx* X, int32_t sim, int64_t ntri, const double* tri, const double* rmesh) {
+// A rectangle needs a right angle at corner 0 and corner 2 at corner 1 +
+// corner 3 - corner 0, each to 1e-6 relative to its edges.
+static bool is_rectangle(const double* v) {
+  double e[3], g[3], h[3];
+  for (int a = 0; a < 3; ++a) {
+    e[a] = v[3 + a] - v[a];
+    g[a] = v[9 + a] - v[a];
+    h[a] = v[6 + a] - ((v[3 + a] + v[9 + a]) - v[a]);
+  }
+  const double le = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  const double lg = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  const double lh = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  if (fabs(e[0] * g[0] + e[1] * g[1] + e[2] * g[2]) > 1e-6 * le * lg) return false;
+  return lh <= 1e-6 * (le + lg);
+}
+
+static int upload_mesh(sdem_ctx* X);
+
+// Elements of nv[m] = 1..4 vertices, verts [nel][4][3] (tri != NULL instead
+// gives triangles [nel][3][3]).
+static int set_mesh(sdem_ctx* X, int32_t sim, int64_t nel, const int32_t* nv, const double* verts,
+                    const double* tri, const double* rmesh) {
   if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
   if (X->stepped) return fail(SDEM_ESTATE, "meshes are fixed once stepping has started");
   if (sim < 0 || sim >= X->nsims) return fail(SDEM_EINVAL, "sim %d out of range", sim);
-  if (ntri < 0 || (ntri > 0 && !tri)) return fail(SDEM_EINVAL, "bad triangle array");
-  for (int64_t m = 0; m < 9 * ntri; ++m)
-    if (!isfinite(tri[m])) return fail(SDEM_EINVAL, "triangle vertex %lld is not finite", (long long)m);
-  for (int64_t m = 0; rmesh && m < ntri; ++m)
+  if (nel < 0 || (nel > 0 && !tri && (!nv || !verts)))
+    return fail(SDEM_EINVAL, "bad mesh element arrays");
+  std::vector<double> packed((size_t)9 * nel);
+  std::vector<int32_t> counts((size_t)nel, 3);
+  for (int64_t m = 0; m < nel; ++m) {
+    const int k = tri ? 3 : nv[m];
+    if (k < 1 || k > 4)
+      return fail(SDEM_EINVAL, "element %lld has %d vertices (1..4 allowed)", (long long)m, k);
+    const double* v = tri ? tri + 9 * m : verts + 12 * m;
+    for (int j = 0; j < 3 * k; ++j)
+      if (!isfinite(v[j]))
+        return fail(SDEM_EINVAL, "vertex coordinate of element %lld is not finite", (long long)m);
+    if (k == 4 && !is_rectangle(v))
+      return fail(SDEM_EINVAL, "element %lld is not a rectangle (corners in cyclic order)",
+                  (long long)m);
+    // stored slots: the vertex three times, the ends and the last end again,
+    // the three corners, or corners 0, 1 and 3 of a rectangle
+    static const int slots[5][3] = {{0, 0, 0}, {0, 0, 0}, {0, 1, 1}, {0, 1, 2}, {0, 1, 3}};
+    for (int j = 0; j < 3; ++j)
+      for (int a = 0; a < 3; ++a) packed[9 * m + 3 * j + a] = v[3 * slots[k][j] + a];
+    counts[m] = k;
+  }
+  for (int64_t m = 0; rmesh && m < nel; ++m)
     if (!(rmesh[m] >= 0) || !isfinite(rmesh[m]))
       return fail(SDEM_EINVAL, "mesh radius %lld must be >= 0", (long long)m);
-  int64_t total = ntri;
+  int64_t total = nel;
   for (int s = 0; s < X->nsims; ++s)
     if (s != sim) total += (int64_t)X->mesh_r[s].size();
   if (total > X->cfg.tri_max)
-    return fail(SDEM_ECAPACITY, "%lld triangles exceed tri_max = %lld", (long long)total,
+    return fail(SDEM_ECAPACITY, "%lld mesh elements exceed tri_max = %lld", (long long)total,
                 (long long)X->cfg.tri_max);
-  X->mesh_tri[sim].assign(tri, tri + 9 * ntri);
-  X->mesh_r[sim].assign((size_t)ntri, 0.0);
-  if (rmesh) X->mesh_r[sim].assign(rmesh, rmesh + ntri);
+  X->mesh_tri[sim] = std::move(packed);
+  X->mesh_nv[sim] = std::move(counts);
+  X->mesh_r[sim].assign((size_t)nel, 0.0);
+  if (rmesh) X->mesh_r[sim].assign(rmesh, rmesh + nel);
+  return upload_mesh(X);
+}
+
+// Uploads the meshes of every simulation and builds their element bins
+// (reach R_max + R_m of each simulation).
+static int upload_mesh(sdem_ctx* X) {
+  drop_graphs(X);
   // concatenate every simulation's mesh
   std::vector<double> all, rad;
-  std::vector<int32_t> owner;
+  std::vector<int32_t> owner, nva;
   for (int s = 0; s < X->nsims; ++s) {
     all.insert(all.end(), X->mesh_tri[s].begin(), X->mesh_tri[s].end());
     rad.insert(rad.end(), X->mesh_r[s].begin(), X->mesh_r[s].end());
+    nva.insert(nva.end(), X->mesh_nv[s].begin(), X->mesh_nv[s].end());
     owner.insert(owner.end(), X->mesh_r[s].size(), s);
   }
   Ctx& c = X->c;
@@ -589,6 +688,8 @@ int sdem_add_mesh(sdem_ctx* X, int32_t sim, int64_t ntri, const double* tri, con
     HIP_TRY(hipMemcpyAsync(c.rmesh, rad.data(), sizeof(double) * rad.size(), hipMemcpyHostToDevice,
                            st));
     HIP_TRY(hipMemcpyAsync(c.tri_sim, owner.data(), sizeof(int32_t) * owner.size(),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.tri_nv, nva.data(), sizeof(int32_t) * nva.size(),
                            hipMemcpyHostToDevice, st));
   }
   int rc = upload_params(X);
@@ -604,7 +705,8 @@ int sdem_add_mesh(sdem_ctx* X, int32_t sim, int64_t ntri, const double* tri, con
     mg[s].off = (int32_t)nbins;
     if (!nt) continue;
     const int64_t bb = bins_cap(X->cfg) * nt / tmax, eb = bin_entries_cap(X->cfg) * nt / tmax;
-    mg[s] = mesh_grid(X->mesh_tri[s], X->mesh_r[s], X->rmax[s], derive(X->params[s], 1.0, X->rmax[s]).rotating,
+    mg[s] = mesh_grid(X->mesh_tri[s], X->mesh_nv[s], X->mesh_r[s], X->rmax[s],
+                      derive(X->params[s], 1.0, X->rmax[s]).rotating,
                       X->params[s].mesh_center, std::max<int64_t>(bb, 1), eb, (int32_t)nbins);
     if (mg[s].dim[0] <= 0) return fail(SDEM_ECAPACITY, "no triangle bin grid fits simulation %d", s);
     nbins += (int64_t)mg[s].dim[0] * mg[s].dim[1] * mg[s].dim[2];
@@ -620,10 +722,20 @@ int sdem_add_mesh(sdem_ctx* X, int32_t sim, int64_t ntri, const double* tri, con
   HIP_TRY(hipStreamSynchronize(st));
   if (ctr.flags & kFlagCapBins) {
     X->failed = true;
-    return fail(SDEM_ECAPACITY, "the triangle bins overflowed their table of %d entries",
+    return fail(SDEM_ECAPACITY, "the mesh element bins overflowed their table of %d entries",
                 c.cap_bin_entries);
   }
   return SDEM_OK;
+}
+
+int sdem_add_mesh(sdem_ctx* X, int32_t sim, int64_t ntri, const double* tri, const double* rmesh) {
+  if (ntri > 0 && !tri) return fail(SDEM_EINVAL, "bad triangle array");
+  return set_mesh(X, sim, ntri, nullptr, nullptr, ntri > 0 ? tri : nullptr, rmesh);
+}
+
+int sdem_add_mesh_elements(sdem_ctx* X, int32_t sim, int64_t nel, const int32_t* nverts,
+                           const double* verts, const double* rmesh) {
+  return set_mesh(X, sim, nel, nverts, verts, nullptr, rmesh);
 }
 
 int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* kj,
@@ -691,6 +803,60 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
   if (nc) {
     HIP_TRY(hipMemcpy(C.key, K.data(), sizeof(int2) * Ctot, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(C.spr, SP.data(), sizeof(double) * kSpr * Ctot, hipMemcpyHostToDevice));
+  }
+  return SDEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// particle spawning (Section 3.1): one simulation per context
+// ---------------------------------------------------------------------------
+// The particle count grows from X->n to n1 (the new particles are already in
+// slots X->n .. n1-1 of the current state): every count-dependent field of
+// the context follows.
+static int grow_n(sdem_ctx* X, int64_t n1) {
+  const int64_t n0 = X->n;
+  Ctx& c = X->c;
+  hipStream_t st = X->stream;
+  X->n = n1;
+  X->offsets[1] = n1;
+  c.n = (int32_t)n1;
+  c.ngroups = (int32_t)((std::max<int64_t>(n1, 1) + kGroup - 1) / kGroup);
+  // one simulation: chunk w is wave w
+  const int64_t w0 = (n0 + kWave - 1) / kWave, w1 = (n1 + kWave - 1) / kWave;
+  if ((int64_t)X->wchunk_host.size() < w1) X->wchunk_host.resize((size_t)w1);
+  for (int64_t w = w0; w < w1; ++w) X->wchunk_host[w] = (int32_t)w;
+  X->chunk_end = (int32_t)w1;
+  c.nchunks = (int32_t)w1;
+  if (w1 > w0)
+    HIP_TRY(hipMemcpyAsync(c.wchunk + w0, X->wchunk_host.data() + w0, sizeof(int32_t) * (w1 - w0),
+                           hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c.chunk0 + 1, &X->chunk_end, sizeof(int32_t), hipMemcpyHostToDevice, st));
+  if (n1 > n0) HIP_TRY(hipMemsetAsync(c.sim_of + n0, 0, sizeof(int32_t) * (n1 - n0), st));
+  drop_graphs(X);
+  return upload_params(X);  // the simulation's particle range
+}
+
+static bool spawning(const sdem_ctx* X) {
+  return X->spawn_on && X->spawn.n_spawn > 0 && X->n < X->spawn.n_max;
+}
+
+// The spawn attempts of the step about to run; waits for them.  *stop is set
+// when an earlier step of the call has failed (the caller reports it).
+static int spawn_now(sdem_ctx* X, bool* stop) {
+  *stop = false;
+  HIP_TRY(launch_spawn(X->c, X->st[X->cur], X->ct[X->cur], X->stream));
+  Counters h;
+  HIP_TRY(hipMemcpyAsync(&h, X->c.ctr, sizeof h, hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  if (h.flags) {
+    *stop = true;
+    return SDEM_OK;
+  }
+  if (h.rebuild_next) X->need_rebuild = true;
+  if (h.spawn_new > 0) {
+    const int rc = grow_n(X, X->n + h.spawn_new);
+    if (rc) return rc;
+    X->need_rebuild = true;  // the new particles need cells
   }
   return SDEM_OK;
 }
@@ -820,6 +986,24 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
   unsigned long long drift0 = before.drift_steps;
   int64_t left = nsteps;
   while (left > 0) {
+    if (spawning(X)) {
+      // steps one at a time, each after its spawn attempts, without graphs
+      // (the particle count may change every step)
+      bool stop = false;
+      int rc = spawn_now(X, &stop);
+      if (rc) return rc;
+      if (stop) break;
+      if (X->c.skin_on && X->since >= X->period && X->since > 0) {
+        rc = adapt_period(X, &drift0);
+        if (rc) return rc;
+      }
+      const bool rb = rebuild_now(X);
+      HIP_TRY(enqueue_steps(X, 1, rb));
+      count_step(X, rb);
+      X->cur ^= 1;
+      --left;
+      continue;
+    }
     int pat;
     if (!X->c.skin_on) {
       pat = left >= 2 ? 0 : 1;
@@ -856,6 +1040,15 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
   const int start = X->cur;
   hipError_t err = hipSuccess;
   for (int64_t i = 0; i < nsteps && !err; ++i) {
+    if (spawning(X)) {
+      bool stop = false;
+      const int rc = spawn_now(X, &stop);
+      if (rc) {
+        for (int k = 0; k < kEvents; ++k) (void)hipEventDestroy(ev[k]);
+        return rc;
+      }
+      if (stop) break;
+    }
     const bool rb = rebuild_now(X);
     err = enqueue_steps(X, 1, rb, ev);
     count_step(X, rb);
@@ -903,6 +1096,19 @@ int sdem_read_state(sdem_ctx* X, double* x, double* v, double* w, double* q, dou
     if (dst[k] && dev[k] != dst[k])
       HIP_TRY(hipMemcpyAsync(dst[k], dev[k], sizeof(double) * words[k] * n, hipMemcpyDeviceToHost,
                              X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  return SDEM_OK;
+}
+
+int sdem_read_radii(sdem_ctx* X, double* R) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  const int64_t n = X->n;
+  if (n == 0) return SDEM_OK;
+  if (!R) return fail(SDEM_EINVAL, "R is NULL");
+  double* dev = is_device_ptr(R) ? R : X->scratch;
+  HIP_TRY(launch_scatter_radii(X->c, X->st[X->cur], dev, X->stream));
+  if (dev != R)
+    HIP_TRY(hipMemcpyAsync(R, dev, sizeof(double) * n, hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipStreamSynchronize(X->stream));
   return SDEM_OK;
 }
@@ -990,6 +1196,100 @@ int sdem_stats(sdem_ctx* X, int64_t* steps, int64_t* pp, int64_t* pw, int64_t* r
   if (pp) *pp = a;
   if (pw) *pw = b;
   if (rebuilds) *rebuilds = (int64_t)h.rebuilds;
+  return SDEM_OK;
+}
+
+int sdem_set_spawn(sdem_ctx* X, int32_t sim, const sdem_spawn_params* p) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (X->failed) return fail(SDEM_ESTATE, "context failed in an earlier step; read it and re-init");
+  if (!p) {
+    X->spawn_on = false;
+    return SDEM_OK;
+  }
+  if (X->nsims != 1 || sim != 0)
+    return fail(SDEM_EINVAL, "spawning needs a context of one simulation (sim 0)");
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(p->smin[k]) || !isfinite(p->smax[k]) || !(p->smax[k] >= p->smin[k]))
+      return fail(SDEM_EINVAL, "spawn box: s_min <= s_max, finite, on every axis");
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(p->v0[k]) || !isfinite(p->w0[k]))
+      return fail(SDEM_EINVAL, "spawn v0 and w0 must be finite");
+  if (!(p->R_min > 0) || !(p->R_max >= p->R_min) || !isfinite(p->R_max))
+    return fail(SDEM_EINVAL, "spawn radii: 0 < R_min <= R_max");
+  if (p->n_spawn < 0 || p->n_spawn > kSpawnMax)
+    return fail(SDEM_EINVAL, "n_spawn must be in [0, %d]", kSpawnMax);
+  if (p->n_max < 0) return fail(SDEM_EINVAL, "n_max must be >= 0");
+  if (p->n_max > X->cfg.n_max)
+    return fail(SDEM_ECAPACITY, "spawn n_max = %lld exceeds the context's n_max = %lld",
+                (long long)p->n_max, (long long)X->cfg.n_max);
+  SpawnParams& S = X->spawn;
+  for (int k = 0; k < 3; ++k) {
+    S.smin[k] = p->smin[k];
+    S.smax[k] = p->smax[k];
+    S.v0[k] = p->v0[k];
+    S.w0[k] = p->w0[k];
+  }
+  S.Rmin = p->R_min;
+  S.Rmax = p->R_max;
+  S.n_spawn = (int32_t)p->n_spawn;
+  S.sim = 0;
+  S.n_max = p->n_max;
+  S.key[0] = (uint32_t)p->seed;
+  S.key[1] = (uint32_t)(p->seed >> 32);
+  hipStream_t st = X->stream;
+  HIP_TRY(hipMemcpyAsync(X->c.spawn, &S, sizeof S, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(&X->c.ctr->spawn_attempts, 0,
+                         sizeof(unsigned long long) + sizeof(double) + sizeof(int32_t), st));
+  // spawned radii up to R_max set the cell edge and the mesh reach
+  if (p->R_max > X->rmax[0]) {
+    X->rmax[0] = p->R_max;
+    const int rc = X->mesh_r[0].empty() ? upload_params(X) : upload_mesh(X);
+    if (rc) return rc;
+  }
+  if (X->wchunk_host.size() < (size_t)((X->n + kWave - 1) / kWave)) {
+    X->wchunk_host.resize((size_t)((X->n + kWave - 1) / kWave));
+    for (size_t w = 0; w < X->wchunk_host.size(); ++w) X->wchunk_host[w] = (int32_t)w;
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  X->spawn_on = true;
+  return SDEM_OK;
+}
+
+int sdem_set_spawn_status(sdem_ctx* X, uint64_t attempts, double carried) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (!(carried == 0.0 || (carried >= X->spawn.Rmin && carried <= X->spawn.Rmax)) || !X->spawn_on)
+    return fail(SDEM_EINVAL, "spawning is off, or the carried radius is outside [R_min, R_max]");
+  struct {
+    unsigned long long a;
+    double r;
+  } h{attempts, carried};
+  HIP_TRY(hipMemcpyAsync(&X->c.ctr->spawn_attempts, &h, sizeof h, hipMemcpyHostToDevice,
+                         X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  return SDEM_OK;
+}
+
+int sdem_set_clock(sdem_ctx* X, int64_t steps) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (steps < 0) return fail(SDEM_EINVAL, "steps must be >= 0");
+  const unsigned long long s = (unsigned long long)steps;
+  HIP_TRY(hipMemcpyAsync(&X->c.ctr->steps, &s, sizeof s, hipMemcpyHostToDevice, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  HIP_TRY(launch_mesh_now(X->c, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  return SDEM_OK;
+}
+
+int sdem_spawn_status(sdem_ctx* X, int64_t* n, uint64_t* attempts, double* carried) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (n) *n = X->n;
+  if (attempts || carried) {
+    Counters h;
+    HIP_TRY(hipMemcpyAsync(&h, X->c.ctr, sizeof h, hipMemcpyDeviceToHost, X->stream));
+    HIP_TRY(hipStreamSynchronize(X->stream));
+    if (attempts) *attempts = h.spawn_attempts;
+    if (carried) *carried = h.spawn_carried;
+  }
   return SDEM_OK;
 }
 

@@ -24,6 +24,7 @@ constexpr int kCand = 32;           // candidates one search lane records at a r
 constexpr int kGroupShift = 8;      // contact records are allocated per group of
 constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots
 constexpr int kBinScanThreads = 1024;  // one workgroup scans the triangle bins
+constexpr int kSpawnMax = 1024;     // spawn attempts per step at most
 
 enum : int {
   kFlagCapContacts = 1,
@@ -86,6 +87,22 @@ struct Counters {
   unsigned long long steps;  // steps started (a failed one included)
   unsigned long long rebuilds;  // steps that rebuilt the cells
   unsigned long long drift_steps;  // steps whose searches reached past the skin
+  unsigned long long spawn_attempts;  // spawn attempts made so far
+  double spawn_carried;  // radius carried over from a failed attempt, 0 if none
+  int32_t spawn_new;     // particles the last spawn placed
+  int32_t pad3;
+};
+
+// Particle spawning (Section 3.1) of simulation `sim`: attempts per step, the
+// box of the centres, the radius range, the initial velocity and spin, the
+// cap on the particle count and the generator key.
+struct SpawnParams {
+  double smin[3], smax[3];
+  double Rmin, Rmax;
+  double v0[3], w0[3];
+  int32_t n_spawn, sim;
+  int64_t n_max;
+  uint32_t key[2];
 };
 
 // One buffer of per-particle state in cell-sorted order, packed per particle
@@ -151,8 +168,9 @@ struct Ctx {
                       // on the owner (3), torque on the partner (3), pad
   double* F;          // [3][n] contact force of the last step, by slot
   double* T;          // [3][n] contact torque of the last step, by slot
-  double* tri_ref;    // [ntri][9] vertices at t = 0
-  double* tri;        // [ntri][9] vertices at the current step
+  double* tri_ref;    // [ntri][9] element vertices at t = 0 (see closest_on_element)
+  double* tri;        // [ntri][9] element vertices at the current step
+  int32_t* tri_nv;    // [ntri] vertices per element, 1..4
   double* tri_pl;     // [ntri][4] unit normal and offset of the plane
   double* rmesh;      // [ntri]
   int32_t* tri_sim;   // [ntri]
@@ -161,6 +179,10 @@ struct Ctx {
   int32_t* bin_start; // [nbins+1]
   int32_t* bin_tri;   // [cap_bin_entries] triangles of each bin, ascending
   Counters* ctr;
+  SpawnParams* spawn;       // [1]
+  double4* spawn_cand;      // [kSpawnMax] candidate centre and radius fraction
+  unsigned long long* spawn_thr;  // [kSpawnMax] smallest radius that would touch
+                            // something, per candidate (bits of a double >= 0)
 };
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -246,11 +268,75 @@ __device__ __forceinline__ void closest_on_triangle(const double p[3], const dou
   out[2] = (a2 + ab2 * bv) + ac2 * bw;
 }
 
+// Closest point of segment (a, b) to p: the projection parameter, clamped to
+// the segment (Ericson Sec. 5.1.2).  A zero-length segment gives a.
+__device__ __forceinline__ void closest_on_segment(const double p[3], const double* t,
+                                                   double out[3]) {
+#pragma clang fp contract(off)
+  const double a0 = t[0], a1 = t[1], a2 = t[2];
+  const double ab0 = t[3] - a0, ab1 = t[4] - a1, ab2 = t[5] - a2;
+  const double u = ((p[0] - a0) * ab0 + (p[1] - a1) * ab1) + (p[2] - a2) * ab2;
+  if (u <= 0.0) {
+    out[0] = a0; out[1] = a1; out[2] = a2;
+    return;
+  }
+  const double ll = (ab0 * ab0 + ab1 * ab1) + ab2 * ab2;
+  if (u >= ll) {
+    out[0] = t[3]; out[1] = t[4]; out[2] = t[5];
+    return;
+  }
+  const double f = u / ll;
+  out[0] = a0 + f * ab0; out[1] = a1 + f * ab1; out[2] = a2 + f * ab2;
+}
+
+// Closest point of the rectangle with corner a = t[0..2] and the two
+// neighbouring corners b = t[3..5], d = t[6..8] (orthogonal edges): the
+// coordinates of p - a along each edge, clamped to the edge one at a time
+// (Ericson Sec. 5.1.4).
+__device__ __forceinline__ void closest_on_rectangle(const double p[3], const double* t,
+                                                     double out[3]) {
+#pragma clang fp contract(off)
+  const double a0 = t[0], a1 = t[1], a2 = t[2];
+  const double e0 = t[3] - a0, e1 = t[4] - a1, e2 = t[5] - a2;
+  const double g0 = t[6] - a0, g1 = t[7] - a1, g2 = t[8] - a2;
+  const double q0 = p[0] - a0, q1 = p[1] - a1, q2 = p[2] - a2;
+  const double se = (q0 * e0 + q1 * e1) + q2 * e2, le = (e0 * e0 + e1 * e1) + e2 * e2;
+  const double sg = (q0 * g0 + q1 * g1) + q2 * g2, lg = (g0 * g0 + g1 * g1) + g2 * g2;
+  const double ce = se >= le ? 1.0 : (se > 0.0 ? se / le : 0.0);
+  const double cg = sg >= lg ? 1.0 : (sg > 0.0 ? sg / lg : 0.0);
+  out[0] = (a0 + ce * e0) + cg * g0;
+  out[1] = (a1 + ce * e1) + cg * g1;
+  out[2] = (a2 + ce * e2) + cg * g2;
+}
+
+// Closest point of mesh element m with nv = 1..4 vertices (point, segment,
+// triangle, rectangle; Section 3.3, Fig. 4A-D).  Nine doubles per element:
+// the vertex (point), the two ends (segment), the three corners (triangle),
+// or corners 0, 1 and 3 of a rectangle (corner 2 is implied).
+__device__ __forceinline__ void closest_on_element(const double p[3], const double* t, int nv,
+                                                   double out[3]) {
+  if (nv == 3) {
+    closest_on_triangle(p, t, out);
+  } else if (nv == 4) {
+    closest_on_rectangle(p, t, out);
+  } else if (nv == 2) {
+    closest_on_segment(p, t, out);
+  } else {
+    out[0] = t[0]; out[1] = t[1]; out[2] = t[2];
+  }
+}
+
 // Host launchers (kernels live in the .hip files).
 // Phases of a step as timed by sdem_step_profiled: grid, sort+reorder (+mesh),
 // narrow phase, contact forces, integration.
 constexpr int kPhases = 5;
 constexpr int kEvents = kPhases + 3;  // phase boundaries, then the force kernel's own pair
+// Spawn attempts of one step (Section 3.1) on the state A at the start of
+// the step, before its broad phase: new particles go to slots n.. of A, with
+// no contacts in cold; the counters tell how many.
+hipError_t launch_spawn(const Ctx& c, const State& A, const Contacts& cold, hipStream_t s);
+hipError_t launch_mesh_now(const Ctx& c, hipStream_t s);
+hipError_t launch_scatter_radii(const Ctx& c, const State& S, double* R, hipStream_t s);
 hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
                        const Contacts& cnew, int precision, int rebuild, hipStream_t s,
                        hipEvent_t* ev = nullptr);

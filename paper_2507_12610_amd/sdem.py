@@ -22,6 +22,9 @@ _NAMES = {SDEM_EINVAL: "EINVAL", SDEM_ECAPACITY: "ECAPACITY", SDEM_ENONFINITE: "
           SDEM_EHIP: "EHIP", SDEM_ESTATE: "ESTATE"}
 
 EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_batch", "sdem_add_mesh",
+           "sdem_add_mesh_elements", "sdem_set_spawn", "sdem_spawn_status", "sdem_read_radii",
+           "sdem_set_spawn_status", "sdem_set_clock", "sdem_read_off", "sdem_write_csv",
+           "sdem_read_csv", "sdem_write_contacts_csv", "sdem_read_contacts_csv",
            "sdem_set_history", "sdem_step", "sdem_read_state", "sdem_read_contacts", "sdem_stats",
            "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding", "sdem_step_profiled")
 PHASES = ("grid", "sort", "detect", "force", "integrate", "force_kernel")
@@ -39,6 +42,21 @@ class Params(C.Structure):
                 ("mu_t", C.c_double), ("eta", C.c_double), ("g", C.c_double * 3),
                 ("dt", C.c_double), ("mesh_omega", C.c_double * 3),
                 ("mesh_center", C.c_double * 3)]
+
+
+class SpawnParams(C.Structure):
+    _fields_ = [("smin", C.c_double * 3), ("smax", C.c_double * 3), ("R_min", C.c_double),
+                ("R_max", C.c_double), ("v0", C.c_double * 3), ("w0", C.c_double * 3),
+                ("n_spawn", C.c_int64), ("n_max", C.c_int64), ("seed", C.c_uint64)]
+
+
+def make_spawn(smin, smax, Rmin, Rmax, v0=(0.0, 0.0, 0.0), w0=(0.0, 0.0, 0.0), n_spawn=100,
+               n_max=1000, seed=0) -> SpawnParams:
+    """Spawn settings (Section 3.1): box of the centres, radius range,
+    initial velocity and spin, attempts per step, cap, generator seed."""
+    return SpawnParams((C.c_double * 3)(*smin), (C.c_double * 3)(*smax), float(Rmin),
+                       float(Rmax), (C.c_double * 3)(*v0), (C.c_double * 3)(*w0), int(n_spawn),
+                       int(n_max), int(seed))
 
 
 class Config(C.Structure):
@@ -70,6 +88,21 @@ def lib():
                                       C.POINTER(Params), _I64, _VP, _VP, _VP, _VP, _VP, _VP,
                                       C.c_size_t, _VP]
         L.sdem_add_mesh.argtypes = [_VP, C.c_int32, C.c_int64, _D, _D]
+        L.sdem_add_mesh_elements.argtypes = [_VP, C.c_int32, C.c_int64, _I32, _D, _D]
+        L.sdem_set_spawn.argtypes = [_VP, C.c_int32, C.POINTER(SpawnParams)]
+        L.sdem_read_radii.argtypes = [_VP, _VP]
+        L.sdem_set_spawn_status.argtypes = [_VP, C.c_uint64, C.c_double]
+        L.sdem_set_clock.argtypes = [_VP, C.c_int64]
+        L.sdem_read_off.argtypes = [C.c_char_p, C.c_int32, _D, C.c_int64, C.POINTER(C.c_int64),
+                                    _I32, _D, _D]
+        L.sdem_write_csv.argtypes = [_VP, C.c_char_p]
+        L.sdem_read_csv.argtypes = [C.c_char_p, C.c_int64, C.POINTER(C.c_int64), _D, _D, _D, _D,
+                                    _D]
+        L.sdem_write_contacts_csv.argtypes = [_VP, C.c_char_p]
+        L.sdem_read_contacts_csv.argtypes = [C.c_char_p, C.c_int64, C.POINTER(C.c_int64), _I32,
+                                             _I32, _D, _D, _D]
+        L.sdem_spawn_status.argtypes = [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_double)]
         L.sdem_set_history.argtypes = [_VP, C.c_int64, _I32, _I32, _D, _D, _D]
         L.sdem_step.argtypes = [_VP, C.c_int64]
         L.sdem_step_profiled.argtypes = [_VP, C.c_int64, _D]
@@ -153,6 +186,76 @@ def autotune(sims, candidates=None, steps=20, warmup=6, precision="fp64", device
     return dict(best), timings
 
 
+def pack_elements(elements):
+    """(nverts [m] int32, verts [m][4][3] float64) for sdem_add_mesh_elements
+    from a list of mesh elements, each an array of 1..4 vertices (point,
+    segment, triangle, rectangle with corners in cyclic order)."""
+    m = len(elements)
+    nv = np.zeros(m, np.int32)
+    verts = np.zeros((m, 4, 3))
+    for k, e in enumerate(elements):
+        e = np.asarray(e, np.float64).reshape(-1, 3)
+        nv[k] = len(e)
+        verts[k, :len(e)] = e
+    return nv, verts
+
+
+def read_off(path, radii=(0.0,)):
+    """Mesh elements from an OFF file (faces of 1..4 vertices, a trailing
+    index into ``radii`` per face): (list of vertex arrays, radii [m])."""
+    L = lib()
+    r = np.ascontiguousarray(radii, np.float64).reshape(-1)
+    m = C.c_int64()
+    _check(L.sdem_read_off(os.fsencode(path), len(r), r.ctypes.data_as(_D), 0, C.byref(m), None,
+                           None, None))
+    nv = np.zeros(max(m.value, 1), np.int32)
+    verts = np.zeros((max(m.value, 1), 4, 3))
+    rm = np.zeros(max(m.value, 1))
+    _check(L.sdem_read_off(os.fsencode(path), len(r), r.ctypes.data_as(_D), m.value, C.byref(m),
+                           nv.ctypes.data_as(_I32), verts.ctypes.data_as(_D),
+                           rm.ctypes.data_as(_D)))
+    return [verts[k, :nv[k]].copy() for k in range(m.value)], rm[:m.value].copy()
+
+
+def read_csv(path):
+    """Particle state from a CSV file (header row, columns by name): dict of
+    x, v, w (n, 3), q (n, 4), R (n)."""
+    L = lib()
+    n = C.c_int64()
+    _check(L.sdem_read_csv(os.fsencode(path), 0, C.byref(n), None, None, None, None, None))
+    k = n.value
+    a = {key: np.zeros((w, max(k, 1))) for key, w in (("x", 3), ("v", 3), ("w", 3), ("q", 4))}
+    R = np.zeros(max(k, 1))
+    _check(L.sdem_read_csv(os.fsencode(path), k, C.byref(n), *[a[key].ctypes.data_as(_D)
+                                                                for key in ("x", "v", "w", "q")],
+                           R.ctypes.data_as(_D)))
+    out = {key: np.ascontiguousarray(val[:, :k].T) for key, val in a.items()}
+    out["R"] = R[:k].copy()
+    return out
+
+
+def read_contacts_csv(path):
+    """Contact keys and springs from a CSV file written by
+    Solver.write_contacts_csv: dict of ki, kj, us, ur, ut."""
+    L = lib()
+    n = C.c_int64()
+    _check(L.sdem_read_contacts_csv(os.fsencode(path), 0, C.byref(n), None, None, None, None,
+                                    None))
+    k = max(n.value, 1)
+    ki, kj = np.zeros(k, np.int32), np.zeros(k, np.int32)
+    us, ur, ut = np.zeros((k, 3)), np.zeros((k, 3)), np.zeros(k)
+    _check(L.sdem_read_contacts_csv(os.fsencode(path), n.value, C.byref(n),
+                                    ki.ctypes.data_as(_I32), kj.ctypes.data_as(_I32),
+                                    us.ctypes.data_as(_D), ur.ctypes.data_as(_D),
+                                    ut.ctypes.data_as(_D)))
+    m = n.value
+    return {"ki": ki[:m], "kj": kj[:m], "us": us[:m], "ur": ur[:m], "ut": ut[:m]}
+
+
+def _mesh_count(s):
+    return len(s["elements"]) if s.get("elements") is not None else len(s.get("tri", ()))
+
+
 class Solver:
     """One context of the HIP solver holding one or several simulations.
 
@@ -162,7 +265,7 @@ class Solver:
 
     def __init__(self, sims, precision="fp64", device="cuda:0", contacts_max=None,
                  cells_max=None, cell_factor=1.0, block=0, cell_slack=8.0, detect_lanes=0,
-                 skin=0.0, rebuild_every=0):
+                 skin=0.0, rebuild_every=0, spawn=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("sdem needs a GPU: torch.cuda.is_available() is False")
@@ -176,17 +279,33 @@ class Solver:
         self.offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
         n = int(self.offsets[-1])
         self.n = n
-        ntri = sum(len(s["tri"]) for s in sims)
+        ntri = sum(_mesh_count(s) for s in sims)
         x = np.concatenate([s["x"] for s in sims]) if n else np.zeros((0, 3))
+        self._spawn = spawn
+        n_cap = n
+        if spawn is not None:
+            if self.nsims != 1:
+                raise ValueError("spawning needs one simulation per solver")
+            n_cap = max(n, int(spawn.get("n_max", 1000)))
         if cells_max is None:
             est = 0
             for s in sims:
-                h = cell_factor * 2.0 * float(np.max(s["R"])) if len(s["R"]) else 1.0
-                est += _grid_cells(s["x"], h)
-            cells_max = int(max(1024, cell_slack * est, 2 * n))
+                pts, rmax = [s["x"]], float(np.max(s["R"])) if len(s["R"]) else 0.0
+                if spawn is not None:
+                    # particles will fill the spawn box and whatever the mesh holds
+                    pts.append(np.array([spawn["smin"], spawn["smax"]], float))
+                    rmax = max(rmax, float(spawn["Rmax"]))
+                    if s.get("elements") is not None:
+                        pts.append(np.concatenate([np.asarray(e, float).reshape(-1, 3)
+                                                   for e in s["elements"]]))
+                    elif len(s.get("tri", ())):
+                        pts.append(np.asarray(s["tri"], float).reshape(-1, 3))
+                h = cell_factor * 2.0 * rmax if rmax > 0 else 1.0
+                est += _grid_cells(np.concatenate(pts), h)
+            cells_max = int(max(1024, cell_slack * est, 2 * n_cap))
         if contacts_max is None:
-            contacts_max = int(max(4096, 8 * n))
-        self.cfg = Config(max(n, 1), contacts_max, cells_max, max(ntri, 1), self.nsims,
+            contacts_max = int(max(4096, 8 * n_cap))
+        self.cfg = Config(max(n_cap, 1), contacts_max, cells_max, max(ntri, 1), self.nsims,
                           SDEM_MIXED if precision == "mixed" else SDEM_FP64, block,
                           int(detect_lanes), float(cell_factor), float(skin),
                           int(rebuild_every), 0)
@@ -212,11 +331,20 @@ class Solver:
                                  self.workspace.data_ptr(), nbytes, self.stream.cuda_stream))
         self._h = h
         for k, s in enumerate(sims):
-            if len(s["tri"]):
+            if s.get("elements") is not None:
+                if len(s.get("tri", ())):
+                    raise ValueError("a simulation gives either 'tri' or 'elements'")
+                nv, verts = pack_elements(s["elements"])
+                rm = np.ascontiguousarray(s.get("rmesh", np.zeros(len(nv))), np.float64)
+                _check(L.sdem_add_mesh_elements(h, k, len(nv), nv.ctypes.data_as(_I32),
+                                                verts.ctypes.data_as(_D), rm.ctypes.data_as(_D)))
+            elif len(s.get("tri", ())):
                 tri = np.ascontiguousarray(s["tri"], np.float64).reshape(-1, 9)
                 rm = np.ascontiguousarray(s.get("rmesh", np.zeros(len(tri))), np.float64)
                 _check(L.sdem_add_mesh(h, k, len(tri), tri.ctypes.data_as(_D),
                                        rm.ctypes.data_as(_D)))
+        if spawn is not None:
+            self.set_spawn(**spawn)
 
     # ---------------------------------------------------------------------
     def close(self):
@@ -232,12 +360,51 @@ class Solver:
 
     def step(self, nsteps=1):
         _check(lib().sdem_step(self._h, int(nsteps)))
+        if self._spawn is not None:
+            self._refresh_n()
+
+    def _refresh_n(self):
+        m = C.c_int64()
+        _check(lib().sdem_spawn_status(self._h, C.byref(m), None, None))
+        self.n = int(m.value)
+        self.offsets = np.array([0, self.n], np.int64)
+
+    def set_spawn(self, **kw):
+        """Particle spawning (Section 3.1) with the keyword arguments of
+        make_spawn; no arguments turn it off."""
+        if kw:
+            sp = make_spawn(**kw)
+            _check(lib().sdem_set_spawn(self._h, 0, C.byref(sp)))
+            self._spawn = dict(kw)
+        else:
+            _check(lib().sdem_set_spawn(self._h, 0, None))
+
+    def set_spawn_status(self, attempts, carried):
+        _check(lib().sdem_set_spawn_status(self._h, int(attempts), float(carried)))
+
+    def set_clock(self, steps):
+        """Step counter (and moving-mesh clock t = steps dt), for a resume."""
+        _check(lib().sdem_set_clock(self._h, int(steps)))
+
+    def write_csv(self, path):
+        _check(lib().sdem_write_csv(self._h, os.fsencode(path)))
+
+    def write_contacts_csv(self, path):
+        _check(lib().sdem_write_contacts_csv(self._h, os.fsencode(path)))
+
+    def spawn_status(self):
+        """(particle count, attempts made, radius carried over)."""
+        m, a, r = C.c_int64(), C.c_uint64(), C.c_double()
+        _check(lib().sdem_spawn_status(self._h, C.byref(m), C.byref(a), C.byref(r)))
+        return int(m.value), int(a.value), float(r.value)
 
     def step_profiled(self, nsteps=1):
         """Steps without a graph, timing each phase with HIP events; returns
         the mean milliseconds per step of each phase."""
         ms = (C.c_double * len(PHASES))()
         _check(lib().sdem_step_profiled(self._h, int(nsteps), ms))
+        if self._spawn is not None:
+            self._refresh_n()
         return dict(zip(PHASES, list(ms)))
 
     def set_history(self, ki, kj, us, ur, ut):
@@ -259,6 +426,12 @@ class Solver:
         _check(lib().sdem_read_state(self._h, ptr("x"), ptr("v"), ptr("w"), ptr("q"),
                                      ptr("F") if forces else None, ptr("T") if forces else None))
         return {k: np.ascontiguousarray(a.T) for k, a in out.items()}
+
+    def radii(self):
+        """Radii by persistent id (spawned particles included)."""
+        out = np.empty(self.n)
+        _check(lib().sdem_read_radii(self._h, out.ctypes.data if self.n else None))
+        return out
 
     def contacts(self):
         """Contacts of the last step in key order, with their springs."""

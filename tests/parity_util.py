@@ -46,17 +46,24 @@ def keys(c):
     return np.stack([c["ki"], c["kj"]], 1) if len(c["ki"]) else np.zeros((0, 2), np.int32)
 
 
+def mesh_args(w):
+    """Oracle mesh arguments of a workload: triangles, or mesh elements of
+    one to four vertices."""
+    if w.get("elements") is not None:
+        return dict(elements=w["elements"], rmesh=w["rmesh"])
+    if len(w["tri"]):
+        return dict(tri=w["tri"], rmesh=w["rmesh"])
+    return {}
+
+
 def oracle_from(w):
-    return oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"],
-                      tri=w["tri"] if len(w["tri"]) else None,
-                      rmesh=w["rmesh"] if len(w["tri"]) else None)
+    return oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"], **mesh_args(w))
 
 
 def oracle_resync(w, st, c, t):
     """Oracle started from a GPU state and GPU springs at time t."""
     o = oracle.Sim(w["params"], st["x"], v=st["v"], w=st["w"], q=st["q"], R=w["R"],
-                   tri=w["tri"] if len(w["tri"]) else None,
-                   rmesh=w["rmesh"] if len(w["tri"]) else None)
+                   **mesh_args(w))
     o.set_time(t)
     if len(c["ki"]):
         o.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])

@@ -5,9 +5,9 @@ autotuner for the column, 1.0 as the reference stencil).
 * 200,000-sphere column: the complete contact set bit for bit and every
   particle's force, torque and new state against the oracle, after the first
   step and again 100 steps later (oracle restarted from the GPU state and
-  springs).
+  springs); also with the cells kept between rebuilds (skin 0.05 R_max).
 * 256 uneven box drops in one context: after 1,500 steps (all landed), eight
-  simulations re-synced and compared one step later.
+  simulations re-synced and compared one step later; also with skin 1.0 R_max.
 * 2,000,000 spheres in the rotating 8,192-triangle drum, FP64 and mixed
   precision: after 600 steps (the bed has landed on the shell), the oracle
   restarted from the GPU state and springs evaluates one step for sampled
@@ -52,10 +52,10 @@ def compare(g, o, w, tol=TOL64):
     return len(co["ki"])
 
 
-@pytest.mark.parametrize("cf", [0.4, 1.0])
-def test_column_200k_first_step_and_resync(column, cf):
+@pytest.mark.parametrize("cf,skin", [(0.4, 0.0), (1.0, 0.0), (0.4, 0.05)])
+def test_column_200k_first_step_and_resync(column, cf, skin):
     w = column
-    g = solver(w, cell_factor=cf, detect_lanes=1)
+    g = solver(w, cell_factor=cf, detect_lanes=1, skin=skin)
     o = oracle_from(w)
     g.step(1)
     o.step(1)
@@ -71,10 +71,11 @@ def test_column_200k_first_step_and_resync(column, cf):
     compare(g, o2, w2)
 
 
-def test_batch_256_after_landing():
+@pytest.mark.parametrize("skin", [0.0, 1.0])
+def test_batch_256_after_landing(skin):
     from paper_2507_12610_amd import Solver
     sims = W.cfg4()
-    g = Solver(sims, device="cuda:0", cell_factor=1.0, detect_lanes=1)
+    g = Solver(sims, device="cuda:0", cell_factor=1.0, detect_lanes=1, skin=skin)
     g.step(1500)
     st, c = g.state(forces=False), g.contacts()
     g.step(1)

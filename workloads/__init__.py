@@ -184,6 +184,58 @@ def primitive_mesh(box, seed):
     return els, np.array(rm)
 
 
+def hopper_elements():
+    """A hopper in the spirit of the default scene of Section 4 (a container
+    with a narrowing throat and a spherical and a cylindrical obstacle),
+    built from every kind of element, with the radii of Table 2's R_mesh list
+    {2, 20, 10} mm:
+      - floor z = 0, |x|, |y| <= 0.15: one rectangle (R_m = 0);
+      - four side walls up to z = 0.12: rectangles (R_m = 0);
+      - a square funnel from half width 0.04 at z = 0.12 to 0.16 at
+        z = 0.28: eight triangles (R_m = 2 mm);
+      - a spherical obstacle below the throat: a point at z = 0.07
+        (R_m = 20 mm), and a cylindrical one: a segment along y at
+        x = 0.07, z = 0.04 (R_m = 10 mm).
+    Particles spawn in the box (-0.1, -0.1, 0.3) .. (0.1, 0.1, 0.4) above it.
+    Returns (elements, rmesh)."""
+    els, rm = [], []
+    h = 0.15
+    els.append([[-h, -h, 0.0], [h, -h, 0.0], [h, h, 0.0], [-h, h, 0.0]])
+    rm.append(0.0)
+    for a, b in (((-h, -h), (h, -h)), ((h, -h), (h, h)), ((h, h), (-h, h)), ((-h, h), (-h, -h))):
+        els.append([[a[0], a[1], 0.0], [b[0], b[1], 0.0], [b[0], b[1], 0.12], [a[0], a[1], 0.12]])
+        rm.append(0.0)
+    lo, hi = 0.04, 0.16
+    ring = lambda s, z: [[-s, -s, z], [s, -s, z], [s, s, z], [-s, s, z]]
+    r0, r1 = ring(lo, 0.12), ring(hi, 0.28)
+    for k in range(4):
+        a0, b0, a1, b1 = r0[k], r0[(k + 1) % 4], r1[k], r1[(k + 1) % 4]
+        els.append([a0, b0, b1])
+        els.append([a0, b1, a1])
+        rm += [0.002, 0.002]
+    els.append([[0.0, 0.0, 0.07]])
+    rm.append(0.02)
+    els.append([[0.07, -0.1, 0.04], [0.07, 0.1, 0.04]])
+    rm.append(0.01)
+    return [np.asarray(e, float) for e in els], np.array(rm)
+
+
+def hopper_spawn(n_max=1000, n_spawn=100, seed=2507):
+    """Spawn settings of Table 2's defaults: box (-0.1, -0.1, 0.3) ..
+    (0.1, 0.1, 0.4), R in [2, 10] mm, v0 = (0, 0, -1) m/s, w0 = 0."""
+    return dict(smin=(-0.1, -0.1, 0.3), smax=(0.1, 0.1, 0.4), Rmin=0.002, Rmax=0.01,
+                v0=(0.0, 0.0, -1.0), w0=(0.0, 0.0, 0.0), n_spawn=n_spawn, n_max=n_max,
+                seed=seed)
+
+
+def hopper_params():
+    """Table 2 defaults: rho 1000, E 1e6, nu 0.3, e_n 0.5, mu_s 0.3,
+    mu_r 0.3, mu_t 2 mu_s / 3, eta 0, g = (0, 0, -9.81), dt by Eq. dt for
+    R_min = 2 mm."""
+    return default_params(rho=1000.0, E=1e6, nu=0.3, e_n=0.5, mu_s=0.3, mu_r=0.3, mu_t=0.2,
+                          eta=0.0, g=(0.0, 0.0, -9.81), dt=dt_eq(0.002, 1000.0, 1e6, 0.3))
+
+
 def drum_mesh(radius, length, nseg=128, nring=31):
     """Closed drum around the y axis: nseg x nring x 2 shell triangles plus
     two end-cap fans of nseg triangles (8,192 for the defaults)."""
