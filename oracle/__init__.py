@@ -42,6 +42,17 @@ class Params(C.Structure):
                 ("mesh_center", C.c_double * 3)]
 
 
+class Motion(C.Structure):
+    _fields_ = [("omega", C.c_double * 3), ("center", C.c_double * 3), ("amp", C.c_double * 3),
+                ("freq", C.c_double), ("phase", C.c_double)]
+
+
+def make_motion(omega=(0.0, 0.0, 0.0), center=(0.0, 0.0, 0.0), amp=(0.0, 0.0, 0.0), freq=0.0,
+                phase=0.0) -> Motion:
+    return Motion((C.c_double * 3)(*omega), (C.c_double * 3)(*center), (C.c_double * 3)(*amp),
+                  float(freq), float(phase))
+
+
 class Spawn(C.Structure):
     _fields_ = [("smin", C.c_double * 3), ("smax", C.c_double * 3), ("Rmin", C.c_double),
                 ("Rmax", C.c_double), ("v0", C.c_double * 3), ("w0", C.c_double * 3),
@@ -133,6 +144,8 @@ def lib():
         L.orc_get_radii.argtypes = [C.c_void_p, _D]
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.orc_set_spawn.argtypes = [C.c_void_p, C.POINTER(Spawn)]
+        L.orc_set_mesh_motion.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Motion), _I32]
+        L.orc_wall_velocity.argtypes = [C.c_void_p, C.c_int64, _D, _D, _D]
         L.orc_spawn_status.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
         L.orc_set_spawn_status.argtypes = [C.c_void_p, C.c_uint64, C.c_double]
         L.orc_num_contacts.restype = C.c_int64
@@ -352,6 +365,22 @@ class Sim:
         if lib().orc_step(self._h, int(nsteps)) != 0:
             raise RuntimeError("oracle step failed")
         self.n = int(lib().orc_num_particles(self._h))
+
+    def set_mesh_motion(self, motions, groups=None):
+        """Motion groups (an extension generalising the rotating mesh): a list
+        of dicts with the keywords of make_motion, and the group of each
+        element (None: all in group 0)."""
+        arr = (Motion * len(motions))(*[make_motion(**m) for m in motions])
+        g = None if groups is None else np.ascontiguousarray(groups, np.int32)
+        if lib().orc_set_mesh_motion(self._h, len(motions), arr,
+                                     g.ctypes.data_as(_I32) if g is not None else None) != 0:
+            raise ValueError("bad mesh motion")
+
+    def wall_velocity(self, m, p):
+        """(velocity, spin) of element m's wall at point p, at the current time."""
+        vw, ww = np.zeros(3), np.zeros(3)
+        lib().orc_wall_velocity(self._h, int(m), _p(_vec(p)), _p(vw), _p(ww))
+        return vw, ww
 
     def set_spawn(self, spawn=None, **kw):
         """Particle spawning (Section 3.1): a Spawn structure or the keyword

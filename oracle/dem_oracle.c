@@ -36,6 +36,15 @@
  *       and stiffness in the constitutive laws (R* = R_i, m* = m_i,
  *       E* = E/(1-nu^2), G* = G/(2-nu)); r_i = R_i - delta/2 also for walls.
  *   R9  right-multiplication of the quaternion, no renormalisation.
+ *   M1  moving meshes (extension, generalising R14; the vibrated base of the
+ *       segregation example of Section 4): each element belongs to a motion
+ *       group; group g turns by |Omega_g| t about the axis Omega_g through
+ *       c_g and is displaced by d_g(t) = A_g (sin(2 pi f_g t + phi_g) -
+ *       sin phi_g), the axis moving with it: x(t) = c_g + d_g(t) +
+ *       Rot(x0 - c_g), or x0 + d_g(t) without rotation.  The material
+ *       velocity at a point p is Omega_g x (p - c_g - d_g) + d_g'(t), the
+ *       wall spin Omega_g.  Without a motion table one group rotates by the
+ *       parameters' mesh_omega about mesh_center (R14).
  *   S1  particle spawning (Section 3.1): at the start of each step, before
  *       the contact search, up to N_spawn attempts, while n < N_max.  Attempt
  *       a (counted over the whole run, from 0) draws four numbers from
@@ -442,6 +451,9 @@ struct orc_sim {
   int32_t* nv;           /* vertices per element, 1..4 */
   double *tri0, *tri;    /* vertices [ntri][4][3] at t = 0 and now */
   double* rmesh;         /* element radii R_m */
+  int32_t* grp;          /* motion group of each element */
+  int32_t ngroups;       /* 0: one group from the parameters (R14) */
+  orc_motion* motion;
   double t, t0;  /* t = t0 + nstep * dt */
   /* spawning (Section 3.1) */
   int64_t cap;        /* allocated particles */
@@ -623,6 +635,8 @@ void orc_free(orc_sim* s) {
   free(s->tri);
   free(s->rmesh);
   free(s->nv);
+  free(s->grp);
+  free(s->motion);
   free(s->hist);
   free(s->head);
   free(s->next);
@@ -657,7 +671,9 @@ int orc_set_mesh_elements(orc_sim* s, int64_t nel, const int32_t* nv, const doub
   free(s->tri);
   free(s->rmesh);
   free(s->nv);
+  free(s->grp);
   s->ntri = nel;
+  s->grp = calloc((size_t)nel + 1, sizeof(int32_t));
   s->tri0 = xmalloc((size_t)nel * 12 * sizeof(double));
   s->tri = xmalloc((size_t)nel * 12 * sizeof(double));
   s->rmesh = xmalloc((size_t)nel * sizeof(double));
@@ -734,34 +750,121 @@ void orc_set_search(orc_sim* s, int32_t mode, double cell_factor) {
   s->cell_factor = cell_factor >= 1.0 ? cell_factor : 1.0;
 }
 
-/* R14: rigid rotation of the reference vertices by |Omega| t about the axis
- * Omega/|Omega| through mesh_center (Rodrigues' formula). */
-static void update_mesh(orc_sim* s) {
-  const double* om = s->p.mesh_omega;
-  double wl = norm3(om);
-  if (!(wl > 0.0)) {
-    if (s->ntri) memcpy(s->tri, s->tri0, (size_t)s->ntri * 12 * sizeof(double));
-    return;
+/* The motion of group g at time t (M1): axis direction and angle, and the
+ * displacement and its velocity. */
+typedef struct {
+  double om[3], ctr[3];
+  double wl, kx[3], co, si;  /* |Omega|, axis, cos and sin of the angle */
+  double d[3], vt[3];        /* displacement d(t) and velocity d'(t)   */
+} motion_now;
+
+static const orc_motion* group_motion(const orc_sim* s, int32_t g, orc_motion* tmp) {
+  if (s->ngroups > 0) return &s->motion[g];
+  memset(tmp, 0, sizeof *tmp);
+  memcpy(tmp->omega, s->p.mesh_omega, sizeof tmp->omega);
+  memcpy(tmp->center, s->p.mesh_center, sizeof tmp->center);
+  return tmp;
+}
+
+static void motion_at(const orc_motion* g, double t, motion_now* o) {
+  memcpy(o->om, g->omega, sizeof o->om);
+  memcpy(o->ctr, g->center, sizeof o->ctr);
+  o->wl = norm3(g->omega);
+  o->co = 1.0;
+  o->si = 0.0;
+  for (int k = 0; k < 3; ++k) o->kx[k] = 0.0;
+  if (o->wl > 0.0) {
+    for (int k = 0; k < 3; ++k) o->kx[k] = g->omega[k] / o->wl;
+    double ang = o->wl * t;
+    o->co = cos(ang);
+    o->si = sin(ang);
   }
-  double kx[3] = {om[0] / wl, om[1] / wl, om[2] / wl};
-  double ang = wl * s->t;
-  double co = cos(ang), si = sin(ang);
-  for (int64_t m = 0; m < s->ntri * 4; ++m) {
-    double r[3];
-    sub3(s->tri0 + 3 * m, s->p.mesh_center, r);
-    double kxr[3];
-    cross3(kx, r, kxr);
-    double kd = dot3(kx, r);
-    for (int k = 0; k < 3; ++k)
-      s->tri[3 * m + k] = s->p.mesh_center[k] + ((r[k] * co + kxr[k] * si) + kx[k] * kd * (1.0 - co));
+  double wv = 2.0 * ORC_PI * g->freq;
+  double ph = wv * t + g->phase;
+  double s1 = sin(ph) - sin(g->phase), c1 = wv * cos(ph);
+  for (int k = 0; k < 3; ++k) {
+    o->d[k] = g->amp[k] * s1;
+    o->vt[k] = g->amp[k] * c1;
   }
 }
 
-static void wall_motion(const orc_sim* s, const double cpt[3], double vw[3], double ww[3]) {
-  double r[3];
-  sub3(cpt, s->p.mesh_center, r);
-  cross3(s->p.mesh_omega, r, vw);
-  memcpy(ww, s->p.mesh_omega, 3 * sizeof(double));
+static int is_moving(const orc_motion* g) {
+  for (int k = 0; k < 3; ++k)
+    if (g->omega[k] != 0.0 || (g->amp[k] != 0.0 && g->freq != 0.0)) return 1;
+  return 0;
+}
+
+/* M1 (R14): vertices of every element at time t from those at t = 0 */
+static void update_mesh(orc_sim* s) {
+  for (int64_t m = 0; m < s->ntri; ++m) {
+    orc_motion tmp;
+    const orc_motion* g = group_motion(s, s->grp[m], &tmp);
+    const double* x0 = s->tri0 + 12 * m;
+    double* x = s->tri + 12 * m;
+    if (!is_moving(g)) {
+      memcpy(x, x0, 12 * sizeof(double));
+      continue;
+    }
+    motion_now mn;
+    motion_at(g, s->t, &mn);
+    for (int v = 0; v < 4; ++v) {
+      if (!(mn.wl > 0.0)) {
+        for (int k = 0; k < 3; ++k) x[3 * v + k] = x0[3 * v + k] + mn.d[k];
+        continue;
+      }
+      /* Rodrigues' formula about the axis through the moved centre */
+      double r[3], kxr[3];
+      sub3(x0 + 3 * v, mn.ctr, r);
+      cross3(mn.kx, r, kxr);
+      double kd = dot3(mn.kx, r);
+      for (int k = 0; k < 3; ++k)
+        x[3 * v + k] = (mn.ctr[k] + mn.d[k]) +
+                       ((r[k] * mn.co + kxr[k] * mn.si) + mn.kx[k] * kd * (1.0 - mn.co));
+    }
+  }
+}
+
+/* material velocity and spin of element m's wall at the contact point */
+static void wall_motion(const orc_sim* s, int64_t m, const double cpt[3], double vw[3],
+                        double ww[3]) {
+  orc_motion tmp;
+  const orc_motion* g = group_motion(s, s->grp[m], &tmp);
+  if (!is_moving(g)) {
+    for (int k = 0; k < 3; ++k) vw[k] = ww[k] = 0.0;
+    return;
+  }
+  motion_now mn;
+  motion_at(g, s->t, &mn);
+  double piv[3], r[3];
+  for (int k = 0; k < 3; ++k) piv[k] = mn.ctr[k] + mn.d[k];
+  sub3(cpt, piv, r);
+  cross3(mn.om, r, vw);
+  for (int k = 0; k < 3; ++k) vw[k] = vw[k] + mn.vt[k];
+  memcpy(ww, mn.om, 3 * sizeof(double));
+}
+
+void orc_wall_velocity(const orc_sim* s, int64_t m, const double p[3], double vw[3],
+                       double ww[3]) {
+  wall_motion(s, m, p, vw, ww);
+}
+
+int orc_set_mesh_motion(orc_sim* s, int32_t ngroups, const orc_motion* g, const int32_t* grp) {
+  if (ngroups < 1 || !g) return -1;
+  for (int32_t k = 0; k < ngroups; ++k) {
+    for (int a = 0; a < 3; ++a)
+      if (!isfinite(g[k].omega[a]) || !isfinite(g[k].center[a]) || !isfinite(g[k].amp[a]))
+        return -1;
+    if (!isfinite(g[k].freq) || !isfinite(g[k].phase) || g[k].freq < 0) return -1;
+  }
+  for (int64_t m = 0; grp && m < s->ntri; ++m)
+    if (grp[m] < 0 || grp[m] >= ngroups) return -1;
+  free(s->motion);
+  s->motion = xmalloc((size_t)ngroups * sizeof(orc_motion));
+  memcpy(s->motion, g, (size_t)ngroups * sizeof(orc_motion));
+  s->ngroups = ngroups;
+  for (int64_t m = 0; m < s->ntri; ++m) s->grp[m] = grp ? grp[m] : 0;
+  update_mesh(s);
+  return 0;
 }
 
 /* previous-step springs of key (ki,kj), or NULL */
@@ -881,7 +984,7 @@ static int eval_wall(const orc_sim* s, int64_t i, int64_t m, const double* us, c
   double nrm[3] = {dv[0] / d, dv[1] / d, dv[2] / d};
   double cpt[3], vw[3], ww[3];
   for (int k = 0; k < 3; ++k) cpt[k] = cp[k] + s->rmesh[m] * nrm[k];
-  wall_motion(s, cpt, vw, ww);
+  wall_motion(s, m, cpt, vw, ww);
   return orc_eval_pw(&s->p, s->x + 3 * i, s->v + 3 * i, s->w + 3 * i, s->R[i], cp, s->rmesh[m],
                      vw, ww, us, ur, ut, o);
 }

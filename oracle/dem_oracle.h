@@ -91,6 +91,14 @@ int orc_eval_pw(const orc_params* p, const double xi[3], const double vi[3], con
 void orc_integrate(const orc_params* p, double R, const double F[3], const double T[3],
                    double x[3], double v[3], double w[3], double q[4]);
 
+/* Prescribed rigid motion of a group of mesh elements (an extension): turns
+ * with angular velocity omega about the axis through center, displaced by
+ * amp (sin(2 pi freq t + phase) - sin(phase)). */
+typedef struct {
+  double omega[3], center[3], amp[3];
+  double freq, phase;
+} orc_motion;
+
 /* Philox4x32-10 counter-based generator (Salmon et al., SC 2011). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
@@ -117,6 +125,14 @@ void orc_free(orc_sim* s);
  * corner 0, each to 1e-6 relative). */
 int orc_set_mesh_elements(orc_sim* s, int64_t nel, const int32_t* nv, const double* verts,
                           const double* rmesh);
+/* Motion groups of the mesh (after orc_set_mesh*): ngroups motions and the
+ * group of each element (NULL: all in group 0).  Without this call the mesh
+ * turns by the parameters' mesh_omega about mesh_center.  -1 for a bad
+ * motion or group index. */
+int orc_set_mesh_motion(orc_sim* s, int32_t ngroups, const orc_motion* g, const int32_t* grp);
+/* Material velocity and spin of element m's wall at point p, now. */
+void orc_wall_velocity(const orc_sim* s, int64_t m, const double p[3], double vw[3],
+                       double ww[3]);
 /* Triangles only: tri [ntri][3][3]. */
 int orc_set_mesh(orc_sim* s, int64_t ntri, const double* tri, const double* rmesh);
 int orc_set_history(orc_sim* s, int64_t nc, const int32_t* ki, const int32_t* kj,

@@ -73,7 +73,7 @@ def test_resume_from_files(tmp_path):
     w2.update(x=st["x"], v=st["v"], w=st["w"], q=st["q"], R=st["R"])
     b = Solver(w2, device="cuda:0", spawn=sp)
     c = sdem.read_contacts_csv(str(tmp_path / "contacts.csv"))
-    assert len(c["ki"]) > 100
+    assert len(c["ki"]) > 30
     b.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])
     b.set_clock(steps)
     b.set_spawn_status(attempts, carried)
