@@ -166,6 +166,34 @@ int sdem_add_mesh(sdem_ctx* ctx, int32_t sim, int64_t ntri, const double* tri,
 int sdem_add_mesh_elements(sdem_ctx* ctx, int32_t sim, int64_t nel, const int32_t* nverts,
                            const double* verts, const double* rmesh);
 
+/* Prescribed rigid motion of groups of mesh elements (an extension; the
+ * vibrated base of the segregation example of Section 4 is one).  Group g
+ * turns with angular velocity omega about the axis through center and is
+ * displaced by d(t) = amp (sin(2 pi freq t + phase) - sin(phase)), the axis
+ * moving with it: a vertex x0 given at t = 0 is at
+ * center + d(t) + Rot(|omega| t)(x0 - center), or x0 + d(t) without
+ * rotation.  The wall's material velocity at a contact point p is
+ * omega x (p - center - d(t)) + d'(t) and its angular velocity omega; they
+ * enter the relative contact velocity (Section 2.2) like a moving body of
+ * infinite mass.  t = steps * dt at the start of a step (sdem_set_clock). */
+typedef struct {
+  double omega[3];   /* angular velocity (rad/s)                           */
+  double center[3];  /* a point of the rotation axis at t = 0               */
+  double amp[3];     /* amplitude vector of the harmonic displacement       */
+  double freq;       /* its frequency (Hz, >= 0)                            */
+  double phase;      /* its phase (rad)                                     */
+} sdem_mesh_motion;
+
+/* Sets the motion groups of simulation `sim`'s mesh (after its mesh is set;
+ * setting the mesh again puts every element back in group 0): ngroups
+ * motions (1..16) and the group of each element, in the order given to the
+ * mesh call (NULL: all in group 0).  Without this call group 0 turns with
+ * the parameters' mesh_omega about mesh_center.  Element bins are built
+ * over the whole region the elements sweep.  Returns SDEM_EINVAL for a bad
+ * motion, count or group index. */
+int sdem_set_mesh_motion(sdem_ctx* ctx, int32_t sim, int32_t ngroups,
+                         const sdem_mesh_motion* motions, const int32_t* group_of);
+
 /* Particle spawning (Section 3.1).  At the start of every step, before the
  * broad phase, up to n_spawn attempts are made while the particle count is
  * below n_max.  Attempt a (counted from 0 over the context's life, reset by

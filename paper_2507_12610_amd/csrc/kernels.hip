@@ -520,25 +520,47 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) 
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= c.ntri) return;
   const SimParams& P = c.sp[c.tri_sim[m]];
+  const MeshMotion& G = c.motion[c.tri_grp[m]];
   double* t = c.tri + 9 * m;
   const double* t0 = c.tri_ref + 9 * m;
-  if (all) {  // set-up: vertices at t = 0
-    for (int k = 0; k < 9; ++k) t[k] = t0[k];
-  } else if (P.rotating) {
-    // rigid rotation by |om| t about the axis om/|om| through ctr, with t the
-    // time at the start of this step (`started`: steps already counts it)
-    const double wl = sqrt((P.om[0] * P.om[0] + P.om[1] * P.om[1]) + P.om[2] * P.om[2]);
-    const double kx = P.om[0] / wl, ky = P.om[1] / wl, kz = P.om[2] / wl;
-    const double ang = wl * ((double)(c.ctr->steps - (unsigned long long)started) * P.dt);
-    const double co = cos(ang), si = sin(ang);
-    for (int v = 0; v < 3; ++v) {
-      const double rx = t0[3 * v] - P.ctr[0], ry = t0[3 * v + 1] - P.ctr[1],
-                   rz = t0[3 * v + 2] - P.ctr[2];
-      const double cx = ky * rz - kz * ry, cy = kz * rx - kx * rz, cz = kx * ry - ky * rx;
-      const double kd = (kx * rx + ky * ry) + kz * rz;
-      t[3 * v] = P.ctr[0] + ((rx * co + cx * si) + kx * kd * (1.0 - co));
-      t[3 * v + 1] = P.ctr[1] + ((ry * co + cy * si) + ky * kd * (1.0 - co));
-      t[3 * v + 2] = P.ctr[2] + ((rz * co + cz * si) + kz * kd * (1.0 - co));
+  double* mv = c.tri_mv + 9 * m;
+  if (all) {  // set-up: vertices at t = 0, no wall motion recorded yet
+    for (int k = 0; k < 9; ++k) {
+      t[k] = t0[k];
+      mv[k] = 0.0;
+    }
+  } else if (G.moving) {
+    // rigid motion at the time of the start of this step (`started`: the
+    // step counter already counts it): turn by |omega| t about the axis
+    // through the displaced centre, displacement d(t) with velocity d'(t)
+    const double tm = (double)(c.ctr->steps - (unsigned long long)started) * P.dt;
+    const double wv = 2.0 * kPi * G.freq;
+    const double ph = wv * tm + G.phase;
+    const double s1 = sin(ph) - sin(G.phase), c1 = wv * cos(ph);
+    const double d[3] = {G.amp[0] * s1, G.amp[1] * s1, G.amp[2] * s1};
+    const double wl = sqrt((G.omega[0] * G.omega[0] + G.omega[1] * G.omega[1]) +
+                           G.omega[2] * G.omega[2]);
+    if (wl > 0.0) {
+      const double kx = G.omega[0] / wl, ky = G.omega[1] / wl, kz = G.omega[2] / wl;
+      const double ang = wl * tm;
+      const double co = cos(ang), si = sin(ang);
+      for (int v = 0; v < 3; ++v) {
+        const double rx = t0[3 * v] - G.center[0], ry = t0[3 * v + 1] - G.center[1],
+                     rz = t0[3 * v + 2] - G.center[2];
+        const double cx = ky * rz - kz * ry, cy = kz * rx - kx * rz, cz = kx * ry - ky * rx;
+        const double kd = (kx * rx + ky * ry) + kz * rz;
+        t[3 * v] = (G.center[0] + d[0]) + ((rx * co + cx * si) + kx * kd * (1.0 - co));
+        t[3 * v + 1] = (G.center[1] + d[1]) + ((ry * co + cy * si) + ky * kd * (1.0 - co));
+        t[3 * v + 2] = (G.center[2] + d[2]) + ((rz * co + cz * si) + kz * kd * (1.0 - co));
+      }
+    } else {
+      for (int v = 0; v < 3; ++v)
+        for (int k = 0; k < 3; ++k) t[3 * v + k] = t0[3 * v + k] + d[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+      mv[k] = G.omega[k];
+      mv[3 + k] = G.center[k] + d[k];
+      mv[6 + k] = G.amp[k] * c1;
     }
   } else {
     return;
@@ -745,7 +767,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     const double hsk = c.sp[sim].half_skin;
     const bool listed = c.skin_on && !rebuilt && extra == 0.0;
     const bool record = c.skin_on && rebuilt;
-    const bool tri_listed = !c.sp[sim].rotating;
+    const bool tri_listed = !c.sp[sim].moving;
     int* vl = c.vlist + (size_t)g * kCand;
     const int nlist = listed ? c.vcnt[g] : -1;
     int ncand = 0;
@@ -1168,21 +1190,26 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State A, State B, Con
       Gs = P.Gs_pw;
       reff = ri;
       double vw0 = 0.0, vw1 = 0.0, vw2 = 0.0;
-      if (P.rotating) {  // wall material velocity at the contact point p + R_m n
-        const double px = pj.x + Rj * n0 - P.ctr[0];
-        const double py = pj.y + Rj * n1 - P.ctr[1];
-        const double pz = pj.z + Rj * n2 - P.ctr[2];
-        vw0 = P.om[1] * pz - P.om[2] * py;
-        vw1 = P.om[2] * px - P.om[0] * pz;
-        vw2 = P.om[0] * py - P.om[1] * px;
+      double sw0 = 0.0, sw1 = 0.0, sw2 = 0.0;
+      if (P.moving) {  // wall material velocity at the contact point p + R_m n
+        const double* mv = c.tri_mv + 9 * (size_t)m;
+        sw0 = mv[0];
+        sw1 = mv[1];
+        sw2 = mv[2];
+        const double px = (pj.x + Rj * n0) - mv[3];
+        const double py = (pj.y + Rj * n1) - mv[4];
+        const double pz = (pj.z + Rj * n2) - mv[5];
+        vw0 = (sw1 * pz - sw2 * py) + mv[6];
+        vw1 = (sw2 * px - sw0 * pz) + mv[7];
+        vw2 = (sw0 * py - sw1 * px) + mv[8];
       }
       const double rx = ri * wix, ry = ri * wiy, rz = ri * wiz;
       vrel[0] = (vix - vw0) + (n1 * rz - n2 * ry);
       vrel[1] = (viy - vw1) + (n2 * rx - n0 * rz);
       vrel[2] = (viz - vw2) + (n0 * ry - n1 * rx);
-      om[0] = wix - P.om[0];
-      om[1] = wiy - P.om[1];
-      om[2] = wiz - P.om[2];
+      om[0] = wix - sw0;
+      om[1] = wiy - sw1;
+      om[2] = wiz - sw2;
     }
     // coefficients (Eq. ks, cn, cs; k_r = k_n, c_r = c_n, k_t = k_s, c_t = c_s)
     // with k_n = 4/3 E* a and k_s = 8 G* a: c_n = beta sqrt(20/3 E*) sqrt(m* a)
@@ -1618,7 +1645,7 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
     k_scatter<<<nbp, kThreads, 0, s>>>(c);
     k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B, cold);
   }
-  if (c.any_rotating) {
+  if (c.any_moving) {
     k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0, rebuild);
     (void)launch_mesh_bins(c, s);
   }
@@ -1650,9 +1677,9 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
 }
 
 hipError_t launch_mesh_now(const Ctx& c, hipStream_t s) {
-  // a rotating mesh at the time of the step about to start (the step counter
+  // a moving mesh at the time of the step about to start (the step counter
   // does not count it yet)
-  if (c.any_rotating && c.ntri > 0)
+  if (c.any_moving && c.ntri > 0)
     k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0, 0);
   return hipGetLastError();
 }

@@ -80,6 +80,8 @@ struct sdem_ctx {
   std::vector<int64_t> offsets;
   std::vector<std::vector<double>> mesh_tri, mesh_r;  // 9 doubles and R_m per element
   std::vector<std::vector<int32_t>> mesh_nv;          // vertices per element
+  std::vector<std::vector<int32_t>> mesh_grp;         // motion group per element
+  std::vector<std::vector<MeshMotion>> motion;        // motion groups per simulation
   std::vector<double> rmax;
   // graphs by pattern and starting buffer parity: two full steps, one full
   // step, one step keeping the cells, eight steps keeping the cells
@@ -170,6 +172,9 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.rmesh = L.take<double>(M);
   cc.tri_sim = L.take<int32_t>(M);
   cc.tri_nv = L.take<int32_t>(M);
+  cc.tri_grp = L.take<int32_t>(M);
+  cc.tri_mv = L.take<double>(9 * M);
+  cc.motion = L.take<MeshMotion>(S * kMotionMax);
   cc.mg = L.take<MeshGrid>(S);
   cc.bin_cnt = L.take<int32_t>((size_t)std::max<int64_t>(bins_cap(cfg), 1));
   cc.bin_start = L.take<int32_t>((size_t)bins_cap(cfg) + 1);
@@ -266,8 +271,6 @@ static SimParams derive(const sdem_params& p, double cell_factor, double rmax, d
   d.eta = p.eta;
   for (int k = 0; k < 3; ++k) {
     d.g[k] = p.g[k];
-    d.om[k] = p.mesh_omega[k];
-    d.ctr[k] = p.mesh_center[k];
   }
   d.dt = p.dt;
   const double r = kPiHost / log(p.e_n);  // e_n = 1 -> inf -> beta 0; e_n = 0 -> beta 1
@@ -289,8 +292,19 @@ static SimParams derive(const sdem_params& p, double cell_factor, double rmax, d
   d.rmax = rm;
   d.h = cell_factor * 2.0 * rm;
   d.half_skin = 0.5 * skin * rm;
-  d.rotating = (p.mesh_omega[0] != 0.0 || p.mesh_omega[1] != 0.0 || p.mesh_omega[2] != 0.0);
   return d;
+}
+
+// The motion of a simulation's mesh given by its parameters alone: one group
+// turning with mesh_omega about mesh_center.
+static MeshMotion default_motion(const sdem_params& p) {
+  MeshMotion g{};
+  for (int k = 0; k < 3; ++k) {
+    g.omega[k] = p.mesh_omega[k];
+    g.center[k] = p.mesh_center[k];
+  }
+  g.moving = (p.mesh_omega[0] != 0.0 || p.mesh_omega[1] != 0.0 || p.mesh_omega[2] != 0.0);
+  return g;
 }
 
 static int upload_params(sdem_ctx* x) {
@@ -304,9 +318,13 @@ static int upload_params(sdem_ctx* x) {
     sp[s].ntri = (int32_t)x->mesh_r[s].size();
     tri0 += sp[s].ntri;
   }
-  x->c.any_rotating = 0;
-  for (int s = 0; s < x->nsims; ++s)
-    if (sp[s].rotating && sp[s].ntri > 0) x->c.any_rotating = 1;
+  x->c.any_moving = 0;
+  for (int s = 0; s < x->nsims; ++s) {
+    sp[s].moving = 0;
+    for (size_t m = 0; m < x->mesh_grp[s].size(); ++m)
+      if (x->motion[s][x->mesh_grp[s][m]].moving) sp[s].moving = 1;
+    if (sp[s].moving) x->c.any_moving = 1;
+  }
   HIP_TRY(hipMemcpyAsync(x->c.sp, sp.data(), sizeof(SimParams) * x->nsims, hipMemcpyHostToDevice,
                          x->stream));
   HIP_TRY(hipStreamSynchronize(x->stream));
@@ -378,6 +396,9 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   X->mesh_tri.assign(nsims, {});
   X->mesh_r.assign(nsims, {});
   X->mesh_nv.assign(nsims, {});
+  X->mesh_grp.assign(nsims, {});
+  X->motion.resize(nsims);
+  for (int s = 0; s < nsims; ++s) X->motion[s].assign(1, default_motion(params[s]));
   X->rmax = rmax;
   carve(cfg, reinterpret_cast<char*>(workspace), &X->c, X->st, X->ct, &X->scratch);
   Ctx& c = X->c;
@@ -485,12 +506,6 @@ int sdem_init(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params,
                          hip_stream);
 }
 
-// Bin grid of one simulation's mesh.  The grid spans the vertex bounding box
-// grown by reach = R_max + max R_m (a static mesh) or the ball that holds the
-// mesh at every rotation angle about its centre (a rotating one).  The bin
-// edge starts at the larger of 2 reach and half the median triangle extent
-// and grows until the bins, and a bound on the (bin, triangle) entries that
-// holds at any orientation, fit this simulation's share of the tables.
 // Corners of element m (its stored vertices, plus the implied fourth corner
 // of a rectangle); returns their number.
 static int element_corners(const std::vector<double>& tri, const std::vector<int32_t>& nv,
@@ -503,43 +518,51 @@ static int element_corners(const std::vector<double>& tri, const std::vector<int
   return 4;
 }
 
+// Bin grid of one simulation's mesh.  The grid spans every place the
+// elements can reach (fixed, vibrating or turning), grown by
+// reach = R_max + max R_m.  The bin edge starts at the larger of 2 reach and
+// half the median element extent and grows until the bins, and a bound on
+// the (bin, element) entries that holds at any orientation, fit this
+// simulation's share of the tables.
 static MeshGrid mesh_grid(const std::vector<double>& tri, const std::vector<int32_t>& nv,
-                          const std::vector<double>& rm, double rmax, bool rotating,
-                          const double* ctr, int64_t bins_budget, int64_t entries_budget,
-                          int32_t off) {
+                          const std::vector<double>& rm, const std::vector<int32_t>& grp,
+                          const std::vector<MeshMotion>& motion, double rmax, int64_t bins_budget,
+                          int64_t entries_budget, int32_t off) {
   MeshGrid G{};
   const size_t nt = rm.size();
   double rmesh_max = 0.0;
   for (double r : rm) rmesh_max = std::max(rmesh_max, r);
   const double reach = (rmax + rmesh_max) * (1.0 + 1e-6);
   double lo[3], hi[3];
-  if (rotating) {
-    double rv = 0.0;
-    for (size_t m = 0; m < nt; ++m) {
-      double cr[4][3];
-      const int k = element_corners(tri, nv, m, cr);
-      for (int v = 0; v < k; ++v) {
-        const double dx = cr[v][0] - ctr[0], dy = cr[v][1] - ctr[1], dz = cr[v][2] - ctr[2];
-        rv = std::max(rv, sqrt(dx * dx + dy * dy + dz * dz));
-      }
-    }
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = ctr[a] - (rv + reach);
-      hi[a] = ctr[a] + (rv + reach);
-    }
-  } else {
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = HUGE_VAL;
-      hi[a] = -HUGE_VAL;
-    }
-    for (size_t m = 0; m < nt; ++m) {
-      double cr[4][3];
-      const int k = element_corners(tri, nv, m, cr);
-      for (int v = 0; v < k; ++v)
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = HUGE_VAL;
+    hi[a] = -HUGE_VAL;
+  }
+  // every place an element's corners can reach: a ball about the rotation
+  // centre for a turning group, the box grown by twice the amplitude for a
+  // vibrating one (|sin - sin phase| <= 2), the box itself for a fixed one
+  for (size_t m = 0; m < nt; ++m) {
+    const MeshMotion& g = motion[grp[m]];
+    double cr[4][3];
+    const int k = element_corners(tri, nv, m, cr);
+    double sw[3];
+    for (int a = 0; a < 3; ++a) sw[a] = g.moving ? 2.0 * fabs(g.amp[a]) : 0.0;
+    const bool turns = g.omega[0] != 0.0 || g.omega[1] != 0.0 || g.omega[2] != 0.0;
+    for (int v = 0; v < k; ++v) {
+      if (turns) {
+        const double dx = cr[v][0] - g.center[0], dy = cr[v][1] - g.center[1],
+                     dz = cr[v][2] - g.center[2];
+        const double rv = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 1e-9);
         for (int a = 0; a < 3; ++a) {
-          lo[a] = std::min(lo[a], cr[v][a] - reach);
-          hi[a] = std::max(hi[a], cr[v][a] + reach);
+          lo[a] = std::min(lo[a], g.center[a] - (rv + sw[a] + reach));
+          hi[a] = std::max(hi[a], g.center[a] + (rv + sw[a] + reach));
         }
+      } else {
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::min(lo[a], cr[v][a] - (sw[a] + reach));
+          hi[a] = std::max(hi[a], cr[v][a] + (sw[a] + reach));
+        }
+      }
     }
   }
   double span[3], smax = 0.0;
@@ -661,6 +684,7 @@ static int set_mesh(sdem_ctx* X, int32_t sim, int64_t nel, const int32_t* nv, co
                 (long long)X->cfg.tri_max);
   X->mesh_tri[sim] = std::move(packed);
   X->mesh_nv[sim] = std::move(counts);
+  X->mesh_grp[sim].assign((size_t)nel, 0);
   X->mesh_r[sim].assign((size_t)nel, 0.0);
   if (rmesh) X->mesh_r[sim].assign(rmesh, rmesh + nel);
   return upload_mesh(X);
@@ -672,12 +696,15 @@ static int upload_mesh(sdem_ctx* X) {
   drop_graphs(X);
   // concatenate every simulation's mesh
   std::vector<double> all, rad;
-  std::vector<int32_t> owner, nva;
+  std::vector<int32_t> owner, nva, grp;
+  std::vector<MeshMotion> table((size_t)X->nsims * kMotionMax);
   for (int s = 0; s < X->nsims; ++s) {
     all.insert(all.end(), X->mesh_tri[s].begin(), X->mesh_tri[s].end());
     rad.insert(rad.end(), X->mesh_r[s].begin(), X->mesh_r[s].end());
     nva.insert(nva.end(), X->mesh_nv[s].begin(), X->mesh_nv[s].end());
     owner.insert(owner.end(), X->mesh_r[s].size(), s);
+    for (int32_t g : X->mesh_grp[s]) grp.push_back(s * kMotionMax + g);
+    for (size_t g = 0; g < X->motion[s].size(); ++g) table[(size_t)s * kMotionMax + g] = X->motion[s][g];
   }
   Ctx& c = X->c;
   c.ntri = (int32_t)rad.size();
@@ -691,7 +718,11 @@ static int upload_mesh(sdem_ctx* X) {
                            hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c.tri_nv, nva.data(), sizeof(int32_t) * nva.size(),
                            hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.tri_grp, grp.data(), sizeof(int32_t) * grp.size(),
+                           hipMemcpyHostToDevice, st));
   }
+  HIP_TRY(hipMemcpyAsync(c.motion, table.data(), sizeof(MeshMotion) * table.size(),
+                         hipMemcpyHostToDevice, st));
   int rc = upload_params(X);
   if (rc) return rc;
   // triangle bins: each simulation gets a share of the tables in proportion
@@ -705,9 +736,8 @@ static int upload_mesh(sdem_ctx* X) {
     mg[s].off = (int32_t)nbins;
     if (!nt) continue;
     const int64_t bb = bins_cap(X->cfg) * nt / tmax, eb = bin_entries_cap(X->cfg) * nt / tmax;
-    mg[s] = mesh_grid(X->mesh_tri[s], X->mesh_nv[s], X->mesh_r[s], X->rmax[s],
-                      derive(X->params[s], 1.0, X->rmax[s]).rotating,
-                      X->params[s].mesh_center, std::max<int64_t>(bb, 1), eb, (int32_t)nbins);
+    mg[s] = mesh_grid(X->mesh_tri[s], X->mesh_nv[s], X->mesh_r[s], X->mesh_grp[s], X->motion[s],
+                      X->rmax[s], std::max<int64_t>(bb, 1), eb, (int32_t)nbins);
     if (mg[s].dim[0] <= 0) return fail(SDEM_ECAPACITY, "no triangle bin grid fits simulation %d", s);
     nbins += (int64_t)mg[s].dim[0] * mg[s].dim[1] * mg[s].dim[2];
   }
@@ -1196,6 +1226,49 @@ int sdem_stats(sdem_ctx* X, int64_t* steps, int64_t* pp, int64_t* pw, int64_t* r
   if (pp) *pp = a;
   if (pw) *pw = b;
   if (rebuilds) *rebuilds = (int64_t)h.rebuilds;
+  return SDEM_OK;
+}
+
+int sdem_set_mesh_motion(sdem_ctx* X, int32_t sim, int32_t ngroups,
+                         const sdem_mesh_motion* motions, const int32_t* group_of) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (X->failed) return fail(SDEM_ESTATE, "context failed in an earlier step; read it and re-init");
+  if (sim < 0 || sim >= X->nsims) return fail(SDEM_EINVAL, "sim %d out of range", sim);
+  if (ngroups < 1 || ngroups > kMotionMax || !motions)
+    return fail(SDEM_EINVAL, "ngroups must be in [1, %d]", kMotionMax);
+  std::vector<MeshMotion> table((size_t)ngroups);
+  for (int32_t g = 0; g < ngroups; ++g) {
+    const sdem_mesh_motion& in = motions[g];
+    MeshMotion& o = table[g];
+    for (int k = 0; k < 3; ++k) {
+      if (!isfinite(in.omega[k]) || !isfinite(in.center[k]) || !isfinite(in.amp[k]))
+        return fail(SDEM_EINVAL, "motion %d: omega, center and amp must be finite", g);
+      o.omega[k] = in.omega[k];
+      o.center[k] = in.center[k];
+      o.amp[k] = in.amp[k];
+    }
+    if (!isfinite(in.freq) || !(in.freq >= 0) || !isfinite(in.phase))
+      return fail(SDEM_EINVAL, "motion %d: freq >= 0 and phase must be finite", g);
+    o.freq = in.freq;
+    o.phase = in.phase;
+    o.moving = 0;
+    for (int k = 0; k < 3; ++k)
+      if (o.omega[k] != 0.0 || (o.amp[k] != 0.0 && o.freq != 0.0)) o.moving = 1;
+  }
+  const size_t nel = X->mesh_r[sim].size();
+  std::vector<int32_t> grp(nel, 0);
+  for (size_t m = 0; group_of && m < nel; ++m) {
+    if (group_of[m] < 0 || group_of[m] >= ngroups)
+      return fail(SDEM_EINVAL, "element %zu: motion group %d out of range", m, group_of[m]);
+    grp[m] = group_of[m];
+  }
+  X->motion[sim] = std::move(table);
+  X->mesh_grp[sim] = std::move(grp);
+  int rc = upload_mesh(X);  // bins over the swept region, parameters, planes
+  if (rc) return rc;
+  // the mesh at the current time, with its wall motion
+  HIP_TRY(launch_mesh_now(X->c, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
   return SDEM_OK;
 }
 

@@ -25,6 +25,7 @@ constexpr int kGroupShift = 8;      // contact records are allocated per group o
 constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots
 constexpr int kBinScanThreads = 1024;  // one workgroup scans the triangle bins
 constexpr int kSpawnMax = 1024;     // spawn attempts per step at most
+constexpr int kMotionMax = 16;      // motion groups of a simulation's mesh
 
 enum : int {
   kFlagCapContacts = 1,
@@ -39,7 +40,6 @@ struct SimParams {
   double rho, E, nu, e_n, mu_s, mu_r, mu_t, eta;
   double g[3];
   double dt;
-  double om[3], ctr[3];
   double beta;                 // 1/sqrt(1 + (pi/ln e_n)^2)
   double Es_pp, Gs_pp;         // uniform material, two spheres
   double Es_pw, Gs_pw;         // sphere against a rigid wall
@@ -48,9 +48,19 @@ struct SimParams {
   double h;                    // cell edge
   double rmax;                 // largest radius of the simulation
   double half_skin;            // skin * rmax / 2: allowed drift from the binned position
-  int32_t rotating;            // mesh rotates (|om| > 0)
+  int32_t moving;              // some element of the mesh moves
   int32_t tri0, ntri;          // global triangle range
   int32_t p0, np;              // particle range (fixed positions in sorted order)
+  int32_t pad;
+};
+
+// Prescribed rigid motion of a group of mesh elements: turns with angular
+// velocity omega about the axis through center, displaced by
+// amp (sin(2 pi freq t + phase) - sin(phase)), the axis moving with it.
+struct MeshMotion {
+  double omega[3], center[3], amp[3];
+  double freq, phase;
+  int32_t moving;  // omega != 0, or amp != 0 with freq != 0
   int32_t pad;
 };
 
@@ -130,7 +140,7 @@ struct Contacts {
 // Everything a step's kernels read or write.
 struct Ctx {
   int32_t n, nsims, ntri, cap_contacts, cap_cells, nchunks;
-  int32_t any_rotating, force_blocks;
+  int32_t any_moving, force_blocks;
   int32_t skin_on;           // cells are kept between steps (skin > 0)
   int32_t detect_sub;        // lanes per particle in the narrow phase (1, 2, 4, 8)
   int32_t ngroups, gcap;     // slot groups, contact records per group
@@ -174,6 +184,10 @@ struct Ctx {
   double* tri_pl;     // [ntri][4] unit normal and offset of the plane
   double* rmesh;      // [ntri]
   int32_t* tri_sim;   // [ntri]
+  int32_t* tri_grp;   // [ntri] motion of each element: sim * kMotionMax + group
+  MeshMotion* motion; // [nsims * kMotionMax]
+  double* tri_mv;     // [ntri][9] wall motion now: spin, moved centre, translation
+                      // velocity (zero for elements that do not move)
   MeshGrid* mg;       // [nsims]
   int32_t* bin_cnt;   // [nbins] zero between builds
   int32_t* bin_start; // [nbins+1]

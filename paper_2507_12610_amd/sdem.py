@@ -24,6 +24,7 @@ _NAMES = {SDEM_EINVAL: "EINVAL", SDEM_ECAPACITY: "ECAPACITY", SDEM_ENONFINITE: "
 EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_batch", "sdem_add_mesh",
            "sdem_add_mesh_elements", "sdem_set_spawn", "sdem_spawn_status", "sdem_read_radii",
            "sdem_set_spawn_status", "sdem_set_clock", "sdem_read_off", "sdem_write_csv",
+           "sdem_set_mesh_motion",
            "sdem_read_csv", "sdem_write_contacts_csv", "sdem_read_contacts_csv",
            "sdem_set_history", "sdem_step", "sdem_read_state", "sdem_read_contacts", "sdem_stats",
            "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding", "sdem_step_profiled")
@@ -42,6 +43,20 @@ class Params(C.Structure):
                 ("mu_t", C.c_double), ("eta", C.c_double), ("g", C.c_double * 3),
                 ("dt", C.c_double), ("mesh_omega", C.c_double * 3),
                 ("mesh_center", C.c_double * 3)]
+
+
+class MeshMotion(C.Structure):
+    _fields_ = [("omega", C.c_double * 3), ("center", C.c_double * 3), ("amp", C.c_double * 3),
+                ("freq", C.c_double), ("phase", C.c_double)]
+
+
+def make_motion(omega=(0.0, 0.0, 0.0), center=(0.0, 0.0, 0.0), amp=(0.0, 0.0, 0.0), freq=0.0,
+                phase=0.0) -> MeshMotion:
+    """Rigid motion of a group of mesh elements: turning with omega about the
+    axis through center, displaced by amp (sin(2 pi freq t + phase) -
+    sin(phase))."""
+    return MeshMotion((C.c_double * 3)(*omega), (C.c_double * 3)(*center),
+                      (C.c_double * 3)(*amp), float(freq), float(phase))
 
 
 class SpawnParams(C.Structure):
@@ -93,6 +108,7 @@ def lib():
         L.sdem_read_radii.argtypes = [_VP, _VP]
         L.sdem_set_spawn_status.argtypes = [_VP, C.c_uint64, C.c_double]
         L.sdem_set_clock.argtypes = [_VP, C.c_int64]
+        L.sdem_set_mesh_motion.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(MeshMotion), _I32]
         L.sdem_read_off.argtypes = [C.c_char_p, C.c_int32, _D, C.c_int64, C.POINTER(C.c_int64),
                                     _I32, _D, _D]
         L.sdem_write_csv.argtypes = [_VP, C.c_char_p]
@@ -343,6 +359,9 @@ class Solver:
                 rm = np.ascontiguousarray(s.get("rmesh", np.zeros(len(tri))), np.float64)
                 _check(L.sdem_add_mesh(h, k, len(tri), tri.ctypes.data_as(_D),
                                        rm.ctypes.data_as(_D)))
+        for k, s in enumerate(sims):
+            if s.get("motion") is not None:
+                self.set_mesh_motion(k, s["motion"], s.get("motion_groups"))
         if spawn is not None:
             self.set_spawn(**spawn)
 
@@ -378,6 +397,15 @@ class Solver:
             self._spawn = dict(kw)
         else:
             _check(lib().sdem_set_spawn(self._h, 0, None))
+
+    def set_mesh_motion(self, sim, motions, groups=None):
+        """Motion groups of simulation sim's mesh: a list of dicts with the
+        keywords of make_motion and the group of each element (None: all in
+        group 0)."""
+        arr = (MeshMotion * len(motions))(*[make_motion(**m) for m in motions])
+        g = None if groups is None else np.ascontiguousarray(groups, np.int32)
+        _check(lib().sdem_set_mesh_motion(self._h, int(sim), len(motions), arr,
+                                          g.ctypes.data_as(_I32) if g is not None else None))
 
     def set_spawn_status(self, attempts, carried):
         _check(lib().sdem_set_spawn_status(self._h, int(attempts), float(carried)))

@@ -56,14 +56,22 @@ def mesh_args(w):
     return {}
 
 
+def with_motion(o, w):
+    """Applies a workload's mesh motion groups, if any, to an oracle run."""
+    if w.get("motion") is not None:
+        o.set_mesh_motion(w["motion"], w.get("motion_groups"))
+    return o
+
+
 def oracle_from(w):
-    return oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"], **mesh_args(w))
+    return with_motion(oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"],
+                                  **mesh_args(w)), w)
 
 
 def oracle_resync(w, st, c, t):
     """Oracle started from a GPU state and GPU springs at time t."""
-    o = oracle.Sim(w["params"], st["x"], v=st["v"], w=st["w"], q=st["q"], R=w["R"],
-                   **mesh_args(w))
+    o = with_motion(oracle.Sim(w["params"], st["x"], v=st["v"], w=st["w"], q=st["q"], R=w["R"],
+                               **mesh_args(w)), w)
     o.set_time(t)
     if len(c["ki"]):
         o.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])

@@ -236,6 +236,28 @@ def hopper_params():
                           eta=0.0, g=(0.0, 0.0, -9.81), dt=dt_eq(0.002, 1000.0, 1e6, 0.3))
 
 
+def vibrated_box(n=400, seed=61, box=16 * MM):
+    """The agitated bath of the segregation example of Section 4 in a box:
+    spheres R ~ U[0.8, 1.2] mm at random in a cube of side `box`, walls of
+    two triangles each (fixed, motion group 0), and a floor rectangle
+    vibrated vertically (group 1) with amplitude A = R_min and frequency f
+    such that A (2 pi f)^2 = 3 g, phase pi/2 (at rest at t = 0)."""
+    w = random_cluster(n, seed, box=box, overlap=0.1, vel=0.02, spin=5.0)
+    lo, hi = -0.3 * MM, box + 0.3 * MM
+    tri = cube_mesh([lo] * 3, [hi] * 3)
+    walls = [t for t in tri if not np.allclose(np.asarray(t)[:, 2], lo)]
+    els = [np.asarray(t, float) for t in walls]
+    els.append(np.array([[lo, lo, lo], [hi, lo, lo], [hi, hi, lo], [lo, hi, lo]]))
+    A = 0.8 * MM
+    f = math.sqrt(3.0 * 9.81 / A) / (2.0 * math.pi)
+    w["tri"] = np.zeros((0, 3, 3))
+    w["elements"], w["rmesh"] = els, np.zeros(len(els))
+    w["motion"] = [dict(), dict(amp=(0.0, 0.0, A), freq=f, phase=math.pi / 2)]
+    w["motion_groups"] = np.array([0] * (len(els) - 1) + [1], np.int32)
+    w["params"].update(g=(0.0, 0.0, -9.81), dt=2e-6)
+    return w
+
+
 def drum_mesh(radius, length, nseg=128, nring=31):
     """Closed drum around the y axis: nseg x nring x 2 shell triangles plus
     two end-cap fans of nseg triangles (8,192 for the defaults)."""
