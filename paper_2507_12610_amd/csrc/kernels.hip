@@ -1071,80 +1071,38 @@ __device__ __forceinline__ int find_old(const Contacts& co, int b0, int n, int2 
 }
 
 template <typename RT>
-__global__ __launch_bounds__(kThreads) void k_force(Ctx c, State A, State B, Contacts cur,
-                                                   Contacts old, int rebuilt) {
+__global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, Contacts cur,
+                                                      Contacts old, int rebuilt) {
   if (c.ctr->flags) return;
   const State S = rebuilt ? B : A;
-  // (previous slot, its previous contact segment, id): carried by the
-  // reorder, or the slot itself when the order was kept
-  auto origin = [&](int p) {
-    return rebuilt ? c.os[p] : make_int4(p, old.off[p], old.cnt[p], S.pid[p]);
-  };
+  const int tid = (int)threadIdx.x;
   // one workgroup per slot group (consecutive groups on one XCD share its L2)
   const int grp = xcd_remap(blockIdx.x, gridDim.x);
-  const int cnt = min(c.gcnt[grp], c.gcap);
   const int gbase = grp * c.gcap;
+  // loads that depend on nothing else, issued together: this lane's record
+  // of the first pass, the group's record count and, when the slot order was
+  // kept, the group's previous record count
+  int ra = 0, rb = 0;
+  if (tid < c.gcap) {
+    ra = cur.a[gbase + tid];
+    rb = cur.b[gbase + tid];
+  }
+  const int ng = rebuilt ? 0 : old.ng[grp];
+  const int cnt = min(c.gcnt[grp], c.gcap);
+  if (tid == 0) cur.ng[grp] = cnt;
   int npp = 0, npw = 0;
   // the spring and result records of one pass are staged in LDS and written
   // out as contiguous runs (per-lane 64- and 80-byte records written
   // directly would make every store instruction scatter)
   __shared__ double2 st_spr[kThreads * kSpr / 2];
   __shared__ double2 st_res[kThreads * kRes / 2];
-  for (int base = 0; base < cnt; base += kThreads) {
-  const int l = base + (int)threadIdx.x;
-  if (l < cnt) {
-    const int e = gbase + l;
-    const int a = cur.a[e], b = cur.b[e];
-    const bool wall = b < 0;
-    const SimParams& P = c.sp[c.sim_of[a]];
-    // both bodies are gathered at once; the canonical orientation is then
-    // chosen in registers
-    const double4 pa = S.xr[a];
-    const int4 oa = origin(a);
-    const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
-    const double2 va0 = va[0], va1 = va[1], va2 = va[2];
-    double4 pb;
-    int4 ob = oa;
-    double2 vb0 = make_double2(0.0, 0.0), vb1 = vb0, vb2 = vb0;
-    int m = 0;
-    if (!wall) {
-      pb = S.xr[b];
-      ob = origin(b);
-      const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
-      vb0 = vb[0];
-      vb1 = vb[1];
-      vb2 = vb[2];
-    } else {
-      m = -1 - b;
-      const double p[3] = {pa.x, pa.y, pa.z};
-      double cp[3];
-      closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
-      pb = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
-    }
-    // canonical orientation: body I carries the lower id (the particle for walls)
-    const int ida = oa.w, idb = ob.w;
-    const bool swap = !wall && ida > idb;
-    const double4 pi = swap ? pb : pa, pj = swap ? pa : pb;
-    const int2 key = wall ? make_int2(ida, -(m - P.tri0))
-                          : make_int2(swap ? idb : ida, swap ? ida : idb);
-    // springs of the previous step (zero for a new contact), looked up among
-    // the records of the previous owner: the lower previous slot of the two
-    double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
-    {
-      const bool bown = !wall && ob.x < oa.x;
-      const int eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
-      if (eo >= 0) {
-        const double2* r = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
-        const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-        us[0] = r0.x;
-        us[1] = r0.y;
-        us[2] = r1.x;
-        ur[0] = r1.y;
-        ur[1] = r2.x;
-        ur[2] = r2.y;
-        ut = r3.x;
-      }
-    }
+  // The contact law of one record (body I carries the lower id): the updated
+  // springs are staged in LDS at this lane's place, the forces and torques
+  // returned in o.
+  auto law = [&](const SimParams& P, const bool wall, const int m, const bool swap,
+                 const double4 pi, const double4 pj, const double2 va0, const double2 va1,
+                 const double2 va2, const double2 vb0, const double2 vb1, const double2 vb2,
+                 double* us, double* ur, double ut, const int e, const int2 key, double* o) {
     const double Ri = pi.w, Rj = pj.w;
     double dx, dy, dz, d;
     const double delta = pair_gap(pi.x, pi.y, pi.z, Ri, pj.x, pj.y, pj.z, Rj, &dx, &dy, &dz, &d);
@@ -1257,7 +1215,6 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State A, State B, Con
     const RT rif = (RT)ri, rjf = (RT)rj;
     npp += wall ? 0 : 1;
     npw += wall ? 1 : 0;
-    double o[kRes];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double f = (double)fn[k] + (double)fs[k];
@@ -1270,19 +1227,192 @@ __global__ __launch_bounds__(kThreads) void k_force(Ctx c, State A, State B, Con
       o[6 + k] = swap ? ti : tj;
     }
     o[9] = 0.0;
+  };
+  auto stage_res = [&](const double* o) {
     double2* r = st_res + (kRes / 2) * threadIdx.x;
 #pragma unroll
     for (int k = 0; k < kRes / 2; ++k) r[k] = make_double2(o[2 * k], o[2 * k + 1]);
-  }
-  __syncthreads();
-  {
+  };
+  auto write_out = [&](const int base) {
     const int nrec = min(cnt - base, kThreads);
     double2* gs = reinterpret_cast<double2*>(cur.spr + (size_t)kSpr * (gbase + base));
-    for (int k = threadIdx.x; k < nrec * (kSpr / 2); k += kThreads) gs[k] = st_spr[k];
+    for (int k = tid; k < nrec * (kSpr / 2); k += kThreads) gs[k] = st_spr[k];
     double2* gr = reinterpret_cast<double2*>(c.res + (size_t)kRes * (gbase + base));
-    for (int k = threadIdx.x; k < nrec * (kRes / 2); k += kThreads) gr[k] = st_res[k];
-  }
-  __syncthreads();
+    for (int k = tid; k < nrec * (kRes / 2); k += kThreads) gr[k] = st_res[k];
+  };
+  if (!rebuilt && cnt <= kThreads) {
+    // The slot order was kept and the group's records fit one pass: the
+    // previous step's records owned by this group's slots are the previous
+    // records of the same group range.  Their keys and springs (the first
+    // 256) come to LDS in contiguous runs while the bodies are gathered, and
+    // each contact finds its springs there (the owner is the lower slot, a
+    // slot of this group).  Two rounds of dependent loads instead of four.
+    // The previous springs are held in the result staging buffer, which the
+    // law's results overwrite only after every lane has read its springs.
+    __shared__ int2 okey[kThreads];
+    const bool act = tid < cnt;
+    const int on = min(ng, kThreads);
+    if (tid < on) {
+      okey[tid] = old.key[gbase + tid];
+      const double2* r = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * (gbase + tid));
+      double2* d = st_res + (kSpr / 2) * tid;
+      d[0] = r[0];
+      d[1] = r[1];
+      d[2] = r[2];
+      d[3] = r[3];
+    }
+    const int a = ra, b = rb;
+    const bool wall = b < 0;
+    const SimParams* Pp = c.sp;
+    double4 pa = make_double4(0.0, 0.0, 0.0, 0.0), pb = pa;
+    double2 va0 = make_double2(0.0, 0.0), va1 = va0, va2 = va0, vb0 = va0, vb1 = va0, vb2 = va0;
+    int ida = 0, idb = 0, m = 0, off = 0, n_o = 0;
+    if (act) {
+      Pp = c.sp + c.sim_of[a];
+      pa = S.xr[a];
+      ida = S.pid[a];
+      off = old.off[a];  // the owner's previous segment
+      n_o = old.cnt[a];
+      const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
+      va0 = va[0];
+      va1 = va[1];
+      va2 = va[2];
+      if (!wall) {
+        pb = S.xr[b];
+        idb = S.pid[b];
+        const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
+        vb0 = vb[0];
+        vb1 = vb[1];
+        vb2 = vb[2];
+      } else {
+        m = -1 - b;
+        const double p[3] = {pa.x, pa.y, pa.z};
+        double cp[3];
+        closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
+        pb = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
+      }
+    }
+    __syncthreads();
+    double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
+    bool swap = false;
+    int2 key = make_int2(0, 0);
+    if (act) {
+      swap = !wall && ida > idb;
+      key = wall ? make_int2(ida, -(m - Pp->tri0)) : make_int2(swap ? idb : ida, swap ? ida : idb);
+      const int rel = off - gbase;
+      double2 r0 = make_double2(0.0, 0.0), r1 = r0, r2 = r0, r3 = r0;
+      bool found = false;
+      if (n_o > 0 && rel >= 0 && rel + n_o <= on) {
+        for (int k = 0; k < n_o; ++k) {
+          const int2 kk = okey[rel + k];
+          if (kk.x == key.x && kk.y == key.y) {
+            const double2* q = st_res + (kSpr / 2) * (rel + k);
+            r0 = q[0];
+            r1 = q[1];
+            r2 = q[2];
+            r3 = q[3];
+            found = true;
+            break;
+          }
+        }
+      } else {
+        const int eo = find_old(old, off, n_o, key);
+        if (eo >= 0) {
+          const double2* q = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
+          r0 = q[0];
+          r1 = q[1];
+          r2 = q[2];
+          r3 = q[3];
+          found = true;
+        }
+      }
+      if (found) {
+        us[0] = r0.x;
+        us[1] = r0.y;
+        us[2] = r1.x;
+        ur[0] = r1.y;
+        ur[1] = r2.x;
+        ur[2] = r2.y;
+        ut = r3.x;
+      }
+    }
+    double o[kRes];
+    if (act)
+      law(*Pp, wall, m, swap, swap ? pb : pa, swap ? pa : pb, va0, va1, va2, vb0, vb1, vb2, us, ur,
+          ut, gbase + tid, key, o);
+    __syncthreads();  // every lane has read its previous springs
+    if (act) stage_res(o);
+    __syncthreads();
+    write_out(0);
+  } else {
+    // (previous slot, its previous contact segment, id): carried by the
+    // reorder, or the slot itself when the order was kept
+    auto origin = [&](int p) {
+      return rebuilt ? c.os[p] : make_int4(p, old.off[p], old.cnt[p], S.pid[p]);
+    };
+    for (int base = 0; base < cnt; base += kThreads) {
+      const int l = base + tid;
+      if (l < cnt) {
+        const int e = gbase + l;
+        const int a = cur.a[e], b = cur.b[e];
+        const bool wall = b < 0;
+        const SimParams& P = c.sp[c.sim_of[a]];
+        // both bodies are gathered at once; the canonical orientation is then
+        // chosen in registers
+        const double4 pa = S.xr[a];
+        const int4 oa = origin(a);
+        const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
+        const double2 va0 = va[0], va1 = va[1], va2 = va[2];
+        double4 pb;
+        int4 ob = oa;
+        double2 vb0 = make_double2(0.0, 0.0), vb1 = vb0, vb2 = vb0;
+        int m = 0;
+        if (!wall) {
+          pb = S.xr[b];
+          ob = origin(b);
+          const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
+          vb0 = vb[0];
+          vb1 = vb[1];
+          vb2 = vb[2];
+        } else {
+          m = -1 - b;
+          const double p[3] = {pa.x, pa.y, pa.z};
+          double cp[3];
+          closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
+          pb = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
+        }
+        // canonical orientation: body I carries the lower id (the particle for walls)
+        const int ida = oa.w, idb = ob.w;
+        const bool swap = !wall && ida > idb;
+        const double4 pi = swap ? pb : pa, pj = swap ? pa : pb;
+        const int2 key = wall ? make_int2(ida, -(m - P.tri0))
+                              : make_int2(swap ? idb : ida, swap ? ida : idb);
+        // springs of the previous step (zero for a new contact), looked up among
+        // the records of the previous owner: the lower previous slot of the two
+        double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
+        {
+          const bool bown = !wall && ob.x < oa.x;
+          const int eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
+          if (eo >= 0) {
+            const double2* r = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
+            const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+            us[0] = r0.x;
+            us[1] = r0.y;
+            us[2] = r1.x;
+            ur[0] = r1.y;
+            ur[1] = r2.x;
+            ur[2] = r2.y;
+            ut = r3.x;
+          }
+        }
+        double o[kRes];
+        law(P, wall, m, swap, pi, pj, va0, va1, va2, vb0, vb1, vb2, us, ur, ut, e, key, o);
+        stage_res(o);
+      }
+      __syncthreads();
+      write_out(base);
+      __syncthreads();
+    }
   }
   // contact counts of the group for the statistics (summed by the next step's
   // grid kernel or by the host)
@@ -1362,10 +1492,22 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
   const double2 s0 = vw2[0], s1 = vw2[1], s2 = vw2[2];
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   {
-    // owned contacts in record order, four records in flight
+    // the partner list is loaded first, so that its gathers and those of
+    // the owned records are in flight together
     const int e0 = cur.off[i], e1 = e0 + cur.cnt[i];
     const int m = min(c.pcnt[i], kMaxRev);
     c.pcnt[i] = 0;  // cleared for the next step's narrow phase
+    const int2* pl = c.plist + (size_t)i * kMaxRev;
+    int ka[8], ke[8];
+    if (m <= 8) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int2 v = j < m ? pl[j] : make_int2(0x7fffffff, -1);
+        ka[j] = v.x;
+        ke[j] = v.y;
+      }
+    }
+    // owned contacts in record order, four records in flight
     for (int e = e0; e < e1; e += 4) {
       double2 f[4][3];
 #pragma unroll
@@ -1389,16 +1531,8 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
     }
     // contacts owned by others, in ascending owner slot (the partner lists
     // hold (owner slot, record); owners of one partner are distinct)
-    const int2* pl = c.plist + (size_t)i * kMaxRev;
     if (m <= 8) {
       // sort with a fixed compare-exchange network
-      int ka[8], ke[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int2 v = j < m ? pl[j] : make_int2(0x7fffffff, -1);
-        ka[j] = v.x;
-        ke[j] = v.y;
-      }
 #define SDEM_CX(x, y)                                    \
   if (ka[y] < ka[x]) {                                  \
     const int ta = ka[x], te = ke[x];                   \

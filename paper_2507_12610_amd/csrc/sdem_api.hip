@@ -195,6 +195,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
     k.b = L.take<int32_t>(Cm);
     k.key = L.take<int2>(Cm);
     k.spr = L.take<double>(kSpr * Cm);
+    k.ng = L.take<int32_t>(G);
     if (ct) ct[b] = k;
   }
   double* scr = L.take<double>(19 * N);
@@ -475,6 +476,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   for (int b = 0; b < 2 && !e; ++b) {
     e = hipMemsetAsync(X->ct[b].cnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
     if (!e) e = hipMemsetAsync(X->ct[b].off, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
+    if (!e) e = hipMemsetAsync(X->ct[b].ng, 0, sizeof(int32_t) * groups_of(cfg), st);
   }
   if (!e) e = hipMemsetAsync(c.pcnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
   if (!e) e = hipMemsetAsync(c.gcnt, 0, sizeof(int32_t) * c.ngroups, st);
@@ -826,6 +828,7 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
     SP[(size_t)kSpr * d + 6] = ut[e];
   }
   Contacts& C = X->ct[X->cur];
+  HIP_TRY(hipMemcpy(C.ng, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice));
   if (n) {
     HIP_TRY(hipMemcpy(C.cnt, cnt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(C.off, off.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));

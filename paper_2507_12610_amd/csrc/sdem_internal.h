@@ -135,6 +135,7 @@ struct Contacts {
   int2* key;     // (lower persistent id, higher id) or (id, -local triangle index)
   double* spr;   // [cap][kSpr] sliding spring (3), rolling spring (3), twisting
                  // spring (1), in the orientation of body key.x; one pad
+  int32_t* ng;   // [ngroups] records of each slot group (written by the force kernel)
 };
 
 // Everything a step's kernels read or write.
