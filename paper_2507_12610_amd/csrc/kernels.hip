@@ -711,6 +711,28 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
 template <int SUB>
 __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Contacts cn,
                                                     int rebuilt) {
+  // the sorted copy when this step rebuilt the cells, else the kept order
+  const State S = rebuilt ? B : A;
+  const int n = c.n;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int bg = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x;
+  const int g = bg + threadIdx.x;
+  const int s = g / SUB, sub = g % SUB;
+  // The own centre, simulation and candidate list head are loaded before the
+  // failure flag is examined (a step after a failed one exits there): none
+  // depends on the step's outcome so far.  List entries are only followed
+  // within the recorded count.
+  int sim = 0, vcnt0 = -1, vraw[4] = {s, s, s, s};
+  double4 ps = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (s < n) {
+    sim = c.nsims == 1 ? 0 : c.sim_of[s];
+    ps = S.xr[s];
+    if (c.skin_on && !rebuilt) {
+      vcnt0 = c.vcnt[g];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vraw[u] = c.vlist[(size_t)g * kCand + u];
+    }
+  }
   if (c.ctr->flags) return;
   // a step that keeps the cells starts here (and is counted if its searches
   // must reach past the skin)
@@ -718,14 +740,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     atomicAdd(&c.ctr->steps, 1ull);
     if (c.ctr->rebuild_next) c.ctr->drift_steps += 1ull;
   }
-  // the sorted copy when this step rebuilt the cells, else the kept order
-  const State S = rebuilt ? B : A;
   __shared__ int hits[kThreads / 64][kMaxOwn][64];
-  const int n = c.n;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int bg = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x;
-  const int g = bg + threadIdx.x;
-  const int s = g / SUB, sub = g % SUB;
   // If a particle drifted past half the skin since the cells were built,
   // every search of this step reaches by the excess further: the largest
   // drift of each simulation of this workgroup, from the integration's
@@ -755,10 +770,8 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
   }
   int npp = 0, npw = 0;
   if (s < n) {
-    const int sim = c.sim_of[s];
     const SimGrid gr = c.sg[sim];
     const double extra = (!rebuilt && c.ctr->rebuild_next) ? xdrift[sim - sim_lo] : 0.0;
-    const double4 ps = S.xr[s];
     const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
     // Between rebuilds, with no drift past half the skin in this simulation,
     // the candidates recorded at the last rebuild suffice: every particle
@@ -769,7 +782,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     const bool record = c.skin_on && rebuilt;
     const bool tri_listed = !c.sp[sim].moving;
     int* vl = c.vlist + (size_t)g * kCand;
-    const int nlist = listed ? c.vcnt[g] : -1;
+    const int nlist = listed ? vcnt0 : -1;
     int ncand = 0;
     auto test_wall = [&](int m) {
       const double p[3] = {xs, ys, zs};
@@ -825,13 +838,20 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     }
     // ---- particles (and listed triangles)
     if (nlist >= 0) {
+      // four candidates per iteration; the next four slots are loaded while
+      // these are tested (slots past the list read the own slot)
+      int tn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tn[u] = u < nlist ? vraw[u] : s;
       for (int k = 0; k < nlist; k += 4) {
         int tt[4];
         double4 pt[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) tt[u] = vl[k + u < nlist ? k + u : k];
+        for (int u = 0; u < 4; ++u) tt[u] = tn[u];
 #pragma unroll
         for (int u = 0; u < 4; ++u) pt[u] = S.xr[tt[u] >= 0 ? tt[u] : s];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tn[u] = k + 4 + u < nlist ? vl[k + 4 + u] : s;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (k + u >= nlist) continue;
@@ -982,15 +1002,25 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
       cn.off[s] = first;
       cn.cnt[s] = slot_end - first;
     }
-    for (int k = 0; k < mine; ++k) {
-      const int e = first + k;
-      const int t = hits[wv][k][lane];
-      cn.a[e] = s;
-      cn.b[e] = t;
-      if (t >= 0) {
-        const int r = atomicAdd(&c.pcnt[t], 1);
-        if (r < kMaxRev)
-          c.plist[(size_t)t * kMaxRev + r] = make_int2(s, e);
+    for (int k0 = 0; k0 < mine; k0 += 4) {
+      int tk[4], rk[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tk[u] = k0 + u < mine ? hits[wv][k0 + u][lane] : -1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (k0 + u < mine) {
+          cn.a[first + k0 + u] = s;
+          cn.b[first + k0 + u] = tk[u];
+        }
+      }
+      // the partner-list places of up to four pairs are reserved together
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rk[u] = tk[u] >= 0 ? atomicAdd(&c.pcnt[tk[u]], 1) : 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (tk[u] < 0) continue;
+        if (rk[u] < kMaxRev)
+          c.plist[(size_t)tk[u] * kMaxRev + rk[u]] = make_int2(s, first + k0 + u);
         else
           raise_flag(c.ctr, kFlagCapPerParticle);
       }
@@ -1073,7 +1103,6 @@ __device__ __forceinline__ int find_old(const Contacts& co, int b0, int n, int2 
 template <typename RT>
 __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, Contacts cur,
                                                       Contacts old, int rebuilt) {
-  if (c.ctr->flags) return;
   const State S = rebuilt ? B : A;
   const int tid = (int)threadIdx.x;
   // one workgroup per slot group (consecutive groups on one XCD share its L2)
@@ -1089,6 +1118,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
   }
   const int ng = rebuilt ? 0 : old.ng[grp];
   const int cnt = min(c.gcnt[grp], c.gcap);
+  // (the failure flag is examined once these loads are in flight; the
+  // records are only followed after it)
+  if (c.ctr->flags) return;
   if (tid == 0) cur.ng[grp] = cnt;
   int npp = 0, npw = 0;
   // the spring and result records of one pass are staged in LDS and written
@@ -1268,7 +1300,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
     double2 va0 = make_double2(0.0, 0.0), va1 = va0, va2 = va0, vb0 = va0, vb1 = va0, vb2 = va0;
     int ida = 0, idb = 0, m = 0, off = 0, n_o = 0;
     if (act) {
-      Pp = c.sp + c.sim_of[a];
+      Pp = c.sp + (c.nsims == 1 ? 0 : c.sim_of[a]);
       pa = S.xr[a];
       ida = S.pid[a];
       off = old.off[a];  // the owner's previous segment
@@ -1356,7 +1388,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
         const int e = gbase + l;
         const int a = cur.a[e], b = cur.b[e];
         const bool wall = b < 0;
-        const SimParams& P = c.sp[c.sim_of[a]];
+        const SimParams& P = c.sp[c.nsims == 1 ? 0 : c.sim_of[a]];
         // both bodies are gathered at once; the canonical orientation is then
         // chosen in registers
         const double4 pa = S.xr[a];
@@ -1429,8 +1461,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
       ta += red[0][w];
       tb += red[1][w];
     }
-    c.gstat[2 * grp] += (unsigned long long)ta;  // running sums, one writer per group
-    c.gstat[2 * grp + 1] += (unsigned long long)tb;
+    // running sums, one writer per group: adds without a return value, so
+    // the kernel's end does not wait for a read
+    atomicAdd(&c.gstat[2 * grp], (unsigned long long)ta);
+    atomicAdd(&c.gstat[2 * grp + 1], (unsigned long long)tb);
   }
 }
 
@@ -1470,32 +1504,45 @@ __device__ __forceinline__ void qmul(const double a[4], const double b[4], doubl
 
 __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B, Contacts cur,
                                                        int rebuilt) {
-  if (c.ctr->flags) return;
   // reads the step's state (the sorted copy B, or A when the order was
   // kept) and writes the new state to B
   const State S = rebuilt ? B : A;
   const int n = c.n;
   const int i0 = blockIdx.x * kThreads;
   const int i = i0 + (int)threadIdx.x;
+  // The particle's own state and contact counts are loaded before the
+  // failure flag is examined (a step after a failed one exits here): these
+  // loads do not depend on the step's outcome so far, and the flag's round
+  // trip then overlaps them.
+  int sim = 0, e0 = 0, ne = 0, pc = 0;
+  double4 xr = make_double4(0.0, 0.0, 0.0, 0.0), q4 = xr;
+  double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
+  if (i < n) {
+    sim = c.nsims == 1 ? 0 : c.sim_of[i];
+    xr = S.xr[i];
+    q4 = S.q[i];
+    const double2* vw2 = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)i);
+    s0 = vw2[0];
+    s1 = vw2[1];
+    s2 = vw2[2];
+    e0 = cur.off[i];
+    ne = cur.cnt[i];
+    pc = c.pcnt[i];
+  }
+  if (c.ctr->flags) return;
   // new states are staged in LDS and written out as contiguous runs
   __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
   bool drift = false;
   double ddrift = 0.0;
   if (i < n) {
   const double* res = c.res;
-  // the particle's own state first, so that its loads overlap the gathers
-  const SimParams& P = c.sp[c.sim_of[i]];
-  const double4 xr = S.xr[i];
-  const double4 q4 = S.q[i];
-  double* vwp = S.vw + 6 * (size_t)i;
-  const double2* vw2 = reinterpret_cast<const double2*>(vwp);
-  const double2 s0 = vw2[0], s1 = vw2[1], s2 = vw2[2];
+  const SimParams& P = c.sp[sim];
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   {
     // the partner list is loaded first, so that its gathers and those of
     // the owned records are in flight together
-    const int e0 = cur.off[i], e1 = e0 + cur.cnt[i];
-    const int m = min(c.pcnt[i], kMaxRev);
+    const int e1 = e0 + ne;
+    const int m = min(pc, kMaxRev);
     c.pcnt[i] = 0;  // cleared for the next step's narrow phase
     const int2* pl = c.plist + (size_t)i * kMaxRev;
     int ka[8], ke[8];
@@ -1549,27 +1596,32 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
       SDEM_CX(2, 4) SDEM_CX(3, 5)
       SDEM_CX(3, 4)
 #undef SDEM_CX
-      // force on the owner (doubles 0..2) and torque on the partner (6..8)
-      double2 g[8][4];
+      // force on the owner (doubles 0..2) and torque on the partner (6..8),
+      // four records in flight
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (j < m) {
-          const double2* r = reinterpret_cast<const double2*>(res + (size_t)kRes * ke[j]);
-          g[j][0] = r[0];
-          g[j][1] = r[1];
-          g[j][2] = r[3];
-          g[j][3] = r[4];
+      for (int j0 = 0; j0 < 8; j0 += 4) {
+        if (j0 >= m) break;
+        double2 g[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (j0 + u < m) {
+            const double2* r = reinterpret_cast<const double2*>(res + (size_t)kRes * ke[j0 + u]);
+            g[u][0] = r[0];
+            g[u][1] = r[1];
+            g[u][2] = r[3];
+            g[u][3] = r[4];
+          }
         }
-      }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (j < m) {
-          F[0] -= g[j][0].x;
-          F[1] -= g[j][0].y;
-          F[2] -= g[j][1].x;
-          T[0] += g[j][2].x;
-          T[1] += g[j][2].y;
-          T[2] += g[j][3].x;
+        for (int u = 0; u < 4; ++u) {
+          if (j0 + u < m) {
+            F[0] -= g[u][0].x;
+            F[1] -= g[u][0].y;
+            F[2] -= g[u][1].x;
+            T[0] += g[u][2].x;
+            T[1] += g[u][2].y;
+            T[2] += g[u][3].x;
+          }
         }
       }
     } else {
