@@ -128,6 +128,38 @@ BATCH_CANDIDATES = [(1.0, 1, 1.0), (0.7, 1, 1.0), (1.0, 1, 0.6), (0.7, 1, 0.6), 
                     (1.0, 1, 0.0)]
 
 
+def packing_forms(warmup=10, steps=40):
+    """The 8,000,000-sphere pre-compressed packing (six contacts per sphere
+    at the start), FP64 and mixed precision with the same settings: where the
+    contact law's arithmetic weighs more than at 200,000 spheres."""
+    import torch
+
+    import workloads as W
+    from paper_2507_12610_amd import Solver
+    w = W.cfg5()
+    n = len(w["R"])
+    print(f"[bench] packing: {n} particles", file=sys.stderr, flush=True)
+    out = {"workload": w["name"], "particles": n, "cell_factor": 1.0, "skin": 0.05,
+           "steps": steps}
+    for prec in ("fp64", "mixed"):
+        g = Solver(w, precision=prec, device="cuda:0", cell_factor=1.0, detect_lanes=1, skin=0.05)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        s0 = g.stats()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s1 = g.stats()
+        g.close()
+        del g
+        out[prec] = {"ms_per_step": round(1e3 * dt / steps, 4),
+                     "particle_steps_per_s": round(n * steps / dt, 1),
+                     "contacts_per_step": round((s1["pp"] + s1["pw"] - s0["pp"] - s0["pw"]) / steps, 1)}
+    out["mixed_speedup_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"], 4)
+    return out
+
+
 def batched_forms(landing_steps, steps, precision_list=("fp64", "mixed")):
     """Configuration 4: 256 box drops of uneven size in one context, timed after
     the sims have landed, against the same 256 states stepped one simulation
@@ -146,7 +178,7 @@ def batched_forms(landing_steps, steps, precision_list=("fp64", "mixed")):
     b.close()
     landed = [sim_slice(sims[k], st, c, b.offsets[k], b.offsets[k + 1]) for k in range(len(sims))]
     # tuned on the landed state (the regime that is timed)
-    best, _ = autotune([p[0] for p in landed], candidates=BATCH_CANDIDATES, steps=40, warmup=4)
+    best, _ = autotune([p[0] for p in landed], candidates=BATCH_CANDIDATES, steps=96, warmup=4)
     cf, skin = best["cell_factor"], best["skin"]
     out = {"workload": "cfg4_256_box_drops", "sims": len(sims), "particles": total,
            "landing_steps": landing_steps, "steps": steps, "cell_factor": cf, "skin": skin}
@@ -242,7 +274,10 @@ def main():
           flush=True)
     tuned = None
     if args.cell_factor is None or args.detect_lanes is None or args.skin is None:
-        best, timings = autotune(w, candidates=TUNE_CANDIDATES, steps=40, precision=args.precision)
+        # trials of three rebuild periods: a thin skin looks fast over a few
+        # steps and loses once particles drift past it
+        best, timings = autotune(w, candidates=TUNE_CANDIDATES, steps=192, warmup=10,
+                                 precision=args.precision)
         tuned = {"chosen": best, "trials": timings}
         print(f"[bench] autotuned: {best}", file=sys.stderr, flush=True)
         cf, lanes, skin = best["cell_factor"], best["detect_lanes"], best["skin"]
@@ -331,6 +366,7 @@ def main():
                 "workload": w["name"], "ms_per_step": round(ms_rb, 5),
                 "particle_steps_per_s": round(n * 1e3 / ms_rb, 1)}
         forms["batched"] = batched_forms(args.batch_landing_steps, args.batch_steps)
+        forms["packing_8M"] = packing_forms()
         out["forms"] = forms
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
