@@ -952,6 +952,12 @@ static hipError_t enqueue_steps(sdem_ctx* X, int k, bool rebuild, hipEvent_t* ev
   return hipSuccess;
 }
 
+// Contexts from this many particles look at the drift flag after every step
+// that keeps the cells (a step there takes milliseconds, the look tens of
+// microseconds), so that a drift past half the skin is followed by a rebuild
+// at the next step instead of widened searches until the period ends.
+constexpr int64_t kDriftCheckEachStep = int64_t(1) << 20;
+
 // Graph patterns: {steps, rebuild}.  A graph bakes in the pointers of both
 // buffers for its starting parity.
 constexpr int kPatSteps[4] = {2, 1, 1, 8};
@@ -1047,13 +1053,20 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
       }
       if (rebuild_now(X))
         pat = 1;
-      else if (left >= 8 && X->since + 8 <= X->period)
+      else if (left >= 8 && X->since + 8 <= X->period && X->n < kDriftCheckEachStep)
         pat = 3;
       else
         pat = 2;
     }
     HIP_TRY(run_pattern(X, pat));
     left -= kPatSteps[pat];
+    if (X->c.skin_on && !kPatRebuild[pat] && X->n >= kDriftCheckEachStep) {
+      int32_t next = 0;
+      HIP_TRY(hipMemcpyAsync(&next, &X->c.ctr->rebuild_next, sizeof next, hipMemcpyDeviceToHost,
+                             X->stream));
+      HIP_TRY(hipStreamSynchronize(X->stream));
+      if (next) X->need_rebuild = true;
+    }
   }
   return finish_steps(X, before, start);
 }

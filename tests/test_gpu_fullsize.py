@@ -144,11 +144,15 @@ def packing():
     return W.cfg5()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", TOL32)])
-def test_packing_8M_sampled(packing, precision, tol):
+@pytest.mark.parametrize("precision,tol,skin", [("fp64", TOL64, 0.0), ("mixed", TOL32, 0.0),
+                                               ("fp64", TOL64, 0.05)])
+def test_packing_8M_sampled(packing, precision, tol, skin):
+    """With a skin the relaxing packing drifts past half of it within the
+    first steps: the host sees the drift flag after each step at this size
+    and rebuilds at the next one."""
     w = packing
     n = len(w["R"])
-    g = solver(w, precision=precision, cell_factor=1.0, detect_lanes=1)
+    g = solver(w, precision=precision, cell_factor=1.0, detect_lanes=1, skin=skin)
     empty = {"ki": np.zeros(0, np.int32), "kj": np.zeros(0, np.int32)}
     idx = sample_ids(n, empty, 5)
     st0 = {k: w[k] for k in ("x", "v", "w", "q")}
@@ -164,4 +168,6 @@ def test_packing_8M_sampled(packing, precision, tol):
     print(precision, "step 51 sampled contacts", nc, {q: f"{e:.2e}" for q, e in err.items()})
     assert same
     assert max(err.values()) < tol, err
+    if skin > 0:
+        assert g.stats()["rebuilds"] >= 2
     g.close()
