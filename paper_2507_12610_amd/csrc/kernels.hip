@@ -1255,8 +1255,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
       const double tj = wall ? 0.0 : (double)(rjf * fsxn[k]) - ttr;
       // per-contact results for the owner slot a and the partner b
       o[k] = swap ? -f : f;
-      o[3 + k] = swap ? tj : ti;
-      o[6 + k] = swap ? ti : tj;
+      o[3 + k] = swap ? ti : tj;  // torque on the partner
+      o[6 + k] = swap ? tj : ti;  // torque on the owner
     }
     o[9] = 0.0;
   };
@@ -1554,15 +1554,17 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
         ke[j] = v.y;
       }
     }
-    // owned contacts in record order, four records in flight
+    // owned contacts in record order, four records in flight: the force
+    // (doubles 0..2) and the owner's torque (6..8)
     for (int e = e0; e < e1; e += 4) {
-      double2 f[4][3];
+      double2 f[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const double2* r = reinterpret_cast<const double2*>(res + (size_t)kRes * (e + u < e1 ? e + u : e));
         f[u][0] = r[0];
         f[u][1] = r[1];
-        f[u][2] = r[2];
+        f[u][2] = r[3];
+        f[u][3] = r[4];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -1570,9 +1572,9 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
           F[0] += f[u][0].x;
           F[1] += f[u][0].y;
           F[2] += f[u][1].x;
-          T[0] += f[u][1].y;
-          T[1] += f[u][2].x;
-          T[2] += f[u][2].y;
+          T[0] += f[u][2].x;
+          T[1] += f[u][2].y;
+          T[2] += f[u][3].x;
         }
       }
     }
@@ -1596,20 +1598,19 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
       SDEM_CX(2, 4) SDEM_CX(3, 5)
       SDEM_CX(3, 4)
 #undef SDEM_CX
-      // force on the owner (doubles 0..2) and torque on the partner (6..8),
-      // four records in flight
+      // force on the owner and torque on the partner: the first six doubles
+      // of a record, four records in flight
 #pragma unroll
       for (int j0 = 0; j0 < 8; j0 += 4) {
         if (j0 >= m) break;
-        double2 g[4][4];
+        double2 g[4][3];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (j0 + u < m) {
             const double2* r = reinterpret_cast<const double2*>(res + (size_t)kRes * ke[j0 + u]);
             g[u][0] = r[0];
             g[u][1] = r[1];
-            g[u][2] = r[3];
-            g[u][3] = r[4];
+            g[u][2] = r[2];
           }
         }
 #pragma unroll
@@ -1618,9 +1619,9 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
             F[0] -= g[u][0].x;
             F[1] -= g[u][0].y;
             F[2] -= g[u][1].x;
-            T[0] += g[u][2].x;
-            T[1] += g[u][2].y;
-            T[2] += g[u][3].x;
+            T[0] += g[u][1].y;
+            T[1] += g[u][2].x;
+            T[2] += g[u][2].y;
           }
         }
       }
@@ -1641,7 +1642,7 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           F[k] -= r[k];
-          T[k] += r[6 + k];
+          T[k] += r[3 + k];
         }
       }
     }

@@ -176,7 +176,8 @@ struct Ctx {
                       // rebuild (-1: more than kCand, search the cells)
   int32_t* vlist;     // [n * lanes][kCand] their slots, in search order
   double* res;        // [cap][kRes] per contact: force on the owner (3), torque
-                      // on the owner (3), torque on the partner (3), pad
+                      // on the partner (3), torque on the owner (3), pad (the
+                      // partner's part first: it is gathered, the owner's streamed)
   double* F;          // [3][n] contact force of the last step, by slot
   double* T;          // [3][n] contact torque of the last step, by slot
   double* tri_ref;    // [ntri][9] element vertices at t = 0 (see closest_on_element)
