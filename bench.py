@@ -247,8 +247,9 @@ def main():
                     help="also run a plain device copy of this size (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has "
+              "no multi-GPU path (batched simulations would shard by simulation, one large "
+              "system by slabs with halo exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch

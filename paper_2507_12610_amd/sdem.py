@@ -93,7 +93,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2507_12610_amd/build.py")
         L = C.CDLL(LIB_PATH)
         L.sdem_workspace_bytes.restype = C.c_size_t
         L.sdem_workspace_bytes.argtypes = [C.POINTER(Config)]
