@@ -75,6 +75,45 @@ def cpu_baseline(w, budget_s=12.0, max_steps=40):
                       f"{total:.1f} s"}
 
 
+CPU_CHILD = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+import workloads as W
+w = W.cfg2()
+o = oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"], tri=w["tri"],
+               rmesh=w["rmesh"])
+steps = int(sys.argv[2])
+t0 = time.perf_counter()
+o.step(steps)
+print(json.dumps({"n": len(w["R"]), "steps": steps, "s": time.perf_counter() - t0}))
+"""
+
+
+def cpu_all_cores(steps=3, max_procs=16):
+    """The same serial oracle in one process per host core (at most 16, the
+    host share of one GPU), each stepping its own copy of the workload:
+    whole-host throughput = all their particle-steps over the slowest one's
+    time.  Child processes, started fresh (never forked from this one)."""
+    import subprocess
+    k = max(1, min(max_procs, os.cpu_count() or 1))
+    procs = [subprocess.Popen([sys.executable, "-c", CPU_CHILD, ROOT, str(steps)],
+                              stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
+             for _ in range(k)]
+    res = []
+    for p in procs:
+        out, _ = p.communicate(timeout=900)
+        if p.returncode == 0:
+            res.append(json.loads(out.strip().splitlines()[-1]))
+    if not res:
+        return None
+    n, slowest = res[0]["n"], max(r["s"] for r in res)
+    return {"value": len(res) * n * steps / slowest, "unit": "particle-steps/s", "cores": len(res),
+            "kind": "oracle",
+            "sample": f"first {steps} steps of the same workload (N={n}) in {len(res)} serial "
+                      f"FP64 oracle processes at once, slowest {slowest:.1f} s"}
+
+
 def sim_slice(w, st, c, lo, hi):
     """Workload dict of particles [lo, hi) of a batched state, with its contacts
     (keys made local) for sdem_set_history."""
@@ -372,6 +411,8 @@ def main():
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
+        print("[bench] timing the CPU oracle on every host core", file=sys.stderr, flush=True)
+        out["cpu_all_cores"] = cpu_all_cores()
     print(json.dumps(out), flush=True)
 
 
