@@ -35,16 +35,25 @@ def force_bytes(n, c):
     return 128.0 * n + 120.0 * c
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_force_cfg2_column_200k_hbm_traffic.md")
+# bench workloads: the headline column, and the 8M packing whose state is
+# far larger than the 256 MB Infinity Cache; each with its counter summary
+# and its settings when none are given (None: autotuned)
+WORKLOADS = {
+    "column_200k": {"make": "cfg2", "radii": "lognormal, median 1 mm, sigma 0.2",
+                    "traffic": "k_force_cfg2_column_200k_hbm_traffic.md", "settings": None},
+    "packing_8M": {"make": "cfg5", "radii": "half 1.0 mm, half 1.4 mm (rock-salt lattice)",
+                   "traffic": "k_force_cfg5_packing_8M_hbm_traffic.md",
+                   "settings": (1.0, 1, 0.05)},
+}
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """HBM bytes per contact-force launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when
     the kernel source changed since those counters were taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(os.path.join(ROOT, "profiles", WORKLOADS[workload]["traffic"])).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and
@@ -282,6 +291,8 @@ def main():
                     help="skip the mixed-precision and batched forms")
     ap.add_argument("--batch-landing-steps", type=int, default=1500)
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="column_200k",
+                    help="column_200k (the headline configuration) or packing_8M")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -308,12 +319,18 @@ def main():
         print(f"[bench] copy calibration: 3 copies of {nb} bytes", file=sys.stderr, flush=True)
         del src, dst
 
-    w = W.cfg2()
+    spec = WORKLOADS[args.workload]
+    w = getattr(W, spec["make"])()
     n = len(w["R"])
     print(f"[bench] workload {w['name']}: N={n}, {len(w['tri'])} triangles", file=sys.stderr,
           flush=True)
     tuned = None
-    if args.cell_factor is None or args.detect_lanes is None or args.skin is None:
+    if spec["settings"] is not None:
+        fixed = spec["settings"]
+        cf, lanes, skin = (fixed[0] if args.cell_factor is None else args.cell_factor,
+                           fixed[1] if args.detect_lanes is None else args.detect_lanes,
+                           fixed[2] if args.skin is None else args.skin)
+    elif args.cell_factor is None or args.detect_lanes is None or args.skin is None:
         # trials of three rebuild periods: a thin skin looks fast over a few
         # steps and loses once particles drift past it
         best, timings = autotune(w, candidates=TUNE_CANDIDATES, steps=192, warmup=10,
@@ -350,7 +367,7 @@ def main():
     dominant = max((k for k in phases if k != "force_kernel"), key=phases.get)
     roofline = {"kernel": "k_force (contact forces, torques, spring carry-over)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
                 "mean_ms": round(fms, 5), "algorithmic_bytes": force_bytes(n, c_prof),
                 "contacts_per_launch": round(c_prof, 1),
                 "phase_ms": {k: round(v, 5) for k, v in phases.items() if k != "force_kernel"},
@@ -363,7 +380,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": w["name"], "particles": n, "triangles": len(w["tri"]),
                       "dt": w["params"]["dt"], "precision": args.precision,
-                      "radii": "lognormal, median 1 mm, sigma 0.2",
+                      "radii": spec["radii"],
                       "friction": [w["params"]["mu_s"], w["params"]["mu_r"], w["params"]["mu_t"]],
                       "cell_factor": cf, "detect_lanes": lanes, "skin": skin,
                       "cell_rebuilds": f"{st1['rebuilds'] - st0['rebuilds']} of {args.steps} steps"},
@@ -406,7 +423,8 @@ def main():
                 "workload": w["name"], "ms_per_step": round(ms_rb, 5),
                 "particle_steps_per_s": round(n * 1e3 / ms_rb, 1)}
         forms["batched"] = batched_forms(args.batch_landing_steps, args.batch_steps)
-        forms["packing_8M"] = packing_forms()
+        if args.workload != "packing_8M":
+            forms["packing_8M"] = packing_forms()
         out["forms"] = forms
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

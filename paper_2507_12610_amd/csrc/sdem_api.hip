@@ -1084,22 +1084,34 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
   HIP_TRY(hipMemcpyAsync(&before, X->c.ctr, sizeof before, hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipStreamSynchronize(X->stream));
   const int start = X->cur;
+  unsigned long long drift0 = before.drift_steps;
   hipError_t err = hipSuccess;
   for (int64_t i = 0; i < nsteps && !err; ++i) {
+    // the same rebuild decisions as sdem_step: the period adapted at its
+    // end, and large contexts look at the drift flag after each kept step
+    int rc = SDEM_OK;
     if (spawning(X)) {
       bool stop = false;
-      const int rc = spawn_now(X, &stop);
-      if (rc) {
-        for (int k = 0; k < kEvents; ++k) (void)hipEventDestroy(ev[k]);
-        return rc;
-      }
-      if (stop) break;
+      rc = spawn_now(X, &stop);
+      if (!rc && stop) break;
+    }
+    if (!rc && X->c.skin_on && X->since >= X->period && X->since > 0) rc = adapt_period(X, &drift0);
+    if (rc) {
+      for (int k = 0; k < kEvents; ++k) (void)hipEventDestroy(ev[k]);
+      return rc;
     }
     const bool rb = rebuild_now(X);
     err = enqueue_steps(X, 1, rb, ev);
     count_step(X, rb);
     X->cur ^= 1;
     if (!err) err = hipEventSynchronize(ev[kPhases]);
+    if (!err && X->c.skin_on && !rb && X->n >= kDriftCheckEachStep && !spawning(X)) {
+      int32_t next = 0;
+      err = hipMemcpyAsync(&next, &X->c.ctr->rebuild_next, sizeof next, hipMemcpyDeviceToHost,
+                           X->stream);
+      if (!err) err = hipStreamSynchronize(X->stream);
+      if (!err && next) X->need_rebuild = true;
+    }
     for (int k = 0; k < kPhases && !err; ++k) {
       float ms = 0.f;
       err = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);

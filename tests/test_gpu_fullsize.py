@@ -170,4 +170,14 @@ def test_packing_8M_sampled(packing, precision, tol, skin):
     assert max(err.values()) < tol, err
     if skin > 0:
         assert g.stats()["rebuilds"] >= 2
+        # steps timed phase by phase see the drift flag after each step too
+        r0 = g.stats()["rebuilds"]
+        h = solver(w, precision=precision, cell_factor=1.0, detect_lanes=1, skin=skin)
+        for k in (1, 49, 1):  # the calls g took
+            h.step_profiled(k)
+        assert h.stats()["rebuilds"] == r0
+        sh, sg = h.state(forces=False), g.state(forces=False)
+        for k in ("x", "v", "w", "q"):
+            assert np.array_equal(sh[k], sg[k]), k
+        h.close()
     g.close()

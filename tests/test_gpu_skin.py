@@ -142,3 +142,23 @@ def test_drift_past_the_skin_within_one_call():
     # the next call starts with a rebuild and stays exact
     check_resync(g, w, every=10, checks=3, t0=60 * w["params"]["dt"])
     assert g.stats()["rebuilds"] >= 2
+
+
+def test_profiled_steps_rebuild_like_plain_steps():
+    """Steps timed phase by phase take the same rebuild decisions as plain
+    steps (period adapted at its end, drift past the skin seen): the same
+    rebuild count and the same state bit for bit after 300 steps."""
+    tri = W.cube_mesh([-0.2e-3] * 3, [18.2e-3] * 3)
+    w = W.random_cluster(600, 41, box=18e-3, overlap=0.2, r_lo=0.4e-3, r_hi=1.4e-3, vel=0.5,
+                         spin=200.0, tri=tri)
+    w["params"].update(g=(0.0, 0.0, -9.81), dt=2e-6)
+    a = solver(w, cell_factor=0.5, detect_lanes=1, skin=0.02)
+    b = solver(w, cell_factor=0.5, detect_lanes=1, skin=0.02)
+    a.step(300)
+    ph = b.step_profiled(300)
+    assert all(v >= 0.0 for v in ph.values())
+    ra, rb = a.stats()["rebuilds"], b.stats()["rebuilds"]
+    assert ra == rb and 10 < ra < 300, (ra, rb)
+    sa, sb = a.state(), b.state()
+    for k in ("x", "v", "w", "q", "F", "T"):
+        assert np.array_equal(sa[k], sb[k]), k
