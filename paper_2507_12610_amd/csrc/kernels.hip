@@ -1105,7 +1105,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
                                                       Contacts old, int rebuilt) {
   const State S = rebuilt ? B : A;
   const int tid = (int)threadIdx.x;
-  // one workgroup per slot group (consecutive groups on one XCD share its L2)
+  // one workgroup per slot group (on grids of one round, consecutive groups
+  // share an XCD and its L2)
   const int grp = xcd_remap(blockIdx.x, gridDim.x);
   const int gbase = grp * c.gcap;
   // loads that depend on nothing else, issued together: this lane's record
@@ -1508,7 +1509,7 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
   // kept) and writes the new state to B
   const State S = rebuilt ? B : A;
   const int n = c.n;
-  const int i0 = blockIdx.x * kThreads;
+  const int i0 = xcd_remap(blockIdx.x, gridDim.x) * kThreads;
   const int i = i0 + (int)threadIdx.x;
   // The particle's own state and contact counts are loaded before the
   // failure flag is examined (a step after a failed one exits here): these

@@ -201,9 +201,18 @@ struct Ctx {
                             // something, per candidate (bits of a double >= 0)
 };
 
+// Grids up to this many workgroups are resident all at once (four per CU
+// on 256 CUs).
+constexpr int kOneRoundBlocks = 1024;
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
-  // The dispatcher hands workgroup b to XCD b % 8; give each XCD one
-  // contiguous range of logical blocks so that neighbouring slots share an L2.
+  // The dispatcher hands workgroup b to XCD b % 8.  When the whole grid is
+  // resident at once, each XCD gets one contiguous range of logical blocks,
+  // so that its L2 holds one share of the slots and their neighbours (200k
+  // spheres: 3 % faster steps).  Larger grids keep the dispatch order, in
+  // which all XCDs sweep the same region of the sorted state together
+  // (8M spheres: 2 % faster steps than with contiguous ranges).
+  if (nb > kOneRoundBlocks) return b;
   const int q = nb >> 3, r = nb & 7;
   const int xcd = b & 7, idx = b >> 3;
   return xcd * q + (xcd < r ? xcd : r) + idx;
