@@ -9,9 +9,11 @@ sort and state reorder, narrow phase, contact forces with spring carry-over,
 integration.  The state is resident in HBM before timing starts.
 
 Prints one JSON line: particle-steps/s (value) and contacts/s, the roofline
-of the contact-force kernel (algorithmic bytes 128 N + 120 C per launch over
-its mean duration, timed with HIP events on the solver's stream), and the
-CPU oracle timed on a bounded sample of the same workload.
+of the kernel that computes the contact law on steps that keep the cells
+(the fused narrow phase and contact law on grids of at most 1,024 slot groups,
+128 N + 128 C algorithmic bytes per launch; else the contact-force kernel,
+128 N + 120 C) over its mean duration, timed with HIP events on its own
+dispatch, and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -35,12 +37,25 @@ def force_bytes(n, c):
     return 128.0 * n + 120.0 * c
 
 
+def fused_bytes(n, c):
+    """Algorithmic HBM bytes of one launch of the fused narrow phase and
+    contact law: those of the contact-force kernel, with the pair record and
+    the partner-list entry written per contact (16 B) in place of the pair
+    read."""
+    return 128.0 * n + 128.0 * c
+
+
+# grids of at most this many slot groups of 256 run the narrow phase and the
+# contact law in one kernel on steps that keep the cells (one search lane)
+ONE_ROUND_GROUPS = 1024
+
+
 # bench workloads: the headline column, and the 8M packing whose state is
 # far larger than the 256 MB Infinity Cache; each with its counter summary
 # and its settings when none are given (None: autotuned)
 WORKLOADS = {
     "column_200k": {"make": "cfg2", "radii": "lognormal, median 1 mm, sigma 0.2",
-                    "traffic": "k_force_cfg2_column_200k_hbm_traffic.md", "settings": None},
+                    "traffic": "k_detect_force_cfg2_column_200k_hbm_traffic.md", "settings": None},
     "packing_8M": {"make": "cfg5", "radii": "half 1.0 mm, half 1.4 mm (rock-salt lattice)",
                    "traffic": "k_force_cfg5_packing_8M_hbm_traffic.md",
                    "settings": (1.0, 1, 0.05)},
@@ -357,19 +372,39 @@ def main():
     print(f"[bench] {args.steps} steps in {wall:.3f} s, {contacts / args.steps:.0f} contacts/step",
           file=sys.stderr, flush=True)
 
-    # per-phase times with HIP events (no graph) on the solver's stream
-    st2 = s.stats()
-    phases = s.step_profiled(args.profile_steps)
-    st3 = s.stats()
-    c_prof = ((st3["pp"] - st2["pp"]) + (st3["pw"] - st2["pw"])) / args.profile_steps
-    fms = phases["force_kernel"]  # start/stop events attached to the force kernel's dispatch
-    achieved = force_bytes(n, c_prof) / (fms * 1e-3) / 1e9
+    # per-phase times with HIP events (no graph) on the solver's stream, one
+    # step at a time so that the steps that rebuild the cells are told apart
+    prof = []
+    for _ in range(args.profile_steps):
+        a = s.stats()
+        ph = s.step_profiled(1)
+        b = s.stats()
+        prof.append((b["rebuilds"] > a["rebuilds"], ph, (b["pp"] - a["pp"]) + (b["pw"] - a["pw"])))
+    keep = [p for p in prof if not p[0]] or prof
+    phases = {k: sum(p[1][k] for p in prof) / len(prof) for k in prof[0][1]}
+    # start/stop events attached to the dispatch of the kernel in the force
+    # phase, over the steps that keep the cells (the timed steps are such
+    # steps but for a few rebuilds)
+    fms = sum(p[1]["force_kernel"] for p in keep) / len(keep)
+    c_prof = sum(p[2] for p in keep) / len(keep)
+    fused = skin > 0 and lanes == 1 and -(-n // 256) <= ONE_ROUND_GROUPS
+    if fused:
+        # the search ran inside the force phase: its own phase is as empty as
+        # the sort phase of a step that keeps the cells (two events in a row)
+        assert all(p[1]["detect"] < p[1]["sort"] + 3e-3 for p in keep), "narrow phase not fused"
+        kname = "k_detect_force (narrow phase, contact law, spring carry-over)"
+        alg = fused_bytes(n, c_prof)
+    else:
+        kname = "k_force (contact forces, torques, spring carry-over)"
+        alg = force_bytes(n, c_prof)
+    achieved = alg / (fms * 1e-3) / 1e9
     dominant = max((k for k in phases if k != "force_kernel"), key=phases.get)
-    roofline = {"kernel": "k_force (contact forces, torques, spring carry-over)", "bound": "hbm",
+    roofline = {"kernel": kname, "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
-                "mean_ms": round(fms, 5), "algorithmic_bytes": force_bytes(n, c_prof),
+                "mean_ms": round(fms, 5), "algorithmic_bytes": alg,
                 "contacts_per_launch": round(c_prof, 1),
+                "launches_timed": len(keep),
                 "phase_ms": {k: round(v, 5) for k, v in phases.items() if k != "force_kernel"},
                 "dominant_phase": dominant}
 

@@ -708,14 +708,22 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
 //    per wave reserves the wave's records.  Pair records are also entered in
 //    the partner's list (one integer atomic per pair).
 // ---------------------------------------------------------------------------
-template <int SUB>
-__global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Contacts cn,
-                                                    int rebuilt) {
+// The search of logical block blk.  LDS comes from the caller: the hit lists,
+// the drift reach per simulation, a reduction buffer and the wave totals.
+// With FUSED (one lane per slot), the group's first kThreads records are also
+// left in LDS (rec_a: owner slot within the group, rec_b: partner).  Returns
+// the group's record count (one lane per slot; 0 otherwise), or -1 when an
+// earlier failure is flagged.
+template <int SUB, bool FUSED>
+__device__ __forceinline__ int detect_group(const Ctx& c, const State& A, const State& B,
+                                            const Contacts& cn, const int rebuilt, const int blk,
+                                            int (*hits)[kMaxOwn][64], double* xdrift, double* red,
+                                            int* wtots, unsigned char* rec_a, int* rec_b) {
   // the sorted copy when this step rebuilt the cells, else the kept order
   const State S = rebuilt ? B : A;
   const int n = c.n;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int bg = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x;
+  const int bg = blk * kThreads;
   const int g = bg + threadIdx.x;
   const int s = g / SUB, sub = g % SUB;
   // The own centre, simulation and candidate list head are loaded before the
@@ -733,20 +741,23 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
       for (int u = 0; u < 4; ++u) vraw[u] = c.vlist[(size_t)g * kCand + u];
     }
   }
-  if (c.ctr->flags) return;
+  // A wave that sees a failure flagged searches nothing.  Another workgroup
+  // may raise a flag while this one starts, so with one lane per slot a
+  // wave that sees it still posts a zero total for the workgroup's record
+  // offsets before it leaves: the records of the waves that go on stay
+  // consistent (the step is failed and repeated anyway).
+  const bool dead = c.ctr->flags != 0;
+  if (dead && SUB != 1) return -1;
   // a step that keeps the cells starts here (and is counted if its searches
   // must reach past the skin)
-  if (!rebuilt && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (!rebuilt && !dead && blockIdx.x == 0 && threadIdx.x == 0) {
     atomicAdd(&c.ctr->steps, 1ull);
     if (c.ctr->rebuild_next) c.ctr->drift_steps += 1ull;
   }
-  __shared__ int hits[kThreads / 64][kMaxOwn][64];
   // If a particle drifted past half the skin since the cells were built,
   // every search of this step reaches by the excess further: the largest
   // drift of each simulation of this workgroup, from the integration's
   // per-wave partials (a rare step; the others skip this).
-  __shared__ double xdrift[kThreads];
-  __shared__ double red[kThreads / 64];
   int sim_lo = 0;
   if (!rebuilt && c.ctr->rebuild_next && bg / SUB < n) {
     sim_lo = c.sim_of[bg / SUB];
@@ -769,7 +780,7 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
     __syncthreads();
   }
   int npp = 0, npw = 0;
-  if (s < n) {
+  if (s < n && !dead) {
     const SimGrid gr = c.sg[sim];
     const double extra = (!rebuilt && c.ctr->rebuild_next) ? xdrift[sim - sim_lo] : 0.0;
     const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
@@ -971,19 +982,18 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
   const int incl = wave_incl_scan(mine, lane);
   const int wtot = __shfl(incl, 63, 64);
   const int grp = __shfl(g / SUB, 0, 64) >> kGroupShift;
-  int base = 0;
+  int base = 0, tot = 0;
   if (SUB == 1) {
     // one lane per slot: the workgroup is the slot group, so the waves'
     // offsets come from a scan of their totals, in slot order
-    __shared__ int wtots[kThreads / 64];
     if (lane == 63) wtots[wv] = wtot;
     __syncthreads();
-    int tot = 0;
     for (int w = 0; w < kThreads / 64; ++w) {
       if (w < wv) base += wtots[w];
       tot += wtots[w];
     }
-    if (threadIdx.x == 0 && grp < c.ngroups) c.gcnt[grp] = tot;
+    if (threadIdx.x == 0 && grp < c.ngroups && !dead) c.gcnt[grp] = tot;
+    if (dead) return -1;
   } else {
     if (lane == 63 && wtot > 0 && grp < c.ngroups) base = atomicAdd(&c.gcnt[grp], wtot);
     base = __shfl(base, 63, 64);
@@ -1011,6 +1021,11 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
         if (k0 + u < mine) {
           cn.a[first + k0 + u] = s;
           cn.b[first + k0 + u] = tk[u];
+          const int l = base + incl - mine + k0 + u;  // record within the group
+          if (FUSED && l < kThreads) {
+            rec_a[l] = (unsigned char)(s - bg);
+            rec_b[l] = tk[u];
+          }
         }
       }
       // the partner-list places of up to four pairs are reserved together
@@ -1026,6 +1041,18 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
       }
     }
   }
+  return tot;
+}
+
+template <int SUB>
+__global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Contacts cn,
+                                                    int rebuilt) {
+  __shared__ int hits[kThreads / 64][kMaxOwn][64];
+  __shared__ double xdrift[kThreads];
+  __shared__ double red[kThreads / 64];
+  __shared__ int wtots[kThreads / 64];
+  (void)detect_group<SUB, false>(c, A, B, cn, rebuilt, xcd_remap(blockIdx.x, gridDim.x), hits,
+                                 xdrift, red, wtots, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1100,35 +1127,22 @@ __device__ __forceinline__ int find_old(const Contacts& co, int b0, int n, int2 
   return -1;
 }
 
+// The contact law over the cnt records of slot group grp (the lane's record
+// of the first pass in ra, rb; ng: the group's previous record count).  The
+// spring and result records of one pass are staged in LDS (st_spr, st_res)
+// and written out as contiguous runs (per-lane 64- and 80-byte records
+// written directly would make every store instruction scatter); okey and red
+// are LDS for the previous keys and the contact counts.
 template <typename RT>
-__global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, Contacts cur,
-                                                      Contacts old, int rebuilt) {
-  const State S = rebuilt ? B : A;
+__device__ __forceinline__ void force_group(const Ctx& c, const State& S, const Contacts& cur,
+                                            const Contacts& old, const int rebuilt, const int grp,
+                                            const int ra, const int rb, const int ng,
+                                            const int cnt, double2* st_spr, double2* st_res,
+                                            int2* okey, int (*red)[kThreads / 64]) {
   const int tid = (int)threadIdx.x;
-  // one workgroup per slot group (on grids of one round, consecutive groups
-  // share an XCD and its L2)
-  const int grp = xcd_remap(blockIdx.x, gridDim.x);
   const int gbase = grp * c.gcap;
-  // loads that depend on nothing else, issued together: this lane's record
-  // of the first pass, the group's record count and, when the slot order was
-  // kept, the group's previous record count
-  int ra = 0, rb = 0;
-  if (tid < c.gcap) {
-    ra = cur.a[gbase + tid];
-    rb = cur.b[gbase + tid];
-  }
-  const int ng = rebuilt ? 0 : old.ng[grp];
-  const int cnt = min(c.gcnt[grp], c.gcap);
-  // (the failure flag is examined once these loads are in flight; the
-  // records are only followed after it)
-  if (c.ctr->flags) return;
   if (tid == 0) cur.ng[grp] = cnt;
   int npp = 0, npw = 0;
-  // the spring and result records of one pass are staged in LDS and written
-  // out as contiguous runs (per-lane 64- and 80-byte records written
-  // directly would make every store instruction scatter)
-  __shared__ double2 st_spr[kThreads * kSpr / 2];
-  __shared__ double2 st_res[kThreads * kRes / 2];
   // The contact law of one record (body I carries the lower id): the updated
   // springs are staged in LDS at this lane's place, the forces and torques
   // returned in o.
@@ -1282,7 +1296,6 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
     // slot of this group).  Two rounds of dependent loads instead of four.
     // The previous springs are held in the result staging buffer, which the
     // law's results overwrite only after every lane has read its springs.
-    __shared__ int2 okey[kThreads];
     const bool act = tid < cnt;
     const int on = min(ng, kThreads);
     if (tid < on) {
@@ -1449,7 +1462,6 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
   }
   // contact counts of the group for the statistics (summed by the next step's
   // grid kernel or by the host)
-  __shared__ int red[2][kThreads / 64];
   const int a = wave_sum_i32(npp), b = wave_sum_i32(npw);
   if ((threadIdx.x & 63) == 0) {
     red[0][threadIdx.x >> 6] = a;
@@ -1467,6 +1479,73 @@ __global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, 
     atomicAdd(&c.gstat[2 * grp], (unsigned long long)ta);
     atomicAdd(&c.gstat[2 * grp + 1], (unsigned long long)tb);
   }
+}
+
+template <typename RT>
+__global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, Contacts cur,
+                                                      Contacts old, int rebuilt) {
+  const State S = rebuilt ? B : A;
+  const int tid = (int)threadIdx.x;
+  // one workgroup per slot group (on grids of one round, consecutive groups
+  // share an XCD and its L2)
+  const int grp = xcd_remap(blockIdx.x, gridDim.x);
+  const int gbase = grp * c.gcap;
+  // loads that depend on nothing else, issued together: this lane's record
+  // of the first pass, the group's record count and, when the slot order was
+  // kept, the group's previous record count
+  int ra = 0, rb = 0;
+  if (tid < c.gcap) {
+    ra = cur.a[gbase + tid];
+    rb = cur.b[gbase + tid];
+  }
+  const int ng = rebuilt ? 0 : old.ng[grp];
+  const int cnt = min(c.gcnt[grp], c.gcap);
+  // (the failure flag is examined once these loads are in flight; the
+  // records are only followed after it)
+  if (c.ctr->flags) return;
+  __shared__ double2 st_spr[kThreads * kSpr / 2];
+  __shared__ double2 st_res[kThreads * kRes / 2];
+  __shared__ int2 okey[kThreads];
+  __shared__ int red[2][kThreads / 64];
+  force_group<RT>(c, S, cur, old, rebuilt, grp, ra, rb, ng, cnt, st_spr, st_res, okey, red);
+}
+
+// The search and the contact law of one slot group in one workgroup, for
+// steps that keep the cells with one search lane per slot: the group's
+// records reach the law through LDS (no second launch, no reload of the
+// records), and the law's staging reuses the search's LDS (hit lists, drift
+// reach), which is dead once the records are written.
+template <typename RT>
+__global__ __launch_bounds__(kThreads, 4) void k_detect_force(Ctx c, State A, State B,
+                                                             Contacts cn, Contacts old) {
+  constexpr int kHits2 = (kThreads / 64) * kMaxOwn * 64 * (int)sizeof(int) / 16;
+  constexpr int kSearch2 = kHits2 + kThreads * (int)sizeof(double) / 16;
+  constexpr int kLaw2 = kThreads * (kSpr + kRes) / 2;
+  __shared__ double2 pool[kLaw2 > kSearch2 ? kLaw2 : kSearch2];
+  __shared__ int2 okey[kThreads];
+  __shared__ int rec_b[kThreads];
+  __shared__ unsigned char rec_a[kThreads];
+  __shared__ double red_d[kThreads / 64];
+  __shared__ int wtots[kThreads / 64];
+  __shared__ int red_i[2][kThreads / 64];
+  const int grp = xcd_remap(blockIdx.x, gridDim.x);
+  const int ng = old.ng[grp];
+  const int tot = detect_group<1, true>(c, A, B, cn, 0, grp,
+                                        reinterpret_cast<int(*)[kMaxOwn][64]>(pool),
+                                        reinterpret_cast<double*>(pool + kHits2), red_d, wtots,
+                                        rec_a, rec_b);
+  // no forces after a flagged failure, or when this group's records did not
+  // fit (flagged by the search: the step is repeated with more room)
+  if (tot < 0 || tot > c.gcap) return;
+  __syncthreads();  // the records are in LDS and global memory; the hit lists are dead
+  const int tid = (int)threadIdx.x;
+  int ra = 0, rb = 0;
+  if (tid < tot) {
+    ra = grp * kThreads + rec_a[tid];
+    rb = rec_b[tid];
+  }
+  force_group<RT>(c, A, cn, old, 0, grp, ra, rb, ng, tot, pool, pool + kThreads * kSpr / 2, okey,
+                  red_i);
 }
 
 // ---------------------------------------------------------------------------
@@ -1838,14 +1917,33 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
     (void)launch_mesh_bins(c, s);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
-  switch (c.detect_sub) {
+  // A step that keeps the cells with one search lane per slot runs the
+  // search and the contact law in one kernel (in the force phase) when the
+  // grid is resident in one round: there the second launch and the records'
+  // round trip weigh (200k spheres: 3.4 us of 31 saved).  On larger grids the
+  // two kernels are faster (8M spheres: 2.38 ms against 2.42 ms fused).
+  const bool fused = !rebuild && c.detect_sub == 1 && c.ngroups <= kOneRoundBlocks;
+  if (!fused) switch (c.detect_sub) {
     case 1: k_detect<1><<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
     case 2: k_detect<2><<<blocks_for(2 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
     case 8: k_detect<8><<<blocks_for(8 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
     default: k_detect<4><<<blocks_for(4 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
   }
   if (ev) (void)hipEventRecord(ev[3], s);
-  if (ev) {
+  if (fused && ev) {
+    // profiled: the dispatch itself records start and stop of the kernel
+    const dim3 grid(c.ngroups), block(kThreads);
+    if (precision == SDEM_MIXED)
+      hipExtLaunchKernelGGL(k_detect_force<float>, grid, block, 0, s, ev[kPhases + 1],
+                            ev[kPhases + 2], 0, c, A, B, cnew, cold);
+    else
+      hipExtLaunchKernelGGL(k_detect_force<double>, grid, block, 0, s, ev[kPhases + 1],
+                            ev[kPhases + 2], 0, c, A, B, cnew, cold);
+  } else if (fused && precision == SDEM_MIXED) {
+    k_detect_force<float><<<c.ngroups, kThreads, 0, s>>>(c, A, B, cnew, cold);
+  } else if (fused) {
+    k_detect_force<double><<<c.ngroups, kThreads, 0, s>>>(c, A, B, cnew, cold);
+  } else if (ev) {
     // profiled: the dispatch itself records start and stop of the kernel
     if (precision == SDEM_MIXED)
       hipExtLaunchKernelGGL(k_force<float>, dim3(c.ngroups), dim3(kThreads), 0, s, ev[kPhases + 1],
