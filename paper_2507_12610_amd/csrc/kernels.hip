@@ -738,7 +738,7 @@ __device__ __forceinline__ int detect_group(const Ctx& c, const State& A, const 
     if (c.skin_on && !rebuilt) {
       vcnt0 = c.vcnt[g];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) vraw[u] = c.vlist[(size_t)g * kCand + u];
+      for (int u = 0; u < 4; ++u) vraw[u] = c.vlist[(size_t)u * c.vstride + g];
     }
   }
   // A wave that sees a failure flagged searches nothing.  Another workgroup
@@ -792,7 +792,8 @@ __device__ __forceinline__ int detect_group(const Ctx& c, const State& A, const 
     const bool listed = c.skin_on && !rebuilt && extra == 0.0;
     const bool record = c.skin_on && rebuilt;
     const bool tri_listed = !c.sp[sim].moving;
-    int* vl = c.vlist + (size_t)g * kCand;
+    // entry k of this lane's candidate list
+    auto vl = [&](int k) -> int& { return c.vlist[(size_t)k * c.vstride + g]; };
     const int nlist = listed ? vcnt0 : -1;
     int ncand = 0;
     auto test_wall = [&](int m) {
@@ -842,7 +843,7 @@ __device__ __forceinline__ int detect_group(const Ctx& c, const State& A, const 
         if (fabs(pd) > reach * (1.0 + 1e-9) + 1e-300) continue;
         const double d = test_wall(m);
         if (rec_tri && d <= reach * (1.0 + 1e-9)) {
-          if (ncand < kCand) vl[ncand] = -1 - m;
+          if (ncand < kCand) vl(ncand) = -1 - m;
           ++ncand;
         }
       }
@@ -862,7 +863,7 @@ __device__ __forceinline__ int detect_group(const Ctx& c, const State& A, const 
 #pragma unroll
         for (int u = 0; u < 4; ++u) pt[u] = S.xr[tt[u] >= 0 ? tt[u] : s];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) tn[u] = k + 4 + u < nlist ? vl[k + 4 + u] : s;
+        for (int u = 0; u < 4; ++u) tn[u] = k + 4 + u < nlist ? vl(k + 4 + u) : s;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (k + u >= nlist) continue;
@@ -963,7 +964,7 @@ __device__ __forceinline__ int detect_group(const Ctx& c, const State& A, const 
             const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
             const double sr = (Rs + pt[u].w) + 2.0 * hsk;
             if ((ex * ex + ey * ey) + ez * ez <= sr * sr * (1.0 + 1e-9)) {
-              if (ncand < kCand) vl[ncand] = t + u;
+              if (ncand < kCand) vl(ncand) = t + u;
               ++ncand;
             }
           }

@@ -162,6 +162,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
     const size_t NL = cfg.skin > 0.0 ? N * lanes : 1;
     cc.vcnt = L.take<int32_t>(NL);
     cc.vlist = L.take<int32_t>(NL * kCand);
+    cc.vstride = (int64_t)NL;
   }
   cc.res = L.take<double>(kRes * Cm);
   cc.F = L.take<double>(3 * N);

@@ -174,7 +174,10 @@ struct Ctx {
   double4* xb;        // [n] centre when the cells were built (w unused)
   int32_t* vcnt;      // [n * lanes] candidates recorded by each search lane at the last
                       // rebuild (-1: more than kCand, search the cells)
-  int32_t* vlist;     // [n * lanes][kCand] their slots, in search order
+  int32_t* vlist;     // [kCand][vstride] their slots, in search order: entry k of
+                      // lane g at k * vstride + g (the first entries of a wave's
+                      // lanes are read together)
+  int64_t vstride;    // search lanes the candidate lists have room for
   double* res;        // [cap][kRes] per contact: force on the owner (3), torque
                       // on the partner (3), torque on the owner (3), pad (the
                       // partner's part first: it is gathered, the owner's streamed)
