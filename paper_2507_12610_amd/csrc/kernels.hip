@@ -1036,7 +1036,7 @@ __device__ __forceinline__ int detect_group(const Ctx& c, const State& A, const 
       for (int u = 0; u < 4; ++u) {
         if (tk[u] < 0) continue;
         if (rk[u] < kMaxRev)
-          c.plist[(size_t)tk[u] * kMaxRev + rk[u]] = make_int2(s, first + k0 + u);
+          c.plist[(size_t)rk[u] * c.pstride + tk[u]] = make_int2(s, first + k0 + u);
         else
           raise_flag(c.ctr, kFlagCapPerParticle);
       }
@@ -1625,12 +1625,12 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
     const int e1 = e0 + ne;
     const int m = min(pc, kMaxRev);
     c.pcnt[i] = 0;  // cleared for the next step's narrow phase
-    const int2* pl = c.plist + (size_t)i * kMaxRev;
+    auto pl = [&](int j) { return c.plist[(size_t)j * c.pstride + i]; };
     int ka[8], ke[8];
     if (m <= 8) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int2 v = j < m ? pl[j] : make_int2(0x7fffffff, -1);
+        const int2 v = j < m ? pl(j) : make_int2(0x7fffffff, -1);
         ka[j] = v.x;
         ke[j] = v.y;
       }
@@ -1711,7 +1711,7 @@ __global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B,
       for (int it = 0; it < m; ++it) {  // ascending owner slot
         int best = -1, ba = 0x7fffffff;
         for (int j = 0; j < m; ++j) {
-          const int2 v = pl[j];
+          const int2 v = pl(j);
           if (v.x > last && v.x < ba) {
             ba = v.x;
             best = v.y;

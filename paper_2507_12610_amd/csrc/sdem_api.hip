@@ -153,6 +153,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.gcnt = L.take<int32_t>(G);
   cc.gstat = L.take<unsigned long long>(2 * G);
   cc.plist = L.take<int2>(N * kMaxRev);
+  cc.pstride = (int64_t)N;
   cc.key = L.take<int32_t>(N);
   cc.os = L.take<int4>(N);
   cc.xb = L.take<double4>(N);

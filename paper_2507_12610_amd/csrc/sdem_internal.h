@@ -166,7 +166,10 @@ struct Ctx {
   int32_t* perm;      // [n] new slot -> previous slot (unstable within a cell)
   int32_t* scan_tmp;  // [kScanBlocks+1]
   int32_t* pcnt;      // [n] contacts in which the slot is the partner
-  int2* plist;        // [n][kMaxRev] those contacts: (owner slot, record)
+  int2* plist;        // [kMaxRev][pstride] those contacts: (owner slot, record);
+                      // entry k of slot i at k * pstride + i (the first entries
+                      // of a wave's slots are read together)
+  int64_t pstride;    // slots the partner lists have room for
   // per slot, written by the reorder at a rebuild and kept until the next:
   int32_t* key;       // [n] cell key
   int4* os;           // [n] (slot in the previous step's order, first and number of the
