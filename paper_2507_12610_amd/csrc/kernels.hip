@@ -1416,7 +1416,9 @@ __device__ __forceinline__ void force_group(const Ctx& c, const State& S, const 
         int m = 0;
         if (!wall) {
           pb = S.xr[b];
-          ob = origin(b);
+          // with the order kept the owner is the lower slot, so only the
+          // partner's id is needed
+          ob = rebuilt ? c.os[b] : make_int4(b, 0, 0, S.pid[b]);
           const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
           vb0 = vb[0];
           vb1 = vb[1];
