@@ -285,3 +285,36 @@ def test_contact_set_independent_of_cell_size(cf):
                          tri=W.cube_mesh([-0.2e-3] * 3, [18.2e-3] * 3))
     w["params"].update(g=(0.0, 0.0, -9.81))
     compare_one_step(w, cell_factor=cf)
+
+
+def test_contact_capacity_error_on_a_step_that_keeps_the_cells():
+    """One slot group (at most 256 spheres), cells kept between rebuilds and
+    one search lane, so steps that keep the cells run the search and the
+    contact law in one kernel: with room for exactly the most contacts of
+    the steps before, the first step that needs more, one that keeps the
+    cells, fails with ECAPACITY and leaves the previous step's state."""
+    from paper_2507_12610_amd import SdemError
+    w = W.random_cluster(220, 5, box=9e-3, overlap=0.1, r_lo=0.4e-3, r_hi=0.9e-3, vel=0.4,
+                         spin=50.0, tri=W.cube_mesh([-0.2e-3] * 3, [9.2e-3] * 3))
+    w["params"].update(g=(0.0, 0.0, -9.81), dt=2e-6)
+    kw = dict(cell_factor=0.5, detect_lanes=1, skin=0.3)
+    ref = solver(w, **kw)
+    counts, rebuilt, states = [], [], [ref.state(forces=False)["x"]]
+    for _ in range(300):
+        a = ref.stats()
+        ref.step(1)
+        b = ref.stats()
+        counts.append((b["pp"] - a["pp"]) + (b["pw"] - a["pw"]))
+        rebuilt.append(b["rebuilds"] > a["rebuilds"])
+        states.append(ref.state(forces=False)["x"])
+    t = next(t for t in range(1, len(counts))
+             if counts[t] > max(counts[:t]) and not rebuilt[t])
+    cap = max(counts[:t])
+    g = solver(w, contacts_max=cap, **kw)
+    for k in range(t):
+        g.step(1)
+    assert np.array_equal(g.state(forces=False)["x"], states[t])
+    with pytest.raises(SdemError) as ei:
+        g.step(1)
+    assert "ECAPACITY" in str(ei.value) and "contacts" in str(ei.value)
+    assert np.array_equal(g.state(forces=False)["x"], states[t])
