@@ -181,9 +181,11 @@ def mixed_vs_fp64(w, cf, lanes, skin, steps_before=200):
             "max_rel_diff": {k: float(f"{v:.3e}") for k, v in out.items()}}
 
 
-# (cell_factor, detect_lanes, skin) tried by the autotuner on the bench workload
-TUNE_CANDIDATES = [(0.4, 1, 0.05), (0.5, 1, 0.05), (0.33, 1, 0.05), (0.7, 1, 0.05), (0.4, 2, 0.05),
-                   (0.4, 1, 0.1), (0.4, 1, 0.02), (0.4, 1, 0.0)]
+# (cell_factor, detect_lanes, skin, longest rebuild period) tried by the
+# autotuner on the bench workload (0: the library's 64 steps)
+TUNE_CANDIDATES = [(0.4, 1, 0.05, 0), (0.33, 1, 0.05, 0), (0.5, 1, 0.05, 0), (0.4, 2, 0.05, 0),
+                   (0.4, 1, 0.1, 128), (0.4, 1, 0.1, 256), (0.33, 1, 0.1, 256), (0.5, 1, 0.1, 256),
+                   (0.4, 1, 0.2, 256), (0.4, 1, 0.0, 0)]
 
 
 # (cell_factor, detect_lanes, skin) tried for the 256 box drops (bouncier than the column)
@@ -302,6 +304,8 @@ def main():
                     help="lanes per particle in the contact search; default: autotuned")
     ap.add_argument("--skin", type=float, default=None,
                     help="cell skin in units of R_max (0: rebuild every step); default: autotuned")
+    ap.add_argument("--rebuild-every", type=int, default=0,
+                    help="longest rebuild period with a skin (0: 64); autotuned with the rest")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision and batched forms")
     ap.add_argument("--batch-landing-steps", type=int, default=1500)
@@ -345,18 +349,22 @@ def main():
         cf, lanes, skin = (fixed[0] if args.cell_factor is None else args.cell_factor,
                            fixed[1] if args.detect_lanes is None else args.detect_lanes,
                            fixed[2] if args.skin is None else args.skin)
+        every = args.rebuild_every
     elif args.cell_factor is None or args.detect_lanes is None or args.skin is None:
-        # trials of three rebuild periods: a thin skin looks fast over a few
-        # steps and loses once particles drift past it
-        best, timings = autotune(w, candidates=TUNE_CANDIDATES, steps=192, warmup=10,
+        # trials of 512 steps, two of the longest periods tried: a thin skin
+        # or a long period looks fast over a few steps and loses once
+        # particles drift past the skin
+        best, timings = autotune(w, candidates=TUNE_CANDIDATES, steps=512, warmup=10,
                                  precision=args.precision)
         tuned = {"chosen": best, "trials": timings}
         print(f"[bench] autotuned: {best}", file=sys.stderr, flush=True)
         cf, lanes, skin = best["cell_factor"], best["detect_lanes"], best["skin"]
+        every = best["rebuild_every"]
     else:
         cf, lanes, skin = args.cell_factor, args.detect_lanes, args.skin
+        every = args.rebuild_every
     s = Solver(w, precision=args.precision, device="cuda:0", cell_factor=cf, detect_lanes=lanes,
-               skin=skin)
+               skin=skin, rebuild_every=every)
     s.step(args.warmup)
     torch.cuda.synchronize()
     st0 = s.stats()
@@ -418,6 +426,7 @@ def main():
                       "radii": spec["radii"],
                       "friction": [w["params"]["mu_s"], w["params"]["mu_r"], w["params"]["mu_t"]],
                       "cell_factor": cf, "detect_lanes": lanes, "skin": skin,
+                      "rebuild_every": every if every > 0 else 64,
                       "cell_rebuilds": f"{st1['rebuilds'] - st0['rebuilds']} of {args.steps} steps"},
            "contacts_per_s": round(contacts / wall, 1),
            "contacts_per_step": round(contacts / args.steps, 1),
@@ -430,7 +439,7 @@ def main():
         forms = {}
         other = "mixed" if args.precision == "fp64" else "fp64"
         g = Solver(w, precision=other, device="cuda:0", cell_factor=cf, detect_lanes=lanes,
-                   skin=skin)
+                   skin=skin, rebuild_every=every)
         g.step(args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -171,10 +171,12 @@ def _grid_cells(x, h):
 def autotune(sims, candidates=None, steps=20, warmup=6, precision="fp64", device="cuda:0",
              **kw):
     """Picks the cell edge factor, the number of lanes per particle in the
-    contact search and the skin by timing a few steps of each candidate
-    (cell_factor, detect_lanes[, skin]) on the given workload (each trial runs
-    on its own copy of the state).  Returns (best, timings) with best =
-    {"cell_factor", "detect_lanes", "skin", "ms_per_step"}."""
+    contact search, the skin and the longest rebuild period by timing a few
+    steps of each candidate (cell_factor, detect_lanes[, skin[,
+    rebuild_every]]) on the given workload (each trial runs on its own copy of
+    the state; a trial should span several rebuild periods).  Returns (best,
+    timings) with best = {"cell_factor", "detect_lanes", "skin",
+    "rebuild_every", "ms_per_step"}."""
     import time
 
     import torch
@@ -184,8 +186,10 @@ def autotune(sims, candidates=None, steps=20, warmup=6, precision="fp64", device
     for cand in candidates:
         cf, lanes = cand[0], cand[1]
         skin = cand[2] if len(cand) > 2 else kw.get("skin", 0.0)
+        every = cand[3] if len(cand) > 3 else kw.get("rebuild_every", 0)
         opts = dict(kw)
         opts["skin"] = skin
+        opts["rebuild_every"] = every
         s = Solver(sims, precision=precision, device=device, cell_factor=cf, detect_lanes=lanes,
                    **opts)
         s.step(warmup)
@@ -197,7 +201,7 @@ def autotune(sims, candidates=None, steps=20, warmup=6, precision="fp64", device
         s.close()
         del s
         timings.append({"cell_factor": cf, "detect_lanes": lanes, "skin": skin,
-                        "ms_per_step": ms})
+                        "rebuild_every": every, "ms_per_step": ms})
     best = min(timings, key=lambda r: r["ms_per_step"])
     return dict(best), timings
 

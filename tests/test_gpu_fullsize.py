@@ -52,10 +52,11 @@ def compare(g, o, w, tol=TOL64):
     return len(co["ki"])
 
 
-@pytest.mark.parametrize("cf,skin", [(0.4, 0.0), (1.0, 0.0), (0.4, 0.05)])
-def test_column_200k_first_step_and_resync(column, cf, skin):
+@pytest.mark.parametrize("cf,skin,every", [(0.4, 0.0, 0), (1.0, 0.0, 0), (0.4, 0.05, 0),
+                                           (0.4, 0.1, 128), (0.4, 0.2, 256)])
+def test_column_200k_first_step_and_resync(column, cf, skin, every):
     w = column
-    g = solver(w, cell_factor=cf, detect_lanes=1, skin=skin)
+    g = solver(w, cell_factor=cf, detect_lanes=1, skin=skin, rebuild_every=every)
     o = oracle_from(w)
     g.step(1)
     o.step(1)
