@@ -258,13 +258,17 @@ int sdem_step(sdem_ctx* ctx, int64_t nsteps);
 /* Measurement aid: like sdem_step, but launches each step's kernels directly
  * (no graph) with HIP events between its phases on the context's stream,
  * and returns the mean time per step of each phase in phase_ms[0..4], and in
- * phase_ms[5] the mean duration of the contact-force kernel alone, from start
+ * phase_ms[5] the mean duration of the kernel of phase 3 alone, from start
  * and stop events attached to its dispatch (hipExtLaunchKernel):
- *   0 grid (from the bounding box reduced by the previous integration),
+ *   0 bounding box and grid (steps that rebuild the cells),
  *   1 cell sort and state reorder (and mesh motion), 2 narrow phase (contact
  *   records), 3 contact forces and torques with the spring carry-over,
  *   4 integration.
- * Results are identical to sdem_step's. */
+ * On steps that keep the cells with one search lane and at most 1,024 slot
+ * groups of 256, one kernel runs the narrow phase and the contact law: phase
+ * 2 is then empty and phases 3 and 5 time that kernel.  phase_ms holds 6
+ * doubles (caller-owned, host memory).  The rebuild decisions and results
+ * are identical to sdem_step's. */
 int sdem_step_profiled(sdem_ctx* ctx, int64_t nsteps, double* phase_ms);
 
 /* Current state by persistent id: x, v, w [3][n], q [4][n], and the net
