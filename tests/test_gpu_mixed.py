@@ -48,11 +48,14 @@ def test_mixed_one_step(case):
     assert max(e.values()) < TOL32, e
 
 
-def test_mixed_resynced_horizon_cfg1():
+@pytest.mark.parametrize("skin", [0.0, 0.1])
+def test_mixed_resynced_horizon_cfg1(skin):
     """Every 50 of 500 steps of configuration 1: keys bit-exact and all
-    quantities within 1e-5 one step after a resync."""
+    quantities within 1e-5 one step after a resync.  With a skin and one
+    search lane, the steps that keep the cells run the FP32 contact law in
+    the same kernel as the search."""
     w = W.cfg1()
-    g = solver(w)
+    g = solver(w, skin=skin, detect_lanes=1) if skin else solver(w)
     worst = {}
     for t in range(0, 500, 50):
         if t:

@@ -32,13 +32,14 @@ def errors(g, o, w):
     return e, len(co["ki"]), int((co["kj"] == -(len(w["elements"]) - 1)).sum())
 
 
-@pytest.mark.parametrize("skin", [0.0, 0.05])
-def test_vibrated_floor_resynced(skin):
+@pytest.mark.parametrize("skin,lanes", [(0.0, 0), (0.05, 0), (0.05, 1)])
+def test_vibrated_floor_resynced(skin, lanes):
     """Spheres landing on a floor vibrated at 3 g (walls fixed): every 100 of
     800 steps the oracle takes the GPU state, springs and clock and both
-    advance one step."""
+    advance one step.  With a skin and one search lane the steps that keep
+    the cells read the wall motion in the fused search and contact law."""
     w = W.vibrated_box()
-    g = solver(w, skin=skin)
+    g = solver(w, skin=skin, detect_lanes=lanes)
     floor = 0
     for t in range(0, 800, 100):
         if t:

@@ -84,14 +84,14 @@ def test_spawn_sequence_free_running():
     assert 400 < g.n <= 1000
 
 
-@pytest.mark.parametrize("skin", [0.0, 0.05])
-def test_spawn_resynced_in_the_funnel(skin):
+@pytest.mark.parametrize("skin,lanes", [(0.0, 0), (0.05, 0), (0.05, 1)])
+def test_spawn_resynced_in_the_funnel(skin, lanes):
     """A spawn box inside the funnel, 2,000 particles at most: every 100 of
     700 steps the oracle takes the GPU's state, springs and spawn position
     and both advance one step (spawning while particles and funnel walls
     collide; later, attempts failing with a carried radius)."""
     w, sp = hopper(n_max=2000, low=True)
-    g = solver(w, sp, skin=skin)
+    g = solver(w, sp, skin=skin, detect_lanes=lanes)
     pp = pw = 0
     carried_seen = False
     for t in range(0, 700, 100):
