@@ -510,7 +510,9 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
 }
 
 // ---------------------------------------------------------------------------
-// 4. mesh: rigid rotation (extension for rotating drums) and plane data (the
+// 4. mesh: the motion of each element's group (rotation about a centre and
+//    harmonic displacement: an extension for rotating drums and vibrated
+//    bases), the wall record read by the contact law, and plane data (the
 //    plane through the stored slots 0, 1, 2: a triangle's, or a rectangle's
 //    through corners 0, 1 and 3)
 // ---------------------------------------------------------------------------
@@ -1057,7 +1059,11 @@ __global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Co
 }
 
 // ---------------------------------------------------------------------------
-// 6. contact forces and torques (Section 2.2, 2.3, 3.2), one lane per contact
+// 6. contact forces and torques (Section 2.2, 2.3, 3.2), one lane per contact.
+//    On steps that keep the cells with one search lane per slot, on grids
+//    resident in one round, the search of section 5 and this law run in one
+//    workgroup per slot group (k_detect_force); otherwise k_detect and
+//    k_force are launched one after the other.
 // ---------------------------------------------------------------------------
 // Static/kinetic update of a vector friction mode m in {s, r}: rotate the old
 // spring into the tangent plane keeping its length, f = -k u - c v, then keep
