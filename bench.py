@@ -58,7 +58,7 @@ WORKLOADS = {
                     "traffic": "k_detect_force_cfg2_column_200k_hbm_traffic.md", "settings": None},
     "packing_8M": {"make": "cfg5", "radii": "half 1.0 mm, half 1.4 mm (rock-salt lattice)",
                    "traffic": "k_force_cfg5_packing_8M_hbm_traffic.md",
-                   "settings": (1.0, 1, 0.05)},
+                   "settings": (1.0, 1, 0.2)},
 }
 
 
@@ -204,10 +204,10 @@ def packing_forms(warmup=10, steps=40):
     w = W.cfg5()
     n = len(w["R"])
     print(f"[bench] packing: {n} particles", file=sys.stderr, flush=True)
-    out = {"workload": w["name"], "particles": n, "cell_factor": 1.0, "skin": 0.05,
+    out = {"workload": w["name"], "particles": n, "cell_factor": 1.0, "skin": 0.2,
            "steps": steps}
     for prec in ("fp64", "mixed"):
-        g = Solver(w, precision=prec, device="cuda:0", cell_factor=1.0, detect_lanes=1, skin=0.05)
+        g = Solver(w, precision=prec, device="cuda:0", cell_factor=1.0, detect_lanes=1, skin=0.2)
         g.step(warmup)
         torch.cuda.synchronize()
         s0 = g.stats()

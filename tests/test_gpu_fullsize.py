@@ -146,11 +146,12 @@ def packing():
 
 
 @pytest.mark.parametrize("precision,tol,skin", [("fp64", TOL64, 0.0), ("mixed", TOL32, 0.0),
-                                               ("fp64", TOL64, 0.05)])
+                                               ("fp64", TOL64, 0.05), ("fp64", TOL64, 0.2)])
 def test_packing_8M_sampled(packing, precision, tol, skin):
-    """With a skin the relaxing packing drifts past half of it within the
-    first steps: the host sees the drift flag after each step at this size
-    and rebuilds at the next one."""
+    """With a thin skin (0.05 R_max) the relaxing packing drifts past half
+    of it within the first steps: the host sees the drift flag after each
+    step at this size and rebuilds at the next one.  Skin 0.2 R_max is the
+    bench's setting for this workload."""
     w = packing
     n = len(w["R"])
     g = solver(w, precision=precision, cell_factor=1.0, detect_lanes=1, skin=skin)
@@ -170,7 +171,8 @@ def test_packing_8M_sampled(packing, precision, tol, skin):
     assert same
     assert max(err.values()) < tol, err
     if skin > 0:
-        assert g.stats()["rebuilds"] >= 2
+        if skin < 0.1:
+            assert g.stats()["rebuilds"] >= 2  # the drift passed half the skin
         # steps timed phase by phase see the drift flag after each step too
         r0 = g.stats()["rebuilds"]
         h = solver(w, precision=precision, cell_factor=1.0, detect_lanes=1, skin=skin)
