@@ -266,7 +266,7 @@ int sdem_step(sdem_ctx* ctx, int64_t nsteps);
  *   4 integration.
  * On steps that keep the cells with one search lane and at most 1,024 slot
  * groups of 256, one kernel runs the narrow phase and the contact law: phase
- * 2 is then empty and phases 3 and 5 time that kernel.  phase_ms holds 6
+ * 2 then counts as 0 and phases 3 and 5 time that kernel.  phase_ms holds 6
  * doubles (caller-owned, host memory).  The rebuild decisions and results
  * are identical to sdem_step's. */
 int sdem_step_profiled(sdem_ctx* ctx, int64_t nsteps, double* phase_ms);

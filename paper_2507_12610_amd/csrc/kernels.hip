@@ -1926,12 +1926,8 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
     (void)launch_mesh_bins(c, s);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
-  // A step that keeps the cells with one search lane per slot runs the
-  // search and the contact law in one kernel (in the force phase) when the
-  // grid is resident in one round: there the second launch and the records'
-  // round trip weigh (200k spheres: 3.4 us of 31 saved).  On larger grids the
-  // two kernels are faster (8M spheres: 2.38 ms against 2.42 ms fused).
-  const bool fused = !rebuild && c.detect_sub == 1 && c.ngroups <= kOneRoundBlocks;
+  // the search and the contact law in one kernel (in the force phase)
+  const bool fused = fused_search_and_law(c, rebuild);
   if (!fused) switch (c.detect_sub) {
     case 1: k_detect<1><<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
     case 2: k_detect<2><<<blocks_for(2 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
