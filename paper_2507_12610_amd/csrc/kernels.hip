@@ -589,14 +589,17 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) 
 
 // Element bins (the mesh side of the broad phase): count, scan, fill and
 // sort the (bin, element) pairs.  An element enters every bin of its grid
-// that its vertex bounding box, grown by R_max + R_m of its simulation,
-// overlaps; the margin on the growth covers rounding of the box ends, so a
-// particle centre within R_i + R_m of the element lies in one of them.
+// that its vertex bounding box, grown by R_max + half skin + R_m of its
+// simulation, overlaps; the margin on the growth covers rounding of the box
+// ends, so a particle centre within R_i + R_m of the element lies in one of
+// them, and so does a centre within R_i + R_m + half skin (the reach at
+// which a rebuild records elements in the candidate lists).
 __device__ __forceinline__ void tri_bins(const Ctx& c, int m, const MeshGrid& G, int i0[3],
                                          int i1[3]) {
   const double* t = c.tri + 9 * m;
   const bool rect = c.tri_nv[m] == 4;
-  const double reach = (c.sp[c.tri_sim[m]].rmax + c.rmesh[m]) * (1.0 + 1e-9);
+  const SimParams& P = c.sp[c.tri_sim[m]];
+  const double reach = ((P.rmax + P.half_skin) + c.rmesh[m]) * (1.0 + 1e-9);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const double a = t[k], b = t[3 + k], e = t[6 + k];

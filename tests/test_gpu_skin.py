@@ -162,3 +162,37 @@ def test_profiled_steps_rebuild_like_plain_steps():
     sa, sb = a.state(), b.state()
     for k in ("x", "v", "w", "q", "F", "T"):
         assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_static_walls_found_between_rebuilds():
+    """With a skin, a rebuild lists every static element within
+    R_i + R_m + half skin of each particle, taken from the element bin of its
+    centre, so the bins must reach R_max + R_m + half skin.  Spheres of R_max
+    start half a half skin away from contact with the +x, +y and +z faces of
+    a cube, whose element bins (bin edge half the face) have a boundary right
+    where a reach of R_max alone would end, and move onto the faces between
+    rebuilds: the contact keys equal the oracle's at every step."""
+    L, R = 20e-3, 1e-3
+    tri = W.cube_mesh([0.0] * 3, [L] * 3)
+    skin = 1.0
+    gap = 0.25 * skin * R  # half of the half skin
+    c = 0.5 * L
+    x = np.array([[L - R - gap, c, c], [c, L - R - gap, c], [c, c, L - R - gap],
+                  [c - 3e-3, c - 3e-3, c - 3e-3]])
+    v = np.array([[2.0, 0, 0], [0, 2.0, 0], [0, 0, 2.0], [0.1, 0.1, 0.1]])
+    n = len(x)
+    w = {"name": "walls_between_rebuilds", "params": W.default_params(g=(0.0, 0.0, 0.0), dt=2e-6),
+         "x": x, "v": v, "w": np.zeros((n, 3)), "q": np.tile([1.0, 0, 0, 0], (n, 1)),
+         "R": np.full(n, R), "tri": tri, "rmesh": np.zeros(len(tri)), "steps": 0, "R_max": R}
+    g = solver(w, skin=skin, rebuild_every=100000)
+    o = oracle_from(w)
+    rebuilds_at_touch = None
+    for step in range(150):
+        g.step(1)
+        o.step(1)
+        kg, ko = keys(g.contacts()), keys(o.contacts())
+        assert np.array_equal(kg, ko), step
+        if rebuilds_at_touch is None and len(ko) >= 3:
+            rebuilds_at_touch = g.stats()["rebuilds"]
+    # the walls were reached on steps that kept the cells of the first step
+    assert rebuilds_at_touch == 1
