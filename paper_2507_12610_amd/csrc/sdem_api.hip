@@ -524,7 +524,8 @@ static int element_corners(const std::vector<double>& tri, const std::vector<int
 
 // Bin grid of one simulation's mesh.  The grid spans every place the
 // elements can reach (fixed, vibrating or turning), grown by
-// reach = R_max + max R_m.  The bin edge starts at the larger of 2 reach and
+// reach = rmax + max R_m, where rmax is the simulation's R_max plus the half
+// skin (a rebuild records the elements within R_i + R_m + half skin).  The bin edge starts at the larger of 2 reach and
 // half the median element extent and grows until the bins, and a bound on
 // the (bin, element) entries that holds at any orientation, fit this
 // simulation's share of the tables.
@@ -695,7 +696,7 @@ static int set_mesh(sdem_ctx* X, int32_t sim, int64_t nel, const int32_t* nv, co
 }
 
 // Uploads the meshes of every simulation and builds their element bins
-// (reach R_max + R_m of each simulation).
+// (reach R_max + half skin + R_m of each simulation).
 static int upload_mesh(sdem_ctx* X) {
   drop_graphs(X);
   // concatenate every simulation's mesh
@@ -740,8 +741,11 @@ static int upload_mesh(sdem_ctx* X) {
     mg[s].off = (int32_t)nbins;
     if (!nt) continue;
     const int64_t bb = bins_cap(X->cfg) * nt / tmax, eb = bin_entries_cap(X->cfg) * nt / tmax;
+    // the reach of the bins: R_max plus the half skin (as derive() sets it)
+    const double rm = X->rmax[s] > 0 ? X->rmax[s] : 1.0;
+    const double rreach = rm + 0.5 * X->cfg.skin * rm;
     mg[s] = mesh_grid(X->mesh_tri[s], X->mesh_nv[s], X->mesh_r[s], X->mesh_grp[s], X->motion[s],
-                      X->rmax[s], std::max<int64_t>(bb, 1), eb, (int32_t)nbins);
+                      rreach, std::max<int64_t>(bb, 1), eb, (int32_t)nbins);
     if (mg[s].dim[0] <= 0) return fail(SDEM_ECAPACITY, "no triangle bin grid fits simulation %d", s);
     nbins += (int64_t)mg[s].dim[0] * mg[s].dim[1] * mg[s].dim[2];
   }
@@ -987,6 +991,24 @@ static hipGraphExec_t step_graph(sdem_ctx* X, int pat) {
   return ex;
 }
 
+// Instantiates, for both buffer parities, every graph pattern that
+// sdem_step may launch for this context, so that no capture or
+// instantiation happens inside a later run of steps (a timed one, say).
+static void prepare_graphs(sdem_ctx* X) {
+  if (X->graph_failed || !X->stream) return;
+  const int cur = X->cur;
+  for (int pat = 0; pat < 4; ++pat) {
+    const bool used = !X->c.skin_on ? (pat <= 1)
+                                    : (pat >= 1 && (pat != 3 || X->n < kDriftCheckEachStep));
+    if (!used) continue;
+    for (int p = 0; p < 2; ++p) {
+      X->cur = p;
+      (void)step_graph(X, pat);
+    }
+  }
+  X->cur = cur;
+}
+
 static hipError_t run_pattern(sdem_ctx* X, int pat) {
   hipGraphExec_t g = step_graph(X, pat);
   hipError_t e = g ? hipGraphLaunch(g, X->stream) : enqueue_steps(X, kPatSteps[pat], kPatRebuild[pat]);
@@ -1026,6 +1048,7 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
   const int start = X->cur;
   unsigned long long drift0 = before.drift_steps;
   int64_t left = nsteps;
+  if (!spawning(X)) prepare_graphs(X);
   while (left > 0) {
     if (spawning(X)) {
       // steps one at a time, each after its spawn attempts, without graphs
