@@ -1,25 +1,35 @@
 #!/usr/bin/env python3
 """Throughput of the DEM hot path on one MI355X.
 
-Workload (default): 200,000 polydisperse spheres (R = 1 mm exp(0.2 Z)),
-granular column on a 600 x 600 mm two-triangle floor, full friction,
-dt = 5e-7 s, plain FP64 (the configuration the headline metric is quoted on).
-A step is one full time step of the hot path: bounding box and grid, cell
-sort and state reorder, narrow phase, contact forces with spring carry-over,
-integration.  The state is resident in HBM before timing starts.
+Workload (default): the dense static packing of 8,000,000 spheres (half of
+radius 1.0 mm, half 1.4 mm, six contacts per sphere at the start, about
+24M contacts per step) in a closed 12-triangle cube, full friction, gravity,
+dt from Eq. dt at 1.0 mm, plain FP64: the largest single-GPU configuration,
+whose state is far larger than the 256 MB Infinity Cache.  A step is one
+full time step of the hot path: bounding box and grid, cell sort and state
+reorder (on the steps that rebuild the cells), narrow phase, contact forces
+with spring carry-over, integration.  The state is resident in HBM before
+timing starts.
 
-Prints one JSON line: particle-steps/s (value) and contacts/s, the roofline
-of the kernel that computes the contact law on steps that keep the cells
-(the fused narrow phase and contact law on grids of at most 1,024 slot groups,
-128 N + 128 C algorithmic bytes per launch; else the contact-force kernel,
-128 N + 120 C) over its mean duration, timed with HIP events on its own
-dispatch, and the CPU oracle timed on a bounded sample of the same workload.
+Timing: every timed window is exactly --steps steps bracketed by device
+synchronisations; windows follow one another in blocks that span at least
+two rebuild periods of the cells, so rebuilds are counted at their real
+rate; the value is the median block's particle-steps/s over three blocks.
+
+Prints one JSON line: particle-steps/s (value) and contacts/s; the roofline
+of the contact-force kernel (128 N + 120 C algorithmic bytes per launch)
+over its mean duration from HIP events on its own dispatch; other forms
+(mixed precision, cells rebuilt every step, the 200,000-sphere column, the
+2,000,000-sphere rotating drum, 256 batched box drops) with their speedups
+over plain FP64 on the same GPU; and the CPU oracle timed on the same 8M
+workload.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -50,16 +60,34 @@ def fused_bytes(n, c):
 ONE_ROUND_GROUPS = 1024
 
 
-# bench workloads: the headline column, and the 8M packing whose state is
-# far larger than the 256 MB Infinity Cache; each with its counter summary
-# and its settings when none are given (None: autotuned)
+# bench workloads, each with its counter summary and its settings when none
+# are given (None: autotuned)
 WORKLOADS = {
-    "column_200k": {"make": "cfg2", "radii": "lognormal, median 1 mm, sigma 0.2",
-                    "traffic": "k_detect_force_cfg2_column_200k_hbm_traffic.md", "settings": None},
     "packing_8M": {"make": "cfg5", "radii": "half 1.0 mm, half 1.4 mm (rock-salt lattice)",
                    "traffic": "k_force_cfg5_packing_8M_hbm_traffic.md",
                    "settings": (1.0, 1, 0.2)},
+    "column_200k": {"make": "cfg2", "radii": "lognormal, median 1 mm, sigma 0.2",
+                    "traffic": "k_detect_force_cfg2_column_200k_hbm_traffic.md", "settings": None},
 }
+
+
+def host_info():
+    """The host the CPU oracle runs on: logical CPUs visible to this process,
+    the CPU model and the OpenMP thread setting."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
 
 
 def measured_traffic(workload):
@@ -80,62 +108,97 @@ def measured_traffic(workload):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, budget_s=12.0, max_steps=40):
+def cpu_baseline(w, steps=2):
+    """The serial FP64 oracle (one host thread) on the same workload: the
+    first `steps` steps from the same start, wall time per step."""
     import oracle
     o = oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"],
                    tri=w["tri"], rmesh=w["rmesh"])
-    t0 = time.perf_counter()
-    o.step(1)
-    one = time.perf_counter() - t0
-    k = int(max(1, min(max_steps - 1, budget_s / max(one, 1e-9) - 1)))
-    t1 = time.perf_counter()
-    o.step(k)
-    dt = time.perf_counter() - t1
-    steps = k + 1
-    total = one + dt
+    per = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        o.step(1)
+        per.append(time.perf_counter() - t0)
     n = len(w["R"])
+    total = sum(per)
     return {"value": n * steps / total, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} steps of the same workload (N={n}), serial FP64 oracle, "
-                      f"{total:.1f} s"}
+            "sample": f"the first {steps} steps of the same workload (N={n}) from the same "
+                      f"start, serial FP64 oracle in one thread, "
+                      + ", ".join(f"{t:.1f}" for t in per) + " s per step",
+            "host": host_info()}
 
 
-CPU_CHILD = r"""
-import json, sys, time
-sys.path.insert(0, sys.argv[1])
-import oracle
-import workloads as W
-w = W.cfg2()
-o = oracle.Sim(w["params"], w["x"], v=w["v"], w=w["w"], q=w["q"], R=w["R"], tri=w["tri"],
-               rmesh=w["rmesh"])
-steps = int(sys.argv[2])
-t0 = time.perf_counter()
-o.step(steps)
-print(json.dumps({"n": len(w["R"]), "steps": steps, "s": time.perf_counter() - t0}))
-"""
+def timed_blocks(s, n, K, blocks=3, min_block_steps=128):
+    """Times `blocks` blocks of consecutive steps of solver s.  A block is a
+    run of windows of exactly K steps, each window bracketed by device
+    synchronisations and timed on the host clock; a block spans at least
+    min_block_steps steps so that it holds whole rebuild periods.  Returns
+    the median block (by rate) and all blocks: steps, seconds, rebuilds,
+    contacts."""
+    import torch
+    out = []
+    per_block = max(1, -(-min_block_steps // K))
+    for _ in range(blocks):
+        a = s.stats()
+        sec = 0.0
+        for _ in range(per_block):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(K)  # returns after the stream has drained
+            torch.cuda.synchronize()
+            sec += time.perf_counter() - t0
+        b = s.stats()
+        out.append({"steps": per_block * K, "s": sec, "rebuilds": b["rebuilds"] - a["rebuilds"],
+                    "pp": b["pp"] - a["pp"], "pw": b["pw"] - a["pw"]})
+    med = sorted(out, key=lambda r: r["steps"] / r["s"])[len(out) // 2]
+    return med, out
 
 
-def cpu_all_cores(steps=3, max_procs=16):
-    """The same serial oracle in one process per host core (at most 16, the
-    host share of one GPU), each stepping its own copy of the workload:
-    whole-host throughput = all their particle-steps over the slowest one's
-    time.  Child processes, started fresh (never forked from this one)."""
-    import subprocess
-    k = max(1, min(max_procs, os.cpu_count() or 1))
-    procs = [subprocess.Popen([sys.executable, "-c", CPU_CHILD, ROOT, str(steps)],
-                              stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
-             for _ in range(k)]
-    res = []
-    for p in procs:
-        out, _ = p.communicate(timeout=900)
-        if p.returncode == 0:
-            res.append(json.loads(out.strip().splitlines()[-1]))
-    if not res:
-        return None
-    n, slowest = res[0]["n"], max(r["s"] for r in res)
-    return {"value": len(res) * n * steps / slowest, "unit": "particle-steps/s", "cores": len(res),
-            "kind": "oracle",
-            "sample": f"first {steps} steps of the same workload (N={n}) in {len(res)} serial "
-                      f"FP64 oracle processes at once, slowest {slowest:.1f} s"}
+def block_summary(med, blocks, n):
+    return {"ms_per_step": round(1e3 * med["s"] / med["steps"], 5),
+            "particle_steps_per_s": round(n * med["steps"] / med["s"], 1),
+            "contacts_per_s": round((med["pp"] + med["pw"]) / med["s"], 1),
+            "contacts_per_step": round((med["pp"] + med["pw"]) / med["steps"], 1),
+            "cell_rebuilds": f"{med['rebuilds']} of {med['steps']} steps",
+            "blocks_ms_per_step": [round(1e3 * b["s"] / b["steps"], 5) for b in blocks]}
+
+
+def profiled_force_kernel(s, n, steps, fused):
+    """Phase times over `steps` profiled steps (one at a time) and the mean
+    duration of the kernel of the force phase on the steps that keep the
+    cells, from start/stop events attached to its dispatch; with the
+    algorithmic bytes per launch over that duration against the HBM peak."""
+    prof = []
+    for _ in range(steps):
+        a = s.stats()
+        ph = s.step_profiled(1)
+        b = s.stats()
+        prof.append((b["rebuilds"] > a["rebuilds"], ph, (b["pp"] - a["pp"]) + (b["pw"] - a["pw"])))
+    keep = [p for p in prof if not p[0]] or prof
+    phases = {k: sum(p[1][k] for p in prof) / len(prof) for k in prof[0][1]}
+    fms = sum(p[1]["force_kernel"] for p in keep) / len(keep)
+    c_prof = sum(p[2] for p in keep) / len(keep)
+    if fused:
+        assert all(p[1]["detect"] == 0.0 for p in keep), "narrow phase not fused"
+        kname = "k_detect_force (narrow phase, contact law, spring carry-over)"
+        alg = fused_bytes(n, c_prof)
+    else:
+        kname = "k_force (contact forces, torques, spring carry-over)"
+        alg = force_bytes(n, c_prof)
+    achieved = alg / (fms * 1e-3) / 1e9
+    dominant = max((k for k in phases if k != "force_kernel"), key=phases.get)
+    return {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "mean_ms": round(fms, 5), "algorithmic_bytes": alg,
+            "contacts_per_launch": round(c_prof, 1), "launches_timed": len(keep),
+            "phase_ms": {k: round(v, 5) for k, v in phases.items() if k != "force_kernel"},
+            "dominant_phase": dominant}
+
+
+def rel(a, b):
+    import numpy as np
+    den = float(np.abs(b).max()) if np.size(b) else 0.0
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a).max())
 
 
 def sim_slice(w, st, c, lo, hi):
@@ -151,30 +214,24 @@ def sim_slice(w, st, c, lo, hi):
     return d, hist
 
 
-def mixed_vs_fp64(w, cf, lanes, skin, steps_before=200):
+def mixed_vs_fp64(w, opts, steps_before=200):
     """One step of the mixed path and of the FP64 path from the same state
     and springs (taken after steps_before FP64 steps): per quantity, the
     largest difference relative to the largest FP64 value (for x, relative
     to the largest displacement of the step)."""
-    import numpy as np
     from paper_2507_12610_amd import Solver
-    a = Solver(w, precision="fp64", cell_factor=cf, detect_lanes=lanes, skin=skin)
+    a = Solver(w, precision="fp64", **opts)
     a.step(steps_before)
     st, c = a.state(forces=False), a.contacts()
     d = dict(w)
     d.update({k: st[k] for k in ("x", "v", "w", "q")})
-    b = Solver(d, precision="mixed", cell_factor=cf, detect_lanes=lanes, skin=skin)
+    b = Solver(d, precision="mixed", **opts)
     b.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])
     a.step(1)
     b.step(1)
     sa, sb = a.state(), b.state()
     a.close()
     b.close()
-
-    def rel(x, y):
-        den = float(np.abs(y).max())
-        return float(np.abs(x - y).max() / den) if den > 0 else float(np.abs(x).max())
-
     out = {k: rel(sb[k], sa[k]) for k in ("F", "T", "v", "w", "q")}
     out["x"] = rel(sb["x"] - st["x"], sa["x"] - st["x"])
     return {"after_fp64_steps": steps_before, "contacts": int(len(c["ki"])),
@@ -182,8 +239,8 @@ def mixed_vs_fp64(w, cf, lanes, skin, steps_before=200):
 
 
 # (cell_factor, detect_lanes, skin, longest rebuild period) tried by the
-# autotuner on the bench workload (0: the library's 64 steps)
-TUNE_CANDIDATES = [(0.4, 1, 0.05, 0), (0.33, 1, 0.05, 0), (0.5, 1, 0.05, 0), (0.4, 2, 0.05, 0),
+# autotuner on the column (0: the library's 64 steps)
+TUNE_CANDIDATES = [(0.4, 1, 0.05, 0), (0.33, 1, 0.05, 0), (0.5, 1, 0.05, 0), (1.0, 1, 0.1, 128),
                    (0.4, 1, 0.1, 128), (0.4, 1, 0.1, 256), (0.33, 1, 0.1, 256), (0.5, 1, 0.1, 256),
                    (0.4, 1, 0.2, 256), (0.4, 1, 0.0, 0)]
 
@@ -193,43 +250,139 @@ BATCH_CANDIDATES = [(1.0, 1, 1.0), (0.7, 1, 1.0), (1.0, 1, 0.6), (0.7, 1, 0.6), 
                     (1.0, 1, 0.0)]
 
 
-def packing_forms(warmup=10, steps=40):
-    """The 8,000,000-sphere pre-compressed packing (six contacts per sphere
-    at the start), FP64 and mixed precision with the same settings: where the
-    contact law's arithmetic weighs more than at 200,000 spheres."""
-    import torch
-
+def column_forms(K):
+    """The 200,000-sphere column (configuration 2): FP64 and mixed precision
+    with autotuned settings."""
     import workloads as W
-    from paper_2507_12610_amd import Solver
-    w = W.cfg5()
+    from paper_2507_12610_amd import Solver, autotune
+    w = W.cfg2()
     n = len(w["R"])
-    print(f"[bench] packing: {n} particles", file=sys.stderr, flush=True)
-    out = {"workload": w["name"], "particles": n, "cell_factor": 1.0, "skin": 0.2,
-           "steps": steps}
+    print(f"[bench] column: {n} particles", file=sys.stderr, flush=True)
+    best, _ = autotune(w, candidates=TUNE_CANDIDATES, steps=512, warmup=10)
+    cf, lanes, skin, every = (best["cell_factor"], best["detect_lanes"], best["skin"],
+                              best["rebuild_every"])
+    out = {"workload": w["name"], "particles": n, "settings": {
+        "cell_factor": cf, "detect_lanes": lanes, "skin": skin,
+        "rebuild_every": every if every > 0 else 64}}
     for prec in ("fp64", "mixed"):
-        g = Solver(w, precision=prec, device="cuda:0", cell_factor=1.0, detect_lanes=1, skin=0.2)
-        g.step(warmup)
-        torch.cuda.synchronize()
-        s0 = g.stats()
-        t0 = time.perf_counter()
-        g.step(steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        s1 = g.stats()
-        g.close()
-        del g
-        out[prec] = {"ms_per_step": round(1e3 * dt / steps, 4),
-                     "particle_steps_per_s": round(n * steps / dt, 1),
-                     "contacts_per_step": round((s1["pp"] + s1["pw"] - s0["pp"] - s0["pw"]) / steps, 1)}
+        s = Solver(w, precision=prec, cell_factor=cf, detect_lanes=lanes, skin=skin,
+                   rebuild_every=every)
+        s.step(50)
+        med, blocks = timed_blocks(s, n, K, min_block_steps=2 * max(every, 64))
+        out[prec] = block_summary(med, blocks, n)
+        s.close()
     out["mixed_speedup_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"], 4)
     return out
 
 
-def batched_forms(landing_steps, steps, precision_list=("fp64", "mixed")):
+def drum_forms(K, sample=3000):
+    """The 2,000,000-sphere rotating drum (configuration 3, 8,192 triangles,
+    1 rad/s), FP64 and mixed precision after the bed has landed: ms/step,
+    contacts/s and the contact-force kernel's roofline; the mixed path's
+    difference per quantity from the FP64 path after 1 and 20 steps from the
+    same state, and the error of each path against the FP64 oracle re-synced
+    to its own state (one step of `sample` sampled particles, half of them in
+    contact) at the first and the twentieth of those steps."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    from paper_2507_12610_amd import Solver
+    w = W.cfg3()
+    n = len(w["R"])
+    print(f"[bench] drum: {n} particles, {len(w['tri'])} triangles", file=sys.stderr, flush=True)
+    opts = dict(cell_factor=1.0, detect_lanes=1, skin=0.2)
+    land = Solver(w, precision="fp64", **opts)
+    land.step(300)
+    st0, c0 = land.state(forces=False), land.contacts()
+    t_land = 300 * w["params"]["dt"]
+    land.close()
+    d = dict(w)
+    d.update({k: st0[k] for k in ("x", "v", "w", "q")})
+    out = {"workload": w["name"], "particles": n, "triangles": len(w["tri"]),
+           "landing_steps": 300, "settings": opts}
+    for prec in ("fp64", "mixed"):
+        s = Solver(d, precision=prec, **opts)
+        s.set_history(c0["ki"], c0["kj"], c0["us"], c0["ur"], c0["ut"])
+        s.set_clock(300)
+        s.step(20)
+        med, blocks = timed_blocks(s, n, K, min_block_steps=128)
+        out[prec] = block_summary(med, blocks, n)
+        out[prec]["roofline"] = profiled_force_kernel(s, n, 12, fused=False)
+        s.close()
+    out["mixed_speedup_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"], 4)
+
+    # per-quantity differences, mixed against FP64, from the landed state
+    runs = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver(d, precision=prec, **opts)
+        s.set_history(c0["ki"], c0["kj"], c0["us"], c0["ur"], c0["ut"])
+        s.set_clock(300)
+        snaps = {}
+        s.step(1)
+        snaps[1] = (s.state(), s.contacts())
+        s.step(18)
+        snaps[19] = (s.state(forces=False), s.contacts())
+        s.step(1)
+        snaps[20] = (s.state(), s.contacts())
+        runs[prec] = snaps
+        s.close()
+    diff = {}
+    for h in (1, 20):
+        a, b = runs["fp64"][h][0], runs["mixed"][h][0]
+        dd = {k: rel(b[k], a[k]) for k in ("F", "T", "v", "w", "q")}
+        dd["x"] = rel(b["x"] - st0["x"], a["x"] - st0["x"])
+        ca, cb = runs["fp64"][h][1], runs["mixed"][h][1]
+        same = (len(ca["ki"]) == len(cb["ki"]) and np.array_equal(ca["ki"], cb["ki"]) and
+                np.array_equal(ca["kj"], cb["kj"]))
+        if same:
+            dd["us"] = rel(cb["us"], ca["us"])
+            dd["ur"] = rel(cb["ur"], ca["ur"])
+            dd["ut"] = rel(cb["ut"], ca["ut"])
+        diff[f"after_{h}_steps"] = {"same_contact_keys": bool(same),
+                                    "max_rel_diff": {k: float(f"{v:.3e}") for k, v in dd.items()}}
+    out["mixed_vs_fp64"] = diff
+
+    # against the oracle: one sampled step from the GPU path's own state
+    rng = np.random.Generator(np.random.PCG64(3030))
+    touching = np.unique(np.concatenate([c0["ki"], c0["kj"][c0["kj"] > 0]]))
+    idx = np.sort(np.concatenate([rng.choice(touching, sample // 2, replace=False),
+                                  rng.choice(n, sample // 2, replace=False)]))
+    idx = np.unique(idx)
+    vs_oracle = {}
+    for prec in ("fp64", "mixed"):
+        for h in (1, 20):
+            if h == 1:
+                start, hist, t = st0, c0, t_land
+            else:
+                start, hist = runs[prec][19]
+                t = t_land + 19 * w["params"]["dt"]
+            o = oracle.Sim(w["params"], start["x"], v=start["v"], w=start["w"], q=start["q"],
+                           R=w["R"], tri=w["tri"], rmesh=w["rmesh"])
+            o.set_time(t)
+            o.set_history(hist["ki"], hist["kj"], hist["us"], hist["ur"], hist["ut"])
+            smp = o.sample_step(idx)
+            g = runs[prec][h][0]
+            scale_F = np.maximum(smp["Fscale"], 1e-300)
+            errF = float((np.linalg.norm(g["F"][idx] - smp["F"], axis=1) / scale_F).max())
+            errT = float((np.linalg.norm(g["T"][idx] - smp["T"], axis=1) /
+                          np.maximum(smp["Tscale"] + smp["Fscale"] * w["R"][idx], 1e-300)).max())
+            e = {"F": errF, "T": errT, "v": rel(g["v"][idx], smp["v"]),
+                 "q": rel(g["q"][idx], smp["q"]),
+                 "x": rel(g["x"][idx] - start["x"][idx], smp["x"] - start["x"][idx])}
+            vs_oracle[f"{prec}_step_{h}"] = {k: float(f"{v:.3e}") for k, v in e.items()}
+            del o
+    out["vs_oracle_resynced_sampled"] = {"particles": int(len(idx)), "errors": vs_oracle,
+                                        "tolerance": {"fp64": 1e-12, "mixed": 1e-5}}
+    return out
+
+
+def batched_forms(K, landing_steps, precision_list=("fp64", "mixed")):
     """Configuration 4: 256 box drops of uneven size in one context, timed after
     the sims have landed, against the same 256 states stepped one simulation
-    after another (separate contexts, plain FP64), all on the GPU."""
-    import numpy as np
+    after another (separate contexts, plain FP64), all on the GPU.  Every
+    context has stepped (and so instantiated its step graphs) before timing;
+    each form is the median of three blocks."""
     import torch
 
     import workloads as W
@@ -246,23 +399,14 @@ def batched_forms(landing_steps, steps, precision_list=("fp64", "mixed")):
     best, _ = autotune([p[0] for p in landed], candidates=BATCH_CANDIDATES, steps=96, warmup=4)
     cf, skin = best["cell_factor"], best["skin"]
     out = {"workload": "cfg4_256_box_drops", "sims": len(sims), "particles": total,
-           "landing_steps": landing_steps, "steps": steps, "cell_factor": cf, "skin": skin}
-    res = {}
+           "landing_steps": landing_steps, "cell_factor": cf, "skin": skin}
     for prec in precision_list:
         g = Solver([p[0] for p in landed], precision=prec, cell_factor=cf, detect_lanes=1,
                    skin=skin)
         g.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])
-        g.step(2)
-        torch.cuda.synchronize()
-        s0 = g.stats()
-        t0 = time.perf_counter()
-        g.step(steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        s1 = g.stats()
-        cont = (s1["pp"] - s0["pp"]) + (s1["pw"] - s0["pw"])
-        res[prec] = {"ms_per_step": 1e3 * dt / steps, "particle_steps_per_s": total * steps / dt,
-                     "contacts_per_s": cont / dt, "contacts_per_step": cont / steps}
+        g.step(4)
+        med, blocks = timed_blocks(g, total, K, min_block_steps=96)
+        out[prec] = block_summary(med, blocks, total)
         g.close()
     # the same 256 states, one simulation after another (plain FP64)
     seq = []
@@ -272,46 +416,49 @@ def batched_forms(landing_steps, steps, precision_list=("fp64", "mixed")):
         g.set_history(*h)
         seq.append(g)
     for g in seq:
-        g.step(2)
+        g.step(4)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for g in seq:
-        g.step(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    reps = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        for g in seq:
+            g.step(K)
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t0)
     for g in seq:
         g.close()
-    res["sequential_fp64"] = {"ms_per_step": 1e3 * dt / steps,
-                              "particle_steps_per_s": total * steps / dt}
+    dt = statistics.median(reps)
+    out["sequential_fp64"] = {"ms_per_step": round(1e3 * dt / K, 5),
+                              "particle_steps_per_s": round(total * K / dt, 1),
+                              "repeats_ms_per_step": [round(1e3 * r / K, 5) for r in reps]}
     for prec in precision_list:
-        res[prec]["speedup_vs_sequential_fp64"] = (res["sequential_fp64"]["ms_per_step"] /
-                                                   res[prec]["ms_per_step"])
-    out.update(res)
+        out[prec]["speedup_vs_sequential_fp64"] = round(
+            out["sequential_fp64"]["ms_per_step"] / out[prec]["ms_per_step"], 3)
     return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=20, help="steps per timed window")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--cell-factor", type=float, default=None,
-                    help="cell edge / (2 R_max); default: autotuned")
+                    help="cell edge / (2 R_max); default: the workload's setting or autotuned")
     ap.add_argument("--detect-lanes", type=int, default=None,
-                    help="lanes per particle in the contact search; default: autotuned")
+                    help="lanes per particle in the contact search")
     ap.add_argument("--skin", type=float, default=None,
-                    help="cell skin in units of R_max (0: rebuild every step); default: autotuned")
+                    help="cell skin in units of R_max (0: rebuild every step)")
     ap.add_argument("--rebuild-every", type=int, default=0,
-                    help="longest rebuild period with a skin (0: 64); autotuned with the rest")
-    ap.add_argument("--no-forms", action="store_true",
-                    help="skip the mixed-precision and batched forms")
+                    help="longest rebuild period with a skin (0: 64)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the other forms")
+    ap.add_argument("--forms", default="mixed,rebuilt,column,drum,batched",
+                    help="comma-separated forms to run besides the headline")
     ap.add_argument("--batch-landing-steps", type=int, default=1500)
-    ap.add_argument("--batch-steps", type=int, default=100)
-    ap.add_argument("--workload", choices=list(WORKLOADS), default="column_200k",
-                    help="column_200k (the headline configuration) or packing_8M")
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="packing_8M")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -351,9 +498,6 @@ def main():
                            fixed[2] if args.skin is None else args.skin)
         every = args.rebuild_every
     elif args.cell_factor is None or args.detect_lanes is None or args.skin is None:
-        # trials of 512 steps, two of the longest periods tried: a thin skin
-        # or a long period looks fast over a few steps and loses once
-        # particles drift past the skin
         best, timings = autotune(w, candidates=TUNE_CANDIDATES, steps=512, warmup=10,
                                  precision=args.precision)
         tuned = {"chosen": best, "trials": timings}
@@ -363,61 +507,33 @@ def main():
     else:
         cf, lanes, skin = args.cell_factor, args.detect_lanes, args.skin
         every = args.rebuild_every
-    s = Solver(w, precision=args.precision, device="cuda:0", cell_factor=cf, detect_lanes=lanes,
-               skin=skin, rebuild_every=every)
+    period = every if every > 0 else 64
+    opts = dict(device="cuda:0", cell_factor=cf, detect_lanes=lanes, skin=skin,
+                rebuild_every=every)
+    s = Solver(w, precision=args.precision, **opts)
     s.step(args.warmup)
     torch.cuda.synchronize()
-    st0 = s.stats()
-    t0 = time.perf_counter()
-    s.step(args.steps)  # returns after the stream has drained
+    K = args.steps
+    med, blocks = timed_blocks(s, n, K, min_block_steps=2 * period if skin > 0 else K)
+    head = block_summary(med, blocks, n)
+    value = n * med["steps"] / med["s"]
+    print(f"[bench] {med['steps']} steps in {med['s']:.3f} s, "
+          f"{head['contacts_per_step']:.0f} contacts/step", file=sys.stderr, flush=True)
+    # one long window for comparison (a graph build inside it would show)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = s.stats()
-    wall = t1 - t0
-    ms_per_step = 1e3 * wall / args.steps
-    contacts = (st1["pp"] - st0["pp"]) + (st1["pw"] - st0["pw"])
-    value = n * args.steps / wall
-    print(f"[bench] {args.steps} steps in {wall:.3f} s, {contacts / args.steps:.0f} contacts/step",
-          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    s.step(400)
+    torch.cuda.synchronize()
+    long_ms = 1e3 * (time.perf_counter() - t0) / 400
 
-    # per-phase times with HIP events (no graph) on the solver's stream, one
-    # step at a time so that the steps that rebuild the cells are told apart
-    prof = []
-    for _ in range(args.profile_steps):
-        a = s.stats()
-        ph = s.step_profiled(1)
-        b = s.stats()
-        prof.append((b["rebuilds"] > a["rebuilds"], ph, (b["pp"] - a["pp"]) + (b["pw"] - a["pw"])))
-    keep = [p for p in prof if not p[0]] or prof
-    phases = {k: sum(p[1][k] for p in prof) / len(prof) for k in prof[0][1]}
-    # start/stop events attached to the dispatch of the kernel in the force
-    # phase, over the steps that keep the cells (the timed steps are such
-    # steps but for a few rebuilds)
-    fms = sum(p[1]["force_kernel"] for p in keep) / len(keep)
-    c_prof = sum(p[2] for p in keep) / len(keep)
     fused = skin > 0 and lanes == 1 and -(-n // 256) <= ONE_ROUND_GROUPS
-    if fused:
-        # the library counts the narrow phase as 0 on the steps where it
-        # runs inside the force phase's kernel
-        assert all(p[1]["detect"] == 0.0 for p in keep), "narrow phase not fused"
-        kname = "k_detect_force (narrow phase, contact law, spring carry-over)"
-        alg = fused_bytes(n, c_prof)
-    else:
-        kname = "k_force (contact forces, torques, spring carry-over)"
-        alg = force_bytes(n, c_prof)
-    achieved = alg / (fms * 1e-3) / 1e9
-    dominant = max((k for k in phases if k != "force_kernel"), key=phases.get)
-    roofline = {"kernel": kname, "bound": "hbm",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
-                "mean_ms": round(fms, 5), "algorithmic_bytes": alg,
-                "contacts_per_launch": round(c_prof, 1),
-                "launches_timed": len(keep),
-                "phase_ms": {k: round(v, 5) for k, v in phases.items() if k != "force_kernel"},
-                "dominant_phase": dominant}
+    roofline = profiled_force_kernel(s, n, args.profile_steps, fused)
+    roofline["traffic"] = measured_traffic(args.workload)
+    s.close()
+    del s
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+           "steps": K, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f32+f64",
            "data": "synthetic",
@@ -426,55 +542,47 @@ def main():
                       "radii": spec["radii"],
                       "friction": [w["params"]["mu_s"], w["params"]["mu_r"], w["params"]["mu_t"]],
                       "cell_factor": cf, "detect_lanes": lanes, "skin": skin,
-                      "rebuild_every": every if every > 0 else 64,
-                      "cell_rebuilds": f"{st1['rebuilds'] - st0['rebuilds']} of {args.steps} steps"},
-           "contacts_per_s": round(contacts / wall, 1),
-           "contacts_per_step": round(contacts / args.steps, 1),
-           "pair_contacts_per_step": round((st1["pp"] - st0["pp"]) / args.steps, 1),
-           "wall_contacts_per_step": round((st1["pw"] - st0["pw"]) / args.steps, 1),
+                      "rebuild_every": period, "cell_rebuilds": head["cell_rebuilds"]},
+           "contacts_per_s": head["contacts_per_s"],
+           "contacts_per_step": head["contacts_per_step"],
+           "timing": {"window_steps": K, "windows_per_block": med["steps"] // K,
+                      "blocks_ms_per_step": head["blocks_ms_per_step"],
+                      "statistic": "median of 3 blocks",
+                      "one_window_of_400_steps_ms_per_step": round(long_ms, 5)},
            "roofline": roofline}
     if tuned is not None:
         out["autotune"] = tuned
-    if not args.no_forms:
-        forms = {}
+    forms_wanted = set() if args.no_forms else set(f for f in args.forms.split(",") if f)
+    forms = {}
+    if "mixed" in forms_wanted:
         other = "mixed" if args.precision == "fp64" else "fp64"
-        g = Solver(w, precision=other, device="cuda:0", cell_factor=cf, detect_lanes=lanes,
-                   skin=skin, rebuild_every=every)
+        g = Solver(w, precision=other, **opts)
         g.step(args.warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.step(args.steps)
-        torch.cuda.synchronize()
-        ms_other = 1e3 * (time.perf_counter() - t0) / args.steps
+        m2, b2 = timed_blocks(g, n, K, min_block_steps=2 * period if skin > 0 else K)
         g.close()
-        forms[other] = {"workload": w["name"], "ms_per_step": round(ms_other, 5),
-                        "particle_steps_per_s": round(n * 1e3 / ms_other, 1),
-                        "speedup_vs_" + args.precision: round(ms_per_step / ms_other, 4),
-                        "tolerance": 1e-5 if other == "mixed" else 1e-12}
-        forms["mixed_vs_fp64_one_step"] = mixed_vs_fp64(w, cf, lanes, skin)
-        if skin > 0:
-            # the paper's scheme, cells rebuilt every step, same workload
-            g = Solver(w, precision=args.precision, device="cuda:0", cell_factor=cf,
-                       detect_lanes=lanes, skin=0.0)
-            g.step(args.warmup)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            g.step(args.steps)
-            torch.cuda.synchronize()
-            ms_rb = 1e3 * (time.perf_counter() - t0) / args.steps
-            g.close()
-            forms["cells_rebuilt_every_step"] = {
-                "workload": w["name"], "ms_per_step": round(ms_rb, 5),
-                "particle_steps_per_s": round(n * 1e3 / ms_rb, 1)}
-        forms["batched"] = batched_forms(args.batch_landing_steps, args.batch_steps)
-        if args.workload != "packing_8M":
-            forms["packing_8M"] = packing_forms()
+        forms[other] = dict(workload=w["name"], **block_summary(m2, b2, n),
+                            tolerance=1e-5 if other == "mixed" else 1e-12)
+        forms[other]["speedup_vs_" + args.precision] = round(
+            head["ms_per_step"] / forms[other]["ms_per_step"], 4)
+        forms["mixed_vs_fp64_one_step"] = mixed_vs_fp64(w, opts)
+    if "rebuilt" in forms_wanted and skin > 0:
+        # the paper's scheme, cells rebuilt every step, same workload
+        g = Solver(w, precision=args.precision, **dict(opts, skin=0.0))
+        g.step(5)
+        m3, b3 = timed_blocks(g, n, K, min_block_steps=K)
+        g.close()
+        forms["cells_rebuilt_every_step"] = dict(workload=w["name"], **block_summary(m3, b3, n))
+    if "column" in forms_wanted and args.workload != "column_200k":
+        forms["column_200k"] = column_forms(K)
+    if "drum" in forms_wanted:
+        forms["drum_2M"] = drum_forms(K)
+    if "batched" in forms_wanted:
+        forms["batched"] = batched_forms(K, args.batch_landing_steps)
+    if forms:
         out["forms"] = forms
     if not args.no_cpu:
-        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
-        print("[bench] timing the CPU oracle on every host core", file=sys.stderr, flush=True)
-        out["cpu_all_cores"] = cpu_all_cores()
+        print("[bench] timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, steps=args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -6,8 +6,10 @@
  * steps.  A step is, in order (Section 2.3 and Section 3.3 of the paper):
  *   1. broad phase: bounding box of the particle centres, cubic cells of edge
  *      cell_factor * 2 R_max, particles sorted by cell;
- *   2. narrow phase: particle pairs with delta = R_i + R_j - d >= 0 in the
- *      27-cell neighbourhood, and particle-mesh element pairs with
+ *   2. narrow phase: particle pairs with delta = R_i + R_j - d >= 0, found
+ *      among the particles of the cells within R_i + R_max of x_i (or, between
+ *      rebuilds, among the candidates recorded at the last rebuild), and
+ *      particle-mesh element pairs with
  *      delta = R_i + R_m - |x_i - closest point| >= 0, the element being a
  *      point, segment, triangle or rectangle of radius R_m (Fig. 4A-D);
  *   3. contact forces and torques: Hertz normal force with damping (Eq. fn,
@@ -89,8 +91,8 @@ typedef struct {
  *                springs, force sums and integration
  *  block         reserved: 0 or a multiple of 64 in [64, 1024] (workgroups
  *                are 256 threads)
- *  detect_lanes  lanes that share one particle's contact search: 1, 2, 4 or
- *                8; 0 selects 4
+ *  detect_lanes  lanes that share one particle's contact search: 0 or 1 (one
+ *                lane per particle)
  *  cell_factor   cell edge = cell_factor * 2 * R_max, >= 0.125; 0 selects 1.
  *                Each particle searches the cells within R_i + R_max of its
  *                centre, so the contact set does not depend on this value;
@@ -105,14 +107,20 @@ typedef struct {
  *                rebuild_every steps and at the first step of an sdem_step
  *                call after such a drift.  The contact set is the same for
  *                every value; only the work per step changes
- *  rebuild_every with skin > 0: steps between rebuilds, >= 1; 0 selects 64 */
+ *  rebuild_every with skin > 0: steps between rebuilds, >= 1; 0 selects 64
+ *  contacts_per_particle  contacts (pairs and mesh elements) one particle may
+ *                have in a step, in [32, 4096]; 0 selects 64.  The first 32
+ *                are held on chip, the rest in n * (contacts_per_particle -
+ *                32) integers of workspace.  A step where some particle has
+ *                more fails with SDEM_ECAPACITY (state kept, context failed):
+ *                re-init with a larger value to go on */
 typedef struct {
   int64_t n_max, contacts_max, cells_max, tri_max;
   int32_t nsims_max, precision, block, detect_lanes;
   double cell_factor;
   double skin;
   int32_t rebuild_every;
-  int32_t reserved;  /* 0 */
+  int32_t contacts_per_particle;
 } sdem_config;
 
 /* Bytes of device workspace a context with these capacities needs. */
@@ -261,14 +269,13 @@ int sdem_step(sdem_ctx* ctx, int64_t nsteps);
  * phase_ms[5] the mean duration of the kernel of phase 3 alone, from start
  * and stop events attached to its dispatch (hipExtLaunchKernel):
  *   0 bounding box and grid (steps that rebuild the cells),
- *   1 cell sort and state reorder (and mesh motion), 2 narrow phase (contact
- *   records), 3 contact forces and torques with the spring carry-over,
- *   4 integration.
- * On steps that keep the cells with one search lane and at most 1,024 slot
- * groups of 256, one kernel runs the narrow phase and the contact law: phase
- * 2 then counts as 0 and phases 3 and 5 time that kernel.  phase_ms holds 6
- * doubles (caller-owned, host memory).  The rebuild decisions and results
- * are identical to sdem_step's. */
+ *   1 cell sort and state reorder (and mesh motion),
+ *   2 opening of a step that keeps the cells (step count, drift reach),
+ *   3 the step kernel: narrow phase, contact forces and torques with the
+ *     spring carry-over, per-particle sums and integration,
+ *   4 (empty: the integration runs in phase 3).
+ * phase_ms holds 6 doubles (caller-owned, host memory).  The rebuild
+ * decisions and results are identical to sdem_step's. */
 int sdem_step_profiled(sdem_ctx* ctx, int64_t nsteps, double* phase_ms);
 
 /* Current state by persistent id: x, v, w [3][n], q [4][n], and the net

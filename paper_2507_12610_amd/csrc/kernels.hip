@@ -1,11 +1,12 @@
 // HIP kernels of one DEM time step on gfx950 (MI355X).
 //
-// Step = bounding box -> grid -> cell keys + arrival ranks -> scan of the cell
-// counts -> scatter -> stable reorder of the state into cell order -> narrow
-// phase (one pass, wave-compacted contact records, partner lists) -> contact
-// forces with spring carry-over (one lane per contact, no atomics) ->
-// integration, which first gathers each particle's contact sums in a fixed
-// order (so results do not depend on scheduling).
+// Steps that rebuild the cells: bounding box -> grid -> cell keys + arrival
+// ranks -> scan of the cell counts -> scatter -> stable reorder of the state
+// into cell order; then (every step) one kernel per tile of 256 slots: the
+// narrow phase, the contact law with the springs carried over, each
+// particle's sums in a fixed order and the integration, all in one
+// workgroup (steps that keep the cells start with a one-workgroup kernel
+// that counts the step and turns a measured drift into extra reach).
 //
 // Every kernel reads the context's flag word first and does nothing once a
 // capacity or finiteness error has been raised, so a failed step leaves the
@@ -185,8 +186,16 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(Ctx c) {
           g.dim[k] = dm > 1048576.0 ? 1048576 : (int)dm;
           g.lo[k] = L[k];
         }
-        nc *= (long long)g.dim[k];
       }
+    }
+    // bricks of 2^bits cells per axis (bits = min(3, ceil(log2 dim))); the
+    // cell table covers whole bricks
+    for (int k = 0; k < 3; ++k) {
+      int b = 0;
+      while (b < kBrickBits && (1 << b) < g.dim[k]) ++b;
+      g.bits[k] = b;
+      g.nb[k] = (g.dim[k] + (1 << b) - 1) >> b;
+      nc *= (long long)g.nb[k] << b;
     }
     g.inv_h = 1.0 / h;
     g.cell_off = 0;
@@ -287,6 +296,22 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double inv_h, int
   return f < 0.0 ? 0 : (f >= (double)dim ? dim - 1 : (int)f);
 }
 
+// Key of cell (cx, cy, cz) of a simulation's grid: the brick (row order of
+// bricks), then the cell within it with the coordinate bits interleaved
+// (x, y, z from the lowest bit up, axes with fewer bits dropping out).
+__device__ __forceinline__ int cell_key(const SimGrid& g, int cx, int cy, int cz) {
+  const int bx = g.bits[0], by = g.bits[1], bz = g.bits[2];
+  int local = 0, pos = 0;
+#pragma unroll
+  for (int b = 0; b < kBrickBits; ++b) {
+    if (b < bx) local |= ((cx >> b) & 1) << pos++;
+    if (b < by) local |= ((cy >> b) & 1) << pos++;
+    if (b < bz) local |= ((cz >> b) & 1) << pos++;
+  }
+  const int brick = ((cz >> bz) * g.nb[1] + (cy >> by)) * g.nb[0] + (cx >> bx);
+  return g.cell_off + (brick << (bx + by + bz)) + local;
+}
+
 __global__ __launch_bounds__(kThreads) void k_keys(Ctx c, State A) {
   if (c.ctr->flags) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -296,10 +321,9 @@ __global__ __launch_bounds__(kThreads) void k_keys(Ctx c, State A) {
   const int cx = cell_coord(p.x, g.lo[0], g.inv_h, g.dim[0]);
   const int cy = cell_coord(p.y, g.lo[1], g.inv_h, g.dim[1]);
   const int cz = cell_coord(p.z, g.lo[2], g.inv_h, g.dim[2]);
-  const int key = g.cell_off + (cz * g.dim[1] + cy) * g.dim[0] + cx;
+  const int key = cell_key(g, cx, cy, cz);
   c.key_tmp[i] = key;
   c.rank[i] = atomicAdd(&c.cell_cnt[key], 1);
-  c.rowmax[key - cx] = 0ull;  // the reorder takes the maxima of occupied rows
 }
 
 // ---------------------------------------------------------------------------
@@ -448,8 +472,6 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
   const int d0 = blockIdx.x * kThreads;
   const int d = d0 + (int)threadIdx.x;
   __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
-  int rk = -1 - (int)threadIdx.x;  // row of the slot's cell (unique dummy if none)
-  double rr = 0.0;
   if (d < c.n) {
     const int k = c.key_tmp[c.perm[d]];
     const int cs = c.cell_start[k], ce = c.cell_start[k + 1];
@@ -475,29 +497,10 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
     st_v[3 * t + 2] = vin[2];
     st_q[2 * t] = make_double2(q.x, q.y);
     st_q[2 * t + 1] = make_double2(q.z, q.w);
-    {
-      const SimGrid g = c.sg[c.sim_of[d]];
-      rk = k - (k - g.cell_off) % g.dim[0];
-      rr = xr.w;
-    }
     const int id = A.pid[so];
     B.pid[d] = id;
     c.key[d] = k;
     c.os[d] = make_int4(so, cold.off[so], cold.cnt[so], id);
-  }
-  // largest radius per cell row: slots are in row order, so a wave's rows
-  // are runs of lanes; a segmented maximum leaves one atomic per run
-  {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const double ov = __shfl_down(rr, o, 64);
-      const int ok = __shfl_down(rk, o, 64);
-      if (lane + o < 64 && ok == rk) rr = fmax(rr, ov);
-    }
-    const int prev = __shfl_up(rk, 1, 64);
-    if (rk >= 0 && (lane == 0 || prev != rk))
-      atomicMax(&c.rowmax[rk], (unsigned long long)__double_as_longlong(rr));
   }
   __syncthreads();
   const int np = min(c.n - d0, kThreads);
@@ -700,373 +703,25 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
 }
 
 // ---------------------------------------------------------------------------
-// 5. narrow phase (Section 3.3), one pass.  SUB adjacent lanes share one
-//    particle slot s and split its search (every SUB-th triangle of its bin
-//    and every SUB-th cell row of its search box), which shortens each
-//    lane's chain of dependent loads in the latency-bound search.  Partners
-//    are the particles with a higher slot in the cells within R_s + R_max of
-//    x_s on each axis: with cells in (z, y, x) row order each row of that box
-//    is one contiguous slot range, and rows before the own row hold only
-//    lower slots.  Each pair is thus found once, by its lower slot (the
-//    owner).  Hits go to a per-lane list in LDS; a wave prefix scan gives
-//    every lane its place (a slot's SUB lists end up adjacent) and one atomic
-//    per wave reserves the wave's records.  Pair records are also entered in
-//    the partner's list (one integer atomic per pair).
-// ---------------------------------------------------------------------------
-// The search of logical block blk.  LDS comes from the caller: the hit lists,
-// the drift reach per simulation, a reduction buffer and the wave totals.
-// With FUSED (one lane per slot), the group's first kThreads records are also
-// left in LDS (rec_a: owner slot within the group, rec_b: partner).  Returns
-// the group's record count (one lane per slot; 0 otherwise), or -1 when an
-// earlier failure is flagged.
-template <int SUB, bool FUSED>
-__device__ __forceinline__ int detect_group(const Ctx& c, const State& A, const State& B,
-                                            const Contacts& cn, const int rebuilt, const int blk,
-                                            int (*hits)[kMaxOwn][64], double* xdrift, double* red,
-                                            int* wtots, unsigned char* rec_a, int* rec_b) {
-  // the sorted copy when this step rebuilt the cells, else the kept order
-  const State S = rebuilt ? B : A;
-  const int n = c.n;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int bg = blk * kThreads;
-  const int g = bg + threadIdx.x;
-  const int s = g / SUB, sub = g % SUB;
-  // The own centre, simulation and candidate list head are loaded before the
-  // failure flag is examined (a step after a failed one exits there): none
-  // depends on the step's outcome so far.  List entries are only followed
-  // within the recorded count.
-  int sim = 0, vcnt0 = -1, vraw[4] = {s, s, s, s};
-  double4 ps = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (s < n) {
-    sim = c.nsims == 1 ? 0 : c.sim_of[s];
-    ps = S.xr[s];
-    if (c.skin_on && !rebuilt) {
-      vcnt0 = c.vcnt[g];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) vraw[u] = c.vlist[(size_t)u * c.vstride + g];
-    }
-  }
-  // A wave that sees a failure flagged searches nothing.  Another workgroup
-  // may raise a flag while this one starts, so with one lane per slot a
-  // wave that sees it still posts a zero total for the workgroup's record
-  // offsets before it leaves: the records of the waves that go on stay
-  // consistent (the step is failed and repeated anyway).
-  const bool dead = c.ctr->flags != 0;
-  if (dead && SUB != 1) return -1;
-  // a step that keeps the cells starts here (and is counted if its searches
-  // must reach past the skin)
-  if (!rebuilt && !dead && blockIdx.x == 0 && threadIdx.x == 0) {
-    atomicAdd(&c.ctr->steps, 1ull);
-    if (c.ctr->rebuild_next) c.ctr->drift_steps += 1ull;
-  }
-  // If a particle drifted past half the skin since the cells were built,
-  // every search of this step reaches by the excess further: the largest
-  // drift of each simulation of this workgroup, from the integration's
-  // per-wave partials (a rare step; the others skip this).
-  int sim_lo = 0;
-  if (!rebuilt && c.ctr->rebuild_next && bg / SUB < n) {
-    sim_lo = c.sim_of[bg / SUB];
-    const int sim_hi = c.sim_of[min(n - 1, (bg + kThreads - 1) / SUB)];
-    for (int sm = sim_lo; sm <= sim_hi; ++sm) {
-      double dmax = 0.0;
-      for (int q = c.chunk0[sm] + threadIdx.x; q < c.chunk0[sm + 1]; q += kThreads)
-        dmax = fmax(dmax, c.part[kPart * q + 6]);
-      for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
-      __syncthreads();
-      if (lane == 0) red[wv] = dmax;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double m = red[0];
-        for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, red[w]);
-        const double ex = m - c.sp[sm].half_skin;
-        xdrift[sm - sim_lo] = ex > 0.0 ? ex * (1.0 + 1e-6) : 0.0;
-      }
-    }
-    __syncthreads();
-  }
-  int npp = 0, npw = 0;
-  if (s < n && !dead) {
-    const SimGrid gr = c.sg[sim];
-    const double extra = (!rebuilt && c.ctr->rebuild_next) ? xdrift[sim - sim_lo] : 0.0;
-    const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
-    // Between rebuilds, with no drift past half the skin in this simulation,
-    // the candidates recorded at the last rebuild suffice: every particle
-    // within R_s + R_t + 2 (half skin) of x_s then, and (static meshes) every
-    // triangle within R_s + R_m + half skin.
-    const double hsk = c.sp[sim].half_skin;
-    const bool listed = c.skin_on && !rebuilt && extra == 0.0;
-    const bool record = c.skin_on && rebuilt;
-    const bool tri_listed = !c.sp[sim].moving;
-    // entry k of this lane's candidate list
-    auto vl = [&](int k) -> int& { return c.vlist[(size_t)k * c.vstride + g]; };
-    const int nlist = listed ? vcnt0 : -1;
-    int ncand = 0;
-    auto test_wall = [&](int m) {
-      const double p[3] = {xs, ys, zs};
-      double cp[3];
-      closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
-      double dx, dy, dz, d;
-      const double delta = pair_gap(xs, ys, zs, Rs, cp[0], cp[1], cp[2], c.rmesh[m], &dx, &dy, &dz, &d);
-      if (delta >= 0.0) {
-        if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = -1 - m;
-        ++npw;
-      }
-      return d;
-    };
-    auto test = [&](int t, const double4& pt) {
-      const double ex = xs - pt.x, ey = ys - pt.y, ez = zs - pt.z;
-      const double sr = Rs + pt.w;
-      // cheap conservative reject before the exactly rounded test
-      if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) return;
-      double dx, dy, dz, d;
-      const double delta = pair_gap(xs, ys, zs, Rs, pt.x, pt.y, pt.z, pt.w, &dx, &dy, &dz, &d);
-      if (delta >= 0.0) {
-        if (npw + npp < kMaxOwn) hits[wv][npw + npp][lane] = t;
-        ++npp;
-      }
-    };
-    // ---- triangles listed in the bin of x_s (unless the list holds them)
-    if (!(nlist >= 0 && tri_listed)) {
-      int k0 = 0, k1 = 0;
-      if (c.sp[sim].ntri > 0) {
-        const MeshGrid G = c.mg[sim];
-        const double fx = (xs - G.lo[0]) * G.inv_h, fy = (ys - G.lo[1]) * G.inv_h,
-                     fz = (zs - G.lo[2]) * G.inv_h;
-        if (fx >= 0.0 && fy >= 0.0 && fz >= 0.0 && fx < (double)G.dim[0] &&
-            fy < (double)G.dim[1] && fz < (double)G.dim[2]) {
-          const int b = G.off + ((int)fz * G.dim[1] + (int)fy) * G.dim[0] + (int)fx;
-          k0 = c.bin_start[b];
-          k1 = c.bin_start[b + 1];
-        }
-      }
-      const bool rec_tri = record && tri_listed;
-      for (int k = k0 + sub; k < k1; k += SUB) {
-        const int m = c.bin_tri[k];
-        const double* pl = c.tri_pl + 4 * m;
-        const double reach = (Rs + c.rmesh[m]) + (rec_tri ? hsk : 0.0);
-        const double pd = (pl[0] * xs + pl[1] * ys + pl[2] * zs) - pl[3];
-        if (fabs(pd) > reach * (1.0 + 1e-9) + 1e-300) continue;
-        const double d = test_wall(m);
-        if (rec_tri && d <= reach * (1.0 + 1e-9)) {
-          if (ncand < kCand) vl(ncand) = -1 - m;
-          ++ncand;
-        }
-      }
-    }
-    // ---- particles (and listed triangles)
-    if (nlist >= 0) {
-      // four candidates per iteration; the next four slots are loaded while
-      // these are tested (slots past the list read the own slot)
-      int tn[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) tn[u] = u < nlist ? vraw[u] : s;
-      for (int k = 0; k < nlist; k += 4) {
-        int tt[4];
-        double4 pt[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) tt[u] = tn[u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) pt[u] = S.xr[tt[u] >= 0 ? tt[u] : s];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) tn[u] = k + 4 + u < nlist ? vl(k + 4 + u) : s;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (k + u >= nlist) continue;
-          if (tt[u] >= 0)
-            test(tt[u], pt[u]);
-          else
-            (void)test_wall(-1 - tt[u]);
-        }
-      }
-    } else {
-    // The half-shell rows run from the own row through the
-    // rest of the own (y, z) plane, then over the full planes above; lane
-    // `sub` takes every SUB-th of them.  A row is searched over the x cells
-    // within rho = R_s + (largest radius in the row) of x_s, given its (y, z)
-    // distance from x_s; rows farther than rho are skipped.  The row geometry
-    // is done in cell units relative to the own cell, in float, with margins
-    // (1e-5 cell, 1e-6 relative) far above its rounding, so the search only
-    // ever widens.  The largest radius of a row is loaded two rows ahead and
-    // the slot range one row ahead of the candidates being examined.
-    const int loc = c.key[s] - gr.cell_off;
-    const int nx = gr.dim[0], ny = gr.dim[1], nz = gr.dim[2];
-    const int cx = loc % nx, cyz = loc / nx, cy = cyz % ny, cz = cyz / ny;
-    const float fx = (float)((xs - gr.lo[0]) * gr.inv_h - cx);
-    const float fy = (float)((ys - gr.lo[1]) * gr.inv_h - cy);
-    const float fz = (float)((zs - gr.lo[2]) * gr.inv_h - cz);
-    // drift allowed since the cells were built (plus any excess measured);
-    // a rebuild step looks twice as far to record the candidates
-    const double hs = record ? 2.0 * hsk : hsk + extra;
-    const double reach = ((Rs + c.sp[sim].rmax) + hs) * (1.0 + 1e-9);
-    const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, ny);
-    const int y1 = cell_coord(ys + reach, gr.lo[1], gr.inv_h, ny);
-    const int z1 = cell_coord(zs + reach, gr.lo[2], gr.inv_h, nz);
-    auto step1 = [&](int* zz, int* yy) {
-      if (++*yy > y1) {
-        ++*zz;
-        *yy = y0;
-      }
-    };
-    auto advance = [&](int* zz, int* yy) {
-#pragma unroll
-      for (int k = 0; k < SUB; ++k) step1(zz, yy);
-    };
-    auto row_at = [&](int zz, int yy) { return gr.cell_off + (zz * ny + yy) * nx; };
-    auto load_rm = [&](int zz, int yy) {
-      return zz <= z1 ? __longlong_as_double((long long)c.rowmax[row_at(zz, yy)]) : 0.0;
-    };
-    auto bounds = [&](int zz, int yy, double rm, int* t0, int* t1) {
-      *t0 = 0;
-      *t1 = 0;
-      if (zz > z1) return;
-      const float ry = (float)(yy - cy), rz = (float)(zz - cz);
-      const float dy = fmaxf(fmaxf(ry - fy, fy - (ry + 1.0f)) - 1e-5f, 0.0f);
-      const float dz = fmaxf(fmaxf(rz - fz, fz - (rz + 1.0f)) - 1e-5f, 0.0f);
-      const float rho = (float)(((Rs + rm) + hs) * gr.inv_h) * (1.0f + 1e-6f) + 1e-5f;
-      const float d2 = dy * dy + dz * dz;
-      if (d2 > rho * rho) return;
-      const float xr = sqrtf(rho * rho - d2) * (1.0f + 1e-6f) + 1e-5f;
-      const int x0 = max(0, cx + (int)floorf(fx - xr));
-      const int x1 = min(nx - 1, cx + (int)floorf(fx + xr));
-      if (x1 < x0) return;
-      const int row = row_at(zz, yy);
-      *t0 = (zz == cz && yy == cy) ? s + 1 : c.cell_start[row + x0];
-      *t1 = c.cell_start[row + x1 + 1];
-    };
-    // rows: C (candidates now), B (slot range next), A (largest radius next)
-    int zA = cz, yA = cy;
-    for (int k = 0; k < sub; ++k) step1(&zA, &yA);
-    int zB = zA, yB = yA;
-    double rmB = load_rm(zB, yB);
-    advance(&zA, &yA);
-    double rmA = load_rm(zA, yA);
-    int t0n, t1n;
-    bounds(zB, yB, rmB, &t0n, &t1n);
-    int zC = zB;
-    zB = zA;
-    yB = yA;
-    rmB = rmA;
-    advance(&zA, &yA);
-    rmA = load_rm(zA, yA);
-    while (zC <= z1) {
-      const int t0 = t0n, t1 = t1n;
-      bounds(zB, yB, rmB, &t0n, &t1n);
-      zC = zB;
-      zB = zA;
-      yB = yA;
-      rmB = rmA;
-      advance(&zA, &yA);
-      rmA = load_rm(zA, yA);
-      // four candidates per iteration so that four loads are in flight
-      for (int t = t0; t < t1; t += 4) {
-        double4 pt[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u < t1 ? t + u : t];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (t + u >= t1) break;
-          if (record) {
-            const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
-            const double sr = (Rs + pt[u].w) + 2.0 * hsk;
-            if ((ex * ex + ey * ey) + ez * ez <= sr * sr * (1.0 + 1e-9)) {
-              if (ncand < kCand) vl(ncand) = t + u;
-              ++ncand;
-            }
-          }
-          test(t + u, pt[u]);
-        }
-      }
-    }
-    if (record) c.vcnt[g] = ncand <= kCand ? ncand : -1;  // -1: search the cells
-    }
-  }
-  // wave compaction: prefix scan of the per-lane counts, then one atomic per
-  // wave on the counter of the wave's slot group (a wave's slots lie in one
-  // group, and a group's counter sees at most 4*SUB waves)
-  const int total_hits = npw + npp;
-  const int mine = total_hits < kMaxOwn ? total_hits : kMaxOwn;
-  const int incl = wave_incl_scan(mine, lane);
-  const int wtot = __shfl(incl, 63, 64);
-  const int grp = __shfl(g / SUB, 0, 64) >> kGroupShift;
-  int base = 0, tot = 0;
-  if (SUB == 1) {
-    // one lane per slot: the workgroup is the slot group, so the waves'
-    // offsets come from a scan of their totals, in slot order
-    if (lane == 63) wtots[wv] = wtot;
-    __syncthreads();
-    for (int w = 0; w < kThreads / 64; ++w) {
-      if (w < wv) base += wtots[w];
-      tot += wtots[w];
-    }
-    if (threadIdx.x == 0 && grp < c.ngroups && !dead) c.gcnt[grp] = tot;
-    if (dead) return -1;
-  } else {
-    if (lane == 63 && wtot > 0 && grp < c.ngroups) base = atomicAdd(&c.gcnt[grp], wtot);
-    base = __shfl(base, 63, 64);
-  }
-  const int first = grp * c.gcap + base + incl - mine;
-  // end of this slot's records: the last of its SUB lanes
-  const int slot_end = __shfl(first + mine, (lane | (SUB - 1)), 64);
-  if (total_hits > kMaxOwn) raise_flag(c.ctr, kFlagCapPerParticle);
-  const bool fits = base + wtot <= c.gcap;
-  if (!fits && lane == 63) {
-    atomicMax(&c.ctr->need_group, base + wtot);
-    raise_flag(c.ctr, kFlagCapContacts);
-  }
-  if (s < n && fits) {
-    if (sub == 0) {
-      cn.off[s] = first;
-      cn.cnt[s] = slot_end - first;
-    }
-    for (int k0 = 0; k0 < mine; k0 += 4) {
-      int tk[4], rk[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) tk[u] = k0 + u < mine ? hits[wv][k0 + u][lane] : -1;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (k0 + u < mine) {
-          cn.a[first + k0 + u] = s;
-          cn.b[first + k0 + u] = tk[u];
-          const int l = base + incl - mine + k0 + u;  // record within the group
-          if (FUSED && l < kThreads) {
-            rec_a[l] = (unsigned char)(s - bg);
-            rec_b[l] = tk[u];
-          }
-        }
-      }
-      // the partner-list places of up to four pairs are reserved together
-#pragma unroll
-      for (int u = 0; u < 4; ++u) rk[u] = tk[u] >= 0 ? atomicAdd(&c.pcnt[tk[u]], 1) : 0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (tk[u] < 0) continue;
-        if (rk[u] < kMaxRev)
-          c.plist[(size_t)rk[u] * c.pstride + tk[u]] = make_int2(s, first + k0 + u);
-        else
-          raise_flag(c.ctr, kFlagCapPerParticle);
-      }
-    }
-  }
-  return tot;
-}
-
-template <int SUB>
-__global__ __launch_bounds__(kThreads) void k_detect(Ctx c, State A, State B, Contacts cn,
-                                                    int rebuilt) {
-  __shared__ int hits[kThreads / 64][kMaxOwn][64];
-  __shared__ double xdrift[kThreads];
-  __shared__ double red[kThreads / 64];
-  __shared__ int wtots[kThreads / 64];
-  (void)detect_group<SUB, false>(c, A, B, cn, rebuilt, xcd_remap(blockIdx.x, gridDim.x), hits,
-                                 xdrift, red, wtots, nullptr, nullptr);
-}
-
-// ---------------------------------------------------------------------------
-// 6. contact forces and torques (Section 2.2, 2.3, 3.2), one lane per contact.
-//    On steps that keep the cells with one search lane per slot, on grids
-//    resident in one round, the search of section 5 and this law run in one
-//    workgroup per slot group (k_detect_force); otherwise k_detect and
-//    k_force are launched one after the other.
+// 5. one time step of a tile of 256 consecutive slots, in one workgroup:
+//    narrow phase (Section 3.3), contact law with the springs carried over
+//    (Section 2.2, 2.3), per-particle sums (Section 3.2) and integration
+//    (Eq. v, x, spiral, w; Stokes drag of Section 2.1).
+//
+//    Each lane searches for every contact of its particle (full shell: all
+//    neighbours, not only higher slots).  Contacts are then sorted into
+//      - owned: walls and partners in a higher slot: evaluated here, springs
+//        written here;
+//      - cross: partners in a lower slot outside the tile: evaluated here as
+//        well (the partner's tile evaluates the same pair, bit for bit, and
+//        writes its springs), this tile keeps only its own side;
+//      - references: partners in a lower slot inside the tile: the owner's
+//        record gives this particle's side.
+//    So no contact result leaves the workgroup: every particle's force and
+//    torque are complete in LDS, and the tile integrates its particles at
+//    once.  Per particle the sum runs in a fixed order (pass by pass: owned
+//    records, cross records, references), so results do not depend on
+//    scheduling.
 // ---------------------------------------------------------------------------
 // Static/kinetic update of a vector friction mode m in {s, r}: rotate the old
 // spring into the tangent plane keeping its length, f = -k u - c v, then keep
@@ -1122,6 +777,129 @@ __device__ __forceinline__ double sphere_mass(double rho, double R) {
   return (4.0 / 3.0) * kPi * rho * (R * R * R);
 }
 
+// The contact law of one contact.  Body I (centre and radius pi, velocity and
+// spin vi) carries the lower persistent id, or is the particle of a wall
+// contact; body J is the other particle, or for a wall the closest point of
+// element m (pj.xyz) and the element radius (pj.w).  The springs us, ur, ut
+// (orientation of body I) come in as carried over and leave updated.  Out:
+// o[0..2] force on I, o[3..5] torque on I, o[6..8] torque on J (the force on
+// J is -o[0..2]; Section 3.2).
+template <typename RT>
+__device__ __forceinline__ void contact_law(const Ctx& c, const SimParams& P, const bool wall,
+                                            const int m, const double4 pi, const double4 pj,
+                                            const double2 vi0, const double2 vi1,
+                                            const double2 vi2, const double2 vj0,
+                                            const double2 vj1, const double2 vj2, double us[3],
+                                            double ur[3], double* ut, double o[9]) {
+  const double Ri = pi.w, Rj = pj.w;
+  double dx, dy, dz, d;
+  const double delta = pair_gap(pi.x, pi.y, pi.z, Ri, pj.x, pj.y, pj.z, Rj, &dx, &dy, &dz, &d);
+  const double invd = 1.0 / d;
+  const RT nrm[3] = {(RT)(dx * invd), (RT)(dy * invd), (RT)(dz * invd)};
+  const double ri = Ri - 0.5 * delta;
+  const double mi = sphere_mass(P.rho, Ri);
+  const double vix = vi0.x, viy = vi0.y, viz = vi1.x;
+  const double wix = vi1.y, wiy = vi2.x, wiz = vi2.y;
+  double rj, Rs, ms, Es, Gs, cnf, csf, reff;
+  double vrel[3], om[3];
+  const double n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
+  if (!wall) {
+    const double vjx = vj0.x, vjy = vj0.y, vjz = vj1.x;
+    const double wjx = vj1.y, wjy = vj2.x, wjz = vj2.y;
+    rj = Rj - 0.5 * delta;
+    const double mj = sphere_mass(P.rho, Rj);
+    // effective radius and mass 1/(1/a + 1/b) written as a b / (a + b)
+    Rs = (Ri * Rj) / (Ri + Rj);
+    ms = (mi * mj) / (mi + mj);
+    cnf = P.cnf_pp;
+    csf = P.csf_pp;
+    Es = P.Es_pp;
+    Gs = P.Gs_pp;
+    reff = (ri * rj) / (ri + rj);
+    // v = v_i - v_j + n x (r_i w_i + r_j w_j)
+    const double rx = ri * wix + rj * wjx, ry = ri * wiy + rj * wjy, rz = ri * wiz + rj * wjz;
+    vrel[0] = (vix - vjx) + (n1 * rz - n2 * ry);
+    vrel[1] = (viy - vjy) + (n2 * rx - n0 * rz);
+    vrel[2] = (viz - vjz) + (n0 * ry - n1 * rx);
+    om[0] = wix - wjx;
+    om[1] = wiy - wjy;
+    om[2] = wiz - wjz;
+  } else {
+    rj = 0.0;
+    Rs = Ri;
+    ms = mi;
+    cnf = P.cnf_pw;
+    csf = P.csf_pw;
+    Es = P.Es_pw;
+    Gs = P.Gs_pw;
+    reff = ri;
+    double vw0 = 0.0, vw1 = 0.0, vw2 = 0.0;
+    double sw0 = 0.0, sw1 = 0.0, sw2 = 0.0;
+    if (P.moving) {  // wall material velocity at the contact point p + R_m n
+      const double* mv = c.tri_mv + 9 * (size_t)m;
+      sw0 = mv[0];
+      sw1 = mv[1];
+      sw2 = mv[2];
+      const double px = (pj.x + Rj * n0) - mv[3];
+      const double py = (pj.y + Rj * n1) - mv[4];
+      const double pz = (pj.z + Rj * n2) - mv[5];
+      vw0 = (sw1 * pz - sw2 * py) + mv[6];
+      vw1 = (sw2 * px - sw0 * pz) + mv[7];
+      vw2 = (sw0 * py - sw1 * px) + mv[8];
+    }
+    const double rx = ri * wix, ry = ri * wiy, rz = ri * wiz;
+    vrel[0] = (vix - vw0) + (n1 * rz - n2 * ry);
+    vrel[1] = (viy - vw1) + (n2 * rx - n0 * rz);
+    vrel[2] = (viz - vw2) + (n0 * ry - n1 * rx);
+    om[0] = wix - sw0;
+    om[1] = wiy - sw1;
+    om[2] = wiz - sw2;
+  }
+  // coefficients (Eq. ks, cn, cs; k_r = k_n, c_r = c_n, k_t = k_s, c_t = c_s)
+  // with k_n = 4/3 E* a and k_s = 8 G* a: c_n = beta sqrt(20/3 E*) sqrt(m* a)
+  // and c_s = beta sqrt(4/3 G*) sqrt(m* a), the constant factors per simulation
+  const RT ac = (RT)sqrt(Rs * delta);
+  const RT kn = (RT)(4.0 / 3.0) * (RT)Es * ac;
+  const RT ks = (RT)8.0 * (RT)Gs * ac;
+  const RT sm = sqrt((RT)ms * ac);
+  const RT cn = (RT)cnf * sm;
+  const RT cs = (RT)csf * sm;
+  // relative velocities
+  const RT v0 = (RT)vrel[0], v1 = (RT)vrel[1], v2 = (RT)vrel[2];
+  const RT vnn = (v0 * nrm[0] + v1 * nrm[1]) + v2 * nrm[2];
+  const RT vn[3] = {vnn * nrm[0], vnn * nrm[1], vnn * nrm[2]};
+  const RT vs[3] = {v0 - vn[0], v1 - vn[1], v2 - vn[2]};
+  const RT o0 = (RT)om[0], o1 = (RT)om[1], o2 = (RT)om[2];
+  const RT re = (RT)reff;
+  const RT vr[3] = {re * (o1 * nrm[2] - o2 * nrm[1]), re * (o2 * nrm[0] - o0 * nrm[2]),
+                    re * (o0 * nrm[1] - o1 * nrm[0])};
+  const RT vt = (RT)Rs * ((o0 * nrm[0] + o1 * nrm[1]) + o2 * nrm[2]);
+  // normal force f_n = k_n delta n - c_n v_n
+  const RT kd = kn * (RT)delta;
+  const RT fn[3] = {kd * nrm[0] - cn * vn[0], kd * nrm[1] - cn * vn[1], kd * nrm[2] - cn * vn[2]};
+  const RT fnl = sqrt((fn[0] * fn[0] + fn[1] * fn[1]) + fn[2] * fn[2]);
+  RT fs[3], fr[3], ft;
+  friction_vec<RT>(nrm, ks, cs, (RT)P.mu_s * fnl, P.dt, vs, us, fs);
+  friction_vec<RT>(nrm, kn, cn, (RT)P.mu_r * fnl, P.dt, vr, ur, fr);
+  friction_scalar<RT>(ks, cs, (RT)P.mu_t * fnl, P.dt, vt, ut, &ft);
+  // torques: tau_s = r_i f_s x n, tau_r = R* n x f_r, tau_t = f_t R* n;
+  // body j: -f, r_j f_s x n - tau_r - tau_t (Eq. antisymm_*)
+  const RT fsxn[3] = {fs[1] * nrm[2] - fs[2] * nrm[1], fs[2] * nrm[0] - fs[0] * nrm[2],
+                      fs[0] * nrm[1] - fs[1] * nrm[0]};
+  const RT rs = (RT)Rs;
+  const RT tr[3] = {rs * (nrm[1] * fr[2] - nrm[2] * fr[1]), rs * (nrm[2] * fr[0] - nrm[0] * fr[2]),
+                    rs * (nrm[0] * fr[1] - nrm[1] * fr[0])};
+  const RT ftr = ft * rs;
+  const RT rif = (RT)ri, rjf = (RT)rj;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double ttr = (double)tr[k] + (double)(ftr * nrm[k]);
+    o[k] = (double)fn[k] + (double)fs[k];
+    o[3 + k] = (double)(rif * fsxn[k]) + ttr;
+    o[6 + k] = wall ? 0.0 : (double)(rjf * fsxn[k]) - ttr;
+  }
+}
+
 // Record of key (ki, kj) among the n contacts that the previous owner slot
 // owned in the previous step (records b0 ..), or -1 if the pair was not in
 // contact.  Keys are probed four at a time so that their loads overlap.
@@ -1137,435 +915,6 @@ __device__ __forceinline__ int find_old(const Contacts& co, int b0, int n, int2 
   return -1;
 }
 
-// The contact law over the cnt records of slot group grp (the lane's record
-// of the first pass in ra, rb; ng: the group's previous record count).  The
-// spring and result records of one pass are staged in LDS (st_spr, st_res)
-// and written out as contiguous runs (per-lane 64- and 80-byte records
-// written directly would make every store instruction scatter); okey and red
-// are LDS for the previous keys and the contact counts.
-template <typename RT>
-__device__ __forceinline__ void force_group(const Ctx& c, const State& S, const Contacts& cur,
-                                            const Contacts& old, const int rebuilt, const int grp,
-                                            const int ra, const int rb, const int ng,
-                                            const int cnt, double2* st_spr, double2* st_res,
-                                            int2* okey, int (*red)[kThreads / 64]) {
-  const int tid = (int)threadIdx.x;
-  const int gbase = grp * c.gcap;
-  if (tid == 0) cur.ng[grp] = cnt;
-  int npp = 0, npw = 0;
-  // The contact law of one record (body I carries the lower id): the updated
-  // springs are staged in LDS at this lane's place, the forces and torques
-  // returned in o.
-  auto law = [&](const SimParams& P, const bool wall, const int m, const bool swap,
-                 const double4 pi, const double4 pj, const double2 va0, const double2 va1,
-                 const double2 va2, const double2 vb0, const double2 vb1, const double2 vb2,
-                 double* us, double* ur, double ut, const int e, const int2 key, double* o) {
-    const double Ri = pi.w, Rj = pj.w;
-    double dx, dy, dz, d;
-    const double delta = pair_gap(pi.x, pi.y, pi.z, Ri, pj.x, pj.y, pj.z, Rj, &dx, &dy, &dz, &d);
-    const double invd = 1.0 / d;
-    const RT nrm[3] = {(RT)(dx * invd), (RT)(dy * invd), (RT)(dz * invd)};
-    const double ri = Ri - 0.5 * delta;
-    const double mi = sphere_mass(P.rho, Ri);
-    const double2 vi0 = swap ? vb0 : va0, vi1 = swap ? vb1 : va1, vi2 = swap ? vb2 : va2;
-    const double vix = vi0.x, viy = vi0.y, viz = vi1.x;
-    const double wix = vi1.y, wiy = vi2.x, wiz = vi2.y;
-    double rj, Rs, ms, Es, Gs, cnf, csf, reff;
-    double vrel[3], om[3];
-    const double n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
-    if (!wall) {
-      const double2 vj0 = swap ? va0 : vb0, vj1 = swap ? va1 : vb1, vj2 = swap ? va2 : vb2;
-      const double vjx = vj0.x, vjy = vj0.y, vjz = vj1.x;
-      const double wjx = vj1.y, wjy = vj2.x, wjz = vj2.y;
-      rj = Rj - 0.5 * delta;
-      const double mj = sphere_mass(P.rho, Rj);
-      // effective radius and mass 1/(1/a + 1/b) written as a b / (a + b)
-      Rs = (Ri * Rj) / (Ri + Rj);
-      ms = (mi * mj) / (mi + mj);
-      cnf = P.cnf_pp;
-      csf = P.csf_pp;
-      Es = P.Es_pp;
-      Gs = P.Gs_pp;
-      reff = (ri * rj) / (ri + rj);
-      // v = v_i - v_j + n x (r_i w_i + r_j w_j)
-      const double rx = ri * wix + rj * wjx, ry = ri * wiy + rj * wjy, rz = ri * wiz + rj * wjz;
-      vrel[0] = (vix - vjx) + (n1 * rz - n2 * ry);
-      vrel[1] = (viy - vjy) + (n2 * rx - n0 * rz);
-      vrel[2] = (viz - vjz) + (n0 * ry - n1 * rx);
-      om[0] = wix - wjx;
-      om[1] = wiy - wjy;
-      om[2] = wiz - wjz;
-    } else {
-      rj = 0.0;
-      Rs = Ri;
-      ms = mi;
-      cnf = P.cnf_pw;
-      csf = P.csf_pw;
-      Es = P.Es_pw;
-      Gs = P.Gs_pw;
-      reff = ri;
-      double vw0 = 0.0, vw1 = 0.0, vw2 = 0.0;
-      double sw0 = 0.0, sw1 = 0.0, sw2 = 0.0;
-      if (P.moving) {  // wall material velocity at the contact point p + R_m n
-        const double* mv = c.tri_mv + 9 * (size_t)m;
-        sw0 = mv[0];
-        sw1 = mv[1];
-        sw2 = mv[2];
-        const double px = (pj.x + Rj * n0) - mv[3];
-        const double py = (pj.y + Rj * n1) - mv[4];
-        const double pz = (pj.z + Rj * n2) - mv[5];
-        vw0 = (sw1 * pz - sw2 * py) + mv[6];
-        vw1 = (sw2 * px - sw0 * pz) + mv[7];
-        vw2 = (sw0 * py - sw1 * px) + mv[8];
-      }
-      const double rx = ri * wix, ry = ri * wiy, rz = ri * wiz;
-      vrel[0] = (vix - vw0) + (n1 * rz - n2 * ry);
-      vrel[1] = (viy - vw1) + (n2 * rx - n0 * rz);
-      vrel[2] = (viz - vw2) + (n0 * ry - n1 * rx);
-      om[0] = wix - sw0;
-      om[1] = wiy - sw1;
-      om[2] = wiz - sw2;
-    }
-    // coefficients (Eq. ks, cn, cs; k_r = k_n, c_r = c_n, k_t = k_s, c_t = c_s)
-    // with k_n = 4/3 E* a and k_s = 8 G* a: c_n = beta sqrt(20/3 E*) sqrt(m* a)
-    // and c_s = beta sqrt(4/3 G*) sqrt(m* a), the constant factors per simulation
-    const RT ac = (RT)sqrt(Rs * delta);
-    const RT kn = (RT)(4.0 / 3.0) * (RT)Es * ac;
-    const RT ks = (RT)8.0 * (RT)Gs * ac;
-    const RT sm = sqrt((RT)ms * ac);
-    const RT cn = (RT)cnf * sm;
-    const RT cs = (RT)csf * sm;
-    // relative velocities
-    const RT v0 = (RT)vrel[0], v1 = (RT)vrel[1], v2 = (RT)vrel[2];
-    const RT vnn = (v0 * nrm[0] + v1 * nrm[1]) + v2 * nrm[2];
-    const RT vn[3] = {vnn * nrm[0], vnn * nrm[1], vnn * nrm[2]};
-    const RT vs[3] = {v0 - vn[0], v1 - vn[1], v2 - vn[2]};
-    const RT o0 = (RT)om[0], o1 = (RT)om[1], o2 = (RT)om[2];
-    const RT re = (RT)reff;
-    const RT vr[3] = {re * (o1 * nrm[2] - o2 * nrm[1]), re * (o2 * nrm[0] - o0 * nrm[2]),
-                      re * (o0 * nrm[1] - o1 * nrm[0])};
-    const RT vt = (RT)Rs * ((o0 * nrm[0] + o1 * nrm[1]) + o2 * nrm[2]);
-    // normal force f_n = k_n delta n - c_n v_n
-    const RT kd = kn * (RT)delta;
-    const RT fn[3] = {kd * nrm[0] - cn * vn[0], kd * nrm[1] - cn * vn[1], kd * nrm[2] - cn * vn[2]};
-    const RT fnl = sqrt((fn[0] * fn[0] + fn[1] * fn[1]) + fn[2] * fn[2]);
-    RT fs[3], fr[3], ft;
-    friction_vec<RT>(nrm, ks, cs, (RT)P.mu_s * fnl, P.dt, vs, us, fs);
-    friction_vec<RT>(nrm, kn, cn, (RT)P.mu_r * fnl, P.dt, vr, ur, fr);
-    friction_scalar<RT>(ks, cs, (RT)P.mu_t * fnl, P.dt, vt, &ut, &ft);
-    cur.key[e] = key;
-    {
-      double2* r = st_spr + (kSpr / 2) * threadIdx.x;
-      r[0] = make_double2(us[0], us[1]);
-      r[1] = make_double2(us[2], ur[0]);
-      r[2] = make_double2(ur[1], ur[2]);
-      r[3] = make_double2(ut, 0.0);
-    }
-    // torques: tau_s = r_i f_s x n, tau_r = R* n x f_r, tau_t = f_t R* n;
-    // body j: -f, r_j f_s x n - tau_r - tau_t (Eq. antisymm_*)
-    const RT fsxn[3] = {fs[1] * nrm[2] - fs[2] * nrm[1], fs[2] * nrm[0] - fs[0] * nrm[2],
-                        fs[0] * nrm[1] - fs[1] * nrm[0]};
-    const RT rs = (RT)Rs;
-    const RT tr[3] = {rs * (nrm[1] * fr[2] - nrm[2] * fr[1]), rs * (nrm[2] * fr[0] - nrm[0] * fr[2]),
-                      rs * (nrm[0] * fr[1] - nrm[1] * fr[0])};
-    const RT ftr = ft * rs;
-    const RT rif = (RT)ri, rjf = (RT)rj;
-    npp += wall ? 0 : 1;
-    npw += wall ? 1 : 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double f = (double)fn[k] + (double)fs[k];
-      const double ttr = (double)tr[k] + (double)(ftr * nrm[k]);
-      const double ti = (double)(rif * fsxn[k]) + ttr;
-      const double tj = wall ? 0.0 : (double)(rjf * fsxn[k]) - ttr;
-      // per-contact results for the owner slot a and the partner b
-      o[k] = swap ? -f : f;
-      o[3 + k] = swap ? ti : tj;  // torque on the partner
-      o[6 + k] = swap ? tj : ti;  // torque on the owner
-    }
-    o[9] = 0.0;
-  };
-  auto stage_res = [&](const double* o) {
-    double2* r = st_res + (kRes / 2) * threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < kRes / 2; ++k) r[k] = make_double2(o[2 * k], o[2 * k + 1]);
-  };
-  auto write_out = [&](const int base) {
-    const int nrec = min(cnt - base, kThreads);
-    double2* gs = reinterpret_cast<double2*>(cur.spr + (size_t)kSpr * (gbase + base));
-    for (int k = tid; k < nrec * (kSpr / 2); k += kThreads) gs[k] = st_spr[k];
-    double2* gr = reinterpret_cast<double2*>(c.res + (size_t)kRes * (gbase + base));
-    for (int k = tid; k < nrec * (kRes / 2); k += kThreads) gr[k] = st_res[k];
-  };
-  if (!rebuilt && cnt <= kThreads) {
-    // The slot order was kept and the group's records fit one pass: the
-    // previous step's records owned by this group's slots are the previous
-    // records of the same group range.  Their keys and springs (the first
-    // 256) come to LDS in contiguous runs while the bodies are gathered, and
-    // each contact finds its springs there (the owner is the lower slot, a
-    // slot of this group).  Two rounds of dependent loads instead of four.
-    // The previous springs are held in the result staging buffer, which the
-    // law's results overwrite only after every lane has read its springs.
-    const bool act = tid < cnt;
-    const int on = min(ng, kThreads);
-    if (tid < on) {
-      okey[tid] = old.key[gbase + tid];
-      const double2* r = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * (gbase + tid));
-      double2* d = st_res + (kSpr / 2) * tid;
-      d[0] = r[0];
-      d[1] = r[1];
-      d[2] = r[2];
-      d[3] = r[3];
-    }
-    const int a = ra, b = rb;
-    const bool wall = b < 0;
-    const SimParams* Pp = c.sp;
-    double4 pa = make_double4(0.0, 0.0, 0.0, 0.0), pb = pa;
-    double2 va0 = make_double2(0.0, 0.0), va1 = va0, va2 = va0, vb0 = va0, vb1 = va0, vb2 = va0;
-    int ida = 0, idb = 0, m = 0, off = 0, n_o = 0;
-    if (act) {
-      Pp = c.sp + (c.nsims == 1 ? 0 : c.sim_of[a]);
-      pa = S.xr[a];
-      ida = S.pid[a];
-      off = old.off[a];  // the owner's previous segment
-      n_o = old.cnt[a];
-      const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
-      va0 = va[0];
-      va1 = va[1];
-      va2 = va[2];
-      if (!wall) {
-        pb = S.xr[b];
-        idb = S.pid[b];
-        const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
-        vb0 = vb[0];
-        vb1 = vb[1];
-        vb2 = vb[2];
-      } else {
-        m = -1 - b;
-        const double p[3] = {pa.x, pa.y, pa.z};
-        double cp[3];
-        closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
-        pb = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
-      }
-    }
-    __syncthreads();
-    double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
-    bool swap = false;
-    int2 key = make_int2(0, 0);
-    if (act) {
-      swap = !wall && ida > idb;
-      key = wall ? make_int2(ida, -(m - Pp->tri0)) : make_int2(swap ? idb : ida, swap ? ida : idb);
-      const int rel = off - gbase;
-      double2 r0 = make_double2(0.0, 0.0), r1 = r0, r2 = r0, r3 = r0;
-      bool found = false;
-      if (n_o > 0 && rel >= 0 && rel + n_o <= on) {
-        for (int k = 0; k < n_o; ++k) {
-          const int2 kk = okey[rel + k];
-          if (kk.x == key.x && kk.y == key.y) {
-            const double2* q = st_res + (kSpr / 2) * (rel + k);
-            r0 = q[0];
-            r1 = q[1];
-            r2 = q[2];
-            r3 = q[3];
-            found = true;
-            break;
-          }
-        }
-      } else {
-        const int eo = find_old(old, off, n_o, key);
-        if (eo >= 0) {
-          const double2* q = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
-          r0 = q[0];
-          r1 = q[1];
-          r2 = q[2];
-          r3 = q[3];
-          found = true;
-        }
-      }
-      if (found) {
-        us[0] = r0.x;
-        us[1] = r0.y;
-        us[2] = r1.x;
-        ur[0] = r1.y;
-        ur[1] = r2.x;
-        ur[2] = r2.y;
-        ut = r3.x;
-      }
-    }
-    double o[kRes];
-    if (act)
-      law(*Pp, wall, m, swap, swap ? pb : pa, swap ? pa : pb, va0, va1, va2, vb0, vb1, vb2, us, ur,
-          ut, gbase + tid, key, o);
-    __syncthreads();  // every lane has read its previous springs
-    if (act) stage_res(o);
-    __syncthreads();
-    write_out(0);
-  } else {
-    // (previous slot, its previous contact segment, id): carried by the
-    // reorder, or the slot itself when the order was kept
-    auto origin = [&](int p) {
-      return rebuilt ? c.os[p] : make_int4(p, old.off[p], old.cnt[p], S.pid[p]);
-    };
-    for (int base = 0; base < cnt; base += kThreads) {
-      const int l = base + tid;
-      if (l < cnt) {
-        const int e = gbase + l;
-        const int a = cur.a[e], b = cur.b[e];
-        const bool wall = b < 0;
-        const SimParams& P = c.sp[c.nsims == 1 ? 0 : c.sim_of[a]];
-        // both bodies are gathered at once; the canonical orientation is then
-        // chosen in registers
-        const double4 pa = S.xr[a];
-        const int4 oa = origin(a);
-        const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
-        const double2 va0 = va[0], va1 = va[1], va2 = va[2];
-        double4 pb;
-        int4 ob = oa;
-        double2 vb0 = make_double2(0.0, 0.0), vb1 = vb0, vb2 = vb0;
-        int m = 0;
-        if (!wall) {
-          pb = S.xr[b];
-          // with the order kept the owner is the lower slot, so only the
-          // partner's id is needed
-          ob = rebuilt ? c.os[b] : make_int4(b, 0, 0, S.pid[b]);
-          const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
-          vb0 = vb[0];
-          vb1 = vb[1];
-          vb2 = vb[2];
-        } else {
-          m = -1 - b;
-          const double p[3] = {pa.x, pa.y, pa.z};
-          double cp[3];
-          closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
-          pb = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
-        }
-        // canonical orientation: body I carries the lower id (the particle for walls)
-        const int ida = oa.w, idb = ob.w;
-        const bool swap = !wall && ida > idb;
-        const double4 pi = swap ? pb : pa, pj = swap ? pa : pb;
-        const int2 key = wall ? make_int2(ida, -(m - P.tri0))
-                              : make_int2(swap ? idb : ida, swap ? ida : idb);
-        // springs of the previous step (zero for a new contact), looked up among
-        // the records of the previous owner: the lower previous slot of the two
-        double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
-        {
-          const bool bown = !wall && ob.x < oa.x;
-          const int eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
-          if (eo >= 0) {
-            const double2* r = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
-            const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-            us[0] = r0.x;
-            us[1] = r0.y;
-            us[2] = r1.x;
-            ur[0] = r1.y;
-            ur[1] = r2.x;
-            ur[2] = r2.y;
-            ut = r3.x;
-          }
-        }
-        double o[kRes];
-        law(P, wall, m, swap, pi, pj, va0, va1, va2, vb0, vb1, vb2, us, ur, ut, e, key, o);
-        stage_res(o);
-      }
-      __syncthreads();
-      write_out(base);
-      __syncthreads();
-    }
-  }
-  // contact counts of the group for the statistics (summed by the next step's
-  // grid kernel or by the host)
-  const int a = wave_sum_i32(npp), b = wave_sum_i32(npw);
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = a;
-    red[1][threadIdx.x >> 6] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int ta = 0, tb = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      ta += red[0][w];
-      tb += red[1][w];
-    }
-    // running sums, one writer per group: adds without a return value, so
-    // the kernel's end does not wait for a read
-    atomicAdd(&c.gstat[2 * grp], (unsigned long long)ta);
-    atomicAdd(&c.gstat[2 * grp + 1], (unsigned long long)tb);
-  }
-}
-
-template <typename RT>
-__global__ __launch_bounds__(kThreads, 4) void k_force(Ctx c, State A, State B, Contacts cur,
-                                                      Contacts old, int rebuilt) {
-  const State S = rebuilt ? B : A;
-  const int tid = (int)threadIdx.x;
-  // one workgroup per slot group (on grids of one round, consecutive groups
-  // share an XCD and its L2)
-  const int grp = xcd_remap(blockIdx.x, gridDim.x);
-  const int gbase = grp * c.gcap;
-  // loads that depend on nothing else, issued together: this lane's record
-  // of the first pass, the group's record count and, when the slot order was
-  // kept, the group's previous record count
-  int ra = 0, rb = 0;
-  if (tid < c.gcap) {
-    ra = cur.a[gbase + tid];
-    rb = cur.b[gbase + tid];
-  }
-  const int ng = rebuilt ? 0 : old.ng[grp];
-  const int cnt = min(c.gcnt[grp], c.gcap);
-  // (the failure flag is examined once these loads are in flight; the
-  // records are only followed after it)
-  if (c.ctr->flags) return;
-  __shared__ double2 st_spr[kThreads * kSpr / 2];
-  __shared__ double2 st_res[kThreads * kRes / 2];
-  __shared__ int2 okey[kThreads];
-  __shared__ int red[2][kThreads / 64];
-  force_group<RT>(c, S, cur, old, rebuilt, grp, ra, rb, ng, cnt, st_spr, st_res, okey, red);
-}
-
-// The search and the contact law of one slot group in one workgroup, for
-// steps that keep the cells with one search lane per slot: the group's
-// records reach the law through LDS (no second launch, no reload of the
-// records), and the law's staging reuses the search's LDS (hit lists, drift
-// reach), which is dead once the records are written.
-template <typename RT>
-__global__ __launch_bounds__(kThreads, 4) void k_detect_force(Ctx c, State A, State B,
-                                                             Contacts cn, Contacts old) {
-  constexpr int kHits2 = (kThreads / 64) * kMaxOwn * 64 * (int)sizeof(int) / 16;
-  constexpr int kSearch2 = kHits2 + kThreads * (int)sizeof(double) / 16;
-  constexpr int kLaw2 = kThreads * (kSpr + kRes) / 2;
-  __shared__ double2 pool[kLaw2 > kSearch2 ? kLaw2 : kSearch2];
-  __shared__ int2 okey[kThreads];
-  __shared__ int rec_b[kThreads];
-  __shared__ unsigned char rec_a[kThreads];
-  __shared__ double red_d[kThreads / 64];
-  __shared__ int wtots[kThreads / 64];
-  __shared__ int red_i[2][kThreads / 64];
-  const int grp = xcd_remap(blockIdx.x, gridDim.x);
-  const int ng = old.ng[grp];
-  const int tot = detect_group<1, true>(c, A, B, cn, 0, grp,
-                                        reinterpret_cast<int(*)[kMaxOwn][64]>(pool),
-                                        reinterpret_cast<double*>(pool + kHits2), red_d, wtots,
-                                        rec_a, rec_b);
-  // no forces after a flagged failure, or when this group's records did not
-  // fit (flagged by the search: the step is repeated with more room)
-  if (tot < 0 || tot > c.gcap) return;
-  __syncthreads();  // the records are in LDS and global memory; the hit lists are dead
-  const int tid = (int)threadIdx.x;
-  int ra = 0, rb = 0;
-  if (tid < tot) {
-    ra = grp * kThreads + rec_a[tid];
-    rb = rec_b[tid];
-  }
-  force_group<RT>(c, A, cn, old, 0, grp, ra, rb, ng, tot, pool, pool + kThreads * kSpr / 2, okey,
-                  red_i);
-}
-
-// ---------------------------------------------------------------------------
-// 7. integration: gather the contact sums of each particle in a fixed order
-//    (owned contacts in record order, then partner contacts by ascending
-//    owner slot), then semi-implicit Euler (Eq. v, x), SPIRAL (Eq. spiral)
-//    with the old angular velocity, then Eq. w; Stokes drag (Section 2.1)
-// ---------------------------------------------------------------------------
 // sin(x)/x and cos(x).  The rotation angles of one step are tiny (|x| of
 // order 1e-5), where the Taylor polynomials below are exact to far below one
 // rounding (first omitted terms x^8/9! and x^10/10!, < 1e-24 relative for
@@ -1594,239 +943,613 @@ __device__ __forceinline__ void qmul(const double a[4], const double b[4], doubl
   o[3] = z;
 }
 
-__global__ __launch_bounds__(kThreads) void k_integrate(Ctx c, State A, State B, Contacts cur,
-                                                       int rebuilt) {
-  // reads the step's state (the sorted copy B, or A when the order was
-  // kept) and writes the new state to B
-  const State S = rebuilt ? B : A;
-  const int n = c.n;
-  const int i0 = xcd_remap(blockIdx.x, gridDim.x) * kThreads;
-  const int i = i0 + (int)threadIdx.x;
-  // The particle's own state and contact counts are loaded before the
-  // failure flag is examined (a step after a failed one exits here): these
-  // loads do not depend on the step's outcome so far, and the flag's round
-  // trip then overlaps them.
-  int sim = 0, e0 = 0, ne = 0, pc = 0;
-  double4 xr = make_double4(0.0, 0.0, 0.0, 0.0), q4 = xr;
-  double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
-  if (i < n) {
-    sim = c.nsims == 1 ? 0 : c.sim_of[i];
-    xr = S.xr[i];
-    q4 = S.q[i];
-    const double2* vw2 = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)i);
-    s0 = vw2[0];
-    s1 = vw2[1];
-    s2 = vw2[2];
-    e0 = cur.off[i];
-    ne = cur.cnt[i];
-    pc = c.pcnt[i];
+// Block-wide exclusive scan of three counters at once (one value each per
+// lane, lanes in slot order); returns the totals.  w3: LDS [waves][3].
+__device__ __forceinline__ void block_scan3(int a, int b, int d, int* ea, int* eb, int* ed,
+                                            int* ta, int* tb, int* td, int (*w3)[3]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int ia = a, ib = b, id = d;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int ya = __shfl_up(ia, o, 64), yb = __shfl_up(ib, o, 64), yd = __shfl_up(id, o, 64);
+    if (lane >= o) {
+      ia += ya;
+      ib += yb;
+      id += yd;
+    }
   }
+  if (lane == 63) {
+    w3[wv][0] = ia;
+    w3[wv][1] = ib;
+    w3[wv][2] = id;
+  }
+  __syncthreads();
+  int pa = 0, pb = 0, pd = 0, sa = 0, sb = 0, sd = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    if (w < wv) {
+      pa += w3[w][0];
+      pb += w3[w][1];
+      pd += w3[w][2];
+    }
+    sa += w3[w][0];
+    sb += w3[w][1];
+    sd += w3[w][2];
+  }
+  *ea = pa + ia - a;
+  *eb = pb + ib - b;
+  *ed = pd + id - d;
+  *ta = sa;
+  *tb = sb;
+  *td = sd;
+}
+
+// LDS of the step kernel.  The search's hit lists, the law's per-pass results
+// and spring staging, and the integration's state staging share one pool.
+struct StepLds {
+  union {
+    int hits[kThreads / 64][kHit][64];
+    struct {
+      double res[kThreads][9];    // force on I, torque on I, torque on J
+      double spr[kThreads][kSpr];  // updated springs of owned records
+      int2 key[kThreads];
+    } law;
+    struct {
+      double2 x[kThreads * 2], v[kThreads * 3], q[kThreads * 2];
+    } out;
+  } pool;
+  int2 rec[kLdsRec];       // work list: (lane, partner)
+  int ref[kLdsRef];        // references: partner slot, then the owner's record
+  int ooff[kThreads];      // first owned record of each lane
+  int ocnt[kThreads];      // owned records of each lane
+  int w3[kThreads / 64][3];
+  int cnt2[2][kThreads / 64];
+  int flags;
+};
+
+// Opens a step that keeps the cells: counts it, and if the previous step saw
+// a particle drift past half the skin, turns that into this step's extra
+// reach per simulation (largest drift of its particles beyond half the skin,
+// from the per-wave partials).  The step kernel reads what this writes; its
+// own integration raises the flag for the next step.
+constexpr int kBeginThreads = 1024;
+__global__ __launch_bounds__(kBeginThreads) void k_begin(Ctx c) {
   if (c.ctr->flags) return;
-  // new states are staged in LDS and written out as contiguous runs
-  __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
-  bool drift = false;
-  double ddrift = 0.0;
-  if (i < n) {
-  const double* res = c.res;
-  const SimParams& P = c.sp[sim];
-  double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
-  {
-    // the partner list is loaded first, so that its gathers and those of
-    // the owned records are in flight together
-    const int e1 = e0 + ne;
-    const int m = min(pc, kMaxRev);
-    c.pcnt[i] = 0;  // cleared for the next step's narrow phase
-    auto pl = [&](int j) { return c.plist[(size_t)j * c.pstride + i]; };
-    int ka[8], ke[8];
-    if (m <= 8) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int2 v = j < m ? pl(j) : make_int2(0x7fffffff, -1);
-        ka[j] = v.x;
-        ke[j] = v.y;
-      }
-    }
-    // owned contacts in record order, four records in flight: the force
-    // (doubles 0..2) and the owner's torque (6..8)
-    for (int e = e0; e < e1; e += 4) {
-      double2 f[4][4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double2* r = reinterpret_cast<const double2*>(res + (size_t)kRes * (e + u < e1 ? e + u : e));
-        f[u][0] = r[0];
-        f[u][1] = r[1];
-        f[u][2] = r[3];
-        f[u][3] = r[4];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (e + u < e1) {
-          F[0] += f[u][0].x;
-          F[1] += f[u][0].y;
-          F[2] += f[u][1].x;
-          T[0] += f[u][2].x;
-          T[1] += f[u][2].y;
-          T[2] += f[u][3].x;
-        }
-      }
-    }
-    // contacts owned by others, in ascending owner slot (the partner lists
-    // hold (owner slot, record); owners of one partner are distinct)
-    if (m <= 8) {
-      // sort with a fixed compare-exchange network
-#define SDEM_CX(x, y)                                    \
-  if (ka[y] < ka[x]) {                                  \
-    const int ta = ka[x], te = ke[x];                   \
-    ka[x] = ka[y];                                      \
-    ke[x] = ke[y];                                      \
-    ka[y] = ta;                                         \
-    ke[y] = te;                                         \
+  __shared__ int go;
+  __shared__ double red[kBeginThreads / 64];
+  if (threadIdx.x == 0) {
+    c.ctr->steps += 1ull;
+    const int d = c.ctr->rebuild_next;
+    c.ctr->drift_now = d;
+    c.ctr->rebuild_next = 0;
+    if (d) c.ctr->drift_steps += 1ull;
+    go = d;
   }
-      SDEM_CX(0, 1) SDEM_CX(2, 3) SDEM_CX(4, 5) SDEM_CX(6, 7)
-      SDEM_CX(0, 2) SDEM_CX(1, 3) SDEM_CX(4, 6) SDEM_CX(5, 7)
-      SDEM_CX(1, 2) SDEM_CX(5, 6) SDEM_CX(0, 4) SDEM_CX(3, 7)
-      SDEM_CX(1, 5) SDEM_CX(2, 6)
-      SDEM_CX(1, 4) SDEM_CX(3, 6)
-      SDEM_CX(2, 4) SDEM_CX(3, 5)
-      SDEM_CX(3, 4)
-#undef SDEM_CX
-      // force on the owner and torque on the partner: the first six doubles
-      // of a record, four records in flight
+  __syncthreads();
+  if (!go) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int sm = 0; sm < c.nsims; ++sm) {
+    double dmax = 0.0;
+    for (int q = c.chunk0[sm] + (int)threadIdx.x; q < c.chunk0[sm + 1]; q += kBeginThreads)
+      dmax = fmax(dmax, c.part[kPart * q + 6]);
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    if (lane == 0) red[wv] = dmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = red[0];
+      for (int w = 1; w < kBeginThreads / 64; ++w) m = fmax(m, red[w]);
+      const double ex = m - c.sp[sm].half_skin;
+      c.xtra[sm] = ex > 0.0 ? ex * (1.0 + 1e-6) : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// One time step of the tile of slot group blockIdx (remapped per XCD): S is
+// the state at the start of the step (the sorted copy on a step that rebuilt
+// the cells), D receives the next state; cn the contacts of this step, old
+// those of the previous step.
+template <typename RT>
+__global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, Contacts cn,
+                                                     Contacts old, int rebuilt) {
+  __shared__ StepLds L;
+  const int n = c.n;
+  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int grp = xcd_remap(blockIdx.x, gridDim.x);
+  const int base = grp * kThreads;
+  const int s = base + tid;
+  const bool valid = s < n;
+  // The own centre, simulation and candidate list head are loaded before the
+  // failure flag is examined (a step after a failed one exits there): none
+  // depends on the step's outcome so far.  List entries are only followed
+  // within the recorded count.
+  int sim = 0, vcnt0 = -1, vraw[4] = {s, s, s, s};
+  double4 ps = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (valid) {
+    sim = c.nsims == 1 ? 0 : c.sim_of[s];
+    ps = S.xr[s];
+    if (c.skin_on && !rebuilt) {
+      vcnt0 = c.vcnt[s];
 #pragma unroll
-      for (int j0 = 0; j0 < 8; j0 += 4) {
-        if (j0 >= m) break;
-        double2 g[4][3];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (j0 + u < m) {
-            const double2* r = reinterpret_cast<const double2*>(res + (size_t)kRes * ke[j0 + u]);
-            g[u][0] = r[0];
-            g[u][1] = r[1];
-            g[u][2] = r[2];
-          }
+      for (int u = 0; u < 4; ++u) vraw[u] = c.vlist[(size_t)u * c.vstride + s];
+    }
+  }
+  if (tid == 0) L.flags = c.ctr->flags;
+  __syncthreads();
+  if (L.flags) return;  // the whole workgroup leaves together
+  // If a particle drifted past half the skin since the cells were built (seen
+  // by the previous step), every search of this step reaches by the excess
+  // of its simulation further (k_begin)
+  const bool drifted = !rebuilt && c.skin_on && c.ctr->drift_now;
+
+  // ---- narrow phase: every contact of particle s ----------------------------
+  const int spill_cap = c.hit_cap - kHit;
+  int nh = 0;
+  auto put = [&](int t) {
+    if (nh < kHit)
+      L.pool.hits[wv][nh][lane] = t;
+    else if (nh < c.hit_cap)
+      c.spill[(size_t)s * spill_cap + (nh - kHit)] = t;
+    ++nh;
+  };
+  auto hit = [&](int k) -> int {
+    return k < kHit ? L.pool.hits[wv][k][lane] : c.spill[(size_t)s * spill_cap + (k - kHit)];
+  };
+  if (valid) {
+    const double extra = drifted ? c.xtra[sim] : 0.0;
+    const double xs = ps.x, ys = ps.y, zs = ps.z, Rs = ps.w;
+    // Between rebuilds, with no drift past half the skin in this simulation,
+    // the candidates recorded at the last rebuild suffice: every particle
+    // within R_s + R_t + 2 (half skin) of x_s then, and (static meshes) every
+    // element within R_s + R_m + half skin.
+    const double hsk = c.sp[sim].half_skin;
+    const bool listed = c.skin_on && !rebuilt && extra == 0.0;
+    const bool record = c.skin_on && rebuilt;
+    const bool tri_listed = !c.sp[sim].moving;
+    auto vl = [&](int k) -> int& { return c.vlist[(size_t)k * c.vstride + s]; };
+    const int nlist = listed ? vcnt0 : -1;
+    int ncand = 0;
+    auto test_wall = [&](int m) {
+      const double p[3] = {xs, ys, zs};
+      double cp[3];
+      closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
+      double dx, dy, dz, d;
+      const double delta = pair_gap(xs, ys, zs, Rs, cp[0], cp[1], cp[2], c.rmesh[m], &dx, &dy, &dz, &d);
+      if (delta >= 0.0) put(-1 - m);
+      return d;
+    };
+    auto test = [&](int t, const double4& pt) {
+      const double ex = xs - pt.x, ey = ys - pt.y, ez = zs - pt.z;
+      const double sr = Rs + pt.w;
+      // cheap conservative reject before the exactly rounded test
+      if ((ex * ex + ey * ey) + ez * ez > sr * sr * (1.0 + 1e-9)) return;
+      double dx, dy, dz, d;
+      const double delta = pair_gap(xs, ys, zs, Rs, pt.x, pt.y, pt.z, pt.w, &dx, &dy, &dz, &d);
+      if (delta >= 0.0) put(t);
+    };
+    // ---- mesh elements listed in the bin of x_s (unless the list holds them)
+    if (!(nlist >= 0 && tri_listed)) {
+      int k0 = 0, k1 = 0;
+      if (c.sp[sim].ntri > 0) {
+        const MeshGrid G = c.mg[sim];
+        const double fx = (xs - G.lo[0]) * G.inv_h, fy = (ys - G.lo[1]) * G.inv_h,
+                     fz = (zs - G.lo[2]) * G.inv_h;
+        if (fx >= 0.0 && fy >= 0.0 && fz >= 0.0 && fx < (double)G.dim[0] &&
+            fy < (double)G.dim[1] && fz < (double)G.dim[2]) {
+          const int b = G.off + ((int)fz * G.dim[1] + (int)fy) * G.dim[0] + (int)fx;
+          k0 = c.bin_start[b];
+          k1 = c.bin_start[b + 1];
         }
+      }
+      const bool rec_tri = record && tri_listed;
+      for (int k = k0; k < k1; ++k) {
+        const int m = c.bin_tri[k];
+        const double* pl = c.tri_pl + 4 * m;
+        const double reach = (Rs + c.rmesh[m]) + (rec_tri ? hsk : 0.0);
+        const double pd = (pl[0] * xs + pl[1] * ys + pl[2] * zs) - pl[3];
+        if (fabs(pd) > reach * (1.0 + 1e-9) + 1e-300) continue;
+        const double d = test_wall(m);
+        if (rec_tri && d <= reach * (1.0 + 1e-9)) {
+          if (ncand < kCand) vl(ncand) = -1 - m;
+          ++ncand;
+        }
+      }
+    }
+    if (nlist >= 0) {
+      // ---- particles (and listed elements) of the candidate list: four per
+      // iteration; the next four slots are loaded while these are tested
+      // (slots past the list read the own slot)
+      int tn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tn[u] = u < nlist ? vraw[u] : s;
+      for (int k = 0; k < nlist; k += 4) {
+        int tt[4];
+        double4 pt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tt[u] = tn[u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pt[u] = S.xr[tt[u] >= 0 ? tt[u] : s];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tn[u] = k + 4 + u < nlist ? vl(k + 4 + u) : s;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          if (j0 + u < m) {
-            F[0] -= g[u][0].x;
-            F[1] -= g[u][0].y;
-            F[2] -= g[u][1].x;
-            T[0] += g[u][1].y;
-            T[1] += g[u][2].x;
-            T[2] += g[u][2].y;
-          }
+          if (k + u >= nlist) continue;
+          if (tt[u] >= 0)
+            test(tt[u], pt[u]);
+          else
+            (void)test_wall(-1 - tt[u]);
         }
       }
     } else {
-      int last = -1;
-      for (int it = 0; it < m; ++it) {  // ascending owner slot
-        int best = -1, ba = 0x7fffffff;
-        for (int j = 0; j < m; ++j) {
-          const int2 v = pl(j);
-          if (v.x > last && v.x < ba) {
-            ba = v.x;
-            best = v.y;
+      // ---- cells: every cell within reach of x_s (all neighbours), row by
+      // row, each row trimmed to the cells within reach of x_s given its
+      // (y, z) distance (in cell units with margins far above rounding, so
+      // the search only ever widens).  A rebuild looks twice as far to record
+      // the candidates; a kept step reaches by the drift allowed since.
+      const SimGrid gr = c.sg[sim];
+      const double hs = record ? 2.0 * hsk : hsk + extra;
+      const double reach = ((Rs + c.sp[sim].rmax) + hs) * (1.0 + 1e-9);
+      const double rc = reach * gr.inv_h * (1.0 + 1e-9) + 1e-6;  // in cells
+      const double fx = (xs - gr.lo[0]) * gr.inv_h, fy = (ys - gr.lo[1]) * gr.inv_h,
+                   fz = (zs - gr.lo[2]) * gr.inv_h;
+      const int z0 = cell_coord(zs - reach, gr.lo[2], gr.inv_h, gr.dim[2]);
+      const int z1 = cell_coord(zs + reach, gr.lo[2], gr.inv_h, gr.dim[2]);
+      const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, gr.dim[1]);
+      const int y1 = cell_coord(ys + reach, gr.lo[1], gr.inv_h, gr.dim[1]);
+      for (int cz = z0; cz <= z1; ++cz) {
+        const double dz = fmax(fmax((double)cz - fz, fz - (double)(cz + 1)) - 1e-6, 0.0);
+        for (int cy = y0; cy <= y1; ++cy) {
+          const double dy = fmax(fmax((double)cy - fy, fy - (double)(cy + 1)) - 1e-6, 0.0);
+          const double d2 = dy * dy + dz * dz;
+          if (d2 > rc * rc) continue;
+          const double xr = sqrt(rc * rc - d2) * (1.0 + 1e-9) + 1e-6;
+          const int xa = max(0, (int)floor(fx - xr)), xb = min(gr.dim[0] - 1, (int)floor(fx + xr));
+          for (int cx = xa; cx <= xb; ++cx) {
+            const int key = cell_key(gr, cx, cy, cz);
+            const int t0 = c.cell_start[key], t1 = c.cell_start[key + 1];
+            for (int t = t0; t < t1; t += 4) {
+              double4 pt[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u < t1 ? t + u : t];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int tu = t + u;
+                if (tu >= t1) break;
+                if (tu == s) continue;
+                if (record) {
+                  const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
+                  const double sr = (Rs + pt[u].w) + 2.0 * hsk;
+                  if ((ex * ex + ey * ey) + ez * ez <= sr * sr * (1.0 + 1e-9)) {
+                    if (ncand < kCand) vl(ncand) = tu;
+                    ++ncand;
+                  }
+                }
+                test(tu, pt[u]);
+              }
+            }
           }
         }
-        if (best < 0) break;
-        last = ba;
-        const double* r = res + (size_t)kRes * best;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          F[k] -= r[k];
-          T[k] += r[3 + k];
+      }
+    }
+    if (record) c.vcnt[s] = ncand <= kCand ? ncand : -1;  // -1: search the cells
+  }
+  // ---- work lists: owned, cross and referenced contacts of the tile --------
+  const int nk = nh < c.hit_cap ? nh : c.hit_cap;
+  int no = 0, nx = 0, nr = 0;
+  for (int k = 0; k < nk; ++k) {
+    const int t = hit(k);
+    if (t < 0 || t > s)
+      ++no;
+    else if (t >= base)
+      ++nr;
+    else
+      ++nx;
+  }
+  int ooff, xoff, roff, To, Tx, Tr;
+  block_scan3(no, nx, nr, &ooff, &xoff, &roff, &To, &Tx, &Tr, L.w3);
+  const int gbase = grp * c.gcap;   // owned records (springs, keys)
+  const int wbase = 2 * gbase;      // work list past the LDS
+  const bool over_p = nh > c.hit_cap;
+  const bool over_g = To > c.gcap || To + Tx > 2 * c.gcap || Tr > kLdsRef + c.gcap;
+  if (over_p) raise_flag(c.ctr, kFlagCapPerParticle);
+  if (over_g && tid == 0) {
+    atomicMax(&c.ctr->need_group, max(To, (To + Tx + 1) / 2));
+    raise_flag(c.ctr, kFlagCapContacts);
+  }
+  // a tile whose lists do not fit stops here; the step is failed and repeated
+  // by the caller with more room (no state of the step is kept)
+  if (over_g) return;
+  {
+    int jo = 0, jx = 0, jr = 0;
+    for (int k = 0; k < nk; ++k) {
+      const int t = hit(k);
+      if (t < 0 || t > s) {
+        const int r = ooff + jo++;
+        if (r < kLdsRec) L.rec[r] = make_int2(tid, t);
+        else {
+          cn.a[wbase + r] = tid;
+          cn.b[wbase + r] = t;
+        }
+      } else if (t >= base) {
+        const int q = roff + jr++;
+        if (q < kLdsRef) L.ref[q] = t;
+        else cn.ref[gbase + (q - kLdsRef)] = t;
+      } else {
+        const int r = To + xoff + jx++;
+        if (r < kLdsRec) L.rec[r] = make_int2(tid, t);
+        else {
+          cn.a[wbase + r] = tid;
+          cn.b[wbase + r] = t;
         }
       }
     }
   }
+  L.ooff[tid] = ooff;
+  L.ocnt[tid] = no;
+  if (valid) {
+    cn.off[s] = gbase + ooff;
+    cn.cnt[s] = no;
+  }
+  if (tid == 0) cn.ng[grp] = To;
+  __syncthreads();
+  auto rec_at = [&](int r) -> int2 {
+    return r < kLdsRec ? L.rec[r] : make_int2(cn.a[wbase + r], cn.b[wbase + r]);
+  };
+  // references: the record of (lower partner t, s) among t's owned records
+  for (int j = 0; j < nr; ++j) {
+    const int q = roff + j;
+    const int t = q < kLdsRef ? L.ref[q] : cn.ref[gbase + (q - kLdsRef)];
+    const int lt = t - base;
+    const int r0 = L.ooff[lt], r1 = r0 + L.ocnt[lt];
+    int r = -1;
+    for (int rr = r0; rr < r1; ++rr)
+      if (rec_at(rr).y == s) {
+        r = rr;
+        break;
+      }
+    if (q < kLdsRef) L.ref[q] = r;
+    else cn.ref[gbase + (q - kLdsRef)] = r;
+  }
+
+  // ---- contact law, pass by pass over the work list ------------------------
+  const int nrec = To + Tx;
+  double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+  // (previous slot, its previous contact segment, id): carried by the
+  // reorder, or the slot itself when the order was kept
+  auto origin = [&](int p) {
+    return rebuilt ? c.os[p] : make_int4(p, old.off[p], old.cnt[p], S.pid[p]);
+  };
+  int npp = 0, npw = 0;
+  for (int p0 = 0; p0 < nrec; p0 += kThreads) {
+    __syncthreads();  // the pool's last use (hit lists, or the previous pass) is over
+    const int r = p0 + tid;
+    if (r < nrec) {
+      const int2 rb = rec_at(r);
+      const int a = base + rb.x, b = rb.y;
+      const bool wall = b < 0;
+      const SimParams& P = c.sp[c.nsims == 1 ? 0 : c.sim_of[a]];
+      // both bodies are gathered at once; the canonical orientation is then
+      // chosen in registers
+      const double4 pa = S.xr[a];
+      const int4 oa = origin(a);
+      const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
+      const double2 va0 = va[0], va1 = va[1], va2 = va[2];
+      double4 pb;
+      int4 ob = oa;
+      double2 vb0 = make_double2(0.0, 0.0), vb1 = vb0, vb2 = vb0;
+      int m = 0;
+      if (!wall) {
+        pb = S.xr[b];
+        ob = origin(b);
+        const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
+        vb0 = vb[0];
+        vb1 = vb[1];
+        vb2 = vb[2];
+      } else {
+        m = -1 - b;
+        const double p[3] = {pa.x, pa.y, pa.z};
+        double cp[3];
+        closest_on_element(p, c.tri + 9 * m, c.tri_nv[m], cp);
+        pb = make_double4(cp[0], cp[1], cp[2], c.rmesh[m]);
+      }
+      // canonical orientation: body I carries the lower id (the particle for walls)
+      const int ida = oa.w, idb = ob.w;
+      const bool swap = !wall && ida > idb;
+      const int2 key = wall ? make_int2(ida, -(m - P.tri0))
+                            : make_int2(swap ? idb : ida, swap ? ida : idb);
+      // springs of the previous step (zero for a new contact), looked up among
+      // the records of the previous owner: the lower previous slot of the two
+      double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
+      {
+        const bool bown = !wall && ob.x < oa.x;
+        const int eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
+        if (eo >= 0) {
+          const double2* q = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
+          const double2 r0 = q[0], r1 = q[1], r2 = q[2], r3 = q[3];
+          us[0] = r0.x;
+          us[1] = r0.y;
+          us[2] = r1.x;
+          ur[0] = r1.y;
+          ur[1] = r2.x;
+          ur[2] = r2.y;
+          ut = r3.x;
+        }
+      }
+      double o[9];
+      if (swap)
+        contact_law<RT>(c, P, false, m, pb, pa, vb0, vb1, vb2, va0, va1, va2, us, ur, &ut, o);
+      else
+        contact_law<RT>(c, P, wall, m, pa, pb, va0, va1, va2, vb0, vb1, vb2, us, ur, &ut, o);
+      // results by the tile's particle a (force on a, torque on a, torque on b)
+      double* rs = L.pool.law.res[tid];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    c.F[k * n + i] = F[k];
-    c.T[k * n + i] = T[k];
+      for (int k = 0; k < 3; ++k) {
+        rs[k] = swap ? -o[k] : o[k];
+        rs[3 + k] = swap ? o[6 + k] : o[3 + k];
+        rs[6 + k] = swap ? o[3 + k] : o[6 + k];
+      }
+      if (r < To) {
+        double* sp = L.pool.law.spr[tid];
+        sp[0] = us[0];
+        sp[1] = us[1];
+        sp[2] = us[2];
+        sp[3] = ur[0];
+        sp[4] = ur[1];
+        sp[5] = ur[2];
+        sp[6] = ut;
+        sp[7] = 0.0;
+        L.pool.law.key[tid] = key;
+        npp += wall ? 0 : 1;
+        npw += wall ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    // owned records of this pass: springs and keys as contiguous runs
+    {
+      const int no_pass = min(To - p0, kThreads);
+      if (no_pass > 0) {
+        double2* gs = reinterpret_cast<double2*>(cn.spr + (size_t)kSpr * (gbase + p0));
+        const double2* ls = reinterpret_cast<const double2*>(&L.pool.law.spr[0][0]);
+        for (int k = tid; k < no_pass * (kSpr / 2); k += kThreads) gs[k] = ls[k];
+        if (tid < no_pass) cn.key[gbase + p0 + tid] = L.pool.law.key[tid];
+      }
+    }
+    // the tile's particles take their sides of this pass's records
+    if (valid) {
+      const int p1 = p0 + kThreads;
+      for (int rr = max(ooff, p0); rr < min(ooff + no, p1); ++rr) {
+        const double* x = L.pool.law.res[rr - p0];
+        F[0] += x[0]; F[1] += x[1]; F[2] += x[2];
+        T[0] += x[3]; T[1] += x[4]; T[2] += x[5];
+      }
+      const int x0 = To + xoff;
+      for (int rr = max(x0, p0); rr < min(x0 + nx, p1); ++rr) {
+        const double* x = L.pool.law.res[rr - p0];
+        F[0] += x[0]; F[1] += x[1]; F[2] += x[2];
+        T[0] += x[3]; T[1] += x[4]; T[2] += x[5];
+      }
+      for (int j = 0; j < nr; ++j) {
+        const int q = roff + j;
+        const int rr = q < kLdsRef ? L.ref[q] : cn.ref[gbase + (q - kLdsRef)];
+        if (rr < p0 || rr >= p1) continue;
+        const double* x = L.pool.law.res[rr - p0];
+        F[0] -= x[0]; F[1] -= x[1]; F[2] -= x[2];
+        T[0] += x[6]; T[1] += x[7]; T[2] += x[8];
+      }
+    }
   }
-  const double R = xr.w;
-  const double m = sphere_mass(P.rho, R);
-  const double I = 0.4 * m * R * R;
-  const double cd = 9.0 * P.eta / (2.0 * P.rho * R * R);
-  const double gd = (10.0 / 3.0) * cd;
-  const double dt = P.dt;
-  double v[3] = {s0.x, s0.y, s1.x}, w[3] = {s1.y, s2.x, s2.y};
-  double x[3] = {xr.x, xr.y, xr.z}, al[3];
+  // contact counts of the tile for the statistics (running sums, one writer
+  // per group)
+  {
+    const int a = wave_sum_i32(npp), b = wave_sum_i32(npw);
+    if (lane == 0) {
+      L.cnt2[0][wv] = a;
+      L.cnt2[1][wv] = b;
+    }
+  }
+  __syncthreads();  // also: the pool's law results are dead from here
+  if (tid == 0) {
+    int ta = 0, tb = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      ta += L.cnt2[0][w];
+      tb += L.cnt2[1][w];
+    }
+    atomicAdd(&c.gstat[2 * grp], (unsigned long long)ta);
+    atomicAdd(&c.gstat[2 * grp + 1], (unsigned long long)tb);
+  }
+
+  // ---- integration of the tile's particles ---------------------------------
+  bool drift = false;
+  double ddrift = 0.0;
+  if (valid) {
+    const SimParams& P = c.sp[sim];
+    const double2* vw2 = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)s);
+    const double2 s0 = vw2[0], s1 = vw2[1], s2 = vw2[2];
+    const double4 q4 = S.q[s];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double a = (F[k] / m + P.g[k]) - cd * v[k];
-    al[k] = T[k] / I - gd * w[k];
-    v[k] = v[k] + dt * a;
-    x[k] = x[k] + dt * v[k];
-  }
-  double q[4] = {q4.x, q4.y, q4.z, q4.w};
-  const double wl = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
-  if (wl > 0.0) {
-    // sin(phi)/|w| = (dt/2) sin(phi)/phi
-    const double phi = 0.5 * dt * wl;
-    double sc, cp;
-    sinc_cos(phi, &sc, &cp);
-    const double sp = (0.5 * dt) * sc;
-    const double r[4] = {cp, sp * w[0], sp * w[1], sp * w[2]};
-    double o[4];
-    qmul(q, r, o);
-    q[0] = o[0]; q[1] = o[1]; q[2] = o[2]; q[3] = o[3];
-  }
-  const double alen = sqrt((al[0] * al[0] + al[1] * al[1]) + al[2] * al[2]);
-  if (alen > 0.0) {
-    // sin(theta)/|alpha| = (dt/2)^2 sin(theta)/theta
-    const double h2 = (0.5 * dt) * (0.5 * dt);
-    const double th = h2 * alen;
-    double sc, ct;
-    sinc_cos(th, &sc, &ct);
-    const double st = h2 * sc;
-    const double r[4] = {ct, st * al[0], st * al[1], st * al[2]};
-    double o[4];
-    qmul(q, r, o);
-    q[0] = o[0]; q[1] = o[1]; q[2] = o[2]; q[3] = o[3];
-  }
-  bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+      c.F[k * n + s] = F[k];
+      c.T[k * n + s] = T[k];
+    }
+    const double R = ps.w;
+    const double m = sphere_mass(P.rho, R);
+    const double I = 0.4 * m * R * R;
+    const double cd = 9.0 * P.eta / (2.0 * P.rho * R * R);
+    const double gd = (10.0 / 3.0) * cd;
+    const double dt = P.dt;
+    double v[3] = {s0.x, s0.y, s1.x}, w[3] = {s1.y, s2.x, s2.y};
+    double x[3] = {ps.x, ps.y, ps.z}, al[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    w[k] = w[k] + dt * al[k];
-    ok = ok && isfinite(x[k]) && isfinite(v[k]) && isfinite(w[k]);
-  }
-  const int t = threadIdx.x;
-  if (!rebuilt) {  // the kept order: carry the slot's id over to B
-    B.pid[i] = A.pid[i];
-  }
-  if (c.skin_on) {  // drift from the binned centre, and whether beyond half the skin
-    const double4 xb = c.xb[i];
-    const double ex = x[0] - xb.x, ey = x[1] - xb.y, ez = x[2] - xb.z;
-    const double d2 = (ex * ex + ey * ey) + ez * ez;
-    ddrift = sqrt(d2) * (1.0 + 1e-12);
-    drift = d2 > P.half_skin * P.half_skin;
-  }
-  st_x[2 * t] = make_double2(x[0], x[1]);
-  st_x[2 * t + 1] = make_double2(x[2], R);
-  st_v[3 * t] = make_double2(v[0], v[1]);
-  st_v[3 * t + 1] = make_double2(v[2], w[0]);
-  st_v[3 * t + 2] = make_double2(w[1], w[2]);
-  st_q[2 * t] = make_double2(q[0], q[1]);
-  st_q[2 * t + 1] = make_double2(q[2], q[3]);
-  if (!ok) raise_flag(c.ctr, kFlagNonFinite);
-  if ((i & (kGroup - 1)) == 0) c.gcnt[i >> kGroupShift] = 0;  // for the next narrow phase
+    for (int k = 0; k < 3; ++k) {
+      const double a = (F[k] / m + P.g[k]) - cd * v[k];
+      al[k] = T[k] / I - gd * w[k];
+      v[k] = v[k] + dt * a;
+      x[k] = x[k] + dt * v[k];
+    }
+    double q[4] = {q4.x, q4.y, q4.z, q4.w};
+    const double wl = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+    if (wl > 0.0) {
+      // sin(phi)/|w| = (dt/2) sin(phi)/phi
+      const double phi = 0.5 * dt * wl;
+      double sc, cp;
+      sinc_cos(phi, &sc, &cp);
+      const double sp = (0.5 * dt) * sc;
+      const double r4[4] = {cp, sp * w[0], sp * w[1], sp * w[2]};
+      double o4[4];
+      qmul(q, r4, o4);
+      q[0] = o4[0]; q[1] = o4[1]; q[2] = o4[2]; q[3] = o4[3];
+    }
+    const double alen = sqrt((al[0] * al[0] + al[1] * al[1]) + al[2] * al[2]);
+    if (alen > 0.0) {
+      // sin(theta)/|alpha| = (dt/2)^2 sin(theta)/theta
+      const double h2 = (0.5 * dt) * (0.5 * dt);
+      const double th = h2 * alen;
+      double sc, ct;
+      sinc_cos(th, &sc, &ct);
+      const double st = h2 * sc;
+      const double r4[4] = {ct, st * al[0], st * al[1], st * al[2]};
+      double o4[4];
+      qmul(q, r4, o4);
+      q[0] = o4[0]; q[1] = o4[1]; q[2] = o4[2]; q[3] = o4[3];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      w[k] = w[k] + dt * al[k];
+      ok = ok && isfinite(x[k]) && isfinite(v[k]) && isfinite(w[k]);
+    }
+    D.pid[s] = S.pid[s];
+    if (c.skin_on) {  // drift from the binned centre, and whether beyond half the skin
+      const double4 xb = c.xb[s];
+      const double ex = x[0] - xb.x, ey = x[1] - xb.y, ez = x[2] - xb.z;
+      const double d2 = (ex * ex + ey * ey) + ez * ez;
+      ddrift = sqrt(d2) * (1.0 + 1e-12);
+      drift = d2 > P.half_skin * P.half_skin;
+    }
+    L.pool.out.x[2 * tid] = make_double2(x[0], x[1]);
+    L.pool.out.x[2 * tid + 1] = make_double2(x[2], R);
+    L.pool.out.v[3 * tid] = make_double2(v[0], v[1]);
+    L.pool.out.v[3 * tid + 1] = make_double2(v[2], w[0]);
+    L.pool.out.v[3 * tid + 2] = make_double2(w[1], w[2]);
+    L.pool.out.q[2 * tid] = make_double2(q[0], q[1]);
+    L.pool.out.q[2 * tid + 1] = make_double2(q[2], q[3]);
+    if (!ok) raise_flag(c.ctr, kFlagNonFinite);
   }
   // a wave where a particle drifted past half the skin records its largest
   // drift (read by the next step's narrow phase) and raises the flag
-  if (i - (int)(threadIdx.x & 63) < n && __any(drift)) {
-    wave_drift(c, i, i < n, ddrift);
+  if (s - lane < n && __any(drift)) {
+    wave_drift(c, s, valid, ddrift);
     // one write per wave, and none once the flag is up (a single address)
-    if ((threadIdx.x & 63) == 0 && !c.ctr->rebuild_next) atomicOr(&c.ctr->rebuild_next, 1);
+    if (lane == 0 && !c.ctr->rebuild_next) atomicOr(&c.ctr->rebuild_next, 1);
   }
   __syncthreads();
-  const int np = min(n - i0, kThreads);
-  double2* gx = reinterpret_cast<double2*>(B.xr + i0);
-  double2* gv = reinterpret_cast<double2*>(B.vw + 6 * (size_t)i0);
-  double2* gq = reinterpret_cast<double2*>(B.q + i0);
-  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gx[k] = st_x[k];
-  for (int k = threadIdx.x; k < 3 * np; k += kThreads) gv[k] = st_v[k];
-  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gq[k] = st_q[k];
+  const int np = min(n - base, kThreads);
+  if (np > 0) {
+    double2* gx = reinterpret_cast<double2*>(D.xr + base);
+    double2* gv = reinterpret_cast<double2*>(D.vw + 6 * (size_t)base);
+    double2* gq = reinterpret_cast<double2*>(D.q + base);
+    for (int k = tid; k < 2 * np; k += kThreads) gx[k] = L.pool.out.x[k];
+    for (int k = tid; k < 3 * np; k += kThreads) gv[k] = L.pool.out.v[k];
+    for (int k = tid; k < 2 * np; k += kThreads) gq[k] = L.pool.out.q[k];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1898,13 +1621,13 @@ __global__ void k_selftest(int64_t n, const double* in, const double* in2, doubl
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int n, int t) { return n > 0 ? (n + t - 1) / t : 1; }
 
-hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
-                       const Contacts& cnew, int precision, int rebuild, hipStream_t s,
-                       hipEvent_t* ev) {
-  // rebuild: sort the particles into fresh cells (A -> B); otherwise the
-  // cells and the slot order of A are kept and only the narrow phase, the
-  // forces and the integration (A -> B) run.  ev (optional): kEvents events,
-  // the phase boundaries and the force kernel's own start/stop.
+hipError_t launch_step(const Ctx& c, const State& A, const State& B, const State& T,
+                       const Contacts& cold, const Contacts& cnew, int precision, int rebuild,
+                       hipStream_t s, hipEvent_t* ev) {
+  // rebuild: sort the particles of A into fresh cells (copy T), then step
+  // T -> B; otherwise the cells and the slot order of A are kept and the step
+  // runs A -> B.  ev (optional): kEvents events, the phase boundaries and the
+  // step kernel's own start/stop.
   const int nbp = blocks_for(c.n, kThreads);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (rebuild) {
@@ -1922,50 +1645,31 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Conta
       k_scan_down<<<kScanBlocks, kScanThreads, 0, s>>>(c);
     }
     k_scatter<<<nbp, kThreads, 0, s>>>(c);
-    k_reorder<<<nbp, kThreads, 0, s>>>(c, A, B, cold);
+    k_reorder<<<nbp, kThreads, 0, s>>>(c, A, T, cold);
   }
   if (c.any_moving) {
     k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0, rebuild);
     (void)launch_mesh_bins(c, s);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
-  // the search and the contact law in one kernel (in the force phase)
-  const bool fused = fused_search_and_law(c, rebuild);
-  if (!fused) switch (c.detect_sub) {
-    case 1: k_detect<1><<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
-    case 2: k_detect<2><<<blocks_for(2 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
-    case 8: k_detect<8><<<blocks_for(8 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
-    default: k_detect<4><<<blocks_for(4 * c.n, kThreads), kThreads, 0, s>>>(c, A, B, cnew, rebuild); break;
-  }
+  if (!rebuild) k_begin<<<1, kBeginThreads, 0, s>>>(c);
   if (ev) (void)hipEventRecord(ev[3], s);
-  if (fused && ev) {
-    // profiled: the dispatch itself records start and stop of the kernel
-    const dim3 grid(c.ngroups), block(kThreads);
-    if (precision == SDEM_MIXED)
-      hipExtLaunchKernelGGL(k_detect_force<float>, grid, block, 0, s, ev[kPhases + 1],
-                            ev[kPhases + 2], 0, c, A, B, cnew, cold);
-    else
-      hipExtLaunchKernelGGL(k_detect_force<double>, grid, block, 0, s, ev[kPhases + 1],
-                            ev[kPhases + 2], 0, c, A, B, cnew, cold);
-  } else if (fused && precision == SDEM_MIXED) {
-    k_detect_force<float><<<c.ngroups, kThreads, 0, s>>>(c, A, B, cnew, cold);
-  } else if (fused) {
-    k_detect_force<double><<<c.ngroups, kThreads, 0, s>>>(c, A, B, cnew, cold);
-  } else if (ev) {
+  const State& S = rebuild ? T : A;
+  const dim3 grid(c.ngroups), block(kThreads);
+  if (ev) {
     // profiled: the dispatch itself records start and stop of the kernel
     if (precision == SDEM_MIXED)
-      hipExtLaunchKernelGGL(k_force<float>, dim3(c.ngroups), dim3(kThreads), 0, s, ev[kPhases + 1],
-                            ev[kPhases + 2], 0, c, A, B, cnew, cold, rebuild);
+      hipExtLaunchKernelGGL(k_step<float>, grid, block, 0, s, ev[kPhases + 1], ev[kPhases + 2], 0,
+                            c, S, B, cnew, cold, rebuild);
     else
-      hipExtLaunchKernelGGL(k_force<double>, dim3(c.ngroups), dim3(kThreads), 0, s, ev[kPhases + 1],
-                            ev[kPhases + 2], 0, c, A, B, cnew, cold, rebuild);
+      hipExtLaunchKernelGGL(k_step<double>, grid, block, 0, s, ev[kPhases + 1], ev[kPhases + 2],
+                            0, c, S, B, cnew, cold, rebuild);
   } else if (precision == SDEM_MIXED) {
-    k_force<float><<<c.ngroups, kThreads, 0, s>>>(c, A, B, cnew, cold, rebuild);
+    k_step<float><<<grid, block, 0, s>>>(c, S, B, cnew, cold, rebuild);
   } else {
-    k_force<double><<<c.ngroups, kThreads, 0, s>>>(c, A, B, cnew, cold, rebuild);
+    k_step<double><<<grid, block, 0, s>>>(c, S, B, cnew, cold, rebuild);
   }
   if (ev) (void)hipEventRecord(ev[4], s);
-  k_integrate<<<nbp, kThreads, 0, s>>>(c, A, B, cnew, rebuild);
   if (ev) (void)hipEventRecord(ev[5], s);
   return hipGetLastError();
 }

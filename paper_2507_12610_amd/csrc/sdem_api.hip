@@ -66,7 +66,7 @@ int64_t bin_entries_cap(const sdem_config& c) {
 
 struct sdem_ctx {
   Ctx c{};
-  State st[2]{};
+  State st[3]{};  // st[cur] holds the state; st[2] the sorted copy of a rebuild
   Contacts ct[2]{};
   int cur = 0;  // buffer holding the current state and the last step's contacts
   hipStream_t stream = nullptr;
@@ -112,6 +112,11 @@ static void drop_graphs(sdem_ctx* X) {
       }
 }
 
+// contacts one particle may have in a step (0 selects 64)
+static int32_t hit_cap_of(const sdem_config& cfg) {
+  return cfg.contacts_per_particle ? cfg.contacts_per_particle : 64;
+}
+
 // contact records are allocated per group of kGroup slots: gcap each
 static int64_t groups_of(const sdem_config& cfg) {
   return (std::max<int64_t>(cfg.n_max, 1) + kGroup - 1) / kGroup;
@@ -144,28 +149,24 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.part = L.take<double>(kPart * NC);
   cc.cell_cnt = L.take<int32_t>(Gm);
   cc.cell_start = L.take<int32_t>(Gm + 1);
-  cc.rowmax = L.take<unsigned long long>(Gm);
   cc.key_tmp = L.take<int32_t>(N);
   cc.rank = L.take<int32_t>(N);
   cc.perm = L.take<int32_t>(N);
   cc.scan_tmp = L.take<int32_t>(kScanBlocks + 1);
-  cc.pcnt = L.take<int32_t>(N);
   cc.gcnt = L.take<int32_t>(G);
   cc.gstat = L.take<unsigned long long>(2 * G);
-  cc.plist = L.take<int2>(N * kMaxRev);
-  cc.pstride = (int64_t)N;
+  cc.xtra = L.take<double>(S);
+  cc.spill = L.take<int32_t>(std::max<size_t>(N * (size_t)(hit_cap_of(cfg) - kHit), 1));
   cc.key = L.take<int32_t>(N);
   cc.os = L.take<int4>(N);
   cc.xb = L.take<double4>(N);
   {
-    // candidate lists of the search lanes, kept between rebuilds (skin > 0)
-    const size_t lanes = (size_t)(cfg.detect_lanes ? cfg.detect_lanes : 4);
-    const size_t NL = cfg.skin > 0.0 ? N * lanes : 1;
+    // candidate lists of the particles, kept between rebuilds (skin > 0)
+    const size_t NL = cfg.skin > 0.0 ? N : 1;
     cc.vcnt = L.take<int32_t>(NL);
     cc.vlist = L.take<int32_t>(NL * kCand);
     cc.vstride = (int64_t)NL;
   }
-  cc.res = L.take<double>(kRes * Cm);
   cc.F = L.take<double>(3 * N);
   cc.T = L.take<double>(3 * N);
   cc.tri_ref = L.take<double>(9 * M);
@@ -181,7 +182,9 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.bin_cnt = L.take<int32_t>((size_t)std::max<int64_t>(bins_cap(cfg), 1));
   cc.bin_start = L.take<int32_t>((size_t)bins_cap(cfg) + 1);
   cc.bin_tri = L.take<int32_t>((size_t)std::max<int64_t>(bin_entries_cap(cfg), 1));
-  for (int b = 0; b < 2; ++b) {
+  // two state buffers that alternate every step, and a third for the sorted
+  // copy on steps that rebuild the cells
+  for (int b = 0; b < 3; ++b) {
     State s{};
     s.xr = L.take<double4>(N);
     s.vw = L.take<double>(6 * N);
@@ -193,8 +196,9 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
     Contacts k{};
     k.cnt = L.take<int32_t>(N);
     k.off = L.take<int32_t>(N);
-    k.a = L.take<int32_t>(Cm);
-    k.b = L.take<int32_t>(Cm);
+    k.a = L.take<int32_t>(2 * Cm);
+    k.b = L.take<int32_t>(2 * Cm);
+    k.ref = L.take<int32_t>(Cm);
     k.key = L.take<int2>(Cm);
     k.spr = L.take<double>(kSpr * Cm);
     k.ng = L.take<int32_t>(G);
@@ -223,9 +227,11 @@ static int check_config(const sdem_config* cfg) {
     return fail(SDEM_EINVAL, "unknown precision %d", cfg->precision);
   if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64))
     return fail(SDEM_EINVAL, "block must be a multiple of 64 in [64, 1024]");
-  if (cfg->detect_lanes != 0 && cfg->detect_lanes != 1 && cfg->detect_lanes != 2 &&
-      cfg->detect_lanes != 4 && cfg->detect_lanes != 8)
-    return fail(SDEM_EINVAL, "detect_lanes must be 0, 1, 2, 4 or 8");
+  if (cfg->detect_lanes != 0 && cfg->detect_lanes != 1)
+    return fail(SDEM_EINVAL, "detect_lanes must be 0 or 1 (one lane per particle)");
+  if (cfg->contacts_per_particle != 0 &&
+      (cfg->contacts_per_particle < kHit || cfg->contacts_per_particle > 4096))
+    return fail(SDEM_EINVAL, "contacts_per_particle must be 0 or in [%d, 4096]", kHit);
   if (!(cfg->cell_factor == 0.0 || cfg->cell_factor >= 0.125) || !isfinite(cfg->cell_factor))
     return fail(SDEM_EINVAL, "cell_factor must be >= 0.125 (0 selects 1)");
   if (!(cfg->skin >= 0.0) || !(cfg->skin <= 100.0))
@@ -338,6 +344,7 @@ namespace sdem {
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace sdem
 
+
 extern "C" {
 
 size_t sdem_workspace_bytes(const sdem_config* cfg) {
@@ -356,7 +363,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   sdem_config cfg = *cfg_in;
   if (cfg.cell_factor == 0.0) cfg.cell_factor = 1.0;
   if (cfg.block == 0) cfg.block = kThreads;
-  cfg.reserved = 0;
+  cfg.contacts_per_particle = hit_cap_of(cfg);
   if (nsims < 1 || nsims > cfg.nsims_max)
     return fail(SDEM_ECAPACITY, "nsims %d outside [1, nsims_max=%d]", nsims, cfg.nsims_max);
   if (!params || !offsets) return fail(SDEM_EINVAL, "params and offsets are required");
@@ -410,16 +417,7 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   c.ntri = 0;
   c.cap_contacts = (int32_t)cfg.contacts_max;
   c.cap_cells = (int32_t)cfg.cells_max;
-  {
-    int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      ncu = 256;
-    (void)hipGetLastError();
-    // a multiple of 8 so that every XCD gets the same number of workgroups
-    c.force_blocks = std::max(8, (ncu * kForceBlocksPerCU + 7) / 8 * 8);
-  }
-  c.detect_sub = cfg.detect_lanes ? cfg.detect_lanes : 4;
+  c.hit_cap = hit_cap_of(cfg);
   c.skin_on = cfg.skin > 0.0 ? 1 : 0;
   X->rebuild_every = c.skin_on ? (cfg.rebuild_every > 0 ? cfg.rebuild_every : 64) : 1;
   X->period = X->rebuild_every;
@@ -474,13 +472,11 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   }
   if (!e) e = hipMemsetAsync(c.ctr, 0, sizeof(Counters), st);
   if (!e) e = hipMemsetAsync(c.cell_cnt, 0, sizeof(int32_t) * cfg.cells_max, st);
-  if (!e) e = hipMemsetAsync(c.rowmax, 0, sizeof(unsigned long long) * cfg.cells_max, st);
   for (int b = 0; b < 2 && !e; ++b) {
     e = hipMemsetAsync(X->ct[b].cnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
     if (!e) e = hipMemsetAsync(X->ct[b].off, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
     if (!e) e = hipMemsetAsync(X->ct[b].ng, 0, sizeof(int32_t) * groups_of(cfg), st);
   }
-  if (!e) e = hipMemsetAsync(c.pcnt, 0, sizeof(int32_t) * std::max<int64_t>(n, 1), st);
   if (!e) e = hipMemsetAsync(c.gcnt, 0, sizeof(int32_t) * c.ngroups, st);
   if (!e) e = hipMemsetAsync(c.gstat, 0, sizeof(unsigned long long) * 2 * c.ngroups, st);
   if (!e) e = cp(c.sim_of, sim_of.data(), sizeof(int32_t) * n);
@@ -926,9 +922,9 @@ static int finish_steps(sdem_ctx* X, const Counters& before, int start) {
                 "entries", at, X->c.cap_bin_entries);
   if (after.flags & kFlagCapPerParticle)
     return fail(SDEM_ECAPACITY,
-                "step %lld: a particle has more than %d contacts of one kind (owned or "
-                "partnered)",
-                at, kMaxOwn);
+                "step %lld: a particle has more than contacts_per_particle = %d contacts; "
+                "raise contacts_per_particle",
+                at, X->c.hit_cap);
   return fail(SDEM_ENONFINITE, "step %lld: non-finite position, velocity or spin", at);
 }
 
@@ -951,7 +947,7 @@ static void count_step(sdem_ctx* X, bool rebuild) {
 static hipError_t enqueue_steps(sdem_ctx* X, int k, bool rebuild, hipEvent_t* ev = nullptr) {
   for (int i = 0; i < k; ++i) {
     const int a = (X->cur + i) & 1;
-    hipError_t e = launch_step(X->c, X->st[a], X->st[a ^ 1], X->ct[a], X->ct[a ^ 1],
+    hipError_t e = launch_step(X->c, X->st[a], X->st[a ^ 1], X->st[2], X->ct[a], X->ct[a ^ 1],
                                X->cfg.precision, rebuild ? 1 : 0, X->stream, ev);
     if (e) return e;
   }
@@ -1126,7 +1122,6 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
       return rc;
     }
     const bool rb = rebuild_now(X);
-    const bool fused = fused_search_and_law(X->c, rb ? 1 : 0);
     err = enqueue_steps(X, 1, rb, ev);
     count_step(X, rb);
     X->cur ^= 1;
@@ -1139,7 +1134,6 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
       if (!err && next) X->need_rebuild = true;
     }
     for (int k = 0; k < kPhases && !err; ++k) {
-      if (k == 2 && fused) continue;  // no narrow-phase kernel of its own: counted as 0
       float ms = 0.f;
       err = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
       phase_ms[k] += ms;

@@ -15,14 +15,15 @@ constexpr int kPart = 7;            // doubles per bounding-box partial: min xyz
 constexpr int kWave = 64;           // slots per wave; bounding-box partials are
                                     // per (wave of slots, simulation)
 constexpr int kSpr = 8;             // doubles per contact spring record
-constexpr int kRes = 10;            // doubles per contact result record
 constexpr int kThreads = 256;       // threads per workgroup of the particle kernels
-constexpr int kForceBlocksPerCU = 4;  // grid of the contact kernel: 4 workgroups per CU
-constexpr int kMaxOwn = 32;         // contacts one particle may own in a step
-constexpr int kMaxRev = 32;         // contacts one particle may take part in as partner
+constexpr int kHit = 32;            // contacts of one particle held in LDS by its search
+                                    // lane (more spill to the tile's global overflow)
 constexpr int kCand = 32;           // candidates one search lane records at a rebuild
 constexpr int kGroupShift = 8;      // contact records are allocated per group of
-constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots
+constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots: a tile of the step kernel
+constexpr int kLdsRec = 1024;       // records of a tile held in LDS (the rest in global memory)
+constexpr int kLdsRef = 1024;       // in-tile references held in LDS (the rest in global memory)
+constexpr int kBrickBits = 3;       // cells are ordered in bricks of up to 8 x 8 x 8
 constexpr int kBinScanThreads = 1024;  // one workgroup scans the triangle bins
 constexpr int kSpawnMax = 1024;     // spawn attempts per step at most
 constexpr int kMotionMax = 16;      // motion groups of a simulation's mesh
@@ -64,12 +65,18 @@ struct MeshMotion {
   int32_t pad;
 };
 
-// Per-simulation grid of the current step (computed on the device).
+// Per-simulation grid of the current step (computed on the device).  Cells
+// are numbered brick by brick: bricks of 2^bits[a] cells along axis a
+// (bits[a] = min(3, ceil(log2 dim[a]))), bricks in (z, y, x) row order,
+// the cells of a brick in Morton (bit-interleaved) order, so that a run of
+// consecutive slots is a compact blob of space.
 struct SimGrid {
   double lo[3];
   double inv_h;
   int32_t dim[3];
   int32_t cell_off;
+  int32_t bits[3];
+  int32_t nb[3];  // bricks along each axis
 };
 
 // Per-simulation uniform grid of triangle bins, fixed at set-up.  Bin b lists
@@ -92,7 +99,7 @@ struct Counters {
   int32_t need_cells;    // last required cell capacity (diagnostic)
   uint32_t scan_ticket;  // last-block detection of the scan
   int32_t rebuild_next;  // a particle drifted beyond half the skin since the last rebuild
-  int32_t pad2;
+  int32_t drift_now;     // the step in progress reaches past the skin (set by k_begin)
   int32_t pad;
   unsigned long long steps;  // steps started (a failed one included)
   unsigned long long rebuilds;  // steps that rebuilt the cells
@@ -124,26 +131,30 @@ struct State {
   int32_t* pid;  // persistent id
 };
 
-// One buffer of contacts, grouped by owner slot (owner = lower slot).  The
-// records of slot group g (slots g*256 .. g*256+255) live in
-// [g*gcap, g*gcap + gcnt[g]).
+// One buffer of contacts, grouped by owner slot (owner = lower slot; a
+// particle owns its mesh contacts).  The owned records of slot group g
+// (slots g*256 .. g*256+255) live in [g*gcap, g*gcap + ng[g]), each owner's
+// contiguous.  a, b hold the step kernel's work list of the tile: the owned
+// records, then the records of pairs with a lower slot outside the tile
+// (evaluated by both tiles), at [2*g*gcap, ...) for records past the LDS.
 struct Contacts {
   int32_t* cnt;  // [n] contacts per owner slot
   int32_t* off;  // [n] first contact of each owner slot
-  int32_t* a;    // owner slot
-  int32_t* b;    // partner slot (>= 0) or -1 - global triangle index
+  int32_t* a;    // [2 cap] work list: slot within the tile
+  int32_t* b;    // [2 cap] work list: partner slot (>= 0) or -1 - global element index
+  int32_t* ref;  // [cap] in-tile references past the LDS: record of the lower partner
   int2* key;     // (lower persistent id, higher id) or (id, -local triangle index)
   double* spr;   // [cap][kSpr] sliding spring (3), rolling spring (3), twisting
                  // spring (1), in the orientation of body key.x; one pad
-  int32_t* ng;   // [ngroups] records of each slot group (written by the force kernel)
+  int32_t* ng;   // [ngroups] owned records of each slot group
 };
 
 // Everything a step's kernels read or write.
 struct Ctx {
   int32_t n, nsims, ntri, cap_contacts, cap_cells, nchunks;
-  int32_t any_moving, force_blocks;
+  int32_t any_moving, pad_i;
   int32_t skin_on;           // cells are kept between steps (skin > 0)
-  int32_t detect_sub;        // lanes per particle in the narrow phase (1, 2, 4, 8)
+  int32_t hit_cap;           // contacts one particle may have in a step (>= kHit)
   int32_t ngroups, gcap;     // slot groups, contact records per group
   int32_t nbins, cap_bin_entries;  // triangle bins (all sims), capacity of bin_tri
   int32_t* gcnt;             // [ngroups] contact records used by each group
@@ -154,36 +165,27 @@ struct Ctx {
   int32_t* sim_of;    // [n] simulation of each slot (fixed)
   int32_t* wchunk;    // [n/64] first bounding-box chunk of each wave of slots
   int32_t* chunk0;    // [nsims+1] first chunk of each simulation
+  double* xtra;       // [nsims] extra reach of the step in progress (drift past the skin)
   double* part;       // [nchunks][kPart] bounding-box partials (min xyz, max xyz, drift),
                       // one per (wave, simulation) segment, simulations ascending
   int32_t* cell_cnt;  // [cap_cells] zero between steps
   int32_t* cell_start;// [cap_cells+1]
-  unsigned long long* rowmax;  // [cap_cells] at the first cell of each cell row:
-                      // largest radius in that row (bits of a positive double);
-                      // rows without particles hold stale values >= 0
   int32_t* key_tmp;   // [n] cell key by previous slot
   int32_t* rank;      // [n] arrival rank in the cell
   int32_t* perm;      // [n] new slot -> previous slot (unstable within a cell)
   int32_t* scan_tmp;  // [kScanBlocks+1]
-  int32_t* pcnt;      // [n] contacts in which the slot is the partner
-  int2* plist;        // [kMaxRev][pstride] those contacts: (owner slot, record);
-                      // entry k of slot i at k * pstride + i (the first entries
-                      // of a wave's slots are read together)
-  int64_t pstride;    // slots the partner lists have room for
+  int32_t* spill;     // [n][hit_cap - kHit] contacts of a particle past its kHit in LDS
   // per slot, written by the reorder at a rebuild and kept until the next:
   int32_t* key;       // [n] cell key
   int4* os;           // [n] (slot in the previous step's order, first and number of the
                       // contacts it owned in the previous step, persistent id)
   double4* xb;        // [n] centre when the cells were built (w unused)
-  int32_t* vcnt;      // [n * lanes] candidates recorded by each search lane at the last
+  int32_t* vcnt;      // [n] candidates recorded by each particle at the last
                       // rebuild (-1: more than kCand, search the cells)
   int32_t* vlist;     // [kCand][vstride] their slots, in search order: entry k of
-                      // lane g at k * vstride + g (the first entries of a wave's
-                      // lanes are read together)
-  int64_t vstride;    // search lanes the candidate lists have room for
-  double* res;        // [cap][kRes] per contact: force on the owner (3), torque
-                      // on the partner (3), torque on the owner (3), pad (the
-                      // partner's part first: it is gathered, the owner's streamed)
+                      // slot s at k * vstride + s (the first entries of a wave's
+                      // slots are read together)
+  int64_t vstride;    // slots the candidate lists have room for
   double* F;          // [3][n] contact force of the last step, by slot
   double* T;          // [3][n] contact torque of the last step, by slot
   double* tri_ref;    // [ntri][9] element vertices at t = 0 (see closest_on_element)
@@ -210,15 +212,6 @@ struct Ctx {
 // Grids up to this many workgroups are resident all at once (four per CU
 // on 256 CUs).
 constexpr int kOneRoundBlocks = 1024;
-
-// Whether a step runs the narrow phase and the contact law in one kernel:
-// steps that keep the cells, with one search lane per slot, on grids
-// resident in one round.  There the second launch and the records' round
-// trip weigh (200k spheres: 3.4 us of 31 saved); on larger grids the two
-// kernels are faster (8M spheres: 2.38 ms against 2.42 ms fused).
-inline bool fused_search_and_law(const Ctx& c, int rebuild) {
-  return !rebuild && c.detect_sub == 1 && c.ngroups <= kOneRoundBlocks;
-}
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   // The dispatcher hands workgroup b to XCD b % 8.  When the whole grid is
@@ -375,18 +368,19 @@ __device__ __forceinline__ void closest_on_element(const double p[3], const doub
 
 // Host launchers (kernels live in the .hip files).
 // Phases of a step as timed by sdem_step_profiled: grid, sort+reorder (+mesh),
-// narrow phase, contact forces, integration.
+// step opening (k_begin), the step kernel (narrow phase, contact law,
+// integration), and an empty fifth phase.
 constexpr int kPhases = 5;
-constexpr int kEvents = kPhases + 3;  // phase boundaries, then the force kernel's own pair
+constexpr int kEvents = kPhases + 3;  // phase boundaries, then the step kernel's own pair
 // Spawn attempts of one step (Section 3.1) on the state A at the start of
 // the step, before its broad phase: new particles go to slots n.. of A, with
 // no contacts in cold; the counters tell how many.
 hipError_t launch_spawn(const Ctx& c, const State& A, const Contacts& cold, hipStream_t s);
 hipError_t launch_mesh_now(const Ctx& c, hipStream_t s);
 hipError_t launch_scatter_radii(const Ctx& c, const State& S, double* R, hipStream_t s);
-hipError_t launch_step(const Ctx& c, const State& A, const State& B, const Contacts& cold,
-                       const Contacts& cnew, int precision, int rebuild, hipStream_t s,
-                       hipEvent_t* ev = nullptr);
+hipError_t launch_step(const Ctx& c, const State& A, const State& B, const State& T,
+                       const Contacts& cold, const Contacts& cnew, int precision, int rebuild,
+                       hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_scatter_state(const Ctx& c, const State& S, double* x, double* v, double* w,
                                 double* q, double* F, double* T, hipStream_t s);
 hipError_t launch_bbox(const Ctx& c, const State& S, hipStream_t s);

@@ -179,7 +179,6 @@ __global__ __launch_bounds__(64) void k_spawn_decide(Ctx c, State A, Contacts co
     A.pid[slot] = slot;
     cold.cnt[slot] = 0;
     cold.off[slot] = 0;
-    c.pcnt[slot] = 0;
   }
   // slot groups that start to exist: no records, no statistics yet
   const int g0 = (n0 + kGroup - 1) / kGroup, g1 = (n0 + nacc + kGroup - 1) / kGroup;

@@ -78,7 +78,8 @@ class Config(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("contacts_max", C.c_int64), ("cells_max", C.c_int64),
                 ("tri_max", C.c_int64), ("nsims_max", C.c_int32), ("precision", C.c_int32),
                 ("block", C.c_int32), ("detect_lanes", C.c_int32), ("cell_factor", C.c_double),
-                ("skin", C.c_double), ("rebuild_every", C.c_int32), ("reserved", C.c_int32)]
+                ("skin", C.c_double), ("rebuild_every", C.c_int32),
+                ("contacts_per_particle", C.c_int32)]
 
 
 _lib = None
@@ -285,7 +286,7 @@ class Solver:
 
     def __init__(self, sims, precision="fp64", device="cuda:0", contacts_max=None,
                  cells_max=None, cell_factor=1.0, block=0, cell_slack=8.0, detect_lanes=0,
-                 skin=0.0, rebuild_every=0, spawn=None):
+                 skin=0.0, rebuild_every=0, spawn=None, contacts_per_particle=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("sdem needs a GPU: torch.cuda.is_available() is False")
@@ -328,7 +329,7 @@ class Solver:
         self.cfg = Config(max(n_cap, 1), contacts_max, cells_max, max(ntri, 1), self.nsims,
                           SDEM_MIXED if precision == "mixed" else SDEM_FP64, block,
                           int(detect_lanes), float(cell_factor), float(skin),
-                          int(rebuild_every), 0)
+                          int(rebuild_every), int(contacts_per_particle))
         nbytes = L.sdem_workspace_bytes(C.byref(self.cfg))
         if nbytes == 0:
             _check(SDEM_EINVAL)
