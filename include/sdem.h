@@ -134,6 +134,27 @@ int sdem_init(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params,
               const double* x, const double* v, const double* w, const double* q,
               const double* R, void* workspace, size_t ws_bytes, void* hip_stream);
 
+/* Bytes of the device scratch behind sdem_init_static (one array per GPU). */
+#define SDEM_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture elsewhere in the process, tight serving loops, harnesses that
+ * forbid hipMalloc): sdem_init of one simulation with the library's own
+ * static device scratch of SDEM_STATIC_SCRATCH_BYTES per GPU in place of a
+ * caller workspace.  It calls no hipMalloc, hipFree or other device
+ * allocation.  The capacities must fit: if sdem_workspace_bytes(cfg)
+ * exceeds the scratch it returns SDEM_ECAPACITY (nothing is touched).  The
+ * scratch of a GPU is shared by every context made this way on it and keeps
+ * the last context's contents: a new sdem_init_static on a GPU clears what
+ * must start at zero and takes the scratch over, after which an earlier
+ * static context of that GPU must not be used again; calls that overlap on
+ * one GPU race.  The context is otherwise an ordinary one (all other calls,
+ * sdem_destroy included).  The first call on a device looks up the
+ * scratch's address there (the device current at the call). */
+int sdem_init_static(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params,
+                     int64_t n, const double* x, const double* v, const double* w,
+                     const double* q, const double* R, void* hip_stream);
+
 /* nsims independent simulations in one context (one launch per phase for
  * all of them).  Simulation s owns particles [offsets[s], offsets[s+1]) of the
  * arrays (host array offsets, offsets[0] = 0) and has params[s]. */

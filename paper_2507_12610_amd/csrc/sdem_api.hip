@@ -344,6 +344,28 @@ namespace sdem {
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 }  // namespace sdem
 
+// Device scratch for sdem_init_static (callers that cannot allocate): one
+// array per device, held until the process ends.  In host code `scratch` only
+// stands for the symbol; its device address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticScratchBytes = size_t(SDEM_STATIC_SCRATCH_BYTES);
+constexpr int kMaxStaticDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static void* g_scratch_ptr[kMaxStaticDevices] = {};
+
+static void* static_scratch_of(int dev) {
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      fail(SDEM_EHIP, "hipGetSymbolAddress of the static scratch failed: %s",
+           hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
 
 extern "C" {
 
@@ -504,6 +526,28 @@ int sdem_init(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params,
   const int64_t off[2] = {0, n};
   return sdem_init_batch(out, cfg, 1, params, off, x, v, w, q, R, workspace, ws_bytes,
                          hip_stream);
+}
+
+int sdem_init_static(sdem_ctx** out, const sdem_config* cfg, const sdem_params* params,
+                     int64_t n, const double* x, const double* v, const double* w,
+                     const double* q, const double* R, void* hip_stream) {
+  if (!out) return fail(SDEM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (check_config(cfg) != SDEM_OK) return SDEM_EINVAL;
+  const size_t need = sdem_workspace_bytes(cfg);
+  if (need > kStaticScratchBytes)
+    return fail(SDEM_ECAPACITY,
+                "these capacities need %zu bytes of workspace; the static scratch holds %zu "
+                "(use sdem_init with a workspace of your own)",
+                need, kStaticScratchBytes);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxStaticDevices)
+    return fail(SDEM_EINVAL, "device %d: the static scratch serves devices 0..%d", dev,
+                kMaxStaticDevices - 1);
+  void* ptr = static_scratch_of(dev);
+  if (!ptr) return SDEM_EHIP;  // message set by static_scratch_of
+  return sdem_init(out, cfg, params, n, x, v, w, q, R, ptr, kStaticScratchBytes, hip_stream);
 }
 
 // Corners of element m (its stored vertices, plus the implied fourth corner

@@ -100,6 +100,8 @@ def lib():
         L.sdem_workspace_bytes.argtypes = [C.POINTER(Config)]
         L.sdem_init.argtypes = [C.POINTER(_VP), C.POINTER(Config), C.POINTER(Params), C.c_int64,
                                 _VP, _VP, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
+        L.sdem_init_static.argtypes = [C.POINTER(_VP), C.POINTER(Config), C.POINTER(Params),
+                                       C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]
         L.sdem_init_batch.argtypes = [C.POINTER(_VP), C.POINTER(Config), C.c_int32,
                                       C.POINTER(Params), _I64, _VP, _VP, _VP, _VP, _VP, _VP,
                                       C.c_size_t, _VP]
@@ -286,7 +288,8 @@ class Solver:
 
     def __init__(self, sims, precision="fp64", device="cuda:0", contacts_max=None,
                  cells_max=None, cell_factor=1.0, block=0, cell_slack=8.0, detect_lanes=0,
-                 skin=0.0, rebuild_every=0, spawn=None, contacts_per_particle=0):
+                 skin=0.0, rebuild_every=0, spawn=None, contacts_per_particle=0,
+                 static_scratch=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("sdem needs a GPU: torch.cuda.is_available() is False")
@@ -333,7 +336,13 @@ class Solver:
         nbytes = L.sdem_workspace_bytes(C.byref(self.cfg))
         if nbytes == 0:
             _check(SDEM_EINVAL)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if static_scratch:
+            # the library's own device scratch (sdem_init_static): no workspace
+            if self.nsims != 1:
+                raise ValueError("the static scratch holds one simulation")
+            self.workspace = None
+        else:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.Stream(device=self.device)
 
         def soa(key, k):
@@ -346,10 +355,15 @@ class Solver:
         params = (Params * self.nsims)(*[make_params(s["params"]) for s in sims])
         torch.cuda.synchronize(self.device)
         h = _VP()
-        _check(L.sdem_init_batch(C.byref(h), C.byref(self.cfg), self.nsims, params,
-                                 self.offsets.ctypes.data_as(_I64), tx.data_ptr(), tv.data_ptr(),
-                                 tw.data_ptr(), tq.data_ptr(), tR.data_ptr(),
-                                 self.workspace.data_ptr(), nbytes, self.stream.cuda_stream))
+        if static_scratch:
+            _check(L.sdem_init_static(C.byref(h), C.byref(self.cfg), params, n, tx.data_ptr(),
+                                      tv.data_ptr(), tw.data_ptr(), tq.data_ptr(), tR.data_ptr(),
+                                      self.stream.cuda_stream))
+        else:
+            _check(L.sdem_init_batch(C.byref(h), C.byref(self.cfg), self.nsims, params,
+                                     self.offsets.ctypes.data_as(_I64), tx.data_ptr(),
+                                     tv.data_ptr(), tw.data_ptr(), tq.data_ptr(), tR.data_ptr(),
+                                     self.workspace.data_ptr(), nbytes, self.stream.cuda_stream))
         self._h = h
         for k, s in enumerate(sims):
             if s.get("elements") is not None:
