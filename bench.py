@@ -17,8 +17,9 @@ two rebuild periods of the cells, so rebuilds are counted at their real
 rate; the value is the median block's particle-steps/s over three blocks.
 
 Prints one JSON line: particle-steps/s (value) and contacts/s; the roofline
-of the contact-force kernel (128 N + 120 C algorithmic bytes per launch)
-over its mean duration from HIP events on its own dispatch; other forms
+of the step kernel (narrow phase, contact law, integration: 264 N + 120 C
+algorithmic bytes per launch) over its mean duration from HIP events on its
+own dispatch; other forms
 (mixed precision, cells rebuilt every step, the 200,000-sphere column, the
 2,000,000-sphere rotating drum, 256 batched box drops) with their speedups
 over plain FP64 on the same GPU; and the CPU oracle timed on the same 8M
@@ -40,34 +41,27 @@ METRIC = "particle-steps/s & contacts/s: FP32/batched vs plain FP64 at stated to
 HBM_PEAK_GBS = 8000.0
 
 
-def force_bytes(n, c):
-    """Algorithmic HBM bytes of one contact-force launch: per particle x, v, w,
-    R read (80 B) and F, T written (48 B); per contact the pair (8 B) and the
-    seven spring doubles read and written (112 B)."""
-    return 128.0 * n + 120.0 * c
-
-
-def fused_bytes(n, c):
-    """Algorithmic HBM bytes of one launch of the fused narrow phase and
-    contact law: those of the contact-force kernel, with the pair record and
-    the partner-list entry written per contact (16 B) in place of the pair
-    read."""
-    return 128.0 * n + 128.0 * c
-
-
-# grids of at most this many slot groups of 256 run the narrow phase and the
-# contact law in one kernel on steps that keep the cells (one search lane)
-ONE_ROUND_GROUPS = 1024
+def step_bytes(n, c):
+    """Algorithmic HBM bytes of one launch of the step kernel on a step that
+    keeps the cells (narrow phase, contact law with spring carry-over, sums
+    and integration in one kernel): the contact-force kernel's 128 N + 120 C
+    (x, v, w, R read, F and T written; per contact the pair and the seven
+    spring doubles read and written) plus the integration's 264 N (state and
+    F, T read, state written), less what one kernel does not move twice:
+    F and T read back (48 N) and x, v, w, R read again (80 N).  That is
+    264 N + 120 C: the state read (112 B) and written (104 B), F and T
+    written (48 B) per particle, 120 B per contact."""
+    return 264.0 * n + 120.0 * c
 
 
 # bench workloads, each with its counter summary and its settings when none
 # are given (None: autotuned)
 WORKLOADS = {
     "packing_8M": {"make": "cfg5", "radii": "half 1.0 mm, half 1.4 mm (rock-salt lattice)",
-                   "traffic": "k_force_cfg5_packing_8M_hbm_traffic.md",
+                   "traffic": "k_step_cfg5_packing_8M_hbm_traffic.md",
                    "settings": (1.0, 1, 0.2)},
     "column_200k": {"make": "cfg2", "radii": "lognormal, median 1 mm, sigma 0.2",
-                    "traffic": "k_detect_force_cfg2_column_200k_hbm_traffic.md", "settings": None},
+                    "traffic": "k_step_cfg2_column_200k_hbm_traffic.md", "settings": None},
 }
 
 
@@ -163,11 +157,11 @@ def block_summary(med, blocks, n):
             "blocks_ms_per_step": [round(1e3 * b["s"] / b["steps"], 5) for b in blocks]}
 
 
-def profiled_force_kernel(s, n, steps, fused):
+def profiled_step_kernel(s, n, steps):
     """Phase times over `steps` profiled steps (one at a time) and the mean
-    duration of the kernel of the force phase on the steps that keep the
-    cells, from start/stop events attached to its dispatch; with the
-    algorithmic bytes per launch over that duration against the HBM peak."""
+    duration of the step kernel on the steps that keep the cells, from
+    start/stop events attached to its dispatch; with the algorithmic bytes
+    per launch over that duration against the HBM peak."""
     prof = []
     for _ in range(steps):
         a = s.stats()
@@ -176,22 +170,18 @@ def profiled_force_kernel(s, n, steps, fused):
         prof.append((b["rebuilds"] > a["rebuilds"], ph, (b["pp"] - a["pp"]) + (b["pw"] - a["pw"])))
     keep = [p for p in prof if not p[0]] or prof
     phases = {k: sum(p[1][k] for p in prof) / len(prof) for k in prof[0][1]}
-    fms = sum(p[1]["force_kernel"] for p in keep) / len(keep)
+    fms = sum(p[1]["step_kernel"] for p in keep) / len(keep)
     c_prof = sum(p[2] for p in keep) / len(keep)
-    if fused:
-        assert all(p[1]["detect"] == 0.0 for p in keep), "narrow phase not fused"
-        kname = "k_detect_force (narrow phase, contact law, spring carry-over)"
-        alg = fused_bytes(n, c_prof)
-    else:
-        kname = "k_force (contact forces, torques, spring carry-over)"
-        alg = force_bytes(n, c_prof)
+    alg = step_bytes(n, c_prof)
     achieved = alg / (fms * 1e-3) / 1e9
-    dominant = max((k for k in phases if k != "force_kernel"), key=phases.get)
-    return {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1),
+    dominant = max((k for k in phases if k != "step_kernel"), key=phases.get)
+    return {"kernel": "k_step (narrow phase, contact law with spring carry-over, integration)",
+            "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "mean_ms": round(fms, 5), "algorithmic_bytes": alg,
+            "algorithmic_bytes_formula": "264 N + 120 C",
             "contacts_per_launch": round(c_prof, 1), "launches_timed": len(keep),
-            "phase_ms": {k: round(v, 5) for k, v in phases.items() if k != "force_kernel"},
+            "phase_ms": {k: round(v, 5) for k, v in phases.items() if k != "step_kernel"},
             "dominant_phase": dominant}
 
 
@@ -308,7 +298,7 @@ def drum_forms(K, sample=3000):
         s.step(20)
         med, blocks = timed_blocks(s, n, K, min_block_steps=128)
         out[prec] = block_summary(med, blocks, n)
-        out[prec]["roofline"] = profiled_force_kernel(s, n, 12, fused=False)
+        out[prec]["roofline"] = profiled_step_kernel(s, n, 12)
         s.close()
     out["mixed_speedup_vs_fp64"] = round(out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"], 4)
 
@@ -526,8 +516,7 @@ def main():
     torch.cuda.synchronize()
     long_ms = 1e3 * (time.perf_counter() - t0) / 400
 
-    fused = skin > 0 and lanes == 1 and -(-n // 256) <= ONE_ROUND_GROUPS
-    roofline = profiled_force_kernel(s, n, args.profile_steps, fused)
+    roofline = profiled_step_kernel(s, n, args.profile_steps)
     roofline["traffic"] = measured_traffic(args.workload)
     s.close()
     del s

@@ -460,18 +460,37 @@ __global__ __launch_bounds__(kThreads) void k_scatter(Ctx c) {
   c.perm[c.cell_start[c.key_tmp[i]] + c.rank[i]] = i;
 }
 
+// Writes the staged records of slots d0 .. d0+np-1 as contiguous runs of
+// 16-byte stores (per-lane 32- and 64-byte records written directly would
+// make every store instruction scatter).
+__device__ __forceinline__ void copy_out(const State& B, int d0, int np, const double4* st_x,
+                                         const Aux* st_a, const double4* st_q) {
+  double2* gx = reinterpret_cast<double2*>(B.xr + d0);
+  double2* ga = reinterpret_cast<double2*>(B.a + d0);
+  double2* gq = reinterpret_cast<double2*>(B.q + d0);
+  const double2* lx = reinterpret_cast<const double2*>(st_x);
+  const double2* la = reinterpret_cast<const double2*>(st_a);
+  const double2* lq = reinterpret_cast<const double2*>(st_q);
+  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gx[k] = lx[k];
+  for (int k = threadIdx.x; k < 4 * np; k += kThreads) ga[k] = la[k];
+  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gq[k] = lq[k];
+}
+
 // Slot p of the scatter holds a particle of cell k; its final slot is the
 // cell start plus the number of the cell's particles that came from a lower
 // previous slot, so the order within a cell is the previous order (stable and
 // deterministic).  Moves the whole state record.
-__global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, Contacts cold) {
+__global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B) {
   if (c.ctr->flags) return;
   // Thread d fills new slot d.  The scatter put the particles of each cell in
   // arrival order; slot d of cell k takes the particle whose previous slot
-  // ranks d - cell_start[k] among them (stable order within a cell).
+  // ranks d - cell_start[k] among them (stable order within a cell).  The
+  // record travels whole; its previous slot is noted (its contact segment of
+  // the previous step is already in it).
   const int d0 = blockIdx.x * kThreads;
   const int d = d0 + (int)threadIdx.x;
-  __shared__ double2 st_x[kThreads * 2], st_v[kThreads * 3], st_q[kThreads * 2];
+  __shared__ double4 st_x[kThreads], st_q[kThreads];
+  __shared__ Aux st_a[kThreads];
   if (d < c.n) {
     const int k = c.key_tmp[c.perm[d]];
     const int cs = c.cell_start[k], ce = c.cell_start[k + 1];
@@ -486,30 +505,17 @@ __global__ __launch_bounds__(kThreads) void k_reorder(Ctx c, State A, State B, C
         break;
       }
     }
-    const double4 xr = A.xr[so], q = A.q[so];
+    const double4 xr = A.xr[so];
+    Aux a = A.a[so];
     c.xb[d] = make_double4(xr.x, xr.y, xr.z, 0.0);  // binned centre
-    const double2* vin = reinterpret_cast<const double2*>(A.vw + 6 * (size_t)so);
-    const int t = threadIdx.x;
-    st_x[2 * t] = make_double2(xr.x, xr.y);
-    st_x[2 * t + 1] = make_double2(xr.z, xr.w);
-    st_v[3 * t] = vin[0];
-    st_v[3 * t + 1] = vin[1];
-    st_v[3 * t + 2] = vin[2];
-    st_q[2 * t] = make_double2(q.x, q.y);
-    st_q[2 * t + 1] = make_double2(q.z, q.w);
-    const int id = A.pid[so];
-    B.pid[d] = id;
-    c.key[d] = k;
-    c.os[d] = make_int4(so, cold.off[so], cold.cnt[so], id);
+    a.prev = so;
+    st_x[threadIdx.x] = xr;
+    st_a[threadIdx.x] = a;
+    st_q[threadIdx.x] = A.q[so];
   }
   __syncthreads();
   const int np = min(c.n - d0, kThreads);
-  double2* gx = reinterpret_cast<double2*>(B.xr + d0);
-  double2* gv = reinterpret_cast<double2*>(B.vw + 6 * (size_t)d0);
-  double2* gq = reinterpret_cast<double2*>(B.q + d0);
-  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gx[k] = st_x[k];
-  for (int k = threadIdx.x; k < 3 * np; k += kThreads) gv[k] = st_v[k];
-  for (int k = threadIdx.x; k < 2 * np; k += kThreads) gq[k] = st_q[k];
+  copy_out(B, d0, np, st_x, st_a, st_q);
 }
 
 // ---------------------------------------------------------------------------
@@ -534,6 +540,13 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) 
       t[k] = t0[k];
       mv[k] = 0.0;
     }
+    if (P.frame_bins && m == P.tri0) {
+      double* f = c.frame + 12 * (size_t)c.tri_sim[m];
+      for (int k = 0; k < 12; ++k) f[k] = 0.0;
+      f[2] = 1.0;
+      f[3] = 1.0;
+      for (int k = 0; k < 3; ++k) f[5 + k] = f[8 + k] = G.center[k];
+    }
   } else if (G.moving) {
     // rigid motion at the time of the start of this step (`started`: the
     // step counter already counts it): turn by |omega| t about the axis
@@ -545,6 +558,21 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) 
     const double d[3] = {G.amp[0] * s1, G.amp[1] * s1, G.amp[2] * s1};
     const double wl = sqrt((G.omega[0] * G.omega[0] + G.omega[1] * G.omega[1]) +
                            G.omega[2] * G.omega[2]);
+    if (P.frame_bins && m == P.tri0) {  // the frame the bins are looked up in
+      double* f = c.frame + 12 * (size_t)c.tri_sim[m];
+      const double ang = wl * tm;
+      f[0] = wl > 0.0 ? G.omega[0] / wl : 0.0;
+      f[1] = wl > 0.0 ? G.omega[1] / wl : 0.0;
+      f[2] = wl > 0.0 ? G.omega[2] / wl : 1.0;
+      f[3] = wl > 0.0 ? cos(ang) : 1.0;
+      f[4] = wl > 0.0 ? sin(ang) : 0.0;
+      f[5] = G.center[0] + d[0];
+      f[6] = G.center[1] + d[1];
+      f[7] = G.center[2] + d[2];
+      f[8] = G.center[0];
+      f[9] = G.center[1];
+      f[10] = G.center[2];
+    }
     if (wl > 0.0) {
       const double kx = G.omega[0] / wl, ky = G.omega[1] / wl, kz = G.omega[2] / wl;
       const double ang = wl * tm;
@@ -599,9 +627,9 @@ __global__ __launch_bounds__(kThreads) void k_mesh(Ctx c, int all, int started) 
 // which a rebuild records elements in the candidate lists).
 __device__ __forceinline__ void tri_bins(const Ctx& c, int m, const MeshGrid& G, int i0[3],
                                          int i1[3]) {
-  const double* t = c.tri + 9 * m;
-  const bool rect = c.tri_nv[m] == 4;
   const SimParams& P = c.sp[c.tri_sim[m]];
+  const double* t = (P.frame_bins ? c.tri_ref : c.tri) + 9 * m;
+  const bool rect = c.tri_nv[m] == 4;
   const double reach = ((P.rmax + P.half_skin) + c.rmesh[m]) * (1.0 + 1e-9);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -993,13 +1021,16 @@ struct StepLds {
       int2 key[kThreads];
     } law;
     struct {
-      double2 x[kThreads * 2], v[kThreads * 3], q[kThreads * 2];
+      double4 x[kThreads];
+      Aux a[kThreads];
+      double4 q[kThreads];
     } out;
   } pool;
   int2 rec[kLdsRec];       // work list: (lane, partner)
   int ref[kLdsRef];        // references: partner slot, then the owner's record
   int ooff[kThreads];      // first owned record of each lane
   int ocnt[kThreads];      // owned records of each lane
+  int2 pseg[kThreads];     // each lane's owned records in the previous step (first, count)
   int w3[kThreads / 64][3];
   int cnt2[2][kThreads / 64];
   int flags;
@@ -1063,9 +1094,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   // within the recorded count.
   int sim = 0, vcnt0 = -1, vraw[4] = {s, s, s, s};
   double4 ps = make_double4(0.0, 0.0, 0.0, 0.0);
+  int2 pseg = make_int2(0, 0);
   if (valid) {
     sim = c.nsims == 1 ? 0 : c.sim_of[s];
     ps = S.xr[s];
+    pseg = *reinterpret_cast<const int2*>(&S.a[s].off);
     if (c.skin_on && !rebuilt) {
       vcnt0 = c.vcnt[s];
 #pragma unroll
@@ -1130,8 +1163,22 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       int k0 = 0, k1 = 0;
       if (c.sp[sim].ntri > 0) {
         const MeshGrid G = c.mg[sim];
-        const double fx = (xs - G.lo[0]) * G.inv_h, fy = (ys - G.lo[1]) * G.inv_h,
-                     fz = (zs - G.lo[2]) * G.inv_h;
+        double bx = xs, by = ys, bz = zs;
+        if (c.sp[sim].frame_bins) {
+          // the mesh moved as one rigid body since t = 0: its bins hold the
+          // elements where they were then, so look up the particle moved back
+          // (turned by minus the angle about the moved axis, centre back)
+          const double* f = c.frame + 12 * (size_t)sim;
+          const double rx = xs - f[5], ry = ys - f[6], rz = zs - f[7];
+          const double kx = f[0], ky = f[1], kz = f[2], co = f[3], si = f[4];
+          const double cx = ky * rz - kz * ry, cy = kz * rx - kx * rz, cz = kx * ry - ky * rx;
+          const double kd = (kx * rx + ky * ry) + kz * rz;
+          bx = f[8] + ((rx * co - cx * si) + kx * kd * (1.0 - co));
+          by = f[9] + ((ry * co - cy * si) + ky * kd * (1.0 - co));
+          bz = f[10] + ((rz * co - cz * si) + kz * kd * (1.0 - co));
+        }
+        const double fx = (bx - G.lo[0]) * G.inv_h, fy = (by - G.lo[1]) * G.inv_h,
+                     fz = (bz - G.lo[2]) * G.inv_h;
         if (fx >= 0.0 && fy >= 0.0 && fz >= 0.0 && fx < (double)G.dim[0] &&
             fy < (double)G.dim[1] && fz < (double)G.dim[2]) {
           const int b = G.off + ((int)fz * G.dim[1] + (int)fy) * G.dim[0] + (int)fx;
@@ -1194,37 +1241,66 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       const int z1 = cell_coord(zs + reach, gr.lo[2], gr.inv_h, gr.dim[2]);
       const int y0 = cell_coord(ys - reach, gr.lo[1], gr.inv_h, gr.dim[1]);
       const int y1 = cell_coord(ys + reach, gr.lo[1], gr.inv_h, gr.dim[1]);
-      for (int cz = z0; cz <= z1; ++cz) {
-        const double dz = fmax(fmax((double)cz - fz, fz - (double)(cz + 1)) - 1e-6, 0.0);
-        for (int cy = y0; cy <= y1; ++cy) {
+      // The cells of the box one after another, z then y then x; the slot
+      // range of the next cell is loaded while the candidates of this one
+      // are tested, and a cell whose key follows the previous one (x pairs
+      // of a brick) starts where that one ended.
+      int cz = z0, cy = y0 - 1, cx = 0, xend = -1;
+      auto next_cell = [&]() -> int {
+        for (;;) {
+          if (cx < xend) {
+            ++cx;
+            return cell_key(gr, cx, cy, cz);
+          }
+          if (++cy > y1) {
+            cy = y0;
+            ++cz;
+          }
+          if (cz > z1) return -1;
+          const double dz = fmax(fmax((double)cz - fz, fz - (double)(cz + 1)) - 1e-6, 0.0);
           const double dy = fmax(fmax((double)cy - fy, fy - (double)(cy + 1)) - 1e-6, 0.0);
           const double d2 = dy * dy + dz * dz;
           if (d2 > rc * rc) continue;
           const double xr = sqrt(rc * rc - d2) * (1.0 + 1e-9) + 1e-6;
           const int xa = max(0, (int)floor(fx - xr)), xb = min(gr.dim[0] - 1, (int)floor(fx + xr));
-          for (int cx = xa; cx <= xb; ++cx) {
-            const int key = cell_key(gr, cx, cy, cz);
-            const int t0 = c.cell_start[key], t1 = c.cell_start[key + 1];
-            for (int t = t0; t < t1; t += 4) {
-              double4 pt[4];
+          if (xb < xa) continue;
+          cx = xa;
+          xend = xb;
+          return cell_key(gr, cx, cy, cz);
+        }
+      };
+      int key = next_cell();
+      int c0 = 0, c1 = 0;
+      if (key >= 0) {
+        c0 = c.cell_start[key];
+        c1 = c.cell_start[key + 1];
+      }
+      while (key >= 0) {
+        const int t0 = c0, t1 = c1;
+        const int kn = next_cell();
+        if (kn >= 0) {
+          c0 = kn == key + 1 ? t1 : c.cell_start[kn];
+          c1 = c.cell_start[kn + 1];
+        }
+        key = kn;
+        for (int t = t0; t < t1; t += 4) {
+          double4 pt[4];
 #pragma unroll
-              for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u < t1 ? t + u : t];
+          for (int u = 0; u < 4; ++u) pt[u] = S.xr[t + u < t1 ? t + u : t];
 #pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int tu = t + u;
-                if (tu >= t1) break;
-                if (tu == s) continue;
-                if (record) {
-                  const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
-                  const double sr = (Rs + pt[u].w) + 2.0 * hsk;
-                  if ((ex * ex + ey * ey) + ez * ez <= sr * sr * (1.0 + 1e-9)) {
-                    if (ncand < kCand) vl(ncand) = tu;
-                    ++ncand;
-                  }
-                }
-                test(tu, pt[u]);
+          for (int u = 0; u < 4; ++u) {
+            const int tu = t + u;
+            if (tu >= t1) break;
+            if (tu == s) continue;
+            if (record) {
+              const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
+              const double sr = (Rs + pt[u].w) + 2.0 * hsk;
+              if ((ex * ex + ey * ey) + ez * ez <= sr * sr * (1.0 + 1e-9)) {
+                if (ncand < kCand) vl(ncand) = tu;
+                ++ncand;
               }
             }
+            test(tu, pt[u]);
           }
         }
       }
@@ -1284,6 +1360,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   }
   L.ooff[tid] = ooff;
   L.ocnt[tid] = no;
+  L.pseg[tid] = pseg;
   if (valid) {
     cn.off[s] = gbase + ooff;
     cn.cnt[s] = no;
@@ -1312,10 +1389,12 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   // ---- contact law, pass by pass over the work list ------------------------
   const int nrec = To + Tx;
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
-  // (previous slot, its previous contact segment, id): carried by the
-  // reorder, or the slot itself when the order was kept
+  // (previous slot, its previous contact segment, id) of a particle, in its
+  // record: noted by the reorder, or by the previous step when the order
+  // was kept
   auto origin = [&](int p) {
-    return rebuilt ? c.os[p] : make_int4(p, old.off[p], old.cnt[p], S.pid[p]);
+    const int4 v = *reinterpret_cast<const int4*>(&S.a[p].pid);
+    return make_int4(v.y, v.z, v.w, v.x);
   };
   int npp = 0, npw = 0;
   for (int p0 = 0; p0 < nrec; p0 += kThreads) {
@@ -1330,8 +1409,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       // chosen in registers
       const double4 pa = S.xr[a];
       const int4 oa = origin(a);
-      const double2* va = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)a);
-      const double2 va0 = va[0], va1 = va[1], va2 = va[2];
+      const double2 va0 = S.a[a].vw[0], va1 = S.a[a].vw[1], va2 = S.a[a].vw[2];
       double4 pb;
       int4 ob = oa;
       double2 vb0 = make_double2(0.0, 0.0), vb1 = vb0, vb2 = vb0;
@@ -1339,10 +1417,9 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       if (!wall) {
         pb = S.xr[b];
         ob = origin(b);
-        const double2* vb = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)b);
-        vb0 = vb[0];
-        vb1 = vb[1];
-        vb2 = vb[2];
+        vb0 = S.a[b].vw[0];
+        vb1 = S.a[b].vw[1];
+        vb2 = S.a[b].vw[2];
       } else {
         m = -1 - b;
         const double p[3] = {pa.x, pa.y, pa.z};
@@ -1356,21 +1433,52 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       const int2 key = wall ? make_int2(ida, -(m - P.tri0))
                             : make_int2(swap ? idb : ida, swap ? ida : idb);
       // springs of the previous step (zero for a new contact), looked up among
-      // the records of the previous owner: the lower previous slot of the two
+      // the records of the previous owner: the lower previous slot of the two.
+      // A particle's contacts come out of its search in the same order every
+      // step (candidates in list order) unless some formed or ended, so the
+      // previous record of its j-th owned contact is most often its j-th
+      // previous record: that one (key and springs) is loaded with the bodies,
+      // and the segment is searched only when its key differs.
       double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
       {
-        const bool bown = !wall && ob.x < oa.x;
-        const int eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
+        int2 kg = make_int2(-1, 0);
+        double2 g0 = make_double2(0.0, 0.0), g1 = g0, g2 = g0, g3 = g0;
+        int eg = -1;
+        if (r < To) {
+          const int j = r - L.ooff[rb.x];
+          const int2 ps2 = L.pseg[rb.x];
+          if (j < ps2.y) eg = ps2.x + j;
+        }
+        if (eg >= 0) {
+          kg = old.key[eg];
+          const double2* q = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eg);
+          g0 = q[0];
+          g1 = q[1];
+          g2 = q[2];
+          g3 = q[3];
+        }
+        int eo = -1;
+        if (eg >= 0 && kg.x == key.x && kg.y == key.y) {
+          eo = eg;
+        } else {
+          const bool bown = !wall && ob.x < oa.x;
+          eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
+          if (eo >= 0) {
+            const double2* q = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
+            g0 = q[0];
+            g1 = q[1];
+            g2 = q[2];
+            g3 = q[3];
+          }
+        }
         if (eo >= 0) {
-          const double2* q = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
-          const double2 r0 = q[0], r1 = q[1], r2 = q[2], r3 = q[3];
-          us[0] = r0.x;
-          us[1] = r0.y;
-          us[2] = r1.x;
-          ur[0] = r1.y;
-          ur[1] = r2.x;
-          ur[2] = r2.y;
-          ut = r3.x;
+          us[0] = g0.x;
+          us[1] = g0.y;
+          us[2] = g1.x;
+          ur[0] = g1.y;
+          ur[1] = g2.x;
+          ur[2] = g2.y;
+          ut = g3.x;
         }
       }
       double o[9];
@@ -1461,9 +1569,9 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   double ddrift = 0.0;
   if (valid) {
     const SimParams& P = c.sp[sim];
-    const double2* vw2 = reinterpret_cast<const double2*>(S.vw + 6 * (size_t)s);
-    const double2 s0 = vw2[0], s1 = vw2[1], s2 = vw2[2];
+    const double2 s0 = S.a[s].vw[0], s1 = S.a[s].vw[1], s2 = S.a[s].vw[2];
     const double4 q4 = S.q[s];
+    const int pid = S.a[s].pid;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       c.F[k * n + s] = F[k];
@@ -1516,7 +1624,6 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       w[k] = w[k] + dt * al[k];
       ok = ok && isfinite(x[k]) && isfinite(v[k]) && isfinite(w[k]);
     }
-    D.pid[s] = S.pid[s];
     if (c.skin_on) {  // drift from the binned centre, and whether beyond half the skin
       const double4 xb = c.xb[s];
       const double ex = x[0] - xb.x, ey = x[1] - xb.y, ez = x[2] - xb.z;
@@ -1524,13 +1631,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       ddrift = sqrt(d2) * (1.0 + 1e-12);
       drift = d2 > P.half_skin * P.half_skin;
     }
-    L.pool.out.x[2 * tid] = make_double2(x[0], x[1]);
-    L.pool.out.x[2 * tid + 1] = make_double2(x[2], R);
-    L.pool.out.v[3 * tid] = make_double2(v[0], v[1]);
-    L.pool.out.v[3 * tid + 1] = make_double2(v[2], w[0]);
-    L.pool.out.v[3 * tid + 2] = make_double2(w[1], w[2]);
-    L.pool.out.q[2 * tid] = make_double2(q[0], q[1]);
-    L.pool.out.q[2 * tid + 1] = make_double2(q[2], q[3]);
+    L.pool.out.x[tid] = make_double4(x[0], x[1], x[2], R);
+    L.pool.out.q[tid] = make_double4(q[0], q[1], q[2], q[3]);
+    Aux& o = L.pool.out.a[tid];
+    o.vw[0] = make_double2(v[0], v[1]);
+    o.vw[1] = make_double2(v[2], w[0]);
+    o.vw[2] = make_double2(w[1], w[2]);
+    o.pid = pid;
+    o.prev = s;  // the next step sees this order as its previous one
+    o.off = gbase + ooff;
+    o.cnt = no;
     if (!ok) raise_flag(c.ctr, kFlagNonFinite);
   }
   // a wave where a particle drifted past half the skin records its largest
@@ -1542,14 +1652,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   }
   __syncthreads();
   const int np = min(n - base, kThreads);
-  if (np > 0) {
-    double2* gx = reinterpret_cast<double2*>(D.xr + base);
-    double2* gv = reinterpret_cast<double2*>(D.vw + 6 * (size_t)base);
-    double2* gq = reinterpret_cast<double2*>(D.q + base);
-    for (int k = tid; k < 2 * np; k += kThreads) gx[k] = L.pool.out.x[k];
-    for (int k = tid; k < 3 * np; k += kThreads) gv[k] = L.pool.out.v[k];
-    for (int k = tid; k < 2 * np; k += kThreads) gq[k] = L.pool.out.q[k];
-  }
+  if (np > 0) copy_out(D, base, np, L.pool.out.x, L.pool.out.a, L.pool.out.q);
 }
 
 // ---------------------------------------------------------------------------
@@ -1561,9 +1664,10 @@ __global__ __launch_bounds__(kThreads) void k_scatter_state(Ctx c, State S, doub
   const int n = c.n;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int id = S.pid[i];
+  const Aux r = S.a[i];
   const double4 p = S.xr[i];
-  const double* vw = S.vw + 6 * (size_t)i;
+  const int id = r.pid;
+  const double vw[6] = {r.vw[0].x, r.vw[0].y, r.vw[1].x, r.vw[1].y, r.vw[2].x, r.vw[2].y};
   if (x) {
     x[id] = p.x;
     x[n + id] = p.y;
@@ -1592,21 +1696,34 @@ __global__ __launch_bounds__(kThreads) void k_pack_state(Ctx c, State S, const d
   const int n = c.n;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  Aux r;
   S.xr[i] = make_double4(x[i], x[n + i], x[2 * n + i], R[i]);
-  double* vw = S.vw + 6 * (size_t)i;
+  double vw[6];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     vw[k] = v ? v[k * n + i] : 0.0;
     vw[3 + k] = w ? w[k * n + i] : 0.0;
   }
+  r.vw[0] = make_double2(vw[0], vw[1]);
+  r.vw[1] = make_double2(vw[2], vw[3]);
+  r.vw[2] = make_double2(vw[4], vw[5]);
   S.q[i] = q ? make_double4(q[i], q[n + i], q[2 * n + i], q[3 * n + i])
              : make_double4(1.0, 0.0, 0.0, 0.0);
-  S.pid[i] = i;
-  c.os[i] = make_int4(i, 0, 0, i);
+  r.pid = i;
+  r.prev = i;
+  r.off = 0;
+  r.cnt = 0;
+  S.a[i] = r;
   c.xb[i] = make_double4(x[i], x[n + i], x[2 * n + i], 0.0);
-  c.key[i] = 0;
   c.F[i] = c.F[n + i] = c.F[2 * n + i] = 0.0;
   c.T[i] = c.T[n + i] = c.T[2 * n + i] = 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_set_segments(Ctx c, State S, Contacts cn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  S.a[i].off = cn.off[i];
+  S.a[i].cnt = cn.cnt[i];
 }
 
 __global__ void k_selftest(int64_t n, const double* in, const double* in2, double* out) {
@@ -1645,11 +1762,11 @@ hipError_t launch_step(const Ctx& c, const State& A, const State& B, const State
       k_scan_down<<<kScanBlocks, kScanThreads, 0, s>>>(c);
     }
     k_scatter<<<nbp, kThreads, 0, s>>>(c);
-    k_reorder<<<nbp, kThreads, 0, s>>>(c, A, T, cold);
+    k_reorder<<<nbp, kThreads, 0, s>>>(c, A, T);
   }
   if (c.any_moving) {
     k_mesh<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c, 0, rebuild);
-    (void)launch_mesh_bins(c, s);
+    if (c.rebin) (void)launch_mesh_bins(c, s);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
   if (!rebuild) k_begin<<<1, kBeginThreads, 0, s>>>(c);
@@ -1713,6 +1830,11 @@ hipError_t launch_mesh_bins(const Ctx& c, hipStream_t s) {
     k_bin_fill<<<blocks_for(c.ntri, kThreads), kThreads, 0, s>>>(c);
     k_bin_sort<<<blocks_for(c.nbins, kThreads), kThreads, 0, s>>>(c);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_segments(const Ctx& c, const State& S, const Contacts& cn, hipStream_t s) {
+  if (c.n > 0) k_set_segments<<<blocks_for(c.n, kThreads), kThreads, 0, s>>>(c, S, cn);
   return hipGetLastError();
 }
 

@@ -157,8 +157,6 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.gstat = L.take<unsigned long long>(2 * G);
   cc.xtra = L.take<double>(S);
   cc.spill = L.take<int32_t>(std::max<size_t>(N * (size_t)(hit_cap_of(cfg) - kHit), 1));
-  cc.key = L.take<int32_t>(N);
-  cc.os = L.take<int4>(N);
   cc.xb = L.take<double4>(N);
   {
     // candidate lists of the particles, kept between rebuilds (skin > 0)
@@ -177,6 +175,7 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   cc.tri_nv = L.take<int32_t>(M);
   cc.tri_grp = L.take<int32_t>(M);
   cc.tri_mv = L.take<double>(9 * M);
+  cc.frame = L.take<double>(12 * S);
   cc.motion = L.take<MeshMotion>(S * kMotionMax);
   cc.mg = L.take<MeshGrid>(S);
   cc.bin_cnt = L.take<int32_t>((size_t)std::max<int64_t>(bins_cap(cfg), 1));
@@ -187,9 +186,8 @@ static Layout carve(const sdem_config& cfg, char* base, Ctx* c, State st[2], Con
   for (int b = 0; b < 3; ++b) {
     State s{};
     s.xr = L.take<double4>(N);
-    s.vw = L.take<double>(6 * N);
+    s.a = L.take<Aux>(N);
     s.q = L.take<double4>(N);
-    s.pid = L.take<int32_t>(N);
     if (st) st[b] = s;
   }
   for (int b = 0; b < 2; ++b) {
@@ -316,6 +314,13 @@ static MeshMotion default_motion(const sdem_params& p) {
   return g;
 }
 
+// Every element of the mesh in the same motion group.
+static bool one_motion_group(const std::vector<int32_t>& grp) {
+  for (int32_t g : grp)
+    if (g != grp[0]) return false;
+  return !grp.empty();
+}
+
 static int upload_params(sdem_ctx* x) {
   std::vector<SimParams> sp(x->nsims);
   int tri0 = 0;
@@ -328,11 +333,14 @@ static int upload_params(sdem_ctx* x) {
     tri0 += sp[s].ntri;
   }
   x->c.any_moving = 0;
+  x->c.rebin = 0;
   for (int s = 0; s < x->nsims; ++s) {
     sp[s].moving = 0;
     for (size_t m = 0; m < x->mesh_grp[s].size(); ++m)
       if (x->motion[s][x->mesh_grp[s][m]].moving) sp[s].moving = 1;
+    sp[s].frame_bins = sp[s].moving && one_motion_group(x->mesh_grp[s]) ? 1 : 0;
     if (sp[s].moving) x->c.any_moving = 1;
+    if (sp[s].moving && !sp[s].frame_bins) x->c.rebin = 1;
   }
   HIP_TRY(hipMemcpyAsync(x->c.sp, sp.data(), sizeof(SimParams) * x->nsims, hipMemcpyHostToDevice,
                          x->stream));
@@ -784,8 +792,13 @@ static int upload_mesh(sdem_ctx* X) {
     // the reach of the bins: R_max plus the half skin (as derive() sets it)
     const double rm = X->rmax[s] > 0 ? X->rmax[s] : 1.0;
     const double rreach = rm + 0.5 * X->cfg.skin * rm;
-    mg[s] = mesh_grid(X->mesh_tri[s], X->mesh_nv[s], X->mesh_r[s], X->mesh_grp[s], X->motion[s],
-                      rreach, std::max<int64_t>(bb, 1), eb, (int32_t)nbins);
+    // a mesh moving as one body is binned once in its own frame: the grid
+    // covers its elements at t = 0 only
+    std::vector<MeshMotion> still(X->motion[s].size());
+    const bool frame = one_motion_group(X->mesh_grp[s]) && X->motion[s][X->mesh_grp[s][0]].moving;
+    mg[s] = mesh_grid(X->mesh_tri[s], X->mesh_nv[s], X->mesh_r[s], X->mesh_grp[s],
+                      frame ? still : X->motion[s], rreach, std::max<int64_t>(bb, 1), eb,
+                      (int32_t)nbins);
     if (mg[s].dim[0] <= 0) return fail(SDEM_ECAPACITY, "no triangle bin grid fits simulation %d", s);
     nbins += (int64_t)mg[s].dim[0] * mg[s].dim[1] * mg[s].dim[2];
   }
@@ -828,7 +841,9 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
   hipStream_t st = X->stream;
   HIP_TRY(hipStreamSynchronize(st));
   std::vector<int32_t> pid((size_t)std::max<int64_t>(n, 1)), slot((size_t)std::max<int64_t>(n, 1));
-  if (n) HIP_TRY(hipMemcpy(pid.data(), X->st[X->cur].pid, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  if (n)
+    HIP_TRY(hipMemcpy2D(pid.data(), sizeof(int32_t), &X->st[X->cur].a[0].pid, sizeof(Aux),
+                        sizeof(int32_t), (size_t)n, hipMemcpyDeviceToHost));
   for (int64_t s = 0; s < n; ++s) slot[pid[s]] = (int32_t)s;
   std::vector<int32_t> owner((size_t)nc);
   std::vector<int32_t> simof((size_t)std::max<int64_t>(n, 1));
@@ -883,6 +898,9 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
     HIP_TRY(hipMemcpy(C.key, K.data(), sizeof(int2) * Ctot, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(C.spr, SP.data(), sizeof(double) * kSpr * Ctot, hipMemcpyHostToDevice));
   }
+  // the particles' records carry their segments for the next step
+  HIP_TRY(launch_set_segments(X->c, X->st[X->cur], C, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
   return SDEM_OK;
 }
 

@@ -21,7 +21,7 @@ constexpr int kHit = 32;            // contacts of one particle held in LDS by i
 constexpr int kCand = 32;           // candidates one search lane records at a rebuild
 constexpr int kGroupShift = 8;      // contact records are allocated per group of
 constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots: a tile of the step kernel
-constexpr int kLdsRec = 1024;       // records of a tile held in LDS (the rest in global memory)
+constexpr int kLdsRec = 768;        // records of a tile held in LDS (the rest in global memory)
 constexpr int kLdsRef = 1024;       // in-tile references held in LDS (the rest in global memory)
 constexpr int kBrickBits = 3;       // cells are ordered in bricks of up to 8 x 8 x 8
 constexpr int kBinScanThreads = 1024;  // one workgroup scans the triangle bins
@@ -52,7 +52,9 @@ struct SimParams {
   int32_t moving;              // some element of the mesh moves
   int32_t tri0, ntri;          // global triangle range
   int32_t p0, np;              // particle range (fixed positions in sorted order)
-  int32_t pad;
+  int32_t frame_bins;          // the mesh moves as one rigid body: its element bins
+                               // are built once in the mesh's own frame (t = 0) and
+                               // looked up with the particle mapped back to it
 };
 
 // Prescribed rigid motion of a group of mesh elements: turns with angular
@@ -122,13 +124,25 @@ struct SpawnParams {
   uint32_t key[2];
 };
 
-// One buffer of per-particle state in cell-sorted order, packed per particle
-// so that a gather of one particle is a few 16-byte loads.
+// What the contact law needs of a particle besides its centre and radius, in
+// one 64-byte record, so that gathering a contact partner touches its centre
+// (which the search has just read) and one more 64-byte sector.
+struct alignas(64) Aux {
+  double2 vw[3];  // velocity (vx, vy), (vz, wx), (wy, wz): velocity then spin
+  int32_t pid;    // persistent id
+  int32_t prev;   // slot of the particle in the previous step's order
+  int32_t off;    // its first owned record in the previous step's contacts
+  int32_t cnt;    // and how many it owned
+};
+static_assert(sizeof(Aux) == 64, "one 64-byte sector per particle");
+
+// One buffer of per-particle state in cell-sorted order.  The centres are an
+// array of their own: the search reads many neighbours' centres and nothing
+// else of them.
 struct State {
-  double4* xr;   // [n] centre x, y, z and radius R
-  double* vw;    // [n][6] velocity then angular velocity
-  double4* q;    // [n] orientation quaternion, scalar first
-  int32_t* pid;  // persistent id
+  double4* xr;  // [n] centre x, y, z and radius R
+  Aux* a;       // [n]
+  double4* q;   // [n] orientation quaternion, scalar first
 };
 
 // One buffer of contacts, grouped by owner slot (owner = lower slot; a
@@ -152,7 +166,8 @@ struct Contacts {
 // Everything a step's kernels read or write.
 struct Ctx {
   int32_t n, nsims, ntri, cap_contacts, cap_cells, nchunks;
-  int32_t any_moving, pad_i;
+  int32_t any_moving;        // some simulation's mesh moves
+  int32_t rebin;             // some moving mesh needs its bins rebuilt every step
   int32_t skin_on;           // cells are kept between steps (skin > 0)
   int32_t hit_cap;           // contacts one particle may have in a step (>= kHit)
   int32_t ngroups, gcap;     // slot groups, contact records per group
@@ -176,9 +191,6 @@ struct Ctx {
   int32_t* scan_tmp;  // [kScanBlocks+1]
   int32_t* spill;     // [n][hit_cap - kHit] contacts of a particle past its kHit in LDS
   // per slot, written by the reorder at a rebuild and kept until the next:
-  int32_t* key;       // [n] cell key
-  int4* os;           // [n] (slot in the previous step's order, first and number of the
-                      // contacts it owned in the previous step, persistent id)
   double4* xb;        // [n] centre when the cells were built (w unused)
   int32_t* vcnt;      // [n] candidates recorded by each particle at the last
                       // rebuild (-1: more than kCand, search the cells)
@@ -198,6 +210,8 @@ struct Ctx {
   MeshMotion* motion; // [nsims * kMotionMax]
   double* tri_mv;     // [ntri][9] wall motion now: spin, moved centre, translation
                       // velocity (zero for elements that do not move)
+  double* frame;      // [nsims][12] motion now of a mesh binned in its own frame:
+                      // unit axis, cos and sin of the angle, moved centre, centre
   MeshGrid* mg;       // [nsims]
   int32_t* bin_cnt;   // [nbins] zero between builds
   int32_t* bin_start; // [nbins+1]
@@ -390,5 +404,7 @@ hipError_t launch_mesh_planes(const Ctx& c, hipStream_t s);
 hipError_t launch_mesh_bins(const Ctx& c, hipStream_t s);
 hipError_t launch_selftest(int64_t n, const double* in, const double* in2, double* out,
                            hipStream_t s);
+// copies the owned-contact segments of cn (off, cnt) into the records of S
+hipError_t launch_set_segments(const Ctx& c, const State& S, const Contacts& cn, hipStream_t s);
 
 }  // namespace sdem

@@ -167,16 +167,17 @@ __global__ __launch_bounds__(64) void k_spawn_decide(Ctx c, State A, Contacts co
   for (int k = lane; k < nacc; k += 64) {
     const int slot = n0 + k;
     const double4 b = acc[k];
+    Aux r;
     A.xr[slot] = b;
-    double* vw = A.vw + 6 * (size_t)slot;
-    vw[0] = P.v0[0];
-    vw[1] = P.v0[1];
-    vw[2] = P.v0[2];
-    vw[3] = P.w0[0];
-    vw[4] = P.w0[1];
-    vw[5] = P.w0[2];
     A.q[slot] = make_double4(1.0, 0.0, 0.0, 0.0);
-    A.pid[slot] = slot;
+    r.vw[0] = make_double2(P.v0[0], P.v0[1]);
+    r.vw[1] = make_double2(P.v0[2], P.w0[0]);
+    r.vw[2] = make_double2(P.w0[1], P.w0[2]);
+    r.pid = slot;
+    r.prev = slot;
+    r.off = 0;
+    r.cnt = 0;
+    A.a[slot] = r;
     cold.cnt[slot] = 0;
     cold.off[slot] = 0;
   }
@@ -197,7 +198,9 @@ __global__ __launch_bounds__(64) void k_spawn_decide(Ctx c, State A, Contacts co
 // Radii by persistent id.
 __global__ __launch_bounds__(kThreads) void k_scatter_radii(Ctx c, State S, double* R) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i < c.n) R[S.pid[i]] = S.xr[i].w;
+  if (i < c.n) {
+    R[S.a[i].pid] = S.xr[i].w;
+  }
 }
 
 inline int blocks(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }

@@ -21,14 +21,15 @@ SDEM_FP64, SDEM_MIXED = 0, 1
 _NAMES = {SDEM_EINVAL: "EINVAL", SDEM_ECAPACITY: "ECAPACITY", SDEM_ENONFINITE: "ENONFINITE",
           SDEM_EHIP: "EHIP", SDEM_ESTATE: "ESTATE"}
 
-EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_batch", "sdem_add_mesh",
+EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_static", "sdem_init_batch",
+           "sdem_add_mesh",
            "sdem_add_mesh_elements", "sdem_set_spawn", "sdem_spawn_status", "sdem_read_radii",
            "sdem_set_spawn_status", "sdem_set_clock", "sdem_read_off", "sdem_write_csv",
            "sdem_set_mesh_motion",
            "sdem_read_csv", "sdem_write_contacts_csv", "sdem_read_contacts_csv",
            "sdem_set_history", "sdem_step", "sdem_read_state", "sdem_read_contacts", "sdem_stats",
            "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding", "sdem_step_profiled")
-PHASES = ("grid", "sort", "detect", "force", "integrate", "force_kernel")
+PHASES = ("grid", "sort", "begin", "step", "empty", "step_kernel")
 
 
 class SdemError(RuntimeError):
