@@ -1481,11 +1481,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
           ut = g3.x;
         }
       }
+      // one call of the law for the whole wave: the canonical orientation is
+      // chosen in registers (two calls behind a branch on swap would make a
+      // wave whose lanes differ run both)
       double o[9];
-      if (swap)
-        contact_law<RT>(c, P, false, m, pb, pa, vb0, vb1, vb2, va0, va1, va2, us, ur, &ut, o);
-      else
-        contact_law<RT>(c, P, wall, m, pa, pb, va0, va1, va2, vb0, vb1, vb2, us, ur, &ut, o);
+      {
+        const double4 pi = swap ? pb : pa, pj = swap ? pa : pb;
+        const double2 vi0 = swap ? vb0 : va0, vi1 = swap ? vb1 : va1, vi2 = swap ? vb2 : va2;
+        const double2 vj0 = swap ? va0 : vb0, vj1 = swap ? va1 : vb1, vj2 = swap ? va2 : vb2;
+        contact_law<RT>(c, P, wall, m, pi, pj, vi0, vi1, vi2, vj0, vj1, vj2, us, ur, &ut, o);
+      }
       // results by the tile's particle a (force on a, torque on a, torque on b)
       double* rs = L.pool.law.res[tid];
 #pragma unroll
