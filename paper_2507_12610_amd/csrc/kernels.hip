@@ -751,21 +751,54 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
 //    records, cross records, references), so results do not depend on
 //    scheduling.
 // ---------------------------------------------------------------------------
+// Double-precision reciprocal, quotient and square root for the contact law
+// (not for the contact test, whose square root stays correctly rounded): the
+// hardware estimate refined by Newton steps, within a few ulps, a fraction
+// of the instructions of the correctly rounded forms.  Arguments are finite;
+// the square root takes x >= 0 (0 gives 0).
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+__device__ __forceinline__ double fast_div(double a, double b) {
+  const double r = fast_rcp(b);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+__device__ __forceinline__ double fast_sqrt(double x) {
+  if (!(x > 0.0)) return 0.0;
+  // y ~ 1/sqrt(x); g ~ sqrt(x), h ~ 1/(2 sqrt(x)), two coupled Newton steps
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+// the same for the arithmetic type of the law (float: the library's forms)
+__device__ __forceinline__ double rt_sqrt(double x) { return fast_sqrt(x); }
+__device__ __forceinline__ float rt_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double rt_div(double a, double b) { return fast_div(a, b); }
+__device__ __forceinline__ float rt_div(float a, float b) { return a / b; }
+
 // Static/kinetic update of a vector friction mode m in {s, r}: rotate the old
 // spring into the tangent plane keeping its length, f = -k u - c v, then keep
 // and integrate the spring (|f| <= lim) or clip f and reset the spring.
 template <typename RT>
 __device__ __forceinline__ void friction_vec(const RT n[3], RT k, RT cdmp, RT lim, double dt,
                                              const RT vm[3], double u[3], RT f[3]) {
-  const double ul = sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+  const double ul = fast_sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
   if (ul > 0.0) {
     const double un = (u[0] * (double)n[0] + u[1] * (double)n[1]) + u[2] * (double)n[2];
     double up[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) up[a] = u[a] - un * (double)n[a];
-    const double upl = sqrt((up[0] * up[0] + up[1] * up[1]) + up[2] * up[2]);
+    const double upl = fast_sqrt((up[0] * up[0] + up[1] * up[1]) + up[2] * up[2]);
     if (upl > 0.0) {
-      const double sc = ul / upl;
+      const double sc = fast_div(ul, upl);
 #pragma unroll
       for (int a = 0; a < 3; ++a) u[a] = up[a] * sc;
     } else {
@@ -774,15 +807,15 @@ __device__ __forceinline__ void friction_vec(const RT n[3], RT k, RT cdmp, RT li
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) f[a] = -k * (RT)u[a] - cdmp * vm[a];
-  const RT fl = sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
+  const RT fl = rt_sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
   if (fl <= lim) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = u[a] + dt * (double)vm[a];
   } else {
-    const RT sc = lim / fl;
+    const RT sc = rt_div(lim, fl);
 #pragma unroll
     for (int a = 0; a < 3; ++a) f[a] = f[a] * sc;
-    const double ik = 1.0 / (double)k;
+    const double ik = fast_rcp((double)k);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = -((double)f[a] + (double)cdmp * (double)vm[a]) * ik;
   }
@@ -796,7 +829,7 @@ __device__ __forceinline__ void friction_scalar(RT k, RT cdmp, RT lim, double dt
     *u = *u + dt * (double)vm;
   } else {
     ft = ft > (RT)0 ? lim : -lim;
-    *u = -((double)ft + (double)cdmp * (double)vm) / (double)k;
+    *u = fast_div(-((double)ft + (double)cdmp * (double)vm), (double)k);
   }
   *f = ft;
 }
@@ -822,7 +855,7 @@ __device__ __forceinline__ void contact_law(const Ctx& c, const SimParams& P, co
   const double Ri = pi.w, Rj = pj.w;
   double dx, dy, dz, d;
   const double delta = pair_gap(pi.x, pi.y, pi.z, Ri, pj.x, pj.y, pj.z, Rj, &dx, &dy, &dz, &d);
-  const double invd = 1.0 / d;
+  const double invd = fast_rcp(d);
   const RT nrm[3] = {(RT)(dx * invd), (RT)(dy * invd), (RT)(dz * invd)};
   const double ri = Ri - 0.5 * delta;
   const double mi = sphere_mass(P.rho, Ri);
@@ -837,13 +870,13 @@ __device__ __forceinline__ void contact_law(const Ctx& c, const SimParams& P, co
     rj = Rj - 0.5 * delta;
     const double mj = sphere_mass(P.rho, Rj);
     // effective radius and mass 1/(1/a + 1/b) written as a b / (a + b)
-    Rs = (Ri * Rj) / (Ri + Rj);
-    ms = (mi * mj) / (mi + mj);
+    Rs = fast_div(Ri * Rj, Ri + Rj);
+    ms = fast_div(mi * mj, mi + mj);
     cnf = P.cnf_pp;
     csf = P.csf_pp;
     Es = P.Es_pp;
     Gs = P.Gs_pp;
-    reff = (ri * rj) / (ri + rj);
+    reff = fast_div(ri * rj, ri + rj);
     // v = v_i - v_j + n x (r_i w_i + r_j w_j)
     const double rx = ri * wix + rj * wjx, ry = ri * wiy + rj * wjy, rz = ri * wiz + rj * wjz;
     vrel[0] = (vix - vjx) + (n1 * rz - n2 * ry);
@@ -886,10 +919,10 @@ __device__ __forceinline__ void contact_law(const Ctx& c, const SimParams& P, co
   // coefficients (Eq. ks, cn, cs; k_r = k_n, c_r = c_n, k_t = k_s, c_t = c_s)
   // with k_n = 4/3 E* a and k_s = 8 G* a: c_n = beta sqrt(20/3 E*) sqrt(m* a)
   // and c_s = beta sqrt(4/3 G*) sqrt(m* a), the constant factors per simulation
-  const RT ac = (RT)sqrt(Rs * delta);
+  const RT ac = (RT)fast_sqrt(Rs * delta);
   const RT kn = (RT)(4.0 / 3.0) * (RT)Es * ac;
   const RT ks = (RT)8.0 * (RT)Gs * ac;
-  const RT sm = sqrt((RT)ms * ac);
+  const RT sm = rt_sqrt((RT)ms * ac);
   const RT cn = (RT)cnf * sm;
   const RT cs = (RT)csf * sm;
   // relative velocities
@@ -905,7 +938,7 @@ __device__ __forceinline__ void contact_law(const Ctx& c, const SimParams& P, co
   // normal force f_n = k_n delta n - c_n v_n
   const RT kd = kn * (RT)delta;
   const RT fn[3] = {kd * nrm[0] - cn * vn[0], kd * nrm[1] - cn * vn[1], kd * nrm[2] - cn * vn[2]};
-  const RT fnl = sqrt((fn[0] * fn[0] + fn[1] * fn[1]) + fn[2] * fn[2]);
+  const RT fnl = rt_sqrt((fn[0] * fn[0] + fn[1] * fn[1]) + fn[2] * fn[2]);
   RT fs[3], fr[3], ft;
   friction_vec<RT>(nrm, ks, cs, (RT)P.mu_s * fnl, P.dt, vs, us, fs);
   friction_vec<RT>(nrm, kn, cn, (RT)P.mu_r * fnl, P.dt, vr, ur, fr);
