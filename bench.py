@@ -2,19 +2,19 @@
 """Throughput of the DEM hot path on one MI355X.
 
 Workload (default): the dense static packing of 8,000,000 spheres (half of
-radius 1.0 mm, half 1.4 mm, six contacts per sphere at the start, about
-24M contacts per step) in a closed 12-triangle cube, full friction, gravity,
-dt from Eq. dt at 1.0 mm, plain FP64: the largest single-GPU configuration,
-whose state is far larger than the 256 MB Infinity Cache.  A step is one
-full time step of the hot path: bounding box and grid, cell sort and state
-reorder (on the steps that rebuild the cells), narrow phase, contact forces
-with spring carry-over, integration.  The state is resident in HBM before
-timing starts.
+radius 1.4 mm, half 1.0 mm, body-centred, pre-compressed, eleven contacts
+per sphere, about 44M contacts per step) in force balance in a closed
+12-triangle box, full friction, dt from Eq. dt at 1.0 mm, plain FP64: the
+largest single-GPU configuration, whose state is far larger than the 256 MB
+Infinity Cache.  A step is one full time step of the hot path: bounding box
+and grid, cell sort and state reorder (on the steps that rebuild the
+cells), narrow phase, contact forces with spring carry-over, integration.
+The state is resident in HBM before timing starts.
 
-Timing: every timed window is exactly --steps steps bracketed by device
-synchronisations; windows follow one another in blocks that span at least
-two rebuild periods of the cells, so rebuilds are counted at their real
-rate; the value is the median block's particle-steps/s over three blocks.
+Timing: after --warmup steps, exactly --steps consecutive steps (default:
+the workload's whole run, 10,000 relaxation steps for the packing) in one
+window bracketed by device synchronisations, rebuilds of the cells
+included at their real rate; value = particles x steps / seconds.
 
 Prints one JSON line: particle-steps/s (value) and contacts/s; the roofline
 of the step kernel (narrow phase, contact law, integration: 264 N + 120 C
@@ -57,9 +57,10 @@ def step_bytes(n, c):
 # bench workloads, each with its counter summary and its settings when none
 # are given (None: autotuned)
 WORKLOADS = {
-    "packing_8M": {"make": "cfg5", "radii": "half 1.0 mm, half 1.4 mm (rock-salt lattice)",
+    "packing_8M": {"make": "cfg5",
+                   "radii": "half 1.4 mm, half 1.0 mm (body-centred arrangement)",
                    "traffic": "k_step_cfg5_packing_8M_hbm_traffic.md",
-                   "settings": (1.0, 1, 0.2)},
+                   "settings": (1.0, 1, 0.2, 256)},
     "column_200k": {"make": "cfg2", "radii": "lognormal, median 1 mm, sigma 0.2",
                     "traffic": "k_step_cfg2_column_200k_hbm_traffic.md", "settings": None},
 }
@@ -120,6 +121,36 @@ def cpu_baseline(w, steps=2):
                       f"start, serial FP64 oracle in one thread, "
                       + ", ".join(f"{t:.1f}" for t in per) + " s per step",
             "host": host_info()}
+
+
+def timed_run(s, n, K, chunk=1000):
+    """Times K consecutive steps of solver s as one window on the host clock
+    between device synchronisations (the host schedule runs in calls of at
+    most `chunk` steps, each printing a progress line): ms per step,
+    contacts, rebuilds, and ms per step of each call."""
+    import torch
+    a = s.stats()
+    per = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < K:
+        k = min(chunk, K - done)
+        t1 = time.perf_counter()
+        s.step(k)  # returns after the stream has drained
+        per.append(round(1e3 * (time.perf_counter() - t1) / k, 5))
+        done += k
+        if K > chunk:
+            print(f"[bench]   {done}/{K} steps, {per[-1]:.3f} ms/step", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    b = s.stats()
+    c = (b["pp"] - a["pp"]) + (b["pw"] - a["pw"])
+    return {"s": sec, "ms_per_step": round(1e3 * sec / K, 5),
+            "particle_steps_per_s": round(n * K / sec, 1),
+            "contacts_per_s": round(c / sec, 1), "contacts_per_step": round(c / K, 1),
+            "cell_rebuilds": f"{b['rebuilds'] - a['rebuilds']} of {K} steps",
+            "chunk_steps": chunk, "chunks_ms_per_step": per}
 
 
 def timed_blocks(s, n, K, blocks=3, min_block_steps=128):
@@ -217,6 +248,7 @@ def mixed_vs_fp64(w, opts, steps_before=200):
     d.update({k: st[k] for k in ("x", "v", "w", "q")})
     b = Solver(d, precision="mixed", **opts)
     b.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])
+    b.set_clock(steps_before)
     a.step(1)
     b.step(1)
     sa, sb = a.state(), b.state()
@@ -430,8 +462,11 @@ def batched_forms(K, landing_steps, precision_list=("fp64", "mixed")):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20, help="steps per timed window")
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's run, 10,000 steps for the packing)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--form-window", type=int, default=20,
+                    help="steps per timed window of the other forms")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -442,8 +477,8 @@ def main():
                     help="lanes per particle in the contact search")
     ap.add_argument("--skin", type=float, default=None,
                     help="cell skin in units of R_max (0: rebuild every step)")
-    ap.add_argument("--rebuild-every", type=int, default=0,
-                    help="longest rebuild period with a skin (0: 64)")
+    ap.add_argument("--rebuild-every", type=int, default=None,
+                    help="longest rebuild period with a skin (0: 64; default: the workload's)")
     ap.add_argument("--no-forms", action="store_true", help="skip the other forms")
     ap.add_argument("--forms", default="mixed,rebuilt,column,drum,batched",
                     help="comma-separated forms to run besides the headline")
@@ -486,7 +521,7 @@ def main():
         cf, lanes, skin = (fixed[0] if args.cell_factor is None else args.cell_factor,
                            fixed[1] if args.detect_lanes is None else args.detect_lanes,
                            fixed[2] if args.skin is None else args.skin)
-        every = args.rebuild_every
+        every = fixed[3] if args.rebuild_every is None else args.rebuild_every
     elif args.cell_factor is None or args.detect_lanes is None or args.skin is None:
         best, timings = autotune(w, candidates=TUNE_CANDIDATES, steps=512, warmup=10,
                                  precision=args.precision)
@@ -496,33 +531,24 @@ def main():
         every = best["rebuild_every"]
     else:
         cf, lanes, skin = args.cell_factor, args.detect_lanes, args.skin
-        every = args.rebuild_every
+        every = args.rebuild_every or 0
     period = every if every > 0 else 64
     opts = dict(device="cuda:0", cell_factor=cf, detect_lanes=lanes, skin=skin,
                 rebuild_every=every)
+    K = w["steps"] if args.steps is None else args.steps
     s = Solver(w, precision=args.precision, **opts)
     s.step(args.warmup)
-    torch.cuda.synchronize()
-    K = args.steps
-    med, blocks = timed_blocks(s, n, K, min_block_steps=2 * period if skin > 0 else K)
-    head = block_summary(med, blocks, n)
-    value = n * med["steps"] / med["s"]
-    print(f"[bench] {med['steps']} steps in {med['s']:.3f} s, "
-          f"{head['contacts_per_step']:.0f} contacts/step", file=sys.stderr, flush=True)
-    # one long window for comparison (a graph build inside it would show)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(400)
-    torch.cuda.synchronize()
-    long_ms = 1e3 * (time.perf_counter() - t0) / 400
-
+    run = timed_run(s, n, K)
+    print(f"[bench] {K} steps in {run['s']:.3f} s, {run['contacts_per_step']:.0f} contacts/step",
+          file=sys.stderr, flush=True)
+    value = n * K / run["s"]
     roofline = profiled_step_kernel(s, n, args.profile_steps)
     roofline["traffic"] = measured_traffic(args.workload)
     s.close()
     del s
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
-           "steps": K, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+           "steps": K, "warmup": args.warmup, "ms_per_step": run["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f32+f64",
            "data": "synthetic",
@@ -531,42 +557,48 @@ def main():
                       "radii": spec["radii"],
                       "friction": [w["params"]["mu_s"], w["params"]["mu_r"], w["params"]["mu_t"]],
                       "cell_factor": cf, "detect_lanes": lanes, "skin": skin,
-                      "rebuild_every": period, "cell_rebuilds": head["cell_rebuilds"]},
-           "contacts_per_s": head["contacts_per_s"],
-           "contacts_per_step": head["contacts_per_step"],
-           "timing": {"window_steps": K, "windows_per_block": med["steps"] // K,
-                      "blocks_ms_per_step": head["blocks_ms_per_step"],
-                      "statistic": "median of 3 blocks",
-                      "one_window_of_400_steps_ms_per_step": round(long_ms, 5)},
+                      "rebuild_every": period, "cell_rebuilds": run["cell_rebuilds"],
+                      "run_steps": w["steps"]},
+           "contacts_per_s": run["contacts_per_s"],
+           "contacts_per_step": run["contacts_per_step"],
+           "timing": {"window": f"steps {args.warmup + 1}-{args.warmup + K} of the run, one "
+                                f"window on the host clock between device synchronisations",
+                      "chunk_steps": run["chunk_steps"],
+                      "chunks_ms_per_step": run["chunks_ms_per_step"]},
            "roofline": roofline}
     if tuned is not None:
         out["autotune"] = tuned
     forms_wanted = set() if args.no_forms else set(f for f in args.forms.split(",") if f)
     forms = {}
+    F = args.form_window
     if "mixed" in forms_wanted:
+        # the other precision over the same run
         other = "mixed" if args.precision == "fp64" else "fp64"
+        print(f"[bench] {other}: the same {K} steps", file=sys.stderr, flush=True)
         g = Solver(w, precision=other, **opts)
         g.step(args.warmup)
-        m2, b2 = timed_blocks(g, n, K, min_block_steps=2 * period if skin > 0 else K)
+        r2 = timed_run(g, n, K)
         g.close()
-        forms[other] = dict(workload=w["name"], **block_summary(m2, b2, n),
+        r2.pop("chunk_steps")
+        forms[other] = dict(workload=w["name"], **r2,
                             tolerance=1e-5 if other == "mixed" else 1e-12)
         forms[other]["speedup_vs_" + args.precision] = round(
-            head["ms_per_step"] / forms[other]["ms_per_step"], 4)
+            run["ms_per_step"] / forms[other]["ms_per_step"], 4)
         forms["mixed_vs_fp64_one_step"] = mixed_vs_fp64(w, opts)
     if "rebuilt" in forms_wanted and skin > 0:
         # the paper's scheme, cells rebuilt every step, same workload
+        print("[bench] cells rebuilt every step", file=sys.stderr, flush=True)
         g = Solver(w, precision=args.precision, **dict(opts, skin=0.0))
         g.step(5)
-        m3, b3 = timed_blocks(g, n, K, min_block_steps=K)
+        m3, b3 = timed_blocks(g, n, F, min_block_steps=F)
         g.close()
         forms["cells_rebuilt_every_step"] = dict(workload=w["name"], **block_summary(m3, b3, n))
     if "column" in forms_wanted and args.workload != "column_200k":
-        forms["column_200k"] = column_forms(K)
+        forms["column_200k"] = column_forms(F)
     if "drum" in forms_wanted:
-        forms["drum_2M"] = drum_forms(K)
+        forms["drum_2M"] = drum_forms(F)
     if "batched" in forms_wanted:
-        forms["batched"] = batched_forms(K, args.batch_landing_steps)
+        forms["batched"] = batched_forms(F, args.batch_landing_steps)
     if forms:
         out["forms"] = forms
     if not args.no_cpu:

@@ -408,28 +408,65 @@ def cfg4(nsims=256, seed=404, sizes=None):
     return [cfg4_sim(s, int(sizes[s]), seed) for s in range(nsims)]
 
 
-def cfg5(seed=505, n=8_000_000, pitch=2.38 * MM, jitter=0.004 * MM):
-    """8,000,000 spheres, half R = 1.0 mm and half 1.4 mm, a pre-compressed
-    packing in a closed 12-triangle cube; full friction, g on, eta = 0, dt
-    from Eq. dt at 1.0 mm, 10,000 relaxation steps.
+def cfg5(seed=505, n=8_000_000, dims=(152, 161, 165), d_ls=2.38 * MM, jitter=0.001 * MM):
+    """8,000,000 spheres, half R = 1.4 mm and half 1.0 mm, a pre-compressed
+    static packing in a closed 12-triangle box; full friction, no gravity,
+    eta = 0, dt from Eq. dt at 1.0 mm, 10,000 relaxation steps.
 
-    Start: a rock-salt arrangement on a simple cubic lattice of pitch 2.38 mm
-    (k^3 sites, k = ceil(n^1/3), the first n in (z, y, x) order), large
-    spheres where i + j + k is even, +-0.004 mm jitter per coordinate.  Every
-    face-neighbour pair is large-small and overlaps by 0.02 +- 0.01 mm; the
-    next shells are out of reach, so each sphere starts with exactly six
-    contacts (coordination number 6).  The walls sit 1.39 mm beyond the
-    outermost centres (large spheres there overlap them by 0.01 mm)."""
+    Start: a body-centred (CsCl-type) arrangement.  Large spheres sit on a
+    cubic lattice of dims[0] x dims[1] x dims[2] sites, small ones at the
+    centres of its cells; the lattice constant puts every large-small pair
+    at d_ls (overlap 0.02 mm), which presses the six axial large-large
+    neighbours together by 0.052 mm.  Each small sphere touches 8 large
+    ones, each large sphere 8 small and 6 large ones.  With these radii no
+    body-centred packing keeps large-small contacts without large-large ones
+    (that needs R_small >= 0.732 R_large), and in a rock-salt arrangement
+    every lattice line ends at one wall with a small sphere 0.4 mm short of
+    it, so it cannot be held in place by flat walls.
+
+    The walls stand at the outermost large spheres with the overlap whose
+    textbook Hertz force (4/3 E* sqrt(R*) delta^1.5; E* doubled for a rigid
+    wall, R* = R) balances the contacts a boundary sphere lacks on its outer
+    side: one large-large and four large-small ones at 1/sqrt(3) of their
+    force.  Interior spheres are balanced by symmetry, so the packing starts
+    in equilibrium up to +-jitter per coordinate (uniform); it then relaxes
+    the small imbalances this leaves.  The surplus of the box over n (120
+    sites) are small spheres removed at random (vacancies).
+
+    Gravity is off: under gravity a column of 160 layers of this soft
+    material (E = 1 MPa) loads its bottom contacts with several times the
+    pre-compression force and sags by millimetres instead of relaxing in
+    place."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    k1 = int(math.ceil(n ** (1.0 / 3.0) - 1e-9))
-    idx = np.arange(n, dtype=np.int64)
-    i, j, k = idx % k1, (idx // k1) % k1, idx // (k1 * k1)
-    R = np.where((i + j + k) % 2 == 0, 1.4 * MM, 1.0 * MM)
-    x = np.stack([i, j, k], axis=1) * pitch + rng.uniform(-jitter, jitter, (n, 3))
-    top = (k1 - 1) * pitch
-    tri = cube_mesh([-1.39 * MM] * 3, [top + 1.39 * MM] * 3)
-    p = default_params(dt=dt_eq(1.0 * MM, 2500.0, 1e6, 0.3))
-    return _finish("cfg5_dense_packing_8M", p, x, R, rng, tri, 10000, R_max=1.4 * MM)
+    RL, RS = 1.4 * MM, 1.0 * MM
+    a = 2.0 * d_ls / math.sqrt(3.0)
+    nx, ny, nz = dims
+    gl = np.stack(np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij"),
+                  axis=-1).reshape(-1, 3)[:, ::-1].astype(float)
+    gs = np.stack(np.meshgrid(np.arange(nz - 1), np.arange(ny - 1), np.arange(nx - 1),
+                              indexing="ij"), axis=-1).reshape(-1, 3)[:, ::-1] + 0.5
+    surplus = len(gl) + len(gs) - n
+    if surplus < 0 or surplus > len(gs):
+        raise ValueError("the box does not hold n spheres")
+    if surplus:
+        gs = np.delete(gs, rng.choice(len(gs), surplus, replace=False), axis=0)
+    g = np.concatenate([gl, gs])
+    R = np.concatenate([np.full(len(gl), RL), np.full(len(gs), RS)])
+    order = np.lexsort((g[:, 0], g[:, 1], g[:, 2]))  # (z, y, x) order of sites
+    g, R = g[order], R[order]
+    x = g * a + rng.uniform(-jitter, jitter, (n, 3))
+    # wall overlap: Hertz force on a boundary large sphere from the wall equal
+    # to the outward sum of its missing contacts (the 4/3 factors cancel)
+    E_pair = 1.0 / (2.0 * (1.0 - 0.3 * 0.3))  # E* / E of two spheres; a wall's is twice this
+    d_ll = 2.0 * RL - a
+    f_ll = E_pair * math.sqrt(RL * RL / (2 * RL)) * d_ll ** 1.5
+    f_ls = E_pair * math.sqrt(RL * RS / (RL + RS)) * (RL + RS - d_ls) ** 1.5
+    d_w = ((f_ll + 4.0 * f_ls / math.sqrt(3.0)) / (2.0 * E_pair * math.sqrt(RL))) ** (2.0 / 3.0)
+    lo = np.full(3, -(RL - d_w))
+    hi = (np.array(dims, float) - 1.0) * a + (RL - d_w)
+    tri = cube_mesh(lo, hi)
+    p = default_params(dt=dt_eq(1.0 * MM, 2500.0, 1e6, 0.3), g=(0.0, 0.0, 0.0))
+    return _finish("cfg5_dense_packing_8M", p, x, R, rng, tri, 10000, R_max=RL)
 
 
 # ---------------------------------------------------------------------------
