@@ -1,0 +1,86 @@
+"""A particle with more contacts than its search holds on chip (32): a sphere
+of 10 mm with 64 spheres of 2 mm pressed on it (the ends of Table 2's radius
+range), moving inwards so the 64 contacts last about 20 steps.  With room
+for 32 contacts per particle the first step fails with ECAPACITY and keeps
+the state; a context made again with room for 96 then matches the oracle:
+contact keys bit for bit at every step (the contacts past the 32 pass
+through the overflow area), springs, forces and states within the
+tolerance after the first step and after 24 steps, when the contacts have
+ended."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity_util import force_err, keys, oracle_from, rel, spring_err, torque_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def solver(w, **kw):
+    from paper_2507_12610_amd import Solver
+    return Solver(w, device="cuda:0", **kw)
+
+
+def big_contacts(c):
+    return int(((c["ki"] == 0) | (c["kj"] == 0)).sum())
+
+
+def check_state(g, o, w, tol):
+    cg, co = g.contacts(), o.contacts()
+    assert np.array_equal(keys(cg), keys(co))
+    if len(co["ki"]):
+        se = spring_err(cg, co)
+        assert max(se.values()) < tol, se
+    sg, so = g.state(), o.state()
+    fo = o.forces()
+    assert force_err(sg["F"], fo["F"], fo["Fscale"]) < tol
+    assert torque_err(sg["T"], fo["T"], fo["Tscale"], fo["Fscale"], w["R"]) < tol
+    # every sphere spins far above rounding here: plain normwise checks
+    for k in ("v", "w", "q"):
+        assert rel(sg[k], so[k]) < tol, k
+    assert rel(sg["x"] - w["x"], so["x"] - w["x"]) < tol
+
+
+def test_too_many_contacts_fails_then_more_room_recovers():
+    from paper_2507_12610_amd import SdemError
+    w = W.crowded_sphere()
+    g = solver(w, contacts_per_particle=32)
+    with pytest.raises(SdemError) as ei:
+        g.step(1)
+    msg = str(ei.value)
+    assert "ECAPACITY" in msg and "contacts_per_particle" in msg
+    assert np.array_equal(g.state(forces=False)["x"], w["x"])  # the step is abandoned
+    g.close()
+    g = solver(w, contacts_per_particle=96)
+    o = oracle_from(w)
+    g.step(1)
+    o.step(1)
+    assert big_contacts(o.contacts()) == 64
+    check_state(g, o, w, TOL64)
+    g.close()
+
+
+@pytest.mark.parametrize("skin,precision,tol", [(0.0, "fp64", TOL64), (0.5, "fp64", TOL64),
+                                                (0.5, "mixed", TOL32)])
+def test_crowded_sphere_horizon(skin, precision, tol):
+    """Free-running against the oracle while the 64 contacts form, hold and
+    end.  With a skin the large sphere's candidates (64) exceed the list
+    length, so its kept steps search the cells."""
+    w = W.crowded_sphere()
+    g = solver(w, contacts_per_particle=96, precision=precision, detect_lanes=1, skin=skin)
+    o = oracle_from(w)
+    seen = []
+    for step in range(24):
+        g.step(1)
+        o.step(1)
+        cg, co = g.contacts(), o.contacts()
+        assert np.array_equal(keys(cg), keys(co)), step
+        seen.append(big_contacts(co))
+        if step == 0:
+            check_state(g, o, w, tol)
+    assert seen[0] == 64 and min(seen[:15]) == 64 and seen[-1] == 0, seen
+    check_state(g, o, w, tol)
+    g.close()

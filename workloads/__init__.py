@@ -431,7 +431,8 @@ def cfg5(seed=505, n=8_000_000, dims=(152, 161, 165), d_ls=2.38 * MM, jitter=0.0
     force.  Interior spheres are balanced by symmetry, so the packing starts
     in equilibrium up to +-jitter per coordinate (uniform); it then relaxes
     the small imbalances this leaves.  The surplus of the box over n (120
-    sites) are small spheres removed at random (vacancies).
+    sites) are small spheres removed at random (vacancies); n=None keeps
+    every site (a smaller box of the same packing: dims sites per axis).
 
     Gravity is off: under gravity a column of 160 layers of this soft
     material (E = 1 MPa) loads its bottom contacts with several times the
@@ -445,6 +446,8 @@ def cfg5(seed=505, n=8_000_000, dims=(152, 161, 165), d_ls=2.38 * MM, jitter=0.0
                   axis=-1).reshape(-1, 3)[:, ::-1].astype(float)
     gs = np.stack(np.meshgrid(np.arange(nz - 1), np.arange(ny - 1), np.arange(nx - 1),
                               indexing="ij"), axis=-1).reshape(-1, 3)[:, ::-1] + 0.5
+    if n is None:
+        n = len(gl) + len(gs)
     surplus = len(gl) + len(gs) - n
     if surplus < 0 or surplus > len(gs):
         raise ValueError("the box does not hold n spheres")
@@ -466,12 +469,42 @@ def cfg5(seed=505, n=8_000_000, dims=(152, 161, 165), d_ls=2.38 * MM, jitter=0.0
     hi = (np.array(dims, float) - 1.0) * a + (RL - d_w)
     tri = cube_mesh(lo, hi)
     p = default_params(dt=dt_eq(1.0 * MM, 2500.0, 1e6, 0.3), g=(0.0, 0.0, 0.0))
-    return _finish("cfg5_dense_packing_8M", p, x, R, rng, tri, 10000, R_max=RL)
+    name = "cfg5_dense_packing_8M" if n == 8_000_000 else f"dense_packing_{n}"
+    return _finish(name, p, x, R, rng, tri, 10000, R_max=RL)
 
 
 # ---------------------------------------------------------------------------
 # small cases for tests
 # ---------------------------------------------------------------------------
+def crowded_sphere(n_small=64, seed=77, R_big=10 * MM, r_small=2 * MM, overlap=0.01 * MM,
+                   v_in=0.05, vel=0.005):
+    """One sphere of radius R_big with n_small spheres of radius r_small pressed
+    on it (the ends of Table 2's radius range, 2 and 10 mm): the small ones at
+    the points of a Fibonacci lattice on the sphere of radius R_big + r_small -
+    overlap (directions jittered by 2 degrees), so the large one has n_small
+    contacts at once, more than the 32 a particle's search holds on chip.
+    The small ones move towards the centre at v_in (plus random velocities
+    and spins of scale vel), so the contacts last about 20 steps; no gravity,
+    a closed 12-triangle box well clear of the cluster; dt from Eq. dt at
+    r_small."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = np.arange(n_small) + 0.5
+    ph = np.arccos(1.0 - 2.0 * k / n_small)
+    th = np.pi * (1.0 + 5.0 ** 0.5) * k
+    d = np.stack([np.sin(ph) * np.cos(th), np.sin(ph) * np.sin(th), np.cos(ph)], axis=1)
+    d += rng.normal(0.0, math.radians(2.0), d.shape)
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    x = np.concatenate([np.zeros((1, 3)), d * (R_big + r_small - overlap)])
+    R = np.concatenate([[R_big], np.full(n_small, r_small)])
+    half = R_big + 3.0 * r_small
+    tri = cube_mesh([-half] * 3, [half] * 3)
+    p = default_params(dt=dt_eq(r_small, 2500.0, 1e6, 0.3), g=(0.0, 0.0, 0.0))
+    v = rng.normal(0.0, vel, (len(R), 3))
+    v[1:] -= v_in * d
+    w = rng.normal(0.0, vel / r_small, (len(R), 3))
+    return _finish(f"crowded_sphere{n_small}_{seed}", p, x, R, rng, tri, 200, v=v, w=w)
+
+
 def random_cluster(n, seed, box=10 * MM, r_lo=0.8 * MM, r_hi=1.2 * MM, vel=0.05, spin=20.0,
                    overlap=0.15, params=None, tri=None):
     """n spheres at random in a cube (packing by random sequential addition at
