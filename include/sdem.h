@@ -103,11 +103,19 @@ typedef struct {
  *                particle order are kept between rebuilds, and every search
  *                reaches s R_max / 2 further (plus, should a particle drift
  *                farther than that from where it was binned, the excess,
- *                measured every step).  The cells are rebuilt every
- *                rebuild_every steps and at the first step of an sdem_step
- *                call after such a drift.  The contact set is the same for
- *                every value; only the work per step changes
- *  rebuild_every with skin > 0: steps between rebuilds, >= 1; 0 selects 64
+ *                measured every step).  The cells are rebuilt at the end of
+ *                each rebuild period and at the first step after such a
+ *                drift that the host sees: at the end of an sdem_step call
+ *                or of a period, and in contexts of 2^20 particles or more
+ *                after each step that keeps the cells and runs on its own
+ *                (steps run eight to a graph while the period has room, in
+ *                such contexts only after a whole period without a drift).
+ *                The period doubles after a period without such a drift,
+ *                up to rebuild_every, and halves after one with, down to 4.
+ *                The contact set is the same for every value; only the
+ *                work per step changes
+ *  rebuild_every with skin > 0: the longest rebuild period, >= 1; 0 selects
+ *                64
  *  contacts_per_particle  contacts (pairs and mesh elements) one particle may
  *                have in a step, in [32, 4096]; 0 selects 64.  The first 32
  *                are held on chip, the rest in n * (contacts_per_particle -

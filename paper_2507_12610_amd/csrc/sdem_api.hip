@@ -92,9 +92,10 @@ struct sdem_ctx {
   int64_t since = 0;
   bool need_rebuild = true;
   int rebuild_every = 1;  // the configured longest period
-  int period = 1;         // the current period: halved after a call in which
+  int period = 1;         // the current period: halved after a period in which
                           // searches had to reach past the skin, doubled
                           // (up to rebuild_every) after one without
+  bool quiet = false;     // the last whole period saw no such drift
   // particle spawning (one simulation per context)
   bool spawn_on = false;
   SpawnParams spawn{};
@@ -1016,11 +1017,21 @@ static hipError_t enqueue_steps(sdem_ctx* X, int k, bool rebuild, hipEvent_t* ev
   return hipSuccess;
 }
 
-// Contexts from this many particles look at the drift flag after every step
-// that keeps the cells (a step there takes milliseconds, the look tens of
-// microseconds), so that a drift past half the skin is followed by a rebuild
-// at the next step instead of widened searches until the period ends.
+// Steps that keep the cells run eight to a graph while the rebuild period has
+// room for eight; a drift past half the skin inside such a run widens the
+// searches of its remaining steps (the contact set stays exact) and halves
+// the period at its end.  Contexts from this many particles run their kept
+// steps one at a time and look at the drift flag after each (a step there
+// takes milliseconds, the look tens of microseconds), so that a drift is
+// followed by a rebuild at the next step, unless the last whole period saw
+// no drift: then they too run eight to a graph.
 constexpr int64_t kDriftCheckEachStep = int64_t(1) << 20;
+
+// Whether the next steps that keep the cells run as one eight-step graph.
+static bool eight_kept_steps(const sdem_ctx* X, int64_t left) {
+  return left >= 8 && X->since + 8 <= X->period &&
+         (X->n < kDriftCheckEachStep || X->quiet);
+}
 
 // Graph patterns: {steps, rebuild}.  A graph bakes in the pointers of both
 // buffers for its starting parity.
@@ -1056,8 +1067,7 @@ static void prepare_graphs(sdem_ctx* X) {
   if (X->graph_failed || !X->stream) return;
   const int cur = X->cur;
   for (int pat = 0; pat < 4; ++pat) {
-    const bool used = !X->c.skin_on ? (pat <= 1)
-                                    : (pat >= 1 && (pat != 3 || X->n < kDriftCheckEachStep));
+    const bool used = !X->c.skin_on ? (pat <= 1) : (pat >= 1);
     if (!used) continue;
     for (int p = 0; p < 2; ++p) {
       X->cur = p;
@@ -1086,7 +1096,8 @@ static int adapt_period(sdem_ctx* X, unsigned long long* drift0) {
   HIP_TRY(hipStreamSynchronize(X->stream));
   if (h.flags) return SDEM_OK;  // reported by the caller
   if (h.rebuild_next) X->need_rebuild = true;
-  if (h.drift_steps > *drift0)
+  X->quiet = h.drift_steps == *drift0;
+  if (!X->quiet)
     X->period = std::max(std::min(4, X->rebuild_every), X->period / 2);
   else
     X->period = std::min(X->rebuild_every, X->period * 2);
@@ -1136,14 +1147,14 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
       }
       if (rebuild_now(X))
         pat = 1;
-      else if (left >= 8 && X->since + 8 <= X->period && X->n < kDriftCheckEachStep)
+      else if (eight_kept_steps(X, left))
         pat = 3;
       else
         pat = 2;
     }
     HIP_TRY(run_pattern(X, pat));
     left -= kPatSteps[pat];
-    if (X->c.skin_on && !kPatRebuild[pat] && X->n >= kDriftCheckEachStep) {
+    if (X->c.skin_on && pat == 2 && X->n >= kDriftCheckEachStep) {
       int32_t next = 0;
       HIP_TRY(hipMemcpyAsync(&next, &X->c.ctr->rebuild_next, sizeof next, hipMemcpyDeviceToHost,
                              X->stream));
@@ -1169,9 +1180,11 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
   const int start = X->cur;
   unsigned long long drift0 = before.drift_steps;
   hipError_t err = hipSuccess;
+  int in_run = 0;  // steps left of what sdem_step would run as one eight-step graph
   for (int64_t i = 0; i < nsteps && !err; ++i) {
     // the same rebuild decisions as sdem_step: the period adapted at its
-    // end, and large contexts look at the drift flag after each kept step
+    // end, eight-step runs where sdem_step would launch them, and large
+    // contexts look at the drift flag after each kept step run on its own
     int rc = SDEM_OK;
     if (spawning(X)) {
       bool stop = false;
@@ -1184,11 +1197,15 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
       return rc;
     }
     const bool rb = rebuild_now(X);
+    if (in_run == 0 && !rb && X->c.skin_on && !spawning(X) && eight_kept_steps(X, nsteps - i))
+      in_run = 8;
+    const bool single = in_run == 0;
+    if (in_run > 0) --in_run;
     err = enqueue_steps(X, 1, rb, ev);
     count_step(X, rb);
     X->cur ^= 1;
     if (!err) err = hipEventSynchronize(ev[kPhases]);
-    if (!err && X->c.skin_on && !rb && X->n >= kDriftCheckEachStep && !spawning(X)) {
+    if (!err && X->c.skin_on && !rb && single && X->n >= kDriftCheckEachStep && !spawning(X)) {
       int32_t next = 0;
       err = hipMemcpyAsync(&next, &X->c.ctr->rebuild_next, sizeof next, hipMemcpyDeviceToHost,
                            X->stream);

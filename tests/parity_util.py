@@ -15,15 +15,22 @@ def rel(a, b):
 
 
 def rel_w(wg, wo, R, vo):
-    """Angular velocity error as a surface speed: max|dw| R_max over
-    max(max|v|, max|w| R_max), so rounding-level spins of particles that
-    should not rotate are not compared against themselves."""
+    """Angular velocity error: the larger of (a) the error as a surface speed,
+    max|dw| R_max over max(max|v|, max|w| R_max), so rounding-level spins of
+    particles that should not rotate are not compared against themselves,
+    and (b) the plain normwise relative error over the particles whose
+    surface speed |w| R_i is above 1e-6 of that scale (far above rounding)."""
+    wg, wo = np.asarray(wg), np.asarray(wo)
+    R = np.asarray(R, dtype=float)
     rmax = float(np.max(R)) if len(R) else 1.0
     den = max(float(np.abs(vo).max()) if np.size(vo) else 0.0,
               float(np.abs(wo).max()) * rmax if np.size(wo) else 0.0)
     if den == 0.0:
         return float(np.abs(wg).max()) * rmax if np.size(wg) else 0.0
-    return float(np.abs(np.asarray(wg) - np.asarray(wo)).max() * rmax / den)
+    surface = float(np.abs(wg - wo).max() * rmax / den)
+    spinning = np.linalg.norm(wo, axis=1) * R > 1e-6 * den
+    plain = rel(wg[spinning], wo[spinning]) if spinning.any() else 0.0
+    return max(surface, plain)
 
 
 def force_err(Fg, Fo, scale):

@@ -149,9 +149,11 @@ def packing():
                                                ("fp64", TOL64, 0.001), ("fp64", TOL64, 0.2)])
 def test_packing_8M_sampled(packing, precision, tol, skin):
     """With a very thin skin (0.001 R_max, half of it 0.7 um) the spheres'
-    small relaxation moves pass half of it within the first steps: the host
-    sees the drift flag after each step at this size and rebuilds at the
-    next one.  Skin 0.2 R_max is the bench's setting for this workload."""
+    small relaxation moves pass half of it within the first steps: the
+    searches of the following steps widen by the measured drift (keys still
+    exact at step 51), and the host, seeing the flag at the end of the call,
+    rebuilds at the next step.  Skin 0.2 R_max is the bench's setting for
+    this workload."""
     w = packing
     n = len(w["R"])
     g = solver(w, precision=precision, cell_factor=1.0, detect_lanes=1, skin=skin)

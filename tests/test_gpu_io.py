@@ -3,12 +3,14 @@ back exactly; a hopper whose mesh comes from an OFF file (face radius indices
 into Table 2's radius list) saved mid-run (state, springs, clock, spawn
 position) and resumed in a fresh context, which then follows the original:
 keys bit for bit, states within 1e-12 (the resumed context sums a particle's
-contacts in its own slot order)."""
+contacts in its own slot order); and the same resume from files that hold
+the oracle's run, against the oracle going on."""
 import numpy as np
 import pytest
 
+import oracle
 import workloads as W
-from tests.parity_util import keys, rel, spring_err
+from tests.parity_util import keys, rel, rel_w, spring_err
 
 pytestmark = pytest.mark.gpu
 
@@ -89,3 +91,64 @@ def test_resume_from_files(tmp_path):
         for q in ("x", "v", "w", "q"):
             assert rel(sb[q], sa[q]) < 1e-12, (k, q)
     assert b.stats()["steps"] == steps + 50
+
+
+def write_state_csv(path, st, R):
+    """A state file in the library's column layout, from host arrays."""
+    with open(path, "w") as f:
+        f.write("id,x,y,z,vx,vy,vz,wx,wy,wz,q0,q1,q2,q3,R\n")
+        for i in range(len(R)):
+            vals = [*st["x"][i], *st["v"][i], *st["w"][i], *st["q"][i], R[i]]
+            f.write("%d," % i + ",".join("%.17g" % v for v in vals) + "\n")
+
+
+def write_contacts_csv(path, c):
+    with open(path, "w") as f:
+        f.write("ki,kj,usx,usy,usz,urx,ury,urz,ut\n")
+        for e in range(len(c["ki"])):
+            vals = [*c["us"][e], *c["ur"][e], c["ut"][e]]
+            f.write("%d,%d," % (c["ki"][e], c["kj"][e]) + ",".join("%.17g" % v for v in vals)
+                    + "\n")
+
+
+def test_resume_from_oracle_files(tmp_path):
+    """The oracle runs the hopper for 300 steps (spawning from an empty
+    container); its state and springs are written in the library's file
+    formats by this test, read by the library's parsers, and a fresh GPU
+    context resumes from them with the clock and the spawn position.  It then
+    follows the oracle, which goes on from its own run: spawn status, radii
+    and keys bit for bit, springs and states within 1e-12, every 10 of 50
+    steps."""
+    from paper_2507_12610_amd import Solver, sdem
+    w, sp = scene(tmp_path)
+    o = oracle.Sim(w["params"], np.zeros((0, 3)), R=np.zeros(0), elements=w["elements"],
+                   rmesh=w["rmesh"])
+    o.set_spawn(**sp)
+    o.step(300)
+    attempts, carried = o.spawn_status()
+    c0 = o.contacts()
+    assert o.n > 100 and len(c0["ki"]) > 30
+    write_state_csv(tmp_path / "state.csv", o.state(), o.radii)
+    write_contacts_csv(tmp_path / "contacts.csv", c0)
+    st = sdem.read_csv(str(tmp_path / "state.csv"))
+    w2 = dict(w)
+    w2.update(x=st["x"], v=st["v"], w=st["w"], q=st["q"], R=st["R"])
+    g = Solver(w2, device="cuda:0", spawn=sp)
+    c = sdem.read_contacts_csv(str(tmp_path / "contacts.csv"))
+    g.set_history(c["ki"], c["kj"], c["us"], c["ur"], c["ut"])
+    g.set_clock(300)
+    g.set_spawn_status(attempts, carried)
+    for k in range(5):
+        o.step(10)
+        g.step(10)
+        n, ga, gc = g.spawn_status()
+        assert (n, ga, gc) == (o.n, *o.spawn_status()), k
+        assert np.array_equal(g.radii(), o.radii), k
+        cg, co = g.contacts(), o.contacts()
+        assert np.array_equal(keys(cg), keys(co)), k
+        assert max(spring_err(cg, co).values()) < 1e-12, k
+        sg, so = g.state(forces=False), o.state()
+        for q in ("x", "v", "q"):
+            assert rel(sg[q], so[q]) < 1e-12, (k, q)
+        assert rel_w(sg["w"], so["w"], o.radii, so["v"]) < 1e-12, k
+    assert g.stats()["steps"] == 350
