@@ -315,7 +315,9 @@ def drum_forms(K, sample=3000):
     w = W.cfg3()
     n = len(w["R"])
     print(f"[bench] drum: {n} particles, {len(w['tri'])} triangles", file=sys.stderr, flush=True)
-    opts = dict(cell_factor=1.0, detect_lanes=1, skin=0.2)
+    # skin 0.6 R_max: fewer rebuilds of the turning bed (0.2: 0.45 ms/step,
+    # 0.4: 0.41, 0.6: 0.40, 1.0: 0.52 over 400 steps after landing)
+    opts = dict(cell_factor=1.0, detect_lanes=1, skin=0.6)
     land = Solver(w, precision="fp64", **opts)
     land.step(300)
     st0, c0 = land.state(forces=False), land.contacts()
@@ -431,6 +433,11 @@ def batched_forms(K, landing_steps, precision_list=("fp64", "mixed")):
         g.step(4)
         med, blocks = timed_blocks(g, total, K, min_block_steps=96)
         out[prec] = block_summary(med, blocks, total)
+        # the step kernel's own duration on kept steps: the rest of a step is
+        # launch and host time (what a persistent kernel could remove)
+        rl = profiled_step_kernel(g, total, 12)
+        out[prec]["step_kernel_ms"] = rl["mean_ms"]
+        out[prec]["roofline"] = rl
         g.close()
     # the same 256 states, one simulation after another (plain FP64)
     seq = []

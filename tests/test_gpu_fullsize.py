@@ -124,10 +124,15 @@ def drum():
     return W.cfg3()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("mixed", TOL32)])
-def test_drum_2M_sampled(drum, precision, tol):
+@pytest.mark.parametrize("precision,tol,cf,skin", [("fp64", TOL64, 0.5, 0.0),
+                                                   ("mixed", TOL32, 0.5, 0.0),
+                                                   ("fp64", TOL64, 1.0, 0.6)])
+def test_drum_2M_sampled(drum, precision, tol, cf, skin):
+    """Cells rebuilt every step, and the bench's settings (cell edge 2 R_max,
+    skin 0.6 R_max: the drum's bins are kept in the mesh's own frame and the
+    particles' candidate lists between rebuilds)."""
     w = drum
-    g = solver(w, precision=precision, cell_factor=0.5, detect_lanes=1)
+    g = solver(w, precision=precision, cell_factor=cf, detect_lanes=1, skin=skin)
     k = 600
     g.step(k)
     st, c = g.state(forces=False), g.contacts()
