@@ -107,9 +107,11 @@ typedef struct {
  *                each rebuild period and at the first step after such a
  *                drift that the host sees: at the end of an sdem_step call
  *                or of a period, and in contexts of 2^20 particles or more
- *                after each step that keeps the cells and runs on its own
- *                (steps run eight to a graph while the period has room, in
- *                such contexts only after a whole period without a drift).
+ *                two steps after each step that keeps the cells and runs on
+ *                its own: its flag is copied to pinned host memory (8 bytes
+ *                that such a context allocates at init).  Steps that keep
+ *                the cells run eight to a graph while the period has room,
+ *                in such contexts only after a whole period without a drift.
  *                The period doubles after a period without such a drift,
  *                up to rebuild_every, and halves after one with, down to 4.
  *                The contact set is the same for every value; only the

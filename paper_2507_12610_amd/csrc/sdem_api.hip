@@ -64,6 +64,16 @@ int64_t bin_entries_cap(const sdem_config& c) {
 
 }  // namespace
 
+// Steps that keep the cells run eight to a graph while the rebuild period has
+// room for eight; a drift past half the skin inside such a run widens the
+// searches of its remaining steps (the contact set stays exact) and halves
+// the period at its end.  Contexts from this many particles run their kept
+// steps one at a time and look at the drift flag of each (a step there
+// takes milliseconds), so that a drift is followed by a rebuild two steps
+// later (the flag is read without waiting for the step just queued), unless
+// the last whole period saw no drift: then they too run eight to a graph.
+constexpr int64_t kDriftCheckEachStep = int64_t(1) << 20;
+
 struct sdem_ctx {
   Ctx c{};
   State st[3]{};  // st[cur] holds the state; st[2] the sorted copy of a rebuild
@@ -96,6 +106,18 @@ struct sdem_ctx {
                           // searches had to reach past the skin, doubled
                           // (up to rebuild_every) after one without
   bool quiet = false;     // the last whole period saw no such drift
+  // drift flags of kept steps run one at a time in large contexts: copied to
+  // pinned host memory behind each such step and read two steps later, so
+  // the host never waits for the step it has just queued
+  int32_t* lag_host = nullptr;  // [2]
+  hipEvent_t lag_ev[2] = {};
+  bool lag_valid[2] = {};
+  int lag_slot = 0;
+  ~sdem_ctx() {
+    for (auto& e : lag_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (lag_host) (void)hipHostFree(lag_host);
+  }
   // particle spawning (one simulation per context)
   bool spawn_on = false;
   SpawnParams spawn{};
@@ -452,6 +474,20 @@ int sdem_init_batch(sdem_ctx** out, const sdem_config* cfg_in, int32_t nsims,
   c.skin_on = cfg.skin > 0.0 ? 1 : 0;
   X->rebuild_every = c.skin_on ? (cfg.rebuild_every > 0 ? cfg.rebuild_every : 64) : 1;
   X->period = X->rebuild_every;
+  if (c.skin_on && cfg.n_max >= kDriftCheckEachStep) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+      delete X;
+      return fail(SDEM_EHIP, "pinned host memory for the drift flags: %s",
+                  hipGetErrorString(hipGetLastError()));
+    }
+    X->lag_host = static_cast<int32_t*>(h);
+    for (auto& e : X->lag_ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        delete X;
+        return fail(SDEM_EHIP, "drift flag events");
+      }
+  }
   c.ngroups = (int32_t)((std::max<int64_t>(n, 1) + kGroup - 1) / kGroup);
   c.gcap = (int32_t)group_cap(cfg);
 
@@ -1017,16 +1053,6 @@ static hipError_t enqueue_steps(sdem_ctx* X, int k, bool rebuild, hipEvent_t* ev
   return hipSuccess;
 }
 
-// Steps that keep the cells run eight to a graph while the rebuild period has
-// room for eight; a drift past half the skin inside such a run widens the
-// searches of its remaining steps (the contact set stays exact) and halves
-// the period at its end.  Contexts from this many particles run their kept
-// steps one at a time and look at the drift flag after each (a step there
-// takes milliseconds, the look tens of microseconds), so that a drift is
-// followed by a rebuild at the next step, unless the last whole period saw
-// no drift: then they too run eight to a graph.
-constexpr int64_t kDriftCheckEachStep = int64_t(1) << 20;
-
 // Whether the next steps that keep the cells run as one eight-step graph.
 static bool eight_kept_steps(const sdem_ctx* X, int64_t left) {
   return left >= 8 && X->since + 8 <= X->period &&
@@ -1105,6 +1131,38 @@ static int adapt_period(sdem_ctx* X, unsigned long long* drift0) {
   return SDEM_OK;
 }
 
+// The drift flag copied behind the single kept step two steps ago, if any.
+static hipError_t lag_take(sdem_ctx* X) {
+  const int s = X->lag_slot;
+  if (!X->lag_valid[s]) return hipSuccess;
+  const hipError_t e = hipEventSynchronize(X->lag_ev[s]);
+  if (e) return e;
+  if (X->lag_host[s]) X->need_rebuild = true;
+  X->lag_valid[s] = false;
+  return hipSuccess;
+}
+// Behind a single kept step of a large context: its drift flag to the host.
+static hipError_t lag_put(sdem_ctx* X) {
+  const int s = X->lag_slot;
+  hipError_t e = hipMemcpyAsync(&X->lag_host[s], &X->c.ctr->rebuild_next, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, X->stream);
+  if (!e) e = hipEventRecord(X->lag_ev[s], X->stream);
+  if (e) return e;
+  X->lag_valid[s] = true;
+  X->lag_slot ^= 1;
+  return hipSuccess;
+}
+// A rebuild makes the pending flags moot; at the end of a call both are read.
+static void lag_drop(sdem_ctx* X) { X->lag_valid[0] = X->lag_valid[1] = false; }
+static hipError_t lag_flush(sdem_ctx* X) {
+  hipError_t e = lag_take(X);
+  X->lag_slot ^= 1;
+  if (!e) e = lag_take(X);
+  X->lag_slot ^= 1;
+  return e;
+}
+static bool lag_on(const sdem_ctx* X) { return X->lag_host && X->n >= kDriftCheckEachStep; }
+
 int sdem_step(sdem_ctx* X, int64_t nsteps) {
   if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
   if (X->failed) return fail(SDEM_ESTATE, "context failed in an earlier step; read it and re-init");
@@ -1141,6 +1199,7 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
     if (!X->c.skin_on) {
       pat = left >= 2 ? 0 : 1;
     } else {
+      if (lag_on(X)) HIP_TRY(lag_take(X));
       if (X->since >= X->period && X->since > 0) {
         const int rc = adapt_period(X, &drift0);
         if (rc) return rc;
@@ -1154,14 +1213,14 @@ int sdem_step(sdem_ctx* X, int64_t nsteps) {
     }
     HIP_TRY(run_pattern(X, pat));
     left -= kPatSteps[pat];
-    if (X->c.skin_on && pat == 2 && X->n >= kDriftCheckEachStep) {
-      int32_t next = 0;
-      HIP_TRY(hipMemcpyAsync(&next, &X->c.ctr->rebuild_next, sizeof next, hipMemcpyDeviceToHost,
-                             X->stream));
-      HIP_TRY(hipStreamSynchronize(X->stream));
-      if (next) X->need_rebuild = true;
+    if (X->c.skin_on && lag_on(X)) {
+      if (kPatRebuild[pat])
+        lag_drop(X);
+      else if (pat == 2)
+        HIP_TRY(lag_put(X));
     }
   }
+  if (lag_on(X)) HIP_TRY(lag_flush(X));
   return finish_steps(X, before, start);
 }
 
@@ -1191,6 +1250,9 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
       rc = spawn_now(X, &stop);
       if (!rc && stop) break;
     }
+    const bool lag = X->c.skin_on && lag_on(X) && !spawning(X);
+    if (!rc && lag && in_run == 0 && lag_take(X) != hipSuccess)
+      rc = fail(SDEM_EHIP, "profiled step failed: %s", hipGetErrorString(hipGetLastError()));
     if (!rc && X->c.skin_on && X->since >= X->period && X->since > 0) rc = adapt_period(X, &drift0);
     if (rc) {
       for (int k = 0; k < kEvents; ++k) (void)hipEventDestroy(ev[k]);
@@ -1204,14 +1266,13 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
     err = enqueue_steps(X, 1, rb, ev);
     count_step(X, rb);
     X->cur ^= 1;
-    if (!err) err = hipEventSynchronize(ev[kPhases]);
-    if (!err && X->c.skin_on && !rb && single && X->n >= kDriftCheckEachStep && !spawning(X)) {
-      int32_t next = 0;
-      err = hipMemcpyAsync(&next, &X->c.ctr->rebuild_next, sizeof next, hipMemcpyDeviceToHost,
-                           X->stream);
-      if (!err) err = hipStreamSynchronize(X->stream);
-      if (!err && next) X->need_rebuild = true;
+    if (!err && lag) {
+      if (rb)
+        lag_drop(X);
+      else if (single)
+        err = lag_put(X);
     }
+    if (!err) err = hipEventSynchronize(ev[kPhases]);
     for (int k = 0; k < kPhases && !err; ++k) {
       float ms = 0.f;
       err = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
@@ -1224,6 +1285,7 @@ int sdem_step_profiled(sdem_ctx* X, int64_t nsteps, double* phase_ms) {
     }
   }
   for (int k = 0; k < kEvents; ++k) (void)hipEventDestroy(ev[k]);
+  if (!err && lag_on(X)) err = lag_flush(X);
   if (err) return fail(SDEM_EHIP, "profiled step failed: %s", hipGetErrorString(err));
   for (int k = 0; k <= kPhases; ++k) phase_ms[k] /= (double)nsteps;
   return finish_steps(X, before, start);
