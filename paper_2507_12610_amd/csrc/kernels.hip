@@ -1049,7 +1049,8 @@ struct StepLds {
   union {
     int hits[kThreads / 64][kHit][64];
     struct {
-      double res[kThreads][9];    // force on I, torque on I, torque on J
+      // force on I, torque on I, torque on J (and a pad: 16-byte rows)
+      double2 res[kThreads][5];
       double spr[kThreads][kSpr];  // updated springs of owned records
       int2 key[kThreads];
     } law;
@@ -1403,11 +1404,20 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   auto rec_at = [&](int r) -> int2 {
     return r < kLdsRec ? L.rec[r] : make_int2(cn.a[wbase + r], cn.b[wbase + r]);
   };
-  // references: the record of (lower partner t, s) among t's owned records
+  // references: the record of (lower partner t, s) among t's owned records,
+  // kept in ascending record order (each pass then takes a run of them)
+  auto ref_at = [&](int q) -> int {
+    return q < kLdsRef ? L.ref[q] : cn.ref[gbase + (q - kLdsRef)];
+  };
+  auto ref_set = [&](int q, int v) {
+    if (q < kLdsRef)
+      L.ref[q] = v;
+    else
+      cn.ref[gbase + (q - kLdsRef)] = v;
+  };
   for (int j = 0; j < nr; ++j) {
     const int q = roff + j;
-    const int t = q < kLdsRef ? L.ref[q] : cn.ref[gbase + (q - kLdsRef)];
-    const int lt = t - base;
+    const int lt = ref_at(q) - base;
     const int r0 = L.ooff[lt], r1 = r0 + L.ocnt[lt];
     int r = -1;
     for (int rr = r0; rr < r1; ++rr)
@@ -1415,8 +1425,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
         r = rr;
         break;
       }
-    if (q < kLdsRef) L.ref[q] = r;
-    else cn.ref[gbase + (q - kLdsRef)] = r;
+    int k = q;
+    for (; k > roff; --k) {
+      const int prev = ref_at(k - 1);
+      if (prev <= r) break;
+      ref_set(k, prev);
+    }
+    ref_set(k, r);
   }
 
   // ---- contact law, pass by pass over the work list ------------------------
@@ -1430,6 +1445,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
     return make_int4(v.y, v.z, v.w, v.x);
   };
   int npp = 0, npw = 0;
+  int jr = 0;  // the particle's next reference to sum
   for (int p0 = 0; p0 < nrec; p0 += kThreads) {
     __syncthreads();  // the pool's last use (hit lists, or the previous pass) is over
     const int r = p0 + tid;
@@ -1525,13 +1541,19 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
         contact_law<RT>(c, P, wall, m, pi, pj, vi0, vi1, vi2, vj0, vj1, vj2, us, ur, &ut, o);
       }
       // results by the tile's particle a (force on a, torque on a, torque on b)
-      double* rs = L.pool.law.res[tid];
+      double ra[9];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        rs[k] = swap ? -o[k] : o[k];
-        rs[3 + k] = swap ? o[6 + k] : o[3 + k];
-        rs[6 + k] = swap ? o[3 + k] : o[6 + k];
+        ra[k] = swap ? -o[k] : o[k];
+        ra[3 + k] = swap ? o[6 + k] : o[3 + k];
+        ra[6 + k] = swap ? o[3 + k] : o[6 + k];
       }
+      double2* rs = L.pool.law.res[tid];
+      rs[0] = make_double2(ra[0], ra[1]);
+      rs[1] = make_double2(ra[2], ra[3]);
+      rs[2] = make_double2(ra[4], ra[5]);
+      rs[3] = make_double2(ra[6], ra[7]);
+      rs[4] = make_double2(ra[8], 0.0);
       if (r < To) {
         double* sp = L.pool.law.spr[tid];
         sp[0] = us[0];
@@ -1561,24 +1583,23 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
     // the tile's particles take their sides of this pass's records
     if (valid) {
       const int p1 = p0 + kThreads;
-      for (int rr = max(ooff, p0); rr < min(ooff + no, p1); ++rr) {
-        const double* x = L.pool.law.res[rr - p0];
-        F[0] += x[0]; F[1] += x[1]; F[2] += x[2];
-        T[0] += x[3]; T[1] += x[4]; T[2] += x[5];
-      }
+      auto take = [&](int rr) {
+        const double2* x = L.pool.law.res[rr - p0];
+        const double2 a = x[0], b = x[1], d = x[2];
+        F[0] += a.x; F[1] += a.y; F[2] += b.x;
+        T[0] += b.y; T[1] += d.x; T[2] += d.y;
+      };
+      for (int rr = max(ooff, p0); rr < min(ooff + no, p1); ++rr) take(rr);
       const int x0 = To + xoff;
-      for (int rr = max(x0, p0); rr < min(x0 + nx, p1); ++rr) {
-        const double* x = L.pool.law.res[rr - p0];
-        F[0] += x[0]; F[1] += x[1]; F[2] += x[2];
-        T[0] += x[3]; T[1] += x[4]; T[2] += x[5];
-      }
-      for (int j = 0; j < nr; ++j) {
-        const int q = roff + j;
-        const int rr = q < kLdsRef ? L.ref[q] : cn.ref[gbase + (q - kLdsRef)];
-        if (rr < p0 || rr >= p1) continue;
-        const double* x = L.pool.law.res[rr - p0];
-        F[0] -= x[0]; F[1] -= x[1]; F[2] -= x[2];
-        T[0] += x[6]; T[1] += x[7]; T[2] += x[8];
+      for (int rr = max(x0, p0); rr < min(x0 + nx, p1); ++rr) take(rr);
+      for (; jr < nr; ++jr) {
+        const int rr = ref_at(roff + jr);
+        if (rr >= p1) break;
+        if (rr < p0) continue;  // (-1: no record found)
+        const double2* x = L.pool.law.res[rr - p0];
+        const double2 a = x[0], b = x[1], d = x[3], e = x[4];
+        F[0] -= a.x; F[1] -= a.y; F[2] -= b.x;
+        T[0] += d.x; T[1] += d.y; T[2] += e.x;
       }
     }
   }
