@@ -1063,7 +1063,7 @@ struct StepLds {
   int2 rec[kLdsRec];       // work list: (lane, partner)
   int ref[kLdsRef];        // references: partner slot, then the owner's record
   int ooff[kThreads];      // first owned record of each lane
-  int ocnt[kThreads];      // owned records of each lane
+  int roff[kThreads];      // next free place in each lane's reference list
   int2 pseg[kThreads];     // each lane's owned records in the previous step (first, count)
   int w3[kThreads / 64][3];
   int cnt2[2][kThreads / 64];
@@ -1367,45 +1367,6 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   // a tile whose lists do not fit stops here; the step is failed and repeated
   // by the caller with more room (no state of the step is kept)
   if (over_g) return;
-  {
-    int jo = 0, jx = 0, jr = 0;
-    for (int k = 0; k < nk; ++k) {
-      const int t = hit(k);
-      if (t < 0 || t > s) {
-        const int r = ooff + jo++;
-        if (r < kLdsRec) L.rec[r] = make_int2(tid, t);
-        else {
-          cn.a[wbase + r] = tid;
-          cn.b[wbase + r] = t;
-        }
-      } else if (t >= base) {
-        const int q = roff + jr++;
-        if (q < kLdsRef) L.ref[q] = t;
-        else cn.ref[gbase + (q - kLdsRef)] = t;
-      } else {
-        const int r = To + xoff + jx++;
-        if (r < kLdsRec) L.rec[r] = make_int2(tid, t);
-        else {
-          cn.a[wbase + r] = tid;
-          cn.b[wbase + r] = t;
-        }
-      }
-    }
-  }
-  L.ooff[tid] = ooff;
-  L.ocnt[tid] = no;
-  L.pseg[tid] = pseg;
-  if (valid) {
-    cn.off[s] = gbase + ooff;
-    cn.cnt[s] = no;
-  }
-  if (tid == 0) cn.ng[grp] = To;
-  __syncthreads();
-  auto rec_at = [&](int r) -> int2 {
-    return r < kLdsRec ? L.rec[r] : make_int2(cn.a[wbase + r], cn.b[wbase + r]);
-  };
-  // references: the record of (lower partner t, s) among t's owned records,
-  // kept in ascending record order (each pass then takes a run of them)
   auto ref_at = [&](int q) -> int {
     return q < kLdsRef ? L.ref[q] : cn.ref[gbase + (q - kLdsRef)];
   };
@@ -1415,23 +1376,61 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
     else
       cn.ref[gbase + (q - kLdsRef)] = v;
   };
-  for (int j = 0; j < nr; ++j) {
-    const int q = roff + j;
-    const int lt = ref_at(q) - base;
-    const int r0 = L.ooff[lt], r1 = r0 + L.ocnt[lt];
-    int r = -1;
-    for (int rr = r0; rr < r1; ++rr)
-      if (rec_at(rr).y == s) {
-        r = rr;
-        break;
+  for (int j = 0; j < nr; ++j) ref_set(roff + j, -1);
+  L.ooff[tid] = ooff;
+  L.roff[tid] = roff;
+  L.pseg[tid] = pseg;
+  __syncthreads();
+  {
+    // owned and cross records; an owned record whose partner is a higher
+    // slot of the tile is also that partner's reference (it lists the pair
+    // the other way round), appended to the partner's list
+    int jo = 0, jx = 0;
+    for (int k = 0; k < nk; ++k) {
+      const int t = hit(k);
+      if (t < 0 || t > s) {
+        const int r = ooff + jo++;
+        if (r < kLdsRec) L.rec[r] = make_int2(tid, t);
+        else {
+          cn.a[wbase + r] = tid;
+          cn.b[wbase + r] = t;
+        }
+        if (t > s && t - base < kThreads) {
+          // (past Tr only when a particle's own list was cut at its cap: a
+          // failed step, whose results are not kept)
+          const int q = atomicAdd(&L.roff[t - base], 1);
+          if (q < Tr) ref_set(q, r);
+        }
+      } else if (t < base) {
+        const int r = To + xoff + jx++;
+        if (r < kLdsRec) L.rec[r] = make_int2(tid, t);
+        else {
+          cn.a[wbase + r] = tid;
+          cn.b[wbase + r] = t;
+        }
       }
-    int k = q;
+    }
+  }
+  if (valid) {
+    cn.off[s] = gbase + ooff;
+    cn.cnt[s] = no;
+  }
+  if (tid == 0) cn.ng[grp] = To;
+  __syncthreads();
+  auto rec_at = [&](int r) -> int2 {
+    return r < kLdsRec ? L.rec[r] : make_int2(cn.a[wbase + r], cn.b[wbase + r]);
+  };
+  // the particle's references in ascending record order (each pass then
+  // takes a run of them); they arrived in any order
+  for (int j = 1; j < nr; ++j) {
+    const int v = ref_at(roff + j);
+    int k = roff + j;
     for (; k > roff; --k) {
       const int prev = ref_at(k - 1);
-      if (prev <= r) break;
+      if (prev <= v) break;
       ref_set(k, prev);
     }
-    ref_set(k, r);
+    ref_set(k, v);
   }
 
   // ---- contact law, pass by pass over the work list ------------------------
