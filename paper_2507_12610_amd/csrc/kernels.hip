@@ -1051,14 +1051,7 @@ struct StepLds {
     struct {
       // force on I, torque on I, torque on J (and a pad: 16-byte rows)
       double2 res[kThreads][5];
-      double spr[kThreads][kSpr];  // updated springs of owned records
-      int2 key[kThreads];
     } law;
-    struct {
-      double4 x[kThreads];
-      Aux a[kThreads];
-      double4 q[kThreads];
-    } out;
   } pool;
   int2 rec[kLdsRec];       // work list: (lane, partner)
   int ref[kLdsRef];        // references: partner slot, then the owner's record
@@ -1554,31 +1547,19 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       rs[3] = make_double2(ra[6], ra[7]);
       rs[4] = make_double2(ra[8], 0.0);
       if (r < To) {
-        double* sp = L.pool.law.spr[tid];
-        sp[0] = us[0];
-        sp[1] = us[1];
-        sp[2] = us[2];
-        sp[3] = ur[0];
-        sp[4] = ur[1];
-        sp[5] = ur[2];
-        sp[6] = ut;
-        sp[7] = 0.0;
-        L.pool.law.key[tid] = key;
+        // the owned record's key and springs: consecutive lanes write
+        // consecutive records
+        double2* gs = reinterpret_cast<double2*>(cn.spr + (size_t)kSpr * (gbase + r));
+        gs[0] = make_double2(us[0], us[1]);
+        gs[1] = make_double2(us[2], ur[0]);
+        gs[2] = make_double2(ur[1], ur[2]);
+        gs[3] = make_double2(ut, 0.0);
+        cn.key[gbase + r] = key;
         npp += wall ? 0 : 1;
         npw += wall ? 1 : 0;
       }
     }
     __syncthreads();
-    // owned records of this pass: springs and keys as contiguous runs
-    {
-      const int no_pass = min(To - p0, kThreads);
-      if (no_pass > 0) {
-        double2* gs = reinterpret_cast<double2*>(cn.spr + (size_t)kSpr * (gbase + p0));
-        const double2* ls = reinterpret_cast<const double2*>(&L.pool.law.spr[0][0]);
-        for (int k = tid; k < no_pass * (kSpr / 2); k += kThreads) gs[k] = ls[k];
-        if (tid < no_pass) cn.key[gbase + p0 + tid] = L.pool.law.key[tid];
-      }
-    }
     // the tile's particles take their sides of this pass's records
     if (valid) {
       const int p1 = p0 + kThreads;
@@ -1689,16 +1670,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       ddrift = sqrt(d2) * (1.0 + 1e-12);
       drift = d2 > P.half_skin * P.half_skin;
     }
-    L.pool.out.x[tid] = make_double4(x[0], x[1], x[2], R);
-    L.pool.out.q[tid] = make_double4(q[0], q[1], q[2], q[3]);
-    Aux& o = L.pool.out.a[tid];
+    // the next state; consecutive lanes write consecutive slots.  The record
+    // notes this order as the next step's previous one, and where the
+    // particle's owned records are.
+    D.xr[s] = make_double4(x[0], x[1], x[2], R);
+    D.q[s] = make_double4(q[0], q[1], q[2], q[3]);
+    Aux& o = D.a[s];
     o.vw[0] = make_double2(v[0], v[1]);
     o.vw[1] = make_double2(v[2], w[0]);
     o.vw[2] = make_double2(w[1], w[2]);
-    o.pid = pid;
-    o.prev = s;  // the next step sees this order as its previous one
-    o.off = gbase + ooff;
-    o.cnt = no;
+    *reinterpret_cast<int4*>(&o.pid) = make_int4(pid, s, gbase + ooff, no);
     if (!ok) raise_flag(c.ctr, kFlagNonFinite);
   }
   // a wave where a particle drifted past half the skin records its largest
@@ -1708,9 +1689,6 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
     // one write per wave, and none once the flag is up (a single address)
     if (lane == 0 && !c.ctr->rebuild_next) atomicOr(&c.ctr->rebuild_next, 1);
   }
-  __syncthreads();
-  const int np = min(n - base, kThreads);
-  if (np > 0) copy_out(D, base, np, L.pool.out.x, L.pool.out.a, L.pool.out.q);
 }
 
 // ---------------------------------------------------------------------------

@@ -251,8 +251,8 @@ static int check_config(const sdem_config* cfg) {
   if (cfg->detect_lanes != 0 && cfg->detect_lanes != 1)
     return fail(SDEM_EINVAL, "detect_lanes must be 0 or 1 (one lane per particle)");
   if (cfg->contacts_per_particle != 0 &&
-      (cfg->contacts_per_particle < kHit || cfg->contacts_per_particle > 4096))
-    return fail(SDEM_EINVAL, "contacts_per_particle must be 0 or in [%d, 4096]", kHit);
+      (cfg->contacts_per_particle < kMinHitCap || cfg->contacts_per_particle > 4096))
+    return fail(SDEM_EINVAL, "contacts_per_particle must be 0 or in [%d, 4096]", kMinHitCap);
   if (!(cfg->cell_factor == 0.0 || cfg->cell_factor >= 0.125) || !isfinite(cfg->cell_factor))
     return fail(SDEM_EINVAL, "cell_factor must be >= 0.125 (0 selects 1)");
   if (!(cfg->skin >= 0.0) || !(cfg->skin <= 100.0))

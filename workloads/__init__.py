@@ -482,7 +482,8 @@ def crowded_sphere(n_small=64, seed=77, R_big=10 * MM, r_small=2 * MM, overlap=0
     on it (the ends of Table 2's radius range, 2 and 10 mm): the small ones at
     the points of a Fibonacci lattice on the sphere of radius R_big + r_small -
     overlap (directions jittered by 2 degrees), so the large one has n_small
-    contacts at once, more than the 32 a particle's search holds on chip.
+    contacts at once, more than a particle's search holds on chip (24) and more
+    than the least per-particle capacity a context may ask for (32).
     The small ones move towards the centre at v_in (plus random velocities
     and spins of scale vel), so the contacts last about 20 steps; no gravity,
     a closed 12-triangle box well clear of the cluster; dt from Eq. dt at
