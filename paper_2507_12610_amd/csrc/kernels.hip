@@ -1414,16 +1414,38 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
     return r < kLdsRec ? L.rec[r] : make_int2(cn.a[wbase + r], cn.b[wbase + r]);
   };
   // the particle's references in ascending record order (each pass then
-  // takes a run of them); they arrived in any order
-  for (int j = 1; j < nr; ++j) {
-    const int v = ref_at(roff + j);
-    int k = roff + j;
-    for (; k > roff; --k) {
-      const int prev = ref_at(k - 1);
-      if (prev <= v) break;
-      ref_set(k, prev);
+  // takes a run of them); they arrived in any order.  Up to eight (the usual
+  // case) are sorted in registers by Batcher's odd-even merge network for
+  // eight inputs (19 comparators), more by insertion in place.
+  if (nr > 1 && nr <= 8 && roff + nr <= kLdsRef) {
+    int v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = k < nr ? L.ref[roff + k] : INT_MAX;
+    auto cs = [&](int a, int b) {
+      const int lo = min(v[a], v[b]), hi = max(v[a], v[b]);
+      v[a] = lo;
+      v[b] = hi;
+    };
+    cs(0, 1); cs(2, 3); cs(4, 5); cs(6, 7);
+    cs(0, 2); cs(1, 3); cs(4, 6); cs(5, 7);
+    cs(1, 2); cs(5, 6);
+    cs(0, 4); cs(1, 5); cs(2, 6); cs(3, 7);
+    cs(2, 4); cs(3, 5);
+    cs(1, 2); cs(3, 4); cs(5, 6);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < nr) L.ref[roff + k] = v[k];
+  } else {
+    for (int j = 1; j < nr; ++j) {
+      const int v = ref_at(roff + j);
+      int k = roff + j;
+      for (; k > roff; --k) {
+        const int prev = ref_at(k - 1);
+        if (prev <= v) break;
+        ref_set(k, prev);
+      }
+      ref_set(k, v);
     }
-    ref_set(k, v);
   }
 
   // ---- contact law, pass by pass over the work list ------------------------
