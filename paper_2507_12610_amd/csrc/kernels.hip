@@ -744,12 +744,14 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
 //        well (the partner's tile evaluates the same pair, bit for bit, and
 //        writes its springs), this tile keeps only its own side;
 //      - references: partners in a lower slot inside the tile: the owner's
-//        record gives this particle's side.
+//        record gives this particle's side (the owner appends the record's
+//        index to the partner's reference list; each list is then sorted).
 //    So no contact result leaves the workgroup: every particle's force and
 //    torque are complete in LDS, and the tile integrates its particles at
 //    once.  Per particle the sum runs in a fixed order (pass by pass: owned
-//    records, cross records, references), so results do not depend on
-//    scheduling.
+//    records, cross records, references, each in record order), so results
+//    do not depend on scheduling.  The work list (up to kLdsRec records)
+//    stays in LDS; springs and the next state are stored from registers.
 // ---------------------------------------------------------------------------
 // Double-precision reciprocal, quotient and square root for the contact law
 // (not for the contact test, whose square root stays correctly rounded): the
@@ -1043,8 +1045,9 @@ __device__ __forceinline__ void block_scan3(int a, int b, int d, int* ea, int* e
   *td = sd;
 }
 
-// LDS of the step kernel.  The search's hit lists, the law's per-pass results
-// and spring staging, and the integration's state staging share one pool.
+// LDS of the step kernel.  The search's hit lists and the law's per-pass
+// results share one pool.  Three workgroups fit a CU only while the whole
+// stays below about 53.5 KB (54,112 bytes measured two per CU).
 struct StepLds {
   union {
     int hits[kThreads / 64][kHit][64];
