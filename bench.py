@@ -18,7 +18,7 @@ included at their real rate; value = particles x steps / seconds.
 
 Prints one JSON line: particle-steps/s (value) and contacts/s; the roofline
 of the step kernel (narrow phase, contact law, integration: 264 N + 120 C
-algorithmic bytes per launch) over its mean duration from HIP events on its
+algorithmic bytes per launch, 264 N + 68 C in mixed precision) over its mean duration from HIP events on its
 own dispatch; other forms
 (mixed precision, cells rebuilt every step, the 200,000-sphere column, the
 2,000,000-sphere rotating drum, 256 batched box drops) with their speedups
@@ -41,7 +41,7 @@ METRIC = "particle-steps/s & contacts/s: FP32/batched vs plain FP64 at stated to
 HBM_PEAK_GBS = 8000.0
 
 
-def step_bytes(n, c):
+def step_bytes(n, c, mixed=False):
     """Algorithmic HBM bytes of one launch of the step kernel on a step that
     keeps the cells (narrow phase, contact law with spring carry-over, sums
     and integration in one kernel): the contact-force kernel's 128 N + 120 C
@@ -50,8 +50,14 @@ def step_bytes(n, c):
     F, T read, state written), less what one kernel does not move twice:
     F and T read back (48 N) and x, v, w, R read again (80 N).  That is
     264 N + 120 C: the state read (112 B) and written (104 B), F and T
-    written (48 B) per particle, 120 B per contact."""
-    return 264.0 * n + 120.0 * c
+    written (48 B) per particle, 120 B per contact.  The mixed path keeps the
+    springs as floats between steps: 8 + 28 B read and 8 + 24 B written per
+    contact, 264 N + 68 C."""
+    return 264.0 * n + (68.0 if mixed else 120.0) * c
+
+
+def step_bytes_formula(mixed=False):
+    return "264 N + 68 C" if mixed else "264 N + 120 C"
 
 
 # bench workloads, each with its counter summary and its settings when none
@@ -60,6 +66,7 @@ WORKLOADS = {
     "packing_8M": {"make": "cfg5",
                    "radii": "half 1.4 mm, half 1.0 mm (body-centred arrangement)",
                    "traffic": "k_step_cfg5_packing_8M_hbm_traffic.md",
+                   "traffic_mixed": "k_step_cfg5_packing_8M_mixed_hbm_traffic.md",
                    "settings": (1.0, 1, 0.2, 256)},
     "column_200k": {"make": "cfg2", "radii": "lognormal, median 1 mm, sigma 0.2",
                     "traffic": "k_step_cfg2_column_200k_hbm_traffic.md", "settings": None},
@@ -85,13 +92,17 @@ def host_info():
             "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
 
 
-def measured_traffic(workload):
-    """HBM bytes per contact-force launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when
-    the kernel source changed since those counters were taken."""
+def measured_traffic(workload, precision="fp64"):
+    """HBM bytes per step-kernel launch from the committed counter summary of
+    that workload and precision (FETCH_SIZE and WRITE_SIZE scaled by a copy of
+    known size), or None when there is none or the kernel source changed
+    since those counters were taken."""
     import hashlib
+    name = WORKLOADS[workload].get("traffic" if precision == "fp64" else "traffic_mixed")
+    if name is None:
+        return None
     try:
-        text = open(os.path.join(ROOT, "profiles", WORKLOADS[workload]["traffic"])).read()
+        text = open(os.path.join(ROOT, "profiles", name)).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and
@@ -205,14 +216,16 @@ def profiled_step_kernel(s, n, steps):
     phases = {k: sum(p[1][k] for p in prof) / len(prof) for k in prof[0][1]}
     fms = sum(p[1]["step_kernel"] for p in keep) / len(keep)
     c_prof = sum(p[2] for p in keep) / len(keep)
-    alg = step_bytes(n, c_prof)
+    from paper_2507_12610_amd.sdem import SDEM_MIXED
+    mixed = s.cfg.precision == SDEM_MIXED
+    alg = step_bytes(n, c_prof, mixed)
     achieved = alg / (fms * 1e-3) / 1e9
     dominant = max((k for k in phases if k != "step_kernel"), key=phases.get)
     return {"kernel": "k_step (narrow phase, contact law with spring carry-over, integration)",
             "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "mean_ms": round(fms, 5), "algorithmic_bytes": alg,
-            "algorithmic_bytes_formula": "264 N + 120 C",
+            "algorithmic_bytes_formula": step_bytes_formula(mixed),
             "contacts_per_launch": round(c_prof, 1), "launches_timed": len(keep),
             "phase_ms": {k: round(v, 5) for k, v in phases.items() if k != "step_kernel"},
             "dominant_phase": dominant}
@@ -562,7 +575,7 @@ def main():
           file=sys.stderr, flush=True)
     value = n * K / run["s"]
     roofline = profiled_step_kernel(s, n, args.profile_steps)
-    roofline["traffic"] = measured_traffic(args.workload)
+    roofline["traffic"] = measured_traffic(args.workload, args.precision)
     s.close()
     del s
 

@@ -88,7 +88,9 @@ typedef struct {
  *  precision     SDEM_FP64: all arithmetic in double.  SDEM_MIXED: contact
  *                force and torque arithmetic in float, with double for
  *                positions, velocities, differences, the contact test,
- *                springs, force sums and integration
+ *                the spring updates, force sums and integration; between
+ *                steps each contact's springs are kept as floats (rounded
+ *                to nearest)
  *  block         reserved: 0 or a multiple of 64 in [64, 1024] (workgroups
  *                are 256 threads)
  *  detect_lanes  lanes that share one particle's contact search: 0 or 1 (one
@@ -284,7 +286,8 @@ int sdem_set_clock(sdem_ctx* ctx, int64_t steps);
 
 /* Loads friction-spring history (host arrays): nc keys (ki, kj) as in the
  * conventions above, springs us[nc][3], ur[nc][3], ut[nc] in the orientation
- * of body ki.  Keys that are not in contact at the next step are dropped. */
+ * of body ki.  Keys that are not in contact at the next step are dropped.
+ * An SDEM_MIXED context rounds the springs to the nearest float. */
 int sdem_set_history(sdem_ctx* ctx, int64_t nc, const int32_t* ki, const int32_t* kj,
                      const double* us, const double* ur, const double* ut);
 
@@ -320,7 +323,8 @@ int sdem_read_state(sdem_ctx* ctx, double* x, double* v, double* w, double* q, d
 int sdem_read_radii(sdem_ctx* ctx, double* R);
 
 /* Contacts of the last step in key order (ki ascending, then kj ascending,
- * signed) with their springs after that step: us, ur [cap][3], ut [cap].
+ * signed) with their springs after that step: us, ur [cap][3], ut [cap]
+ * (float values widened to double in an SDEM_MIXED context).
  * *n_out receives the number of contacts; at most cap are written.  Any
  * array may be NULL.  Synchronises the stream. */
 int sdem_read_contacts(sdem_ctx* ctx, int64_t cap, int64_t* n_out, int32_t* ki, int32_t* kj,

@@ -963,6 +963,34 @@ __device__ __forceinline__ void contact_law(const Ctx& c, const SimParams& P, co
   }
 }
 
+// A contact's springs between steps: the FP64 path keeps them as seven
+// doubles in a 64-byte record; the mixed path rounds them to seven floats in
+// a 32-byte record (the same buffer, read as floats), which halves the
+// spring traffic.  Both update them in double within a step.
+struct SpringF {
+  float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f), g1 = g0;
+  __device__ __forceinline__ void load(const double* spr, int e) {
+    const float4* q = reinterpret_cast<const float4*>(spr) + 2 * (size_t)e;
+    g0 = q[0];
+    g1 = q[1];
+  }
+  __device__ __forceinline__ void get(double us[3], double ur[3], double* ut) const {
+    us[0] = g0.x;
+    us[1] = g0.y;
+    us[2] = g0.z;
+    ur[0] = g0.w;
+    ur[1] = g1.x;
+    ur[2] = g1.y;
+    *ut = g1.z;
+  }
+  __device__ __forceinline__ static void store(double* spr, int e, const double us[3],
+                                               const double ur[3], double ut) {
+    float4* q = reinterpret_cast<float4*>(spr) + 2 * (size_t)e;
+    q[0] = make_float4((float)us[0], (float)us[1], (float)us[2], (float)ur[0]);
+    q[1] = make_float4((float)ur[1], (float)ur[2], (float)ut, 0.f);
+  }
+};
+
 // Record of key (ki, kj) among the n contacts that the previous owner slot
 // owned in the previous step (records b0 ..), or -1 if the pair was not in
 // contact.  Keys are probed four at a time so that their loads overlap.
@@ -1506,7 +1534,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       // previous record: that one (key and springs) is loaded with the bodies,
       // and the segment is searched only when its key differs.
       double us[3] = {0.0, 0.0, 0.0}, ur[3] = {0.0, 0.0, 0.0}, ut = 0.0;
-      {
+      if constexpr (sizeof(RT) == sizeof(double)) {
         int2 kg = make_int2(-1, 0);
         double2 g0 = make_double2(0.0, 0.0), g1 = g0, g2 = g0, g3 = g0;
         int eg = -1;
@@ -1546,6 +1574,29 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
           ur[2] = g2.y;
           ut = g3.x;
         }
+      } else {
+        // the same lookup over the 32-byte float records of the mixed path
+        int2 kg = make_int2(-1, 0);
+        SpringF g;
+        int eg = -1;
+        if (r < To) {
+          const int j = r - L.ooff[rb.x];
+          const int2 ps2 = L.pseg[rb.x];
+          if (j < ps2.y) eg = ps2.x + j;
+        }
+        if (eg >= 0) {
+          kg = old.key[eg];
+          g.load(old.spr, eg);
+        }
+        int eo = -1;
+        if (eg >= 0 && kg.x == key.x && kg.y == key.y) {
+          eo = eg;
+        } else {
+          const bool bown = !wall && ob.x < oa.x;
+          eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
+          if (eo >= 0) g.load(old.spr, eo);
+        }
+        if (eo >= 0) g.get(us, ur, &ut);
       }
       // one call of the law for the whole wave: the canonical orientation is
       // chosen in registers (two calls behind a branch on swap would make a
@@ -1574,11 +1625,15 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       if (r < To) {
         // the owned record's key and springs: consecutive lanes write
         // consecutive records
-        double2* gs = reinterpret_cast<double2*>(cn.spr + (size_t)kSpr * (gbase + r));
-        gs[0] = make_double2(us[0], us[1]);
-        gs[1] = make_double2(us[2], ur[0]);
-        gs[2] = make_double2(ur[1], ur[2]);
-        gs[3] = make_double2(ut, 0.0);
+        if constexpr (sizeof(RT) == sizeof(double)) {
+          double2* gs = reinterpret_cast<double2*>(cn.spr + (size_t)kSpr * (gbase + r));
+          gs[0] = make_double2(us[0], us[1]);
+          gs[1] = make_double2(us[2], ur[0]);
+          gs[2] = make_double2(ur[1], ur[2]);
+          gs[3] = make_double2(ut, 0.0);
+        } else {
+          SpringF::store(cn.spr, gbase + r, us, ur, ut);
+        }
         cn.key[gbase + r] = key;
         npp += wall ? 0 : 1;
         npw += wall ? 1 : 0;

@@ -933,7 +933,13 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
   }
   if (nc) {
     HIP_TRY(hipMemcpy(C.key, K.data(), sizeof(int2) * Ctot, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(C.spr, SP.data(), sizeof(double) * kSpr * Ctot, hipMemcpyHostToDevice));
+    if (X->cfg.precision == SDEM_MIXED) {
+      // the mixed path keeps springs as floats, eight to a record
+      std::vector<float> SF(SP.begin(), SP.end());
+      HIP_TRY(hipMemcpy(C.spr, SF.data(), sizeof(float) * kSpr * Ctot, hipMemcpyHostToDevice));
+    } else {
+      HIP_TRY(hipMemcpy(C.spr, SP.data(), sizeof(double) * kSpr * Ctot, hipMemcpyHostToDevice));
+    }
   }
   // the particles' records carry their segments for the next step
   HIP_TRY(launch_set_segments(X->c, X->st[X->cur], C, X->stream));
@@ -1355,7 +1361,13 @@ int sdem_read_contacts(sdem_ctx* X, int64_t cap, int64_t* n_out, int32_t* ki, in
   std::vector<int2> KA(Ctot);
   std::vector<double> SA((size_t)kSpr * Ctot);
   HIP_TRY(hipMemcpy(KA.data(), C.key, sizeof(int2) * Ctot, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(SA.data(), C.spr, sizeof(double) * kSpr * Ctot, hipMemcpyDeviceToHost));
+  if (X->cfg.precision == SDEM_MIXED) {
+    std::vector<float> SF((size_t)kSpr * Ctot);
+    HIP_TRY(hipMemcpy(SF.data(), C.spr, sizeof(float) * kSpr * Ctot, hipMemcpyDeviceToHost));
+    std::copy(SF.begin(), SF.end(), SA.begin());
+  } else {
+    HIP_TRY(hipMemcpy(SA.data(), C.spr, sizeof(double) * kSpr * Ctot, hipMemcpyDeviceToHost));
+  }
   std::vector<int32_t> K1(total), K2(total);
   std::vector<double> SP((size_t)kSpr * total);
   {

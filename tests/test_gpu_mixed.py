@@ -1,6 +1,6 @@
 """Mixed precision (FP32 contact force and torque arithmetic, FP64 positions,
-differences, contact test, springs, sums and integration) against the FP64
-oracle: keys bit-exact, every quantity within 1e-5 normwise relative after one
+differences, contact test, spring updates, sums and integration; springs kept
+as floats between steps) against the FP64 oracle: keys bit-exact, every quantity within 1e-5 normwise relative after one
 step and over a short horizon; the per-quantity errors are printed."""
 import numpy as np
 import pytest
@@ -83,3 +83,39 @@ def test_mixed_free_running_short_horizon():
     e = errors(g, o, w)
     print("20 steps", {k: f"{v:.2e}" for k, v in e.items()})
     assert max(e.values()) < TOL32, e
+
+
+def test_mixed_springs_kept_as_floats():
+    """Between steps the mixed path keeps each contact's springs as floats:
+    springs loaded through sdem_set_history read back rounded to the nearest
+    float, and after a step every spring is a float value, within 1e-5 of the
+    oracle's step from the same (unrounded) history.  The FP64 path reads
+    them back bit for bit."""
+    from paper_2507_12610_amd import Solver
+    w = W.random_cluster(300, 4, box=14e-3, overlap=0.15,
+                         tri=W.cube_mesh([-0.2e-3] * 3, [14.2e-3] * 3))
+    o = oracle_from(w)
+    o.step(3)
+    co, st = o.contacts(), o.state()
+    assert len(co["ki"]) > 100
+    w2 = dict(w)
+    w2.update(x=st["x"], v=st["v"], w=st["w"], q=st["q"])
+    as_f32 = (lambda a: np.asarray(a, np.float64).astype(np.float32).astype(np.float64))
+    for precision in ("fp64", "mixed"):
+        g = Solver(w2, device="cuda:0", precision=precision)
+        g.set_history(co["ki"], co["kj"], co["us"], co["ur"], co["ut"])
+        cg = g.contacts()
+        assert np.array_equal(keys(cg), keys(co))
+        for k in ("us", "ur", "ut"):
+            want = co[k] if precision == "fp64" else as_f32(co[k])
+            assert np.array_equal(cg[k], want), (precision, k)
+        if precision == "mixed":
+            o2 = oracle_resync(w, st, co, 3 * w["params"]["dt"])
+            g.step(1)
+            o2.step(1)
+            cg, c2 = g.contacts(), o2.contacts()
+            assert np.array_equal(keys(cg), keys(c2))
+            for k in ("us", "ur", "ut"):
+                assert np.array_equal(cg[k], as_f32(cg[k])), k
+            assert max(spring_err(cg, c2).values()) < TOL32
+        g.close()
