@@ -736,16 +736,19 @@ __global__ __launch_bounds__(kThreads) void k_bin_sort(Ctx c) {
 //    (Section 2.2, 2.3), per-particle sums (Section 3.2) and integration
 //    (Eq. v, x, spiral, w; Stokes drag of Section 2.1).
 //
-//    Each lane searches for every contact of its particle (full shell: all
-//    neighbours, not only higher slots).  Contacts are then sorted into
-//      - owned: walls and partners in a higher slot: evaluated here, springs
-//        written here;
+//    Each lane searches for the contacts of its particle with walls, with
+//    every neighbour outside its tile, and with the neighbours of its tile
+//    whose pair it owns (slot_owns: about half of them, for every lane
+//    alike).  Contacts are then sorted into
+//      - owned: walls, partners in a higher slot outside the tile, and the
+//        tile's pairs the particle owns: evaluated here, springs written here;
 //      - cross: partners in a lower slot outside the tile: evaluated here as
 //        well (the partner's tile evaluates the same pair, bit for bit, and
 //        writes its springs), this tile keeps only its own side;
-//      - references: partners in a lower slot inside the tile: the owner's
-//        record gives this particle's side (the owner appends the record's
-//        index to the partner's reference list; each list is then sorted).
+//      - references: the tile's pairs that the partner owns, which the
+//        search skips: the partner's record gives this particle's side (the
+//        owner counts it for the particle, then appends the record's index
+//        to the particle's reference list; each list is then sorted).
 //    So no contact result leaves the workgroup: every particle's force and
 //    torque are complete in LDS, and the tile integrates its particles at
 //    once.  Per particle the sum runs in a fixed order (pass by pass: owned
@@ -1087,7 +1090,7 @@ struct StepLds {
   int2 rec[kLdsRec];       // work list: (lane, partner)
   int ref[kLdsRef];        // references: partner slot, then the owner's record
   int ooff[kThreads];      // first owned record of each lane
-  int roff[kThreads];      // next free place in each lane's reference list
+  int roff[kThreads];      // each lane's reference count, then the next free place in its list
   int2 pseg[kThreads];     // each lane's owned records in the previous step (first, count)
   int w3[kThreads / 64][3];
   int cnt2[2][kThreads / 64];
@@ -1164,6 +1167,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
     }
   }
   if (tid == 0) L.flags = c.ctr->flags;
+  L.roff[tid] = 0;  // references of each particle, counted by their owners
   __syncthreads();
   if (L.flags) return;  // the whole workgroup leaves together
   // If a particle drifted past half the skin since the cells were built (seen
@@ -1171,7 +1175,9 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   // of its simulation further (k_begin)
   const bool drifted = !rebuilt && c.skin_on && c.ctr->drift_now;
 
-  // ---- narrow phase: every contact of particle s ----------------------------
+  // ---- narrow phase: every contact of particle s, except those with a slot
+  // of its own tile that owns the pair (slot_owns): that partner finds it
+  // and hands it to s as a reference -------------------------------------------
   const int spill_cap = c.hit_cap - kHit;
   int nh = 0;
   auto put = [&](int t) {
@@ -1349,7 +1355,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
           for (int u = 0; u < 4; ++u) {
             const int tu = t + u;
             if (tu >= t1) break;
-            if (tu == s) continue;
+            // itself, or a pair of the tile that the other side owns
+            if (tu == s || (tu >= base && tu - base < kThreads && !slot_owns(s, tu))) continue;
             if (record) {
               const double ex = xs - pt[u].x, ey = ys - pt[u].y, ez = zs - pt[u].z;
               const double sr = (Rs + pt[u].w) + 2.0 * hsk;
@@ -1366,22 +1373,26 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
     if (record) c.vcnt[s] = ncand <= kCand ? ncand : -1;  // -1: search the cells
   }
   // ---- work lists: owned, cross and referenced contacts of the tile --------
+  // Every pair of the tile found is owned; a particle's references are the
+  // owned records of other lanes whose partner it is: their owners count them.
   const int nk = nh < c.hit_cap ? nh : c.hit_cap;
-  int no = 0, nx = 0, nr = 0;
+  int no = 0, nx = 0;
   for (int k = 0; k < nk; ++k) {
     const int t = hit(k);
-    if (t < 0 || t > s)
+    if (t < 0 || t >= base) {
       ++no;
-    else if (t >= base)
-      ++nr;
-    else
+      if (t >= base && t - base < kThreads) atomicAdd(&L.roff[t - base], 1);
+    } else {
       ++nx;
+    }
   }
+  __syncthreads();
+  const int nr = L.roff[tid];
   int ooff, xoff, roff, To, Tx, Tr;
   block_scan3(no, nx, nr, &ooff, &xoff, &roff, &To, &Tx, &Tr, L.w3);
   const int gbase = grp * c.gcap;   // owned records (springs, keys)
   const int wbase = 2 * gbase;      // work list past the LDS
-  const bool over_p = nh > c.hit_cap;
+  const bool over_p = nh + nr > c.hit_cap;
   const bool over_g = To > c.gcap || To + Tx > 2 * c.gcap || Tr > kLdsRef + c.gcap;
   if (over_p) raise_flag(c.ctr, kFlagCapPerParticle);
   if (over_g && tid == 0) {
@@ -1406,26 +1417,26 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
   L.pseg[tid] = pseg;
   __syncthreads();
   {
-    // owned and cross records; an owned record whose partner is a higher
-    // slot of the tile is also that partner's reference (it lists the pair
-    // the other way round), appended to the partner's list
+    // owned and cross records; an owned record whose partner is a slot of
+    // the tile is also that partner's reference (it lists the pair the other
+    // way round), appended to the partner's list
     int jo = 0, jx = 0;
     for (int k = 0; k < nk; ++k) {
       const int t = hit(k);
-      if (t < 0 || t > s) {
+      if (t < 0 || t >= base) {
         const int r = ooff + jo++;
         if (r < kLdsRec) L.rec[r] = make_int2(tid, t);
         else {
           cn.a[wbase + r] = tid;
           cn.b[wbase + r] = t;
         }
-        if (t > s && t - base < kThreads) {
-          // (past Tr only when a particle's own list was cut at its cap: a
-          // failed step, whose results are not kept)
+        if (t >= base && t - base < kThreads) {
+          // (the same appends were counted above, so q stays within the
+          // partner's list)
           const int q = atomicAdd(&L.roff[t - base], 1);
           if (q < Tr) ref_set(q, r);
         }
-      } else if (t < base) {
+      } else {
         const int r = To + xoff + jx++;
         if (r < kLdsRec) L.rec[r] = make_int2(tid, t);
         else {
@@ -1527,7 +1538,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
       const int2 key = wall ? make_int2(ida, -(m - P.tri0))
                             : make_int2(swap ? idb : ida, swap ? ida : idb);
       // springs of the previous step (zero for a new contact), looked up among
-      // the records of the previous owner: the lower previous slot of the two.
+      // the records of the previous owner (slot_owns of the previous slots).
       // A particle's contacts come out of its search in the same order every
       // step (candidates in list order) unless some formed or ended, so the
       // previous record of its j-th owned contact is most often its j-th
@@ -1555,7 +1566,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
         if (eg >= 0 && kg.x == key.x && kg.y == key.y) {
           eo = eg;
         } else {
-          const bool bown = !wall && ob.x < oa.x;
+          const bool bown = !wall && slot_owns(ob.x, oa.x);
           eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
           if (eo >= 0) {
             const double2* q = reinterpret_cast<const double2*>(old.spr + (size_t)kSpr * eo);
@@ -1592,7 +1603,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_step(Ctx c, State S, State D, C
         if (eg >= 0 && kg.x == key.x && kg.y == key.y) {
           eo = eg;
         } else {
-          const bool bown = !wall && ob.x < oa.x;
+          const bool bown = !wall && slot_owns(ob.x, oa.x);
           eo = find_old(old, bown ? ob.y : oa.y, bown ? ob.z : oa.z, key);
           if (eo >= 0) g.load(old.spr, eo);
         }

@@ -891,7 +891,7 @@ int sdem_set_history(sdem_ctx* X, int64_t nc, const int32_t* ki, const int32_t* 
     if (kj[e] > 0) {
       if (kj[e] >= n || kj[e] <= ki[e] || simof[kj[e]] != simof[ki[e]])
         return fail(SDEM_EINVAL, "history key %lld: bad particle pair", (long long)e);
-      owner[e] = std::min(slot[ki[e]], slot[kj[e]]);
+      owner[e] = slot_owns(slot[ki[e]], slot[kj[e]]) ? slot[ki[e]] : slot[kj[e]];
     } else {
       if (-(int64_t)kj[e] >= (int64_t)X->mesh_r[simof[ki[e]]].size())
         return fail(SDEM_EINVAL, "history key %lld: no such triangle", (long long)e);

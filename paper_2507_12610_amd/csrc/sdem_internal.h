@@ -146,7 +146,17 @@ struct State {
   double4* q;   // [n] orientation quaternion, scalar first
 };
 
-// One buffer of contacts, grouped by owner slot (owner = lower slot; a
+// The slot that owns the pair of slots a != b (evaluates it first-hand and
+// keeps its springs): the lower slot when the two lie in different groups of
+// kGroup; within a group, the lower slot when a + b is even and the higher
+// when it is odd, so that every particle owns about half of its pairs in the
+// group (the step kernel's search lanes then carry balanced loads).
+__host__ __device__ inline bool slot_owns(int a, int b) {
+  if ((a >> kGroupShift) != (b >> kGroupShift)) return a < b;
+  return ((a ^ b) & 1) ? a > b : a < b;
+}
+
+// One buffer of contacts, grouped by owner slot (owner by slot_owns; a
 // particle owns its mesh contacts).  The owned records of slot group g
 // (slots g*256 .. g*256+255) live in [g*gcap, g*gcap + ng[g]), each owner's
 // contiguous.  a, b hold the step kernel's work list of the tile: the owned
@@ -157,7 +167,7 @@ struct Contacts {
   int32_t* off;  // [n] first contact of each owner slot
   int32_t* a;    // [2 cap] work list: slot within the tile
   int32_t* b;    // [2 cap] work list: partner slot (>= 0) or -1 - global element index
-  int32_t* ref;  // [cap] in-tile references past the LDS: record of the lower partner
+  int32_t* ref;  // [cap] in-tile references past the LDS: record of the owning partner
   int2* key;     // (lower persistent id, higher id) or (id, -local triangle index)
   double* spr;   // [cap][kSpr] sliding spring (3), rolling spring (3), twisting
                  // spring (1), in the orientation of body key.x; one pad

@@ -67,8 +67,8 @@ def test_too_many_contacts_fails_then_more_room_recovers():
                                                 (0.5, "mixed", TOL32)])
 def test_crowded_sphere_horizon(skin, precision, tol):
     """Free-running against the oracle while the 64 contacts form, hold and
-    end.  With a skin the large sphere's candidates (64) exceed the list
-    length, so its kept steps search the cells."""
+    end.  With a skin the large sphere's candidates can exceed the list
+    length (32); its kept steps then search the cells."""
     w = W.crowded_sphere()
     g = solver(w, contacts_per_particle=96, precision=precision, detect_lanes=1, skin=skin)
     o = oracle_from(w)
