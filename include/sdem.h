@@ -121,9 +121,10 @@ typedef struct {
  *  rebuild_every with skin > 0: the longest rebuild period, >= 1; 0 selects
  *                64
  *  contacts_per_particle  contacts (pairs and mesh elements) one particle may
- *                have in a step, in [32, 4096]; 0 selects 64.  The first 24
- *                are held on chip, the rest in n * (contacts_per_particle -
- *                24) integers of workspace.  A step where some particle has
+ *                have in a step, in [32, 4096]; 0 selects 64.  The step
+ *                kernel's search keeps the first 16 it finds on chip, the
+ *                rest in n * (contacts_per_particle - 16) integers of
+ *                workspace.  A step where some particle has
  *                more fails with SDEM_ECAPACITY (state kept, context failed):
  *                re-init with a larger value to go on */
 typedef struct {

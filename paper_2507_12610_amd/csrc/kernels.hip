@@ -1078,7 +1078,7 @@ __device__ __forceinline__ void block_scan3(int a, int b, int d, int* ea, int* e
 
 // LDS of the step kernel.  The search's hit lists and the law's per-pass
 // results share one pool.  Three workgroups fit a CU only while the whole
-// stays below about 53.5 KB (54,112 bytes measured two per CU).
+// stays below about 53.5 KB (54,112 bytes measured two per CU; now 51,296).
 struct StepLds {
   union {
     int hits[kThreads / 64][kHit][64];

@@ -16,14 +16,14 @@ constexpr int kWave = 64;           // slots per wave; bounding-box partials are
                                     // per (wave of slots, simulation)
 constexpr int kSpr = 8;             // doubles per contact spring record
 constexpr int kThreads = 256;       // threads per workgroup of the particle kernels
-constexpr int kHit = 24;            // contacts of one particle held in LDS by its search
+constexpr int kHit = 16;            // contacts of one particle held in LDS by its search
 constexpr int kMinHitCap = 32;      // least contacts_per_particle a config may ask for
                                     // lane (more spill to the tile's global overflow)
 constexpr int kCand = 32;           // candidates one search lane records at a rebuild
 constexpr int kGroupShift = 8;      // contact records are allocated per group of
 constexpr int kGroup = 1 << kGroupShift;  // 256 consecutive slots: a tile of the step kernel
 constexpr int kLdsRec = 2560;       // records of a tile held in LDS (the rest in global memory)
-constexpr int kLdsRef = 1024;       // in-tile references held in LDS (the rest in global memory)
+constexpr int kLdsRef = 1536;       // in-tile references held in LDS (the rest in global memory)
 constexpr int kBrickBits = 3;       // cells are ordered in bricks of up to 8 x 8 x 8
 constexpr int kBinScanThreads = 1024;  // one workgroup scans the triangle bins
 constexpr int kSpawnMax = 1024;     // spawn attempts per step at most

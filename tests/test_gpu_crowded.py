@@ -1,10 +1,10 @@
-"""A particle with more contacts than its search holds on chip (24) and than
+"""A particle with more contacts than its search holds on chip (16) and than
 the least room a context may ask for (32): a sphere of 10 mm with 64 spheres
 of 2 mm pressed on it (the ends of Table 2's radius range), moving inwards
 so the 64 contacts last about 20 steps.  With room for 32 contacts per
 particle the first step fails with ECAPACITY and keeps the state; a context
 made again with room for 96 then matches the oracle: contact keys bit for
-bit at every step (the contacts past the 24 on chip pass through the
+bit at every step (the contacts past the 16 on chip pass through the
 overflow area), springs, forces and states within the tolerance after the
 first step and after 24 steps, when the contacts have ended."""
 import numpy as np
