@@ -416,6 +416,42 @@ def drum_forms(K, sample=3000):
     return out
 
 
+def copy_ceiling(achieved_gbs, mib=1024, reps=20):
+    """The HBM bandwidth of a plain streaming copy (the library's copy probe,
+    `mib` MiB each way, mean of `reps` copies after one untimed): the
+    practical ceiling, reported beside the published peak, with the step
+    kernel's algorithmic bandwidth as a fraction of it."""
+    import torch
+
+    from paper_2507_12610_amd import copy_probe
+    nb = mib << 20
+    src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    ms = copy_probe(src, dst, reps)
+    del src, dst
+    gbs = 2.0 * nb / (ms * 1e-3) / 1e9
+    return {"copy_ceiling": {"GB/s": round(gbs, 1), "bytes_moved_per_copy": 2 * nb,
+                             "ms_per_copy": round(ms, 5), "kernel": "sdem_copy_probe"},
+            "frac_of_copy_ceiling": round(achieved_gbs / gbs, 4)}
+
+
+def kept_step_ms(s, windows=24):
+    """Median wall time per step of `windows` calls of eight steps each on
+    solver s, over the calls in which no step rebuilt the cells (None if
+    every call rebuilt)."""
+    import torch
+    per = []
+    for _ in range(windows):
+        r0 = s.stats()["rebuilds"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(8)  # returns after the stream has drained
+        dt = time.perf_counter() - t0
+        if s.stats()["rebuilds"] == r0:
+            per.append(1e3 * dt / 8)
+    return round(statistics.median(per), 5) if per else None
+
+
 def batched_forms(K, landing_steps, precision_list=("fp64", "mixed")):
     """Configuration 4: 256 box drops of uneven size in one context, timed after
     the sims have landed, against the same 256 states stepped one simulation
@@ -446,8 +482,12 @@ def batched_forms(K, landing_steps, precision_list=("fp64", "mixed")):
         g.step(4)
         med, blocks = timed_blocks(g, total, K, min_block_steps=96)
         out[prec] = block_summary(med, blocks, total)
-        # the step kernel's own duration on kept steps: the rest of a step is
-        # launch and host time (what a persistent kernel could remove)
+        # wall time of windows of eight steps that all kept the cells (one
+        # graph replay each), against the step kernel's own duration on such
+        # steps: the difference is the launch and host time per step that a
+        # persistent kernel could remove; the rest of a block's time per step
+        # is its rebuilds
+        out[prec]["kept_step_ms"] = kept_step_ms(g)
         rl = profiled_step_kernel(g, total, 12)
         out[prec]["step_kernel_ms"] = rl["mean_ms"]
         out[prec]["roofline"] = rl
@@ -578,6 +618,7 @@ def main():
     roofline["traffic"] = measured_traffic(args.workload, args.precision)
     s.close()
     del s
+    roofline.update(copy_ceiling(roofline["achieved"]))
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
            "steps": K, "warmup": args.warmup, "ms_per_step": run["ms_per_step"],

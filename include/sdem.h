@@ -351,6 +351,16 @@ const char* sdem_last_error(void);
 int sdem_selftest_rounding(int64_t n, const double* in, const double* in2, double* out,
                            void* hip_stream);
 
+/* Measurement aid, not an operation of the method: copies `bytes` from src
+ * to dst (device memory, 16-byte aligned, not overlapping; bytes > 0 and a
+ * multiple of 16) reps + 1 times with a plain streaming kernel on the given
+ * stream, and writes the mean time of the last reps copies, timed with HIP
+ * events, to *ms_per_copy (host).  2 * bytes / time is the HBM bandwidth such
+ * a kernel reaches, the practical ceiling beside the published peak.
+ * Synchronises the stream; SDEM_EINVAL for bad arguments. */
+int sdem_copy_probe(const void* src, void* dst, int64_t bytes, int32_t reps, void* hip_stream,
+                    double* ms_per_copy);
+
 /* ---- file formats (Section 6 of the paper) ------------------------------ */
 
 /* Reads a mesh in GeomView's Object File Format: "OFF", the vertex and face

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsdem.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("kernels.hip", "spawn.hip", "sdem_api.hip", "sdem_io.cpp")]
+           for f in ("kernels.hip", "spawn.hip", "sdem_api.hip", "sdem_io.cpp", "probe.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -28,7 +28,8 @@ EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_static", "sdem_init_b
            "sdem_set_mesh_motion",
            "sdem_read_csv", "sdem_write_contacts_csv", "sdem_read_contacts_csv",
            "sdem_set_history", "sdem_step", "sdem_read_state", "sdem_read_contacts", "sdem_stats",
-           "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding", "sdem_step_profiled")
+           "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding", "sdem_step_profiled",
+           "sdem_copy_probe")
 PHASES = ("grid", "sort", "begin", "step", "empty", "step_kernel")
 
 
@@ -133,6 +134,7 @@ def lib():
         L.sdem_last_error.restype = C.c_char_p
         L.sdem_last_error.argtypes = []
         L.sdem_selftest_rounding.argtypes = [C.c_int64, _VP, _VP, _VP, _VP]
+        L.sdem_copy_probe.argtypes = [_VP, _VP, C.c_int64, C.c_int32, _VP, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -163,6 +165,20 @@ def selftest_rounding(a, b, device="cuda:0"):
                                         stream.cuda_stream))
     o = out.cpu().numpy()
     return o[: len(a)], o[len(a):]
+
+
+def copy_probe(src, dst, reps=10):
+    """Mean milliseconds per copy of the library's streaming copy kernel from
+    device tensor src to dst (same size, a multiple of 16 bytes), through the
+    C ABI, on the current stream."""
+    import torch
+    if src.device != dst.device or src.nbytes != dst.nbytes:
+        raise ValueError("src and dst must be device tensors of equal size")
+    ms = C.c_double()
+    stream = torch.cuda.current_stream(src.device)
+    _check(lib().sdem_copy_probe(src.data_ptr(), dst.data_ptr(), src.nbytes, int(reps),
+                                 stream.cuda_stream, C.byref(ms)))
+    return ms.value
 
 
 def _grid_cells(x, h):

@@ -2,6 +2,8 @@
 the same seeded inputs.  Contact keys must match bit for bit; forces, springs
 and states within 1e-12 (FP64 path), normwise relative, per-particle forces
 scaled by the sum of the contact contributions (dense packings cancel)."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -34,6 +36,29 @@ def test_device_sqrt_and_division_correctly_rounded():
         ref_q = a / b
     assert np.array_equal(s.view(np.int64), np.sqrt(a).view(np.int64))
     assert np.array_equal(q.view(np.int64), ref_q.view(np.int64))
+
+
+@pytest.mark.parametrize("nbytes", [16, 48 << 10, (3 << 20) + 16 * 37])
+def test_copy_probe_copies_and_rejects_bad_arguments(nbytes):
+    """The bench's bandwidth probe moves every byte (sizes below one
+    workgroup's share, and ragged past a whole number of them) and refuses
+    sizes that are not whole 16-byte words and overlapping buffers, before
+    launching anything."""
+    import torch
+
+    from paper_2507_12610_amd import SdemError, copy_probe, lib
+    g = torch.Generator().manual_seed(nbytes)
+    src = torch.randint(0, 1 << 30, (nbytes // 4,), dtype=torch.int32, generator=g).to("cuda:0")
+    dst = torch.zeros_like(src)
+    ms = copy_probe(src, dst, reps=3)
+    assert ms > 0.0
+    assert torch.equal(src.cpu(), dst.cpu())
+    with pytest.raises(SdemError, match="EINVAL"):
+        copy_probe(src, src, reps=1)
+    out = ctypes.c_double()
+    stream = torch.cuda.current_stream("cuda:0").cuda_stream
+    assert lib().sdem_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes - 8, 1, stream,
+                                 ctypes.byref(out)) != 0
 
 
 def cluster_case(n=400, seed=1, mesh=True, **pk):
