@@ -600,6 +600,7 @@ def main():
     K = w["steps"] if args.steps is None else args.steps
     s = Solver(w, precision=args.precision, **opts)
     s.step(args.warmup)
+    graphs0 = s.graph_stats()
     if K >= 1000:
         run = timed_run(s, n, K)
         window = (f"steps {args.warmup + 1}-{args.warmup + K} of the run, one window on the host "
@@ -613,6 +614,7 @@ def main():
                   f"{args.warmup}, each on the host clock between device synchronisations")
     print(f"[bench] {K} steps in {run['s']:.3f} s, {run['contacts_per_step']:.0f} contacts/step",
           file=sys.stderr, flush=True)
+    graphs1 = s.graph_stats()
     value = n * K / run["s"]
     roofline = profiled_step_kernel(s, n, args.profile_steps)
     roofline["traffic"] = measured_traffic(args.workload, args.precision)
@@ -635,7 +637,11 @@ def main():
            "contacts_per_s": run["contacts_per_s"],
            "contacts_per_step": run["contacts_per_step"],
            "timing": {"window": window, "chunk_steps": run["chunk_steps"],
-                      "chunks_ms_per_step": run["chunks_ms_per_step"]},
+                      "chunks_ms_per_step": run["chunks_ms_per_step"],
+                      "graphs_instantiated_before_window": graphs0["instantiated"],
+                      "graphs_instantiated_in_window":
+                          graphs1["instantiated"] - graphs0["instantiated"],
+                      "graph_capture_failed": graphs1["failed"]},
            "roofline": roofline}
     if tuned is not None:
         out["autotune"] = tuned

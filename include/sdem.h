@@ -338,6 +338,14 @@ int sdem_read_contacts(sdem_ctx* ctx, int64_t cap, int64_t* n_out, int32_t* ki, 
 int sdem_stats(sdem_ctx* ctx, int64_t* steps, int64_t* pp_contacts, int64_t* pw_contacts,
                int64_t* rebuilds);
 
+/* HIP graphs the context has instantiated so far (*instantiated), and
+ * whether capturing one failed (*failed = 1: steps are then enqueued one
+ * kernel at a time).  Every graph a context replays is made at the start of
+ * its first sdem_step call, so the count stays the same over later calls;
+ * a caller timing steps can check that none was made inside its window.
+ * Either pointer may be NULL. */
+int sdem_graph_stats(sdem_ctx* ctx, int64_t* instantiated, int32_t* failed);
+
 /* Releases the host-side context (the workspace stays the caller's). */
 int sdem_destroy(sdem_ctx* ctx);
 

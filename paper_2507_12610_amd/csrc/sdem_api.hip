@@ -97,6 +97,7 @@ struct sdem_ctx {
   // step, one step keeping the cells, eight steps keeping the cells
   hipGraphExec_t graph[4][2] = {};
   bool graph_failed = false;
+  int64_t graphs_made = 0;  // graphs instantiated so far
   // rebuild schedule (skin > 0): steps since the last rebuild, and a drift
   // past half the skin seen at the last synchronisation (or no rebuild yet)
   int64_t since = 0;
@@ -1089,6 +1090,7 @@ static hipGraphExec_t step_graph(sdem_ctx* X, int pat) {
   }
   if (g) (void)hipGraphDestroy(g);
   X->graph[pat][p] = ex;
+  if (ex) ++X->graphs_made;
   return ex;
 }
 
@@ -1405,6 +1407,13 @@ int sdem_read_contacts(sdem_ctx* X, int64_t cap, int64_t* n_out, int32_t* ki, in
     if (ur) HIP_TRY(hipMemcpy(ur, our.data(), sizeof(double) * 3 * m, hipMemcpyDefault));
     if (ut) HIP_TRY(hipMemcpy(ut, out.data(), sizeof(double) * m, hipMemcpyDefault));
   }
+  return SDEM_OK;
+}
+
+int sdem_graph_stats(sdem_ctx* X, int64_t* instantiated, int32_t* failed) {
+  if (!X) return fail(SDEM_EINVAL, "ctx is NULL");
+  if (instantiated) *instantiated = X->graphs_made;
+  if (failed) *failed = X->graph_failed ? 1 : 0;
   return SDEM_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTS = ("sdem_workspace_bytes", "sdem_init", "sdem_init_static", "sdem_init_b
            "sdem_read_csv", "sdem_write_contacts_csv", "sdem_read_contacts_csv",
            "sdem_set_history", "sdem_step", "sdem_read_state", "sdem_read_contacts", "sdem_stats",
            "sdem_destroy", "sdem_last_error", "sdem_selftest_rounding", "sdem_step_profiled",
-           "sdem_copy_probe")
+           "sdem_copy_probe", "sdem_graph_stats")
 PHASES = ("grid", "sort", "begin", "step", "empty", "step_kernel")
 
 
@@ -135,6 +135,7 @@ def lib():
         L.sdem_last_error.argtypes = []
         L.sdem_selftest_rounding.argtypes = [C.c_int64, _VP, _VP, _VP, _VP]
         L.sdem_copy_probe.argtypes = [_VP, _VP, C.c_int64, C.c_int32, _VP, C.POINTER(C.c_double)]
+        L.sdem_graph_stats.argtypes = [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
@@ -516,3 +517,9 @@ class Solver:
         s, pp, pw, rb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().sdem_stats(self._h, C.byref(s), C.byref(pp), C.byref(pw), C.byref(rb)))
         return {"steps": s.value, "pp": pp.value, "pw": pw.value, "rebuilds": rb.value}
+
+    def graph_stats(self):
+        """HIP graphs instantiated so far, and whether capturing one failed."""
+        made, failed = C.c_int64(), C.c_int32()
+        _check(lib().sdem_graph_stats(self._h, C.byref(made), C.byref(failed)))
+        return {"instantiated": made.value, "failed": bool(failed.value)}

@@ -61,6 +61,25 @@ def test_copy_probe_copies_and_rejects_bad_arguments(nbytes):
                                  ctypes.byref(out)) != 0
 
 
+@pytest.mark.parametrize("skin", [0.0, 0.5])
+def test_step_graphs_made_once(skin):
+    """Every HIP graph a context replays is instantiated at the start of its
+    first sdem_step call; later calls of any length (with rebuilds) make
+    none, so a timed window after a warm-up call holds no instantiation."""
+    w = W.cfg1()
+    g = solver(w, skin=skin, detect_lanes=1) if skin else solver(w)
+    assert g.graph_stats()["instantiated"] == 0
+    g.step(3)
+    first = g.graph_stats()
+    assert first["instantiated"] > 0 and not first["failed"]
+    r0 = g.stats()["rebuilds"]
+    for k in (1, 8, 30, 200):
+        g.step(k)
+    assert g.stats()["rebuilds"] > r0
+    assert g.graph_stats() == first
+    g.close()
+
+
 def cluster_case(n=400, seed=1, mesh=True, **pk):
     tri = W.cube_mesh([-0.2e-3] * 3, [16.2e-3] * 3) if mesh else None
     w = W.random_cluster(n, seed, box=16e-3, overlap=0.15, tri=tri)
