@@ -2,7 +2,7 @@
 configurations bench.py times (cell edge 0.4 x 2 R_max chosen by the
 autotuner for the column, 1.0 as the reference stencil).
 
-* 200,000-sphere column: the complete contact set bit for bit and every
+* 200,000-sphere settled column: the complete contact set bit for bit and every
   particle's force, torque and new state against the oracle, after the first
   step and again 100 steps later (oracle restarted from the GPU state and
   springs); also with the cells kept between rebuilds (skin 0.05 R_max).

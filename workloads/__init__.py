@@ -51,6 +51,9 @@ def _packlib():
         D = C.POINTER(C.c_double)
         L.pack_rsa.restype = C.c_int64
         L.pack_rsa.argtypes = [C.c_int64, D, D, D, C.c_int32, D, C.c_uint64, C.c_int64, D]
+        L.pack_deposit.restype = C.c_int64
+        L.pack_deposit.argtypes = [C.c_int64, D, C.c_double, C.c_double, C.c_uint64, D,
+                                   C.POINTER(C.c_int64)]
         _pack = L
     return _pack
 
@@ -76,6 +79,27 @@ def rsa_place(R, lo, hi, seed, shape=0, cyl=(0.0, 0.0, 0.0, 0.0), max_attempts=1
     out = np.empty_like(x)
     out[order] = x
     return out
+
+
+def deposit(R, Lx, Ly, seed):
+    """Sequential deposition with rolling (Visscher and Bolsterli, 1972) of
+    spheres with radii R, in the given order, onto the floor z = 0 of the
+    cell [0, Lx) x [0, Ly), periodic in x and y: each sphere falls from above
+    the pile at a random (x, y) and rolls downhill over the spheres below
+    until it rests on the floor or on supports that carry its weight.
+    Returns the centres (x and y in [0, L)) and the number of spheres whose
+    rolling hit the step limit (left where they were)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    x = np.zeros((len(R), 3))
+    stuck = C.c_int64(0)
+    D = C.POINTER(C.c_double)
+    got = _packlib().pack_deposit(len(R), R.ctypes.data_as(D), float(Lx), float(Ly),
+                                  C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), x.ctypes.data_as(D),
+                                  C.byref(stuck))
+    if got != len(R):
+        raise RuntimeError(f"deposition failed ({got}): radii must be positive and the cell "
+                           f"at least 6 R_max wide")
+    return x, int(stuck.value)
 
 
 # ---------------------------------------------------------------------------
@@ -318,24 +342,25 @@ def cfg1(seed=101, pitch=2.2 * MM):
     return _finish("cfg1_box_drop_1k", default_params(dt=1e-6), x, R, rng, tri, 2000, R_max=1.2 * MM)
 
 
-def cfg2(seed=202, n=200_000, phi_rsa=0.35, shrink=0.93):
+def cfg2(seed=202, n=200_000, shrink=0.999):
     """200,000 spheres, R = 1 mm * exp(0.2 Z), granular column on a
     600 x 600 mm two-triangle floor, full friction, dt = 5e-7 s, 20,000 steps.
 
-    The loose packing: random sequential addition of the spheres at radii
-    shrink*R into a 60 x 60 mm column (packing fraction phi_rsa at the shrunk
-    radii), then the true radii, so neighbours closer than the shrink margin
-    start slightly overlapped (packing fraction phi_rsa/shrink^3 ~ 0.44).  The
-    column height follows from N and the fraction (a 300 mm column cannot
-    hold 200,000 such spheres)."""
+    The settled column before its side walls are taken away: the spheres are
+    poured, one after another in random order, into a 60 x 60 mm column
+    (sequential deposition with rolling at radii shrink*R, periodic across
+    the column's sides so that no side wall shapes the packing), each coming
+    to rest on the floor or on three spheres that carry it (packing fraction
+    about 0.59, about 6 contacts per sphere, a column about 475 mm high).
+    At the true radii every such contact is pressed by (1 - shrink) of the
+    two radii (about 2 micrometres), the bottom layer into the floor alike.
+    The run starts with the column standing free (the collapse)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     R = MM * np.exp(0.2 * rng.standard_normal(n))
-    vol = float(np.sum(4.0 / 3.0 * np.pi * (shrink * R) ** 3))
     L = 60 * MM
-    H = vol / (phi_rsa * L * L)
-    # the bottom layer starts slightly pressed into the floor, like the
-    # overlapping neighbours inside the packing
-    x = rsa_place(shrink * R, [-L / 2, -L / 2, 0.0], [L / 2, L / 2, H], seed)
+    x, _ = deposit(shrink * R, L, L, seed)
+    x[:, 0] -= 0.5 * L
+    x[:, 1] -= 0.5 * L
     tri = floor_mesh(0.0, 0.0, 300 * MM, 0.0)
     return _finish("cfg2_column_collapse_200k", default_params(dt=5e-7), x, R, rng, tri, 20000)
 
