@@ -358,7 +358,9 @@ def cfg2(seed=202, n=200_000, shrink=0.999):
     rng = np.random.Generator(np.random.PCG64(seed))
     R = MM * np.exp(0.2 * rng.standard_normal(n))
     L = 60 * MM
-    x, _ = deposit(shrink * R, L, L, seed)
+    x, stuck = deposit(shrink * R, L, L, seed)
+    if stuck:
+        raise RuntimeError(f"deposition left {stuck} spheres unsettled")
     x[:, 0] -= 0.5 * L
     x[:, 1] -= 0.5 * L
     tri = floor_mesh(0.0, 0.0, 300 * MM, 0.0)
