@@ -97,8 +97,9 @@ def deposit(R, Lx, Ly, seed):
                                   C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), x.ctypes.data_as(D),
                                   C.byref(stuck))
     if got != len(R):
-        raise RuntimeError(f"deposition failed ({got}): radii must be positive and the cell "
-                           f"at least 6 R_max wide")
+        raise RuntimeError(f"deposition failed ({got}): radii must be positive, the cell at "
+                           f"least 6 R_max wide, and the radii not so unequal that a "
+                           f"neighbour query overflows")
     return x, int(stuck.value)
 
 

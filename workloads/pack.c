@@ -142,6 +142,7 @@ typedef struct {
   int64_t nx, ny, nz;
   int64_t* head;
   int64_t* next;
+  int overflow;  // some query found more spheres than its buffer holds
 } Pile;
 
 typedef struct {
@@ -154,7 +155,7 @@ static int64_t wrap_cell(int64_t i, int64_t n) { return ((i % n) + n) % n; }
 // The spheres of the cells that cover the box |x - c.x|, |y - c.y| <= reach,
 // zlo <= z <= zhi, each at its periodic image nearest c.  Returns the count
 // (at most cap).
-static int64_t gather_box(const Pile* P, V3 c, double reach, double zlo, double zhi, Cand* out,
+static int64_t gather_box(Pile* P, V3 c, double reach, double zlo, double zhi, Cand* out,
                           int64_t cap) {
   int64_t x0 = (int64_t)floor((c.x - reach) / P->hx), x1 = (int64_t)floor((c.x + reach) / P->hx);
   int64_t y0 = (int64_t)floor((c.y - reach) / P->hy), y1 = (int64_t)floor((c.y + reach) / P->hy);
@@ -169,7 +170,10 @@ static int64_t gather_box(const Pile* P, V3 c, double reach, double zlo, double 
       for (int64_t ix = x0; ix <= x1; ++ix) {
         int64_t cell = (iz * P->ny + wrap_cell(iy, P->ny)) * P->nx + wrap_cell(ix, P->nx);
         for (int64_t j = P->head[cell]; j >= 0; j = P->next[j]) {
-          if (m >= cap) return m;
+          if (m >= cap) {
+            P->overflow = 1;
+            return m;
+          }
           double dx = P->x[3 * j] - c.x, dy = P->x[3 * j + 1] - c.y;
           dx -= P->Lx * nearbyint(dx / P->Lx);
           dy -= P->Ly * nearbyint(dy / P->Ly);
@@ -182,7 +186,7 @@ static int64_t gather_box(const Pile* P, V3 c, double reach, double zlo, double 
 }
 
 // The same for the cube of half-width reach around c.
-static int64_t gather(const Pile* P, V3 c, double reach, Cand* out, int64_t cap) {
+static int64_t gather(Pile* P, V3 c, double reach, Cand* out, int64_t cap) {
   return gather_box(P, c, reach, c.z - reach, c.z + reach, out, cap);
 }
 
@@ -226,7 +230,8 @@ static int decompose(const V3* n, int k, V3 b, double* coef) {
  * the periodic cell [0, Lx) x [0, Ly) (Lx, Ly at least 6 max(R)).  Writes
  * the centres to x[n][3] and the number of spheres whose rolling stopped at
  * the step limit (placed where they were) to *unsettled.  Returns n, or -1
- * on bad input.
+ * on bad input or if a neighbour query overflowed its buffer (radii too
+ * unequal for it).
  */
 int64_t pack_deposit(int64_t n, const double* R, double Lx, double Ly, uint64_t seed, double* x,
                      int64_t* unsettled) {
@@ -241,6 +246,7 @@ int64_t pack_deposit(int64_t n, const double* R, double Lx, double Ly, uint64_t 
   Pile P;
   P.R = R;
   P.x = x;
+  P.overflow = 0;
   P.Lx = Lx;
   P.Ly = Ly;
   P.rmax = rmax;
@@ -478,5 +484,5 @@ int64_t pack_deposit(int64_t n, const double* R, double Lx, double Ly, uint64_t 
   free(P.next);
   free(cand);
   if (unsettled) *unsettled = stuck;
-  return n;
+  return P.overflow ? -1 : n;
 }
