@@ -616,6 +616,8 @@ def main():
           file=sys.stderr, flush=True)
     graphs1 = s.graph_stats()
     value = n * K / run["s"]
+    # the state after exactly warmup + K steps, for the other precision's run
+    end_state = s.state() if (K >= 1000 and not args.no_forms and "mixed" in args.forms) else None
     roofline = profiled_step_kernel(s, n, args.profile_steps)
     roofline["traffic"] = measured_traffic(args.workload, args.precision)
     s.close()
@@ -654,8 +656,20 @@ def main():
         print(f"[bench] {other}: the same {K} steps", file=sys.stderr, flush=True)
         g = Solver(w, precision=other, **opts)
         g.step(args.warmup)
+        end_diff = None
         if K >= 1000:
             r2 = timed_run(g, n, K)
+            if end_state is not None:
+                # the two precisions after the same whole run, free-running
+                st2 = g.state()
+                end_diff = {"after_steps": args.warmup + K, "max_rel_diff": {
+                    k: round(rel(st2[k], end_state[k]), 10) for k in ("F", "T", "v", "w", "q")}}
+                end_diff["max_rel_diff"]["x"] = round(
+                    rel(st2["x"] - w["x"], end_state["x"] - w["x"]), 10)
+                end_diff["note"] = ("free-running beyond the horizon of agreement: two FP64 runs "
+                                    "one ulp apart differ by as much after this run; the "
+                                    "tolerance applies to one step and short horizons")
+                del st2
         else:
             m2, b2 = timed_blocks(g, n, K, blocks=3, min_block_steps=K)
             r2 = dict(block_summary(m2, b2, n), s=m2["s"])
@@ -666,6 +680,9 @@ def main():
         forms[other]["speedup_vs_" + args.precision] = round(
             run["ms_per_step"] / forms[other]["ms_per_step"], 4)
         forms["mixed_vs_fp64_one_step"] = mixed_vs_fp64(w, opts)
+        if end_diff is not None:
+            forms["mixed_vs_fp64_after_run"] = end_diff
+    end_state = None
     if "rebuilt" in forms_wanted and skin > 0:
         # the paper's scheme, cells rebuilt every step, same workload
         print("[bench] cells rebuilt every step", file=sys.stderr, flush=True)
